@@ -1,0 +1,418 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle.
+
+Each test checks the oracle against something the paper or mathematics
+fixes: products of integer-valued matrices (exact in binary64), identity and
+permutation matrices, brute force against exact rationals with textbook
+rounding-error bounds, Brent's bound (Section 2.3.2), the embedding rule of
+Section 2.4.1 worked by hand, the printed error tables of the Tests section,
+and a brute-force search for the scaling exponent of Section 2.3.2.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+U = 2.0 ** -53
+
+SHAPES = [(1, 1, 1), (1, 7, 1), (3, 5, 7), (8, 8, 8), (16, 17, 18), (33, 64, 31), (40, 33, 50),
+          (64, 65, 64), (2, 1, 3), (5, 2, 4)]
+
+
+def _int_pair(shape, seed, lo=-8, hi=8):
+    N, P, M = shape
+    return synth.integers((N, P), seed, lo, hi), synth.integers((P, M), seed + 1, lo, hi)
+
+
+def _exact(A, B):
+    return (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float64)
+
+
+def _methods(orc):
+    out = {
+        "naive": orc.naive,
+        "kahan": orc.kahan,
+        "winograd": orc.winograd,
+        "winograd_scaled": orc.winograd_scaled,
+        "split_bf16_s1": lambda A, B: orc.split_model(A, B, 1, 8),
+        "split_bf16_s6": lambda A, B: orc.split_model(A, B, 6, 8),
+        "split_fp16_s4": lambda A, B: orc.split_model(A, B, 4, 10),
+        "split_int8_s7": lambda A, B: orc.split_model(A, B, 7, 7),
+    }
+    for v, name in ((0, "sn"), (1, "sw")):
+        out[name + "_paper"] = (lambda v: lambda A, B: orc.strassen(A, B, v, orc.MODE_PAPER))(v)
+        for L in (0, 1, 2, 3):
+            out["%s_L%d" % (name, L)] = (lambda v, L: lambda A, B: orc.strassen(A, B, v, orc.MODE_LEVELS,
+                                                                               L))(v, L)
+    return out
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_integer_products_are_exact(orc, shape):
+    """Integer entries in {-8..8}: every intermediate of every method is an
+    integer far below 2^53 (split digits below 2^24), so each method must
+    return the exact product bit for bit."""
+    A, B = _int_pair(shape, 7 + sum(shape))
+    ref = _exact(A, B)
+    for name, f in _methods(orc).items():
+        C = f(A, B)
+        assert np.array_equal(C, ref), name
+
+
+def test_integer_products_exact_wide_entries(orc):
+    """Larger integers (|a| <= 1000) still give exact products; the split
+    model then needs several digits, which exercises the digit recursion."""
+    A, B = _int_pair((24, 37, 19), 99, -1000, 1000)
+    ref = _exact(A, B)
+    for name in ("naive", "kahan", "winograd", "winograd_scaled", "sn_L2", "sw_L2", "sw_paper"):
+        assert np.array_equal(_methods(orc)[name](A, B), ref), name
+    # two digits hold each entry exactly; the product of the two second
+    # digits (t + u = 4) is kept only from s = 3 on
+    assert np.array_equal(orc.split_model(A, B, 3, 8), ref)
+    assert np.array_equal(orc.split_model(A, B, 3, 7), ref)
+    assert not np.array_equal(orc.split_model(A, B, 2, 8), ref)
+    assert not np.array_equal(orc.split_model(A, B, 1, 8), ref)
+
+
+def test_identity_and_permutation(orc):
+    rng = np.random.default_rng(5)
+    A = synth.uniform((13, 21), 3)
+    I = np.eye(21)
+    perm = rng.permutation(21)
+    Pm = np.eye(21)[:, perm]  # column permutation matrix
+    for f in (orc.naive, orc.kahan):
+        assert np.array_equal(f(A, I), A)
+        assert np.array_equal(f(A, Pm), A[:, perm])
+        assert np.array_equal(f(np.eye(13), A), A)
+
+
+def test_bruteforce_tiny_against_rationals(orc):
+    """All N, P, M in 1..5 with random doubles: NaivStandard obeys the
+    textbook bound |C^ - C| <= gamma_P |A||B| elementwise (gamma_P =
+    P u / (1 - P u)); Kahan obeys the compensated-sum bound
+    (3u + 2 P u^2) sum_k |a_ik b_kj| + u|c_ij|."""
+    rng = np.random.default_rng(11)
+    for N in range(1, 6):
+        for P in range(1, 6):
+            for M in range(1, 6):
+                A = rng.uniform(-1, 1, (N, P)) * 2.0 ** rng.integers(-3, 4, (N, P))
+                B = rng.uniform(-1, 1, (P, M)) * 2.0 ** rng.integers(-3, 4, (P, M))
+                Cn, Ck = orc.naive(A, B), orc.kahan(A, B)
+                g = P * U / (1 - P * U)
+                for i in range(N):
+                    for j in range(M):
+                        ex = sum(Fraction(A[i, k]) * Fraction(B[k, j]) for k in range(P))
+                        ab = sum(abs(Fraction(A[i, k]) * Fraction(B[k, j])) for k in range(P))
+                        assert abs(Fraction(Cn[i, j]) - ex) <= Fraction(g) * ab
+                        kb = Fraction(3 * U + 2 * P * U * U) * ab + Fraction(U) * abs(ex)
+                        assert abs(Fraction(Ck[i, j]) - ex) <= kb
+
+
+def test_kahan_recovers_cancelled_digits(orc):
+    """sum = 1 + 10 * 1e-16: naive accumulation loses every small term,
+    Kahan's compensation returns the correctly rounded exact sum."""
+    x = [1.0] + [1e-16] * 10
+    A = np.array([x])
+    B = np.ones((len(x), 1))
+    exact = float(sum(Fraction(v) for v in x))
+    assert orc.kahan(A, B)[0, 0] == exact
+    assert orc.naive(A, B)[0, 0] == 1.0 != exact
+    # four half-ulp terms: each naive step ties back to 1, Kahan carries them
+    x = [1.0] + [2.0 ** -53] * 4
+    A = np.array([x])
+    B = np.ones((5, 1))
+    assert orc.kahan(A, B)[0, 0] == 1.0 + 2.0 ** -51
+    assert orc.naive(A, B)[0, 0] == 1.0
+
+
+def test_kahan_random_long_sums_within_bound(orc):
+    """Long random dot products (P = 3000): Kahan's error against the exact
+    rational stays within (3u + 2Pu^2) sum|ab| + u|c|, a bound the naive sum
+    exceeds for cancelling data."""
+    rng = np.random.default_rng(3)
+    P = 3000
+    a = rng.uniform(-1, 1, P) * 1e3
+    a[P // 2:] = -a[: P - P // 2] * (1 + 1e-12)
+    b = np.ones(P)
+    A, B = a[None, :], b[:, None]
+    ex = sum(Fraction(v) for v in a)
+    ab = sum(abs(Fraction(v)) for v in a)
+    bound = Fraction(3 * U + 2 * P * U * U) * ab + Fraction(U) * abs(ex)
+    assert abs(Fraction(orc.kahan(A, B)[0, 0]) - ex) <= bound
+
+
+def test_winograd_small_cases(orc):
+    """P = 1 (gamma = 0): the entry is the single product (odd-P tail only).
+    P = 2: the printed pair identity with y and z; integer data makes both
+    exact.  The y and z vectors equal their defining sums."""
+    A = synth.uniform((4, 1), 1)
+    B = synth.uniform((1, 5), 2)
+    C = orc.winograd(A, B)
+    for i in range(4):
+        for k in range(5):
+            assert C[i, k] == A[i, 0] * B[0, k]
+    A, B = _int_pair((6, 9, 4), 17)
+    C, y, z = orc.winograd(A, B, return_yz=True)
+    assert np.array_equal(C, _exact(A, B))
+    Ai, Bi = A.astype(np.int64), B.astype(np.int64)
+    assert np.array_equal(y, np.array([sum(Ai[i, 2 * j] * Ai[i, 2 * j + 1] for j in range(4))
+                                       for i in range(6)], dtype=float))
+    assert np.array_equal(z, np.array([sum(Bi[2 * j, k] * Bi[2 * j + 1, k] for j in range(4))
+                                       for k in range(4)], dtype=float))
+
+
+def test_winograd_within_brent_bound(orc):
+    """Section 2.3.2: ||E|| <= u (n^2 + 12n - 8)/4 (||A|| + ||B||)^2 for
+    WinogradOriginal and u 9/8 (n^2 + 12n - 8) ||A|| ||B|| for the scaled
+    variant, infinity norm, against exact rational products."""
+    for n, P in ((12, 12), (12, 13), (20, 21)):
+        A = synth.uniform((n, P), 40 + P) * 64.0
+        B = synth.uniform((P, n), 41 + P) / 64.0
+        ex = [[sum(Fraction(A[i, k]) * Fraction(B[k, j]) for k in range(P)) for j in range(n)]
+              for i in range(n)]
+        nA, nB = orc.norm_inf(A), orc.norm_inf(B)
+        d = max(n, P)
+        for C, bound in ((orc.winograd(A, B), U * (d * d + 12 * d - 8) / 4 * (nA + nB) ** 2),
+                         (orc.winograd_scaled(A, B), U * 9 / 8 * (d * d + 12 * d - 8) * nA * nB)):
+            err = max(float(sum(abs(Fraction(C[i, j]) - ex[i][j]) for j in range(n))) for i in range(n))
+            assert err <= bound
+
+
+def _lambda_bruteforce(nA, nB):
+    """Largest integer lambda with 1/2 <= 2^(2 lambda) nA / nB <= 2, by
+    exact rational search around the estimate."""
+    r = Fraction(nA) / Fraction(nB)
+    est = int(round(-math.log2(nA / nB) / 2)) if (nA / nB) > 0 else 0
+    ok = []
+    for lam in range(est - 4, est + 5):
+        v = r * (Fraction(2) ** (2 * lam))
+        if Fraction(1, 2) <= v <= 2:
+            ok.append(lam)
+    assert ok, (nA, nB)
+    return max(ok)
+
+
+def test_lambda_rule_against_bruteforce(orc):
+    rng = np.random.default_rng(21)
+    cases = []
+    for _ in range(4000):
+        cases.append((float(rng.uniform(0.5, 1) * 2.0 ** rng.integers(-60, 60)),
+                      float(rng.uniform(0.5, 1) * 2.0 ** rng.integers(-60, 60))))
+    for _ in range(500):  # exact powers of two apart: the two-solution ties
+        a = float(rng.uniform(0.5, 1) * 2.0 ** rng.integers(-30, 30))
+        cases.append((a, a * 2.0 ** int(rng.integers(-20, 21))))
+    for _ in range(500):  # mantissas equal or adjacent
+        a = float(rng.uniform(0.5, 1))
+        b = float(np.nextafter(a, 2.0 if rng.random() < 0.5 else 0.0))
+        cases.append((a * 2.0 ** int(rng.integers(-9, 9)), b * 2.0 ** int(rng.integers(-9, 9))))
+    for nA, nB in cases:
+        assert orc.winograd_lambda(nA, nB) == _lambda_bruteforce(nA, nB), (nA, nB)
+    for bad in (0.0, float("inf"), float("nan")):
+        assert orc.winograd_lambda(bad, 1.0) == 0
+        assert orc.winograd_lambda(1.0, bad) == 0
+
+
+def test_winograd_scaled_structure(orc):
+    """The paper's test B = 8A puts ||B||/||A|| = 2^3 on a tie: lambda is 1
+    or 2, the larger one is taken.  The scaled product equals
+    WinogradOriginal on (2^lambda A, 2^-lambda B); lambda = 0 reproduces
+    WinogradOriginal."""
+    A, B = synth.paper_test_pair(40, 3)
+    C, lam = orc.winograd_scaled(A, B, return_lambda=True)
+    assert lam == 2
+    assert np.array_equal(C, orc.winograd(A * 4.0, B / 4.0))
+    A = synth.uniform((17, 23), 8)
+    B = synth.uniform((23, 9), 9)
+    C, lam = orc.winograd_scaled(A, B, return_lambda=True)
+    nA, nB = orc.norm_inf(A), orc.norm_inf(B)
+    assert Fraction(1, 2) <= Fraction(nA) * Fraction(2) ** (2 * lam) / Fraction(nB) <= 2
+    if lam == 0:
+        assert np.array_equal(C, orc.winograd(A, B))
+    B2 = B * 2.0 ** 40
+    C2, lam2 = orc.winograd_scaled(A, B2, return_lambda=True)
+    assert lam2 != 0
+    assert np.array_equal(C2, orc.winograd(A * 2.0 ** lam2, B2 * 2.0 ** -lam2))
+
+
+def test_strassen_paper_plan_matches_hand_table(orc):
+    with open(os.path.join(GOLDEN, "strassen_paper_plan.json")) as f:
+        table = json.load(f)
+    for c in table["cases"]:
+        X = c["X"]
+        for shape in ((X, 1, 1), (1, X, 3), (2, 2, X)):
+            assert orc.strassen_paper_plan(*shape) == (c["k"], c["m"], c["Y"]), (X, shape)
+
+
+def test_strassen_levels_zero_is_naive(orc):
+    A = synth.uniform((21, 19, ), 1)
+    B = synth.uniform((19, 23), 2)
+    for v in (0, 1):
+        assert np.array_equal(orc.strassen(A, B, v, orc.MODE_LEVELS, 0), orc.naive(A, B))
+        # X = 23 < 32: the paper rule gives k = 0, a single naive product
+        assert np.array_equal(orc.strassen(A, B, v, orc.MODE_PAPER), orc.naive(A, B))
+
+
+def test_strassen_block_identities_noncommuting(orc):
+    """4x4 integer matrices with 2x2 blocks: blocks do not commute, so an
+    operand swapped inside any H term of Section 2.4 would break the exact
+    product.  Many random draws, one level, both variants."""
+    rng = np.random.default_rng(77)
+    for _ in range(200):
+        A = rng.integers(-9, 10, (4, 4)).astype(float)
+        B = rng.integers(-9, 10, (4, 4)).astype(float)
+        for v in (0, 1):
+            assert np.array_equal(orc.strassen(A, B, v, orc.MODE_LEVELS, 1), _exact(A, B))
+
+
+def test_strassen_rounding_level(orc):
+    """Random data: both variants stay within a normwise error a few orders
+    below the 1e-11 tolerance used for the GPU at 3 levels."""
+    A = synth.uniform((128, 128), 1)
+    B = synth.uniform((128, 128), 2)
+    ref = orc.naive(A, B)
+    nA, nB = orc.norm_inf(A), orc.norm_inf(B)
+    for v in (0, 1):
+        for L in (1, 2, 3):
+            e = orc.rel_err_inf(orc.strassen(A, B, v, orc.MODE_LEVELS, L), ref, nA, nB)
+            assert e < 1e-14, (v, L, e)
+
+
+def test_paper_error_tables(orc):
+    """Tests section: the printed NormInf(N - C) with N = NaivKahan and
+    C = A (8A).  The distribution and seed are unstated, so this is a
+    magnitude check (uniform [0,1) reading, mean over seeds): within 25% of
+    every nonzero printed value at n = 800, and at n = 200 each entry rounds
+    to the printed tenth decimal within a factor 1.5."""
+    with open(os.path.join(GOLDEN, "paper_tables.json")) as f:
+        tables = json.load(f)["tables"]
+    names = {"NaivStandard": orc.naive, "WinogradOriginal": orc.winograd,
+             "WinogradScaled": orc.winograd_scaled,
+             "StrassenNaiv": lambda A, B: orc.strassen(A, B, 0, orc.MODE_PAPER),
+             "StrassenWinograd": lambda A, B: orc.strassen(A, B, 1, orc.MODE_PAPER)}
+    for n, seeds in (("200", range(4)), ("800", range(2))):
+        errs = {k: [] for k in names}
+        for s in seeds:
+            A, B = synth.paper_test_pair(int(n), 500 + s)
+            Nk = orc.kahan(A, B)
+            for k, f in names.items():
+                errs[k].append(orc.norm_inf(orc.minus(Nk, f(A, B))))
+        for k, printed in tables[n].items():
+            mean = float(np.mean(errs[k]))
+            if n == "800":
+                assert abs(mean - printed) <= 0.25 * printed, (n, k, mean, printed)
+            else:
+                lo, hi = (0.0, 0.5e-10 * 1.5) if printed == 0.0 else (0.5e-10 / 1.5, 1.5e-10 * 1.5)
+                assert lo <= mean < hi, (n, k, mean, printed)
+
+
+def test_norm_inf_and_aux(orc):
+    A = np.array([[1.0, -2.0, 3.0], [-4.0, 0.5, 0.25], [0.0, 0.0, -0.0]])
+    assert orc.norm_inf(A) == 6.0
+    assert orc.norm_inf(np.zeros((0, 3))) == 0.0
+    assert orc.norm_inf(np.zeros((2, 0))) == 0.0
+    # sums run left to right: 1 + 2^-53 + 2^-53 rounds to 1 twice
+    t = 2.0 ** -53
+    assert orc.norm_inf(np.array([[1.0, t, t]])) == 1.0
+    assert orc.norm_inf(np.array([[t, t, 1.0]])) == 1.0 + 2.0 ** -52
+    X = synth.uniform((7, 9), 1)
+    Y = synth.uniform((7, 9), 2)
+    assert np.array_equal(orc.plus(X, Y), X + Y)
+    assert np.array_equal(orc.minus(X, Y), X - Y)
+    assert np.array_equal(orc.scale(0.375, X), 0.375 * X)
+    assert orc.max_int(3, -2) == 3 and orc.max_int(-5, -5) == -5
+    assert orc.max_double(-0.5, 0.25) == 0.25
+
+
+def test_rel_err_closed_form(orc):
+    C = np.array([[1.0, 2.0], [3.0, 4.0]])
+    R = np.array([[1.0, 2.5], [2.0, 4.0]])
+    # NormInf(C - R) = max(0.5, 1.0) = 1.0
+    assert orc.rel_err_inf(C, R, 2.0, 4.0) == 1.0 / 8.0
+    assert orc.rel_err_inf(C, R, 0.0, 4.0) == 1.0
+
+
+# -- split-precision model ----------------------------------------------------
+
+def test_split_digits_reconstruct(orc):
+    """Digits satisfy |d_t| <= 2^(beta-1) and sum_t d_t 2^(-beta t) is within
+    2^(-beta s - 1) of the scaled entry, exactly (rational arithmetic); row
+    exponents put every scaled entry in [-1/2, 1/2]."""
+    X = synth.wide_range((6, 11), 4)
+    for beta, s in ((8, 3), (7, 4), (10, 2)):
+        for is_b in (False, True):
+            d, e = orc.split_digits(X, s, beta, 0, is_b)
+            assert np.abs(d).max() <= 2 ** (beta - 1)
+            rows, cols = X.shape
+            for i in range(rows):
+                for j in range(cols):
+                    ex = e[j] if is_b else e[i]
+                    x = Fraction(X[i, j]) / Fraction(2) ** int(ex)
+                    assert abs(x) <= Fraction(1, 2)
+                    rec = sum(Fraction(int(d[t, i, j]), 2 ** (beta * (t + 1))) for t in range(s))
+                    assert abs(rec - x) <= Fraction(1, 2 ** (beta * s + 1))
+
+
+def test_split_lambda_invariance(orc):
+    """Per-row and per-column exponents absorb the 2^(+-lambda) scaling
+    exactly, so the model's result does not depend on it."""
+    A = synth.wide_range((20, 33), 1)
+    B = synth.wide_range((33, 17), 2) * 2.0 ** 30
+    assert np.array_equal(orc.split_model(A, B, 5, 8, True), orc.split_model(A, B, 5, 8, False))
+
+
+def test_split_truncation_bound(orc):
+    """Against the exact rational product: dropping pairs with t+u > s+1 and
+    the digit remainders costs at most (s+2) 2^(-beta s - 2) per term of the
+    scaled dot product, plus FP64 rounding of the final s-term sum."""
+    N, P, M = 6, 40, 5
+    A = synth.wide_range((N, P), 11)
+    B = synth.wide_range((P, M), 12)
+    for s, beta in ((3, 8), (4, 8), (5, 7), (3, 10)):
+        C = orc.split_model(A, B, s, beta, False)
+        _, ea = orc.split_digits(A, 1, beta, 0, False)
+        _, fb = orc.split_digits(B, 1, beta, 0, True)
+        for i in range(N):
+            for j in range(M):
+                ex = sum(Fraction(A[i, k]) * Fraction(B[k, j]) for k in range(P))
+                sc = Fraction(2) ** int(ea[i] + fb[j])
+                trunc = P * (s + 2) * Fraction(1, 2 ** (beta * s + 2)) * Fraction(11, 10)
+                rnd = (s + 1) * Fraction(U) * P * Fraction(1, 4) * 2
+                err = abs(Fraction(C[i, j]) - ex)
+                assert err <= (trunc + rnd) * sc, (s, beta, i, j)
+        # one digit fewer must be visibly worse on this data
+        C1 = orc.split_model(A, B, s - 1, beta, False)
+        assert np.abs(C1 - C).max() > 0
+
+
+def test_split_accuracy_fp64_grade(orc):
+    """On the wide-range distribution (rows scaled by 2^v, entries 2^u),
+    6 bf16-sized digits reach a relative infinity-norm error well below
+    1e-13 against the naive product."""
+    A = synth.wide_range((48, 256), 5)
+    B = synth.wide_range((256, 40), 6)
+    ref = orc.naive(A, B)
+    e = orc.rel_err_inf(orc.split_model(A, B, 6, 8), ref, orc.norm_inf(A), orc.norm_inf(B))
+    assert e < 5e-14
+    e3 = orc.rel_err_inf(orc.split_model(A, B, 3, 8), ref, orc.norm_inf(A), orc.norm_inf(B))
+    assert e3 > 1e-10
+
+
+def test_thread_count_does_not_change_bits(orc):
+    A = synth.uniform((70, 90), 1)
+    B = synth.uniform((90, 60), 2)
+    t0 = orc.get_threads()
+    orc.set_threads(1)
+    r1 = [orc.naive(A, B), orc.kahan(A, B), orc.winograd(A, B), orc.split_model(A, B, 4, 8)]
+    orc.set_threads(4)
+    r4 = [orc.naive(A, B), orc.kahan(A, B), orc.winograd(A, B), orc.split_model(A, B, 4, 8)]
+    orc.set_threads(t0)
+    for a, b in zip(r1, r4):
+        assert np.array_equal(a, b)
+    rows = np.array([0, 5, 69, 33])
+    assert np.array_equal(orc.naive_rows(A, B, rows), orc.naive(A, B)[rows])
+    assert np.array_equal(orc.split_model_rows(A, B, rows, 4, 8), orc.split_model(A, B, 4, 8)[rows])
