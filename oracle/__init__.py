@@ -41,6 +41,8 @@ def _load():
         "oracle_naive": (None, [dp, dp, dp, i64, i64, i64]),
         "oracle_naive_rows": (None, [dp, dp, dp, i64, i64, i64, dp, i64]),
         "oracle_kahan": (None, [dp, dp, dp, i64, i64, i64]),
+        "oracle_kahan_rows": (None, [dp, dp, dp, i64, i64, i64, dp, i64]),
+        "oracle_winograd_rows": (None, [dp, dp, dp, i64, i64, i64, dp, i64, ctypes.c_int]),
         "oracle_winograd": (None, [dp, dp, dp, i64, i64, i64, dp, dp]),
         "oracle_winograd_lambda": (ctypes.c_int, [ctypes.c_double, ctypes.c_double]),
         "oracle_winograd_scaled": (ctypes.c_int, [dp, dp, dp, i64, i64, i64]),
@@ -153,6 +155,26 @@ def kahan(A, B):
     C = np.empty((N, M))
     _load().oracle_kahan(_p(A), _p(B), _p(C), N, P, M)
     return C
+
+
+def kahan_rows(A, B, rows):
+    A, B = _f64(A), _f64(B)
+    N, P, M = _shape(A, B)
+    r = np.ascontiguousarray(rows, dtype=np.int64)
+    assert r.size == 0 or (r.min() >= 0 and r.max() < N)
+    out = np.empty((r.size, M))
+    _load().oracle_kahan_rows(_p(A), _p(B), _p(out), N, P, M, _p(r), r.size)
+    return out
+
+
+def winograd_rows(A, B, rows, scaled=False):
+    A, B = _f64(A), _f64(B)
+    N, P, M = _shape(A, B)
+    r = np.ascontiguousarray(rows, dtype=np.int64)
+    assert r.size == 0 or (r.min() >= 0 and r.max() < N)
+    out = np.empty((r.size, M))
+    _load().oracle_winograd_rows(_p(A), _p(B), _p(out), N, P, M, _p(r), r.size, int(bool(scaled)))
+    return out
 
 
 def winograd(A, B, return_yz=False):

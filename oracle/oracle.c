@@ -160,6 +160,28 @@ void oracle_kahan(const double* A, const double* B, double* C, i64 N, i64 P, i64
     }
 }
 
+/* NaivKahan evaluated only for the listed rows of C. */
+void oracle_kahan_rows(const double* A, const double* B, double* out, i64 N, i64 P, i64 M, const i64* rows,
+                       i64 nrows)
+{
+    (void)N;
+#pragma omp parallel for schedule(static) num_threads(g_threads)
+    for (i64 r = 0; r < nrows; ++r) {
+        const i64 i = rows[r];
+        for (i64 j = 0; j < M; ++j) {
+            double sum = 0.0, err = 0.0, t;
+            for (i64 k = 0; k < P; ++k) {
+                const double x = A[i * P + k] * B[k * M + j];
+                err = err + x;
+                t = sum + err;
+                err = (sum - t) + err;
+                sum = t;
+            }
+            out[r * M + j] = sum;
+        }
+    }
+}
+
 /* ---------------------------------------------------------------------- */
 /* Winograd's algorithm, Section 2.3                                      */
 /* ---------------------------------------------------------------------- */
@@ -252,6 +274,43 @@ int oracle_winograd_scaled(const double* A, const double* B, double* C, i64 N, i
     free(As);
     free(Bs);
     return lambda;
+}
+
+/* WinogradOriginal (scaled = 0) or WinogradScaled (scaled = 1) evaluated
+ * only for the listed rows of C; lambda comes from the norms of all of A
+ * and B, y for the listed rows, z for every column. */
+void oracle_winograd_rows(const double* A, const double* B, double* out, i64 N, i64 P, i64 M, const i64* rows,
+                          i64 nrows, int scaled)
+{
+    int lambda = 0;
+    if (scaled) lambda = oracle_winograd_lambda(oracle_norm_inf(A, N, P), oracle_norm_inf(B, P, M));
+    const double sa = ldexp(1.0, lambda), sb = ldexp(1.0, -lambda);
+    const i64 gamma = P / 2;
+    const int odd = (int)(P % 2);
+    double* z = (double*)malloc(sizeof(double) * (size_t)(M > 0 ? M : 1));
+    for (i64 k = 0; k < M; ++k) {
+        double s = 0.0;
+        for (i64 j = 0; j < gamma; ++j) s = s + (sb * B[(2 * j) * M + k]) * (sb * B[(2 * j + 1) * M + k]);
+        z[k] = s;
+    }
+#pragma omp parallel for schedule(static) num_threads(g_threads)
+    for (i64 r = 0; r < nrows; ++r) {
+        const i64 i = rows[r];
+        double y = 0.0;
+        for (i64 j = 0; j < gamma; ++j) y = y + (sa * A[i * P + 2 * j]) * (sa * A[i * P + 2 * j + 1]);
+        for (i64 k = 0; k < M; ++k) {
+            double s = 0.0;
+            for (i64 j = 0; j < gamma; ++j) {
+                const double u = sa * A[i * P + 2 * j] + sb * B[(2 * j + 1) * M + k];
+                const double v = sa * A[i * P + 2 * j + 1] + sb * B[(2 * j) * M + k];
+                s = s + u * v;
+            }
+            double c = (s - y) - z[k];
+            if (odd) c = c + (sa * A[i * P + (P - 1)]) * (sb * B[(P - 1) * M + k]);
+            out[r * M + k] = c;
+        }
+    }
+    free(z);
 }
 
 /* ---------------------------------------------------------------------- */

@@ -1,0 +1,404 @@
+// C ABI of libmmm (declared in include/mmm.h): argument validation,
+// workspace planning and dispatch of the methods to the gfx950 kernels.
+// Nothing here computes matrix entries; every entry is produced by a
+// kernel.  No call allocates device memory except mmm_batch_create.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "common.h"
+#include "launch.h"
+#include "split.h"
+
+using namespace mmm;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+mmm_status fail(mmm_status st, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+mmm_status from_hip(hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return MMM_OK;
+    return fail(MMM_ELAUNCH, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool overlap(const void* a, size_t abytes, const void* b, size_t bbytes)
+{
+    if (!a || !b || abytes == 0 || bbytes == 0) return false;
+    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return a0 < b0 + bbytes && b0 < a0 + abytes;
+}
+
+mmm_status check_cfg(const mmm_config& c)
+{
+    for (int i = 0; i < 9; ++i)
+        if (c.reserved[i] != 0) return fail(MMM_EINVAL, "config: reserved fields must be zero");
+    if (c.strassen_levels < 0 || c.strassen_levels > kMaxDepth)
+        return fail(MMM_EINVAL, "config: strassen_levels %d outside 0..%d", c.strassen_levels, kMaxDepth);
+    if (c.pad_mode != MMM_PAD_PAPER && c.pad_mode != MMM_PAD_LEVELS) return fail(MMM_EINVAL, "config: bad pad_mode");
+    if (c.strassen_leaf != MMM_LEAF_DGEMM && c.strassen_leaf != MMM_LEAF_NAIVE)
+        return fail(MMM_EINVAL, "config: bad strassen_leaf");
+    if (c.split_slices < 1 || c.split_slices > kMaxSlices)
+        return fail(MMM_EINVAL, "config: split_slices %d outside 1..%d", c.split_slices, kMaxSlices);
+    if (c.split_type != MMM_SLICE_BF16 && c.split_type != MMM_SLICE_FP16 && c.split_type != MMM_SLICE_INT8)
+        return fail(MMM_EINVAL, "config: bad split_type");
+    if (c.split_scale_lambda != 0 && c.split_scale_lambda != 1) return fail(MMM_EINVAL, "config: bad split_scale_lambda");
+    if (c.naive_fma != 0 && c.naive_fma != 1) return fail(MMM_EINVAL, "config: bad naive_fma");
+    return MMM_OK;
+}
+
+// ---- Strassen planning (Section 2.4) ---------------------------------------
+
+struct StrassenPlan {
+    int depth = 0;
+    bool direct_naive = false;  // paper rule gave k = 0: one naive product
+    bool pad = false;
+    bool naive_leaf = false;
+    i64 Np = 0, Pp = 0, Mp = 0;
+    i64 n[kMaxDepth + 1], p[kMaxDepth + 1], m[kMaxDepth + 1];
+    size_t off_A = 0, off_B = 0, off_C = 0;
+    size_t off_WA[kMaxDepth + 1], off_WB[kMaxDepth + 1], off_H[kMaxDepth + 1];
+    size_t bytes = 0;
+};
+
+i64 pow7(int e)
+{
+    i64 r = 1;
+    for (int i = 0; i < e; ++i) r *= 7;
+    return r;
+}
+
+// Returns false when the plan would not fit in 64-bit sizes.
+bool plan_strassen(i64 N, i64 P, i64 M, const mmm_config& c, StrassenPlan& pl)
+{
+    if (c.pad_mode == MMM_PAD_PAPER) {
+        // X = max{N,P,M}, k = floor(log2 X) - 4 (at least 0), m = floor(X 2^-k) + 1, Y = m 2^k
+        i64 X = N > P ? N : P;
+        X = X > M ? X : M;
+        int lg = -1;
+        for (i64 t = X; t > 0; t >>= 1) ++lg;
+        int k = lg - 4;
+        if (k < 0) k = 0;
+        if (k == 0) {
+            pl.direct_naive = true;
+            return true;
+        }
+        if (k > kMaxDepth) return false;
+        const i64 mm = (X >> k) + 1;
+        pl.depth = k;
+        pl.Np = pl.Pp = pl.Mp = mm << k;
+        pl.naive_leaf = true;
+    } else {
+        pl.depth = c.strassen_levels;
+        const i64 q = (i64)1 << pl.depth;
+        pl.Np = cdiv(N, q) * q;
+        pl.Pp = cdiv(P, q) * q;
+        pl.Mp = cdiv(M, q) * q;
+        pl.naive_leaf = c.strassen_leaf == MMM_LEAF_NAIVE;
+    }
+    pl.pad = pl.Np != N || pl.Pp != P || pl.Mp != M;
+    size_t off = 0;
+    auto take = [&](double elems) -> size_t {
+        const size_t at = off;
+        off = align_up(off + (size_t)elems * sizeof(double));
+        return at;
+    };
+    // guard against absurd sizes before doing integer arithmetic
+    double total = 0;
+    for (int d = 0; d <= pl.depth; ++d) {
+        pl.n[d] = pl.Np >> d;
+        pl.p[d] = pl.Pp >> d;
+        pl.m[d] = pl.Mp >> d;
+        if (d > 0)
+            total += (double)pow7(d) * ((double)pl.n[d] * pl.p[d] + (double)pl.p[d] * pl.m[d] + (double)pl.n[d] * pl.m[d]);
+    }
+    total += (double)pl.Np * pl.Pp + (double)pl.Pp * pl.Mp + (double)pl.Np * pl.Mp;
+    if (total * 8.0 > 9.0e18) return false;
+    if (pl.pad) {
+        pl.off_A = take((double)pl.Np * pl.Pp);
+        pl.off_B = take((double)pl.Pp * pl.Mp);
+        pl.off_C = take((double)pl.Np * pl.Mp);
+    }
+    for (int d = 1; d <= pl.depth; ++d) {
+        const double nodes = (double)pow7(d);
+        pl.off_WA[d] = take(nodes * pl.n[d] * pl.p[d]);
+        pl.off_WB[d] = take(nodes * pl.p[d] * pl.m[d]);
+        pl.off_H[d] = take(nodes * pl.n[d] * pl.m[d]);
+    }
+    pl.bytes = off;
+    return true;
+}
+
+mmm_status run_strassen(int variant, const double* A, const double* B, double* C, i64 N, i64 P, i64 M,
+                        const StrassenPlan& pl, char* ws, hipStream_t s)
+{
+    hipError_t e;
+    if (pl.direct_naive) return from_hip(launch_naive(Gemm{A, P, B, M, C, M, N, P, M}, false, s), "naive");
+    StrassenTree T;
+    memset(&T, 0, sizeof(T));
+    T.variant = variant;
+    T.depth = pl.depth;
+    double* Croot = C;
+    i64 ldc = M;
+    if (pl.pad) {
+        double* Ap = (double*)(ws + pl.off_A);
+        double* Bp = (double*)(ws + pl.off_B);
+        if ((e = launch_pad_copy(A, P, N, P, Ap, pl.Pp, pl.Np, pl.Pp, s)) != hipSuccess) return from_hip(e, "pad A");
+        if ((e = launch_pad_copy(B, M, P, M, Bp, pl.Mp, pl.Pp, pl.Mp, s)) != hipSuccess) return from_hip(e, "pad B");
+        T.A = Ap;
+        T.lda = pl.Pp;
+        T.B = Bp;
+        T.ldb = pl.Mp;
+        Croot = (double*)(ws + pl.off_C);
+        ldc = pl.Mp;
+    } else {
+        T.A = A;
+        T.lda = P;
+        T.B = B;
+        T.ldb = M;
+    }
+    for (int d = 0; d <= pl.depth; ++d) {
+        T.n[d] = pl.n[d];
+        T.p[d] = pl.p[d];
+        T.m[d] = pl.m[d];
+        if (d > 0) {
+            T.WA[d] = (double*)(ws + pl.off_WA[d]);
+            T.WB[d] = (double*)(ws + pl.off_WB[d]);
+            T.H[d] = (double*)(ws + pl.off_H[d]);
+        }
+    }
+    T.H[0] = Croot;  // the depth-0 "leaf" is the whole product
+    for (int d = 1; d <= pl.depth; ++d)
+        if ((e = launch_strassen_pre(T, d, s)) != hipSuccess) return from_hip(e, "strassen pre");
+    StrassenLeafSrc leaves{T, pow7(pl.depth)};
+    e = pl.naive_leaf ? launch_naive_strassen_leaves(leaves, s) : launch_dgemm_strassen_leaves(leaves, s);
+    if (e != hipSuccess) return from_hip(e, "strassen leaves");
+    for (int d = pl.depth; d >= 1; --d)
+        if ((e = launch_strassen_post(T, d, Croot, ldc, s)) != hipSuccess) return from_hip(e, "strassen post");
+    if (pl.pad && (e = launch_pad_copy(Croot, ldc, N, M, C, M, N, M, s)) != hipSuccess) return from_hip(e, "extract C");
+    return MMM_OK;
+}
+
+// ---- Winograd (Section 2.3) workspace ---------------------------------------
+
+struct WinoLayout {
+    size_t y = 0, z = 0, nA = 0, nB = 0, lam = 0, bytes = 0;
+};
+
+WinoLayout wino_layout(i64 N, i64 M, bool scaled)
+{
+    WinoLayout w;
+    size_t off = 0;
+    w.y = off;
+    off = align_up(off + sizeof(double) * (size_t)(N > 0 ? N : 1));
+    w.z = off;
+    off = align_up(off + sizeof(double) * (size_t)(M > 0 ? M : 1));
+    if (scaled) {
+        w.nA = off;
+        off = align_up(off + sizeof(double));
+        w.nB = off;
+        off = align_up(off + sizeof(double));
+        w.lam = off;
+        off = align_up(off + sizeof(int));
+    }
+    w.bytes = off;
+    return w;
+}
+
+mmm_status run_winograd(const double* A, const double* B, double* C, i64 N, i64 P, i64 M, bool scaled, char* ws,
+                        hipStream_t s)
+{
+    const WinoLayout w = wino_layout(N, M, scaled);
+    double* y = (double*)(ws + w.y);
+    double* z = (double*)(ws + w.z);
+    int* lam = nullptr;
+    hipError_t e;
+    if (scaled) {
+        double* nA = (double*)(ws + w.nA);
+        double* nB = (double*)(ws + w.nB);
+        lam = (int*)(ws + w.lam);
+        if ((e = launch_norm_inf(A, N, P, nA, s)) != hipSuccess) return from_hip(e, "norm A");
+        if ((e = launch_norm_inf(B, P, M, nB, s)) != hipSuccess) return from_hip(e, "norm B");
+        if ((e = launch_lambda(nA, nB, lam, s)) != hipSuccess) return from_hip(e, "lambda");
+    }
+    // y_i over the rows of 2^lambda A, z_k over the columns of 2^-lambda B
+    if ((e = launch_vector_reduce(RED_PAIR_SUM, false, A, P, N, P, y, lam, +1, s)) != hipSuccess) return from_hip(e, "y");
+    if ((e = launch_vector_reduce(RED_PAIR_SUM, true, B, M, M, P, z, lam, -1, s)) != hipSuccess) return from_hip(e, "z");
+    return from_hip(launch_winograd_main(Gemm{A, P, B, M, C, M, N, P, M}, y, z, lam, s), "winograd");
+}
+
+}  // namespace
+
+extern "C" {
+
+mmm_config mmm_config_default(void)
+{
+    mmm_config c;
+    memset(&c, 0, sizeof(c));
+    c.strassen_levels = 2;
+    c.pad_mode = MMM_PAD_LEVELS;
+    c.strassen_leaf = MMM_LEAF_DGEMM;
+    c.split_slices = 6;
+    c.split_type = MMM_SLICE_BF16;
+    c.split_scale_lambda = 1;
+    c.naive_fma = 0;
+    return c;
+}
+
+size_t mmm_workspace_bytes(mmm_method method, int64_t N, int64_t P, int64_t M, const mmm_config* cfgp)
+{
+    const mmm_config c = cfgp ? *cfgp : mmm_config_default();
+    if (N < 0 || P < 0 || M < 0 || check_cfg(c) != MMM_OK) return (size_t)-1;
+    if (N == 0 || M == 0 || P == 0) return 0;
+    switch (method) {
+    case MMM_NAIVE:
+    case MMM_KAHAN:
+    case MMM_DGEMM:
+        return 0;
+    case MMM_WINOGRAD:
+        return wino_layout(N, M, false).bytes;
+    case MMM_WINOGRAD_SCALED:
+        return wino_layout(N, M, true).bytes;
+    case MMM_STRASSEN_NAIVE:
+    case MMM_STRASSEN_WINOGRAD: {
+        StrassenPlan pl;
+        if (!plan_strassen(N, P, M, c, pl)) return (size_t)-1;
+        return pl.bytes;
+    }
+    case MMM_SPLIT:
+        return split_workspace_bytes(N, P, M, c);
+    default:
+        return (size_t)-1;
+    }
+}
+
+mmm_status mmm_multiply(const double* A, const double* B, double* C, int64_t N, int64_t P, int64_t M,
+                        mmm_method method, const mmm_config* cfgp, void* workspace, size_t workspace_bytes,
+                        void* stream)
+{
+    const mmm_config c = cfgp ? *cfgp : mmm_config_default();
+    mmm_status st = check_cfg(c);
+    if (st != MMM_OK) return st;
+    if (N < 0 || P < 0 || M < 0) return fail(MMM_EINVAL, "negative size (%lld, %lld, %lld)", (long long)N, (long long)P, (long long)M);
+    if ((int)method < 0 || (int)method >= MMM_METHOD_COUNT) return fail(MMM_EINVAL, "unknown method %d", (int)method);
+    if (N == 0 || M == 0) return MMM_OK;
+    if (!C) return fail(MMM_EINVAL, "C is null");
+    if (P > 0 && (!A || !B)) return fail(MMM_EINVAL, "A or B is null");
+    const size_t cb = sizeof(double) * (size_t)N * (size_t)M;
+    if (overlap(C, cb, A, sizeof(double) * (size_t)N * (size_t)P) || overlap(C, cb, B, sizeof(double) * (size_t)P * (size_t)M))
+        return fail(MMM_EALIAS, "C overlaps A or B");
+    hipStream_t s = (hipStream_t)stream;
+    if (P == 0) return from_hip(launch_fill_zero(C, N * M, s), "zero C");
+
+    const size_t need = mmm_workspace_bytes(method, N, P, M, &c);
+    if (need == (size_t)-1) return fail(MMM_EINVAL, "problem too large for the chosen plan");
+    if (need > 0) {
+        if (!workspace) return fail(MMM_EWORKSPACE, "workspace of %zu bytes required", need);
+        if (workspace_bytes < need) return fail(MMM_EWORKSPACE, "workspace %zu < %zu bytes", workspace_bytes, need);
+        if ((uintptr_t)workspace % kAlign) return fail(MMM_EWORKSPACE, "workspace must be %zu-byte aligned", kAlign);
+        if (overlap(workspace, need, C, cb) || overlap(workspace, need, A, sizeof(double) * (size_t)N * (size_t)P) ||
+            overlap(workspace, need, B, sizeof(double) * (size_t)P * (size_t)M))
+            return fail(MMM_EALIAS, "workspace overlaps an operand");
+    }
+    char* ws = (char*)workspace;
+    const Gemm g{A, P, B, M, C, M, N, P, M};
+    switch (method) {
+    case MMM_NAIVE:
+        return from_hip(launch_naive(g, c.naive_fma != 0, s), "naive");
+    case MMM_KAHAN:
+        return from_hip(launch_kahan(g, s), "kahan");
+    case MMM_DGEMM:
+        return from_hip(launch_dgemm(g, s), "dgemm");
+    case MMM_WINOGRAD:
+        return run_winograd(A, B, C, N, P, M, false, ws, s);
+    case MMM_WINOGRAD_SCALED:
+        return run_winograd(A, B, C, N, P, M, true, ws, s);
+    case MMM_STRASSEN_NAIVE:
+    case MMM_STRASSEN_WINOGRAD: {
+        StrassenPlan pl;
+        if (!plan_strassen(N, P, M, c, pl)) return fail(MMM_EINVAL, "strassen plan too large");
+        return run_strassen(method == MMM_STRASSEN_NAIVE ? 0 : 1, A, B, C, N, P, M, pl, ws, s);
+    }
+    case MMM_SPLIT: {
+        hipError_t e = run_split(A, B, C, N, P, M, c, ws, s);
+        if (e == hipErrorNotSupported) return fail(MMM_EUNSUPPORTED, "split configuration not supported");
+        return from_hip(e, "split");
+    }
+    default:
+        return fail(MMM_EINVAL, "unknown method");
+    }
+}
+
+static mmm_status ew_call(EwOp op, const double* A, const double* B, double alpha, double* C, int64_t rows,
+                          int64_t cols, void* stream)
+{
+    if (rows < 0 || cols < 0) return fail(MMM_EINVAL, "negative size");
+    const i64 n = rows * cols;
+    if (n == 0) return MMM_OK;
+    if (!A || !C || (op != EW_SCALE && !B)) return fail(MMM_EINVAL, "null pointer");
+    const size_t nb = sizeof(double) * (size_t)n;
+    if ((C != A && overlap(C, nb, A, nb)) || (op != EW_SCALE && C != B && overlap(C, nb, B, nb)))
+        return fail(MMM_EALIAS, "C partially overlaps an operand");
+    return from_hip(launch_elementwise(op, A, B, alpha, C, n, (hipStream_t)stream), "elementwise");
+}
+
+mmm_status mmm_plus(const double* A, const double* B, double* C, int64_t rows, int64_t cols, void* stream)
+{
+    return ew_call(EW_PLUS, A, B, 0.0, C, rows, cols, stream);
+}
+
+mmm_status mmm_minus(const double* A, const double* B, double* C, int64_t rows, int64_t cols, void* stream)
+{
+    return ew_call(EW_MINUS, A, B, 0.0, C, rows, cols, stream);
+}
+
+mmm_status mmm_multiply_with_scalar(double alpha, const double* A, double* C, int64_t rows, int64_t cols, void* stream)
+{
+    return ew_call(EW_SCALE, A, nullptr, alpha, C, rows, cols, stream);
+}
+
+mmm_status mmm_norm_inf(const double* A, int64_t rows, int64_t cols, double* out, void* stream)
+{
+    if (rows < 0 || cols < 0) return fail(MMM_EINVAL, "negative size");
+    if (!out) return fail(MMM_EINVAL, "out is null");
+    if (rows * cols > 0 && !A) return fail(MMM_EINVAL, "A is null");
+    return from_hip(launch_norm_inf(A, rows, cols, out, (hipStream_t)stream), "norm_inf");
+}
+
+mmm_status mmm_winograd_lambda(const double* normA, const double* normB, int32_t* lambda_out, void* stream)
+{
+    if (!normA || !normB || !lambda_out) return fail(MMM_EINVAL, "null pointer");
+    return from_hip(launch_lambda(normA, normB, (int*)lambda_out, (hipStream_t)stream), "lambda");
+}
+
+const char* mmm_status_string(mmm_status s)
+{
+    switch (s) {
+    case MMM_OK: return "ok";
+    case MMM_EINVAL: return "invalid argument";
+    case MMM_EALIAS: return "output overlaps an input";
+    case MMM_EWORKSPACE: return "workspace too small or misaligned";
+    case MMM_EUNSUPPORTED: return "unsupported";
+    case MMM_ELAUNCH: return "kernel launch failed";
+    case MMM_ENOMEM: return "out of memory";
+    default: return "unknown status";
+    }
+}
+
+const char* mmm_last_error(void) { return g_err; }
+
+int32_t mmm_version(void) { return 100; }
+
+}  // extern "C"

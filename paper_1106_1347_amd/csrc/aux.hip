@@ -1,0 +1,280 @@
+// Auxiliary routines of Section 1 (Plus, Minus, MultiplyWithScalar,
+// NormInf) and the sequential vector reductions used by WinogradOriginal's
+// precompute (y_i, z_k), WinogradScaled's norms and the split product's
+// row and column exponents.  All are bound by HBM bandwidth.
+//
+// Built with -ffp-contract=off: every sum and product is rounded on its
+// own, and each reduction runs over its vector in ascending order, so the
+// results equal a sequential binary64 evaluation bit for bit.
+#include "common.h"
+#include "launch.h"
+
+namespace mmm {
+
+namespace {
+
+__device__ inline double max_s13(double x, double y) { return x >= y ? x : y; }  // Section 1.3
+
+template <int OP>
+__device__ inline double ew(double a, double b, double alpha)
+{
+    if (OP == EW_PLUS) return a + b;
+    if (OP == EW_MINUS) return a - b;
+    return alpha * a;
+}
+
+// Plus / Minus / MultiplyWithScalar: 16-byte loads and stores when every
+// pointer is 16-byte aligned, otherwise 8-byte ones; grid-stride loops.
+template <int OP, bool VEC>
+__global__ __launch_bounds__(256) void ew_kernel(const double* A, const double* B, double alpha, double* C, i64 n)
+{
+    const i64 stride = (i64)gridDim.x * 256;
+    const i64 t = (i64)blockIdx.x * 256 + threadIdx.x;
+    if (VEC) {
+        const i64 n2 = n / 2;
+        const double2* A2 = reinterpret_cast<const double2*>(A);
+        const double2* B2 = reinterpret_cast<const double2*>(B);
+        double2* C2 = reinterpret_cast<double2*>(C);
+        for (i64 i = t; i < n2; i += stride) {
+            const double2 a = A2[i];
+            double2 b = make_double2(0.0, 0.0);
+            if (OP != EW_SCALE) b = B2[i];
+            double2 c;
+            c.x = ew<OP>(a.x, b.x, alpha);
+            c.y = ew<OP>(a.y, b.y, alpha);
+            C2[i] = c;
+        }
+        if ((n & 1) && t == 0) C[n - 1] = ew<OP>(A[n - 1], OP != EW_SCALE ? B[n - 1] : 0.0, alpha);
+    } else {
+        for (i64 i = t; i < n; i += stride) C[i] = ew<OP>(A[i], OP != EW_SCALE ? B[i] : 0.0, alpha);
+    }
+}
+
+template <int OP>
+hipError_t launch_ew(const double* A, const double* B, double alpha, double* C, i64 n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const bool vec = ((uintptr_t)A % 16 == 0) && ((uintptr_t)C % 16 == 0) && (OP == EW_SCALE || (uintptr_t)B % 16 == 0);
+    const i64 work = vec ? (n + 1) / 2 : n;
+    i64 blocks = cdiv(work, 256 * 4);
+    if (blocks > 256 * 16) blocks = 256 * 16;
+    if (blocks < 1) blocks = 1;
+    if (vec)
+        hipLaunchKernelGGL((ew_kernel<OP, true>), dim3((unsigned)blocks), dim3(256), 0, s, A, B, alpha, C, n);
+    else
+        hipLaunchKernelGGL((ew_kernel<OP, false>), dim3((unsigned)blocks), dim3(256), 0, s, A, B, alpha, C, n);
+    return hipGetLastError();
+}
+
+// Sequential reduction of 16 vectors per workgroup.  The workgroup streams
+// each vector in chunks of 256 entries through double-buffered LDS with
+// coalesced loads (rows: 2 KiB runs; columns: 128-byte runs of 16
+// neighbouring columns); 16 lanes then fold their vector's chunk in order.
+constexpr int RV = 16, RL = 256, RPER = RV * RL / 256;
+
+template <int OP, bool COLS, bool SCALED, bool FOLD_MAX>
+__global__ __launch_bounds__(256) void vecred_kernel(const double* __restrict__ X, i64 ld, i64 nvec, i64 len,
+                                                     double* __restrict__ out, const int* lam, int sign)
+{
+    __shared__ double T[2][RV][RL + 1];
+    const int tid = threadIdx.x;
+    const i64 v0 = (i64)blockIdx.x * RV;
+    const i64 lim = (OP == RED_PAIR_SUM) ? 2 * (len / 2) : len;
+    const i64 nchunks = (lim + RL - 1) / RL;
+    const double sc = SCALED ? ldexp(1.0, sign * *lam) : 1.0;
+    double r[RPER];
+    auto load = [&](i64 c) {
+#pragma unroll
+        for (int q = 0; q < RPER; ++q) {
+            const int e = q * 256 + tid;
+            const int v = COLS ? (e % RV) : (e / RL);
+            const int x = COLS ? (e / RV) : (e % RL);
+            const i64 gv = v0 + v, gx = c * RL + x;
+            double val = 0.0;
+            if (gv < nvec && gx < lim) val = COLS ? X[gx * ld + gv] : X[gv * ld + gx];
+            r[q] = val;
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < RPER; ++q) {
+            const int e = q * 256 + tid;
+            const int v = COLS ? (e % RV) : (e / RL);
+            const int x = COLS ? (e / RV) : (e % RL);
+            T[buf][v][x] = r[q];
+        }
+    };
+    double acc = 0.0;
+    if (nchunks > 0) {
+        load(0);
+        store(0);
+    }
+    __syncthreads();
+    for (i64 c = 0; c < nchunks; ++c) {
+        const int cur = (int)(c & 1);
+        if (c + 1 < nchunks) load(c + 1);
+        if (tid < RV) {
+            const i64 rem = lim - c * RL;
+            const int cnt = rem < RL ? (int)rem : RL;
+            const double* row = T[cur][tid];
+            if (OP == RED_ABS_SUM) {
+                for (int x = 0; x < cnt; ++x) acc = acc + fabs(SCALED ? row[x] * sc : row[x]);
+            } else if (OP == RED_PAIR_SUM) {
+                for (int x = 0; x < cnt; x += 2) {
+                    const double a = SCALED ? row[x] * sc : row[x];
+                    const double b = SCALED ? row[x + 1] * sc : row[x + 1];
+                    const double p = a * b;
+                    acc = acc + p;
+                }
+            } else {
+                for (int x = 0; x < cnt; ++x) acc = max_s13(acc, fabs(SCALED ? row[x] * sc : row[x]));
+            }
+        }
+        if (c + 1 < nchunks) store(cur ^ 1);
+        __syncthreads();
+    }
+    if (tid < RV && v0 + tid < nvec) {
+        if (FOLD_MAX) {
+            // max over vectors of non-negative values: the order of binary64
+            // bit patterns of non-negative numbers is their numeric order
+            atomicMax(reinterpret_cast<unsigned long long*>(out), (unsigned long long)__double_as_longlong(acc));
+        } else {
+            out[v0 + tid] = acc;
+        }
+    }
+}
+
+template <int OP, bool COLS>
+hipError_t launch_vr2(const double* X, i64 ld, i64 nvec, i64 len, double* out, const int* lam, int sign,
+                      hipStream_t s)
+{
+    const i64 blocks = cdiv(nvec, RV);
+    if (blocks == 0) return hipSuccess;
+    if (lam)
+        hipLaunchKernelGGL((vecred_kernel<OP, COLS, true, false>), dim3((unsigned)blocks), dim3(256), 0, s, X, ld, nvec,
+                           len, out, lam, sign);
+    else
+        hipLaunchKernelGGL((vecred_kernel<OP, COLS, false, false>), dim3((unsigned)blocks), dim3(256), 0, s, X, ld,
+                           nvec, len, out, lam, sign);
+    return hipGetLastError();
+}
+
+template <int OP>
+hipError_t launch_vr1(bool cols, const double* X, i64 ld, i64 nvec, i64 len, double* out, const int* lam, int sign,
+                      hipStream_t s)
+{
+    return cols ? launch_vr2<OP, true>(X, ld, nvec, len, out, lam, sign, s)
+                : launch_vr2<OP, false>(X, ld, nvec, len, out, lam, sign, s);
+}
+
+__global__ __launch_bounds__(256) void max_kernel(const double* v, i64 n, double* out)
+{
+    __shared__ double red[256];
+    double m = 0.0;
+    for (i64 i = threadIdx.x; i < n; i += 256) m = max_s13(m, v[i]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = max_s13(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+__device__ inline long long floor_half(long long x) { return x >= 0 ? x / 2 : -((-x + 1) / 2); }
+
+// Section 2.3.2: largest integer lambda with 1/2 <= 2^(2 lambda) nA/nB <= 2.
+// Write nA = a 2^eA, nB = b 2^eB (a, b in [1/2, 1)), d = eB - eA and
+// x = 2 lambda - d; the condition is 1/2 <= (a/b) 2^x <= 2.  For b > a it
+// holds for x in {0, 1}, for b < a for x in {-1, 0}, for a = b for
+// x in {-1, 0, 1}; the largest lambda is floor((d+1)/2) when b >= a and
+// floor(d/2) otherwise.
+__global__ void lambda_kernel(const double* nA, const double* nB, int* lam)
+{
+    const double a = *nA, b = *nB;
+    int res = 0;
+    if (a > 0.0 && b > 0.0 && !isinf(a) && !isinf(b)) {
+        int eA, eB;
+        const double fa = frexp(a, &eA);
+        const double fb = frexp(b, &eB);
+        const long long d = (long long)eB - (long long)eA;
+        res = (int)(fb >= fa ? floor_half(d + 1) : floor_half(d));
+    }
+    *lam = res;
+}
+
+__global__ __launch_bounds__(256) void pad_kernel(const double* src, i64 lds, i64 r, i64 c, double* dst, i64 ldd,
+                                                   i64 R, i64 C)
+{
+    const i64 total = R * C;
+    for (i64 e = (i64)blockIdx.x * 256 + threadIdx.x; e < total; e += (i64)gridDim.x * 256) {
+        const i64 i = e / C, j = e - i * C;
+        dst[i * ldd + j] = (i < r && j < c) ? src[i * lds + j] : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void zero_kernel(double* dst, i64 n)
+{
+    for (i64 e = (i64)blockIdx.x * 256 + threadIdx.x; e < n; e += (i64)gridDim.x * 256) dst[e] = 0.0;
+}
+
+}  // namespace
+
+hipError_t launch_elementwise(EwOp op, const double* A, const double* B, double alpha, double* C, i64 n,
+                              hipStream_t s)
+{
+    if (op == EW_PLUS) return launch_ew<EW_PLUS>(A, B, alpha, C, n, s);
+    if (op == EW_MINUS) return launch_ew<EW_MINUS>(A, B, alpha, C, n, s);
+    return launch_ew<EW_SCALE>(A, B, alpha, C, n, s);
+}
+
+hipError_t launch_vector_reduce(RedOp op, bool cols, const double* X, i64 ld, i64 nvec, i64 len, double* out,
+                                const int* lam, int sign, hipStream_t s)
+{
+    if (op == RED_ABS_SUM) return launch_vr1<RED_ABS_SUM>(cols, X, ld, nvec, len, out, lam, sign, s);
+    if (op == RED_PAIR_SUM) return launch_vr1<RED_PAIR_SUM>(cols, X, ld, nvec, len, out, lam, sign, s);
+    return launch_vr1<RED_ABS_MAX>(cols, X, ld, nvec, len, out, lam, sign, s);
+}
+
+hipError_t launch_norm_inf(const double* X, i64 rows, i64 cols, double* out, hipStream_t s)
+{
+    hipError_t e = launch_fill_zero(out, 1, s);
+    if (e != hipSuccess || rows <= 0) return e;
+    hipLaunchKernelGGL((vecred_kernel<RED_ABS_SUM, false, false, true>), dim3((unsigned)cdiv(rows, RV)), dim3(256), 0,
+                       s, X, cols, rows, cols, out, nullptr, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_reduce(const double* v, i64 n, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(max_kernel, dim3(1), dim3(256), 0, s, v, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_lambda(const double* nA, const double* nB, int* lam, hipStream_t s)
+{
+    hipLaunchKernelGGL(lambda_kernel, dim3(1), dim3(1), 0, s, nA, nB, lam);
+    return hipGetLastError();
+}
+
+hipError_t launch_pad_copy(const double* src, i64 lds, i64 r, i64 c, double* dst, i64 ldd, i64 R, i64 C,
+                           hipStream_t s)
+{
+    const i64 total = R * C;
+    if (total <= 0) return hipSuccess;
+    i64 blocks = cdiv(total, 256 * 4);
+    if (blocks > 256 * 16) blocks = 256 * 16;
+    hipLaunchKernelGGL(pad_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, lds, r, c, dst, ldd, R, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(double* dst, i64 n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    i64 blocks = cdiv(n, 256 * 4);
+    if (blocks > 256 * 16) blocks = 256 * 16;
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace mmm

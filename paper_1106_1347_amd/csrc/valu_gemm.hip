@@ -1,0 +1,297 @@
+// Inner-product methods of Section 2 on the FP64 vector ALUs of gfx950:
+// NaivStandard (2.1.1), NaivKahan (2.1.3) and the main loop of
+// WinogradOriginal (2.3.1, also used by WinogradScaled 2.3.2).
+//
+// Every output entry is owned by one lane, which runs the paper's recurrence
+// over k (or over the index pairs) in ascending order.  The file is built
+// with -ffp-contract=off, so each product and each sum is rounded on its own
+// exactly as the recurrence is written; with the same order this makes the
+// results equal bit for bit to a sequential binary64 evaluation.  Only the
+// optional fused variant of the naive method calls fma() explicitly.
+//
+// Tiling: 256 threads (16 x 16) per workgroup own a BM x BN tile of C, each
+// thread a TM x TN register block (rows ty*TM + i, columns h*BN/2 +
+// tx*TN/2 + j).  K advances in steps of 16 through double-buffered LDS
+// tiles: the A tile is stored k-major so a thread reads its TM rows as one
+// contiguous run, the B tile row-major.  Global loads are issued for step
+// t+1 before the arithmetic of step t and land in the other LDS buffer.
+#include "common.h"
+#include "launch.h"
+
+namespace mmm {
+
+namespace {
+
+constexpr int BK = 16;
+constexpr int NT = 256;
+
+enum Op { OP_NAIVE = 0, OP_NAIVE_FMA = 1, OP_KAHAN = 2, OP_WINOGRAD = 3 };
+
+__device__ inline i64 xcd_remap(i64 b, i64 total)
+{
+    // Workgroups are dealt round robin to the 8 XCDs; give each XCD a
+    // contiguous range of tiles so that neighbouring tiles share its L2.
+    if (total % 8 != 0) return b;
+    return (b % 8) * (total / 8) + b / 8;
+}
+
+// Tile (tm, tn) of problem `prob` for flattened block b, grouped 8 tile
+// rows at a time inside a problem.
+__device__ inline void tile_of(i64 b, i64 tiles_m, i64 tiles_n, i64& prob, i64& tm, i64& tn)
+{
+    const i64 per = tiles_m * tiles_n;
+    prob = b / per;
+    const i64 r = b - prob * per;
+    const i64 G = 8;
+    const i64 group = r / (G * tiles_n);
+    const i64 first = group * G;
+    const i64 gs = (tiles_m - first) < G ? (tiles_m - first) : G;
+    const i64 w = r - group * G * tiles_n;
+    tm = first + w % gs;
+    tn = w / gs;
+}
+
+template <int BM, int BN, int TM, int TN, int OP, bool SCALED, class Src>
+__global__ __launch_bounds__(NT) void valu_gemm_kernel(Src src, i64 tiles_m, i64 tiles_n, i64 total,
+                                                       const double* __restrict__ yv,
+                                                       const double* __restrict__ zv, const int* lam)
+{
+    static_assert((BM / TM) * (BN / TN) == NT, "256 threads");
+    static_assert(BM / TM == 16 && BN / TN == 16, "16 x 16 thread grid");
+    constexpr int LA = BM * BK / NT;  // A elements each thread moves per step
+    constexpr int LB = BK * BN / NT;
+    constexpr int TH = TN / 2;        // columns per half
+    __shared__ __align__(16) double As[2][BK][BM + 2];
+    __shared__ __align__(16) double Bs[2][BK][BN + 2];
+
+    i64 prob, tm, tn;
+    tile_of(xcd_remap(blockIdx.x, total), tiles_m, tiles_n, prob, tm, tn);
+    const Gemm g = src.get(prob);
+    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+    const i64 m0 = tm * BM, n0 = tn * BN;
+    const i64 kmax = (OP == OP_WINOGRAD) ? 2 * (g.P / 2) : g.P;
+    const i64 ntiles = (kmax + BK - 1) / BK;
+
+    double sa = 1.0, sb = 1.0;
+    if (SCALED) {
+        const int l = *lam;
+        sa = ldexp(1.0, l);
+        sb = ldexp(1.0, -l);
+    }
+
+    double acc[TM][TN];
+    double cmp[(OP == OP_KAHAN) ? TM : 1][(OP == OP_KAHAN) ? TN : 1];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = 0.0;
+    if (OP == OP_KAHAN) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) cmp[i][j] = 0.0;
+    }
+
+    double ra[LA], rb[LB];
+    auto gload = [&](i64 t) {
+        const i64 k0 = t * BK;
+#pragma unroll
+        for (int q = 0; q < LA; ++q) {
+            const int e = q * NT + tid, r = e / BK, k = e % BK;
+            const i64 gm = m0 + r, gk = k0 + k;
+            double v = (gm < g.N && gk < kmax) ? g.A[gm * g.lda + gk] : 0.0;
+            ra[q] = SCALED ? v * sa : v;
+        }
+#pragma unroll
+        for (int q = 0; q < LB; ++q) {
+            const int e = q * NT + tid, k = e / BN, n = e % BN;
+            const i64 gk = k0 + k, gn = n0 + n;
+            double v = (gk < kmax && gn < g.M) ? g.B[gk * g.ldb + gn] : 0.0;
+            rb[q] = SCALED ? v * sb : v;
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < LA; ++q) {
+            const int e = q * NT + tid;
+            As[buf][e % BK][e / BK] = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < LB; ++q) {
+            const int e = q * NT + tid;
+            Bs[buf][e / BN][e % BN] = rb[q];
+        }
+    };
+    auto frag_a = [&](int buf, int k, double* a) {
+#pragma unroll
+        for (int i = 0; i < TM; i += 2) {
+            const double2 v = *reinterpret_cast<const double2*>(&As[buf][k][ty * TM + i]);
+            a[i] = v.x;
+            a[i + 1] = v.y;
+        }
+    };
+    auto frag_b = [&](int buf, int k, double* b) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (TH % 2 == 0) {
+#pragma unroll
+                for (int j = 0; j < TH; j += 2) {
+                    const double2 v =
+                        *reinterpret_cast<const double2*>(&Bs[buf][k][h * (BN / 2) + tx * TH + j]);
+                    b[h * TH + j] = v.x;
+                    b[h * TH + j + 1] = v.y;
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < TH; ++j) b[h * TH + j] = Bs[buf][k][h * (BN / 2) + tx * TH + j];
+            }
+        }
+    };
+    auto step = [&](int buf, int k) {
+        if (OP == OP_WINOGRAD) {
+            // pair (k, k+1): (A_{i,k} + B_{k+1,j}) (A_{i,k+1} + B_{k,j})
+            double a0[TM], a1[TM], b0[TN], b1[TN];
+            frag_a(buf, k, a0);
+            frag_a(buf, k + 1, a1);
+            frag_b(buf, k, b0);
+            frag_b(buf, k + 1, b1);
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    const double u = a0[i] + b1[j];
+                    const double v = a1[i] + b0[j];
+                    const double w = u * v;
+                    acc[i][j] = acc[i][j] + w;
+                }
+        } else {
+            double a[TM], b[TN];
+            frag_a(buf, k, a);
+            frag_b(buf, k, b);
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    if (OP == OP_NAIVE) {
+                        const double x = a[i] * b[j];
+                        acc[i][j] = acc[i][j] + x;
+                    } else if (OP == OP_NAIVE_FMA) {
+                        acc[i][j] = fma(a[i], b[j], acc[i][j]);
+                    } else {
+                        // Kahan as printed: err = err + x; t = sum + err;
+                        // err = (sum - t) + err; sum = t.
+                        const double x = a[i] * b[j];
+                        const double e = cmp[i][j] + x;
+                        const double t = acc[i][j] + e;
+                        cmp[i][j] = (acc[i][j] - t) + e;
+                        acc[i][j] = t;
+                    }
+                }
+        }
+    };
+    constexpr int KSTEP = (OP == OP_WINOGRAD) ? 2 : 1;
+
+    if (ntiles > 0) {
+        gload(0);
+        lstore(0);
+    }
+    __syncthreads();
+    for (i64 t = 0; t < ntiles; ++t) {
+        const int cur = (int)(t & 1);
+        if (t + 1 < ntiles) gload(t + 1);
+        const i64 rem = kmax - t * BK;
+        if (rem >= BK) {
+#pragma unroll
+            for (int k = 0; k < BK; k += KSTEP) step(cur, k);
+        } else {
+            const int kc = (int)rem;
+            for (int k = 0; k < kc; k += KSTEP) step(cur, k);
+        }
+        if (t + 1 < ntiles) lstore(cur ^ 1);
+        __syncthreads();
+    }
+
+    // epilogue
+    const bool odd = (OP == OP_WINOGRAD) && (g.P % 2 == 1);
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        const i64 gm = m0 + ty * TM + i;
+        if (gm >= g.N) continue;
+        double yi = 0.0, alast = 0.0;
+        if (OP == OP_WINOGRAD) {
+            yi = yv[gm];
+            if (odd) alast = SCALED ? g.A[gm * g.lda + (g.P - 1)] * sa : g.A[gm * g.lda + (g.P - 1)];
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int j = 0; j < TH; ++j) {
+                const i64 gn = n0 + h * (BN / 2) + tx * TH + j;
+                if (gn >= g.M) continue;
+                double c = acc[i][h * TH + j];
+                if (OP == OP_WINOGRAD) {
+                    c = (c - yi) - zv[gn];
+                    if (odd) {
+                        const double bl = SCALED ? g.B[(g.P - 1) * g.ldb + gn] * sb : g.B[(g.P - 1) * g.ldb + gn];
+                        const double tail = alast * bl;
+                        c = c + tail;
+                    }
+                }
+                g.C[gm * g.ldc + gn] = c;
+            }
+    }
+}
+
+template <int BM, int BN, int TM, int TN, int OP, bool SCALED, class Src>
+hipError_t launch_valu(const Src& src, i64 N, i64 M, const double* yv, const double* zv, const int* lam,
+                       hipStream_t s)
+{
+    const i64 tiles_m = cdiv(N, BM), tiles_n = cdiv(M, BN);
+    const i64 total = tiles_m * tiles_n * src.count();
+    if (total == 0) return hipSuccess;
+    if (total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((valu_gemm_kernel<BM, BN, TM, TN, OP, SCALED, Src>), dim3((unsigned)total), dim3(NT), 0, s,
+                       src, tiles_m, tiles_n, total, yv, zv, lam);
+    return hipGetLastError();
+}
+
+// Small problems (every dimension <= 48, e.g. the m x m leaves of the
+// paper's Strassen embedding) use 32 x 32 tiles.
+template <int OP, class Src>
+hipError_t launch_naive_like(const Src& src, i64 N, i64 M, hipStream_t s)
+{
+    if (N <= 48 && M <= 48) return launch_valu<32, 32, 2, 2, OP, false>(src, N, M, nullptr, nullptr, nullptr, s);
+    if constexpr (OP == OP_KAHAN)
+        return launch_valu<128, 64, 8, 4, OP, false>(src, N, M, nullptr, nullptr, nullptr, s);
+    else
+        return launch_valu<128, 128, 8, 8, OP, false>(src, N, M, nullptr, nullptr, nullptr, s);
+}
+
+}  // namespace
+
+hipError_t launch_naive(const Gemm& g, bool fused, hipStream_t s)
+{
+    SingleSrc src{g};
+    return fused ? launch_naive_like<OP_NAIVE_FMA>(src, g.N, g.M, s) : launch_naive_like<OP_NAIVE>(src, g.N, g.M, s);
+}
+
+hipError_t launch_naive_strassen_leaves(const StrassenLeafSrc& src, hipStream_t s)
+{
+    const int d = src.T.depth;
+    return launch_naive_like<OP_NAIVE>(src, src.T.n[d], src.T.m[d], s);
+}
+
+hipError_t launch_kahan(const Gemm& g, hipStream_t s)
+{
+    SingleSrc src{g};
+    return launch_naive_like<OP_KAHAN>(src, g.N, g.M, s);
+}
+
+hipError_t launch_winograd_main(const Gemm& g, const double* y, const double* z, const int* lam, hipStream_t s)
+{
+    SingleSrc src{g};
+    if (lam) return launch_valu<128, 128, 8, 8, OP_WINOGRAD, true>(src, g.N, g.M, y, z, lam, s);
+    return launch_valu<128, 128, 8, 8, OP_WINOGRAD, false>(src, g.N, g.M, y, z, nullptr, s);
+}
+
+}  // namespace mmm

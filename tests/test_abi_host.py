@@ -1,0 +1,93 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+include/mmm.h declares, and validates arguments on the host before any
+device work (these calls never reach the GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mmm.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1106_1347_amd import _lib
+
+    return _lib
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mmm_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib._lib, n), n
+
+
+def test_config_default_and_version(lib):
+    c = lib._lib.mmm_config_default()
+    assert (c.strassen_levels, c.pad_mode, c.strassen_leaf, c.split_slices, c.split_type, c.split_scale_lambda,
+            c.naive_fma) == (2, 1, 0, 6, 0, 1, 0)
+    assert list(c.reserved) == [0] * 9
+    assert lib.version() >= 100
+
+
+def test_workspace_arithmetic(lib):
+    ws = lib.workspace_bytes
+    for m in ("naive", "kahan", "dgemm"):
+        assert ws(m, 4096, 4097, 4096) == 0
+    assert ws("winograd", 100, 7, 300) == 1024 + 2560  # y: 800 B -> 1024, z: 2400 B -> 2560
+    assert ws("winograd_scaled", 100, 7, 300) == 1024 + 2560 + 3 * 256
+    cfg = lib.Config(strassen_levels=2)
+    # no padding at 4096^3: two levels of (7^d slots of A, B and products)
+    n1, n2 = 2048 * 2048 * 8, 1024 * 1024 * 8
+    assert ws("strassen_winograd", 4096, 4096, 4096, cfg) == 3 * (7 * n1 + 49 * n2)
+    # P = 4097 pads to 4100; A, B, C padded copies come first
+    b = ws("strassen_winograd", 4096, 4097, 4096, cfg)
+    assert b > 3 * (7 * n1 + 49 * n2)
+    assert ws("strassen_naive", 0, 5, 5) == 0
+    with pytest.raises(ValueError):
+        ws("dgemm", -1, 2, 2)
+    # paper mode at X < 32 is a single naive product (no workspace)
+    assert ws("strassen_naive", 20, 31, 3, lib.Config(pad_mode="paper")) == 0
+    assert ws("strassen_naive", 20, 32, 3, lib.Config(pad_mode="paper")) > 0
+
+
+def test_argument_errors_before_any_launch(lib):
+    f = lib._lib.mmm_multiply
+    c = lib._lib.mmm_config_default()
+    r = ctypes.byref
+    # negative size
+    assert f(8, 8, 8, -1, 2, 2, 6, r(c), None, 0, None) == 1
+    # unknown method
+    assert f(8, 8, 8, 2, 2, 2, 99, r(c), None, 0, None) == 1
+    # null C
+    assert f(8, 8, None, 2, 2, 2, 6, r(c), None, 0, None) == 1
+    # C overlapping A
+    assert f(0x1000, 0x90000, 0x1008, 4, 4, 4, 6, r(c), None, 0, None) == 2
+    # missing / small / misaligned workspace
+    assert f(0x1000, 0x90000, 0x200000, 64, 64, 64, 2, r(c), None, 0, None) == 3
+    assert f(0x1000, 0x90000, 0x200000, 64, 64, 64, 2, r(c), 0x400000, 16, None) == 3
+    assert f(0x1000, 0x90000, 0x200000, 64, 64, 64, 2, r(c), 0x400008, 1 << 20, None) == 3
+    # bad config fields
+    bad = lib._lib.mmm_config_default()
+    bad.strassen_levels = 40
+    assert f(8, 8, 8, 2, 2, 2, 6, r(bad), None, 0, None) == 1
+    bad = lib._lib.mmm_config_default()
+    bad.reserved[3] = 1
+    assert f(8, 8, 8, 2, 2, 2, 6, r(bad), None, 0, None) == 1
+    # empty result: nothing to do, no device call
+    assert f(None, None, None, 0, 5, 5, 6, r(c), None, 0, None) == 0
+    assert lib._lib.mmm_last_error()  # message set by the failures above
+    assert lib._lib.mmm_plus(8, 8, 8, -3, 1, None) == 1
+    assert lib._lib.mmm_minus(0x1000, 0x9000, 0x1008, 4, 4, None) == 2
+    assert lib._lib.mmm_norm_inf(8, 2, 2, None, None) == 1
+    assert lib._lib.mmm_winograd_lambda(None, 8, 8, None) == 1
+    assert lib._lib.mmm_status_string(2) == b"output overlaps an input"

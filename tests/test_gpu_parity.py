@@ -1,0 +1,201 @@
+"""GPU parity of every method against the CPU oracle, through the C ABI.
+
+Bar: methods whose rounding the paper fixes (NaivStandard, NaivKahan,
+WinogradOriginal, WinogradScaled, both Strassen variants with the naive
+leaf, the auxiliaries) must equal the oracle bit for bit; the FP64 matrix
+core paths (DGEMM, Strassen with a DGEMM leaf) must stay within the
+normwise tolerance ||C - C_oracle||inf / (||A||inf ||B||inf) <= 1e-13
+(DGEMM) and <= 1e-11 (Strassen, up to 3 levels); integer-valued inputs
+must give the exact product bit for bit for every method.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_PLAIN = 1e-13
+TOL_STRASSEN = 1e-11
+
+
+@pytest.fixture(scope="module")
+def mmm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1106_1347_amd as m
+
+    return m
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def run(mmm, A, B, method, cfg=None):
+    C = mmm.multiply(dev(A), dev(B), method, cfg)
+    torch.cuda.synchronize()
+    return C.cpu().numpy()
+
+
+def relerr(orc, C, R, A, B):
+    return orc.rel_err_inf(C, R, orc.norm_inf(A), orc.norm_inf(B))
+
+
+def bits_equal(X, Y):
+    return X.shape == Y.shape and np.array_equal(X.view(np.int64), Y.view(np.int64))
+
+
+SHAPES = [(1, 1, 1), (3, 1, 2), (7, 5, 3), (1, 300, 1), (64, 1, 64), (33, 17, 65), (129, 130, 131),
+          (200, 257, 190), (256, 256, 256), (130, 48, 40)]
+
+
+def _strassen_cfgs(mmm):
+    out = []
+    for L in (1, 2, 3):
+        out.append(("L%d_naive" % L, mmm.Config(strassen_levels=L, strassen_leaf="naive")))
+    out.append(("paper", mmm.Config(pad_mode="paper")))
+    return out
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_paper_rounded_methods_bitwise(mmm, orc, shape):
+    N, P, M = shape
+    print("case", shape, flush=True)
+    A = synth.uniform((N, P), 101 + N)
+    B = synth.uniform((P, M), 102 + M)
+    assert bits_equal(run(mmm, A, B, "naive"), orc.naive(A, B))
+    assert bits_equal(run(mmm, A, B, "kahan"), orc.kahan(A, B))
+    assert bits_equal(run(mmm, A, B, "winograd"), orc.winograd(A, B))
+    # an unbalanced pair so that lambda != 0
+    Bs = B * 2.0 ** 13
+    Cws, lam = orc.winograd_scaled(A, Bs, return_lambda=True)
+    assert lam != 0
+    assert bits_equal(run(mmm, A, Bs, "winograd_scaled"), Cws)
+    for tag, cfg in _strassen_cfgs(mmm):
+        for v, name in ((0, "strassen_naive"), (1, "strassen_winograd")):
+            if cfg.pad_mode == "paper":
+                ref = orc.strassen(A, B, v, orc.MODE_PAPER)
+            else:
+                ref = orc.strassen(A, B, v, orc.MODE_LEVELS, cfg.strassen_levels)
+            assert bits_equal(run(mmm, A, B, name, cfg), ref), (name, tag)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_matrix_core_paths_within_tolerance(mmm, orc, shape):
+    N, P, M = shape
+    print("case", shape, flush=True)
+    A = synth.uniform((N, P), 201 + N)
+    B = synth.uniform((P, M), 202 + M)
+    ref = orc.naive(A, B)
+    assert relerr(orc, run(mmm, A, B, "dgemm"), ref, A, B) <= TOL_PLAIN
+    assert relerr(orc, run(mmm, A, B, "naive", mmm.Config(naive_fma=True)), ref, A, B) <= TOL_PLAIN
+    for L in (1, 2, 3):
+        cfg = mmm.Config(strassen_levels=L)
+        for name in ("strassen_naive", "strassen_winograd"):
+            assert relerr(orc, run(mmm, A, B, name, cfg), ref, A, B) <= TOL_STRASSEN, (name, L)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (7, 9, 5), (129, 130, 131), (256, 256, 256), (100, 257, 64)])
+def test_integer_inputs_exact_every_method(mmm, shape):
+    N, P, M = shape
+    print("case", shape, flush=True)
+    A = synth.integers((N, P), 301)
+    B = synth.integers((P, M), 302)
+    ref = (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float64)
+    cfgs = {"naive": [None, mmm.Config(naive_fma=True)], "kahan": [None], "winograd": [None],
+            "winograd_scaled": [None], "dgemm": [None],
+            "strassen_naive": [mmm.Config(strassen_levels=L) for L in (1, 2, 3)] + [mmm.Config(pad_mode="paper")],
+            "strassen_winograd": [mmm.Config(strassen_levels=L) for L in (1, 2, 3)] + [mmm.Config(pad_mode="paper")]}
+    for method, cl in cfgs.items():
+        for cfg in cl:
+            assert np.array_equal(run(mmm, A, B, method, cfg), ref), (method, cfg)
+
+
+def test_auxiliaries_bitwise(mmm, orc):
+    for rows, cols in ((1, 1), (7, 13), (255, 257), (1024, 1023)):
+        print("case", rows, cols, flush=True)
+        X = synth.uniform((rows, cols), 1)
+        Y = synth.uniform((rows, cols), 2)
+        Xd, Yd = dev(X), dev(Y)
+        assert bits_equal(mmm.plus(Xd, Yd).cpu().numpy(), orc.plus(X, Y))
+        assert bits_equal(mmm.minus(Xd, Yd).cpu().numpy(), orc.minus(X, Y))
+        assert bits_equal(mmm.multiply_with_scalar(0.3, Xd).cpu().numpy(), orc.scale(0.3, X))
+        assert mmm.norm_inf(Xd).item() == orc.norm_inf(X)
+        # in place, and an operand that is not 16-byte aligned
+        Z = Xd.clone()
+        mmm.plus(Z, Yd, out=Z)
+        assert bits_equal(Z.cpu().numpy(), orc.plus(X, Y))
+        if rows * cols > 2:
+            flat = dev(np.concatenate([[0.0], X.ravel()]))
+            Xu = flat[1:].view(rows, cols)
+            assert bits_equal(mmm.minus(Xu, Yd).cpu().numpy(), orc.minus(X, Y))
+    # sums run left to right
+    t = 2.0 ** -53
+    assert mmm.norm_inf(dev(np.array([[1.0, t, t]]))).item() == 1.0
+    assert mmm.norm_inf(dev(np.array([[t, t, 1.0]]))).item() == 1.0 + 2.0 ** -52
+
+
+def test_lambda_on_device(mmm, orc):
+    rng = np.random.default_rng(4)
+    vals = [(1.0, 8.0), (3.0, 3.0), (0.0, 1.0), (1.0, float("inf")), (2.5, 0.0001), (7.0, 7.0 * 2 ** 21)]
+    vals += [(float(rng.uniform(0.5, 1)) * 2.0 ** int(rng.integers(-40, 40)),
+              float(rng.uniform(0.5, 1)) * 2.0 ** int(rng.integers(-40, 40))) for _ in range(40)]
+    for a, b in vals:
+        na = torch.tensor(a, dtype=torch.float64, device="cuda")
+        nb = torch.tensor(b, dtype=torch.float64, device="cuda")
+        assert mmm.winograd_lambda(na, nb).item() == orc.winograd_lambda(a, b), (a, b)
+
+
+def test_zero_sizes(mmm):
+    for method in ("naive", "kahan", "winograd", "winograd_scaled", "strassen_naive", "strassen_winograd", "dgemm"):
+        A = torch.zeros((5, 0), dtype=torch.float64, device="cuda")
+        B = torch.zeros((0, 4), dtype=torch.float64, device="cuda")
+        C = torch.full((5, 4), 7.0, dtype=torch.float64, device="cuda")
+        mmm.multiply(A, B, method, out=C)
+        assert torch.count_nonzero(C).item() == 0, method
+        A = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
+        B = torch.ones((3, 4), dtype=torch.float64, device="cuda")
+        assert mmm.multiply(A, B, method).shape == (0, 4)
+
+
+def test_deterministic_bits(mmm):
+    A = dev(synth.uniform((300, 211), 5))
+    B = dev(synth.uniform((211, 190), 6))
+    for method in ("naive", "kahan", "winograd", "winograd_scaled", "dgemm", "strassen_winograd", "strassen_naive"):
+        c1 = mmm.multiply(A, B, method).cpu().numpy()
+        c2 = mmm.multiply(A, B, method).cpu().numpy()
+        assert bits_equal(c1, c2), method
+
+
+@pytest.mark.parametrize("P", [4096, 4097])
+def test_full_size_sampled_rows(mmm, orc, P):
+    """N = M = 4096, P = 4096 and 4097 (odd-P tail): every method run at full
+    size in the launch configuration the benchmark times; checked on sampled
+    rows that the oracle computes one by one."""
+    N = M = 4096
+    print("case full size P =", P, flush=True)
+    A = synth.uniform((N, P), synth.seed_a(1))
+    B = synth.uniform((P, M), synth.seed_b(1))
+    rows = np.array([0, 1, 127, 128, 2047, 3000, 4094, 4095])
+    ref = orc.naive_rows(A, B, rows)
+    nA, nB = orc.norm_inf(A), orc.norm_inf(B)
+    Ad, Bd = dev(A), dev(B)
+
+    def rows_of(method, cfg=None):
+        C = mmm.multiply(Ad, Bd, method, cfg)
+        torch.cuda.synchronize()
+        return C[torch.from_numpy(rows).cuda()].cpu().numpy()
+
+    def err(X):
+        return orc.norm_inf(orc.minus(X, ref)) / (nA * nB)
+
+    assert bits_equal(rows_of("naive"), ref)
+    assert bits_equal(rows_of("kahan"), orc.kahan_rows(A, B, rows))
+    assert bits_equal(rows_of("winograd"), orc.winograd_rows(A, B, rows))
+    assert bits_equal(rows_of("winograd_scaled"), orc.winograd_rows(A, B, rows, scaled=True))
+    assert err(rows_of("dgemm")) <= TOL_PLAIN
+    for L in (2, 3):
+        for name in ("strassen_winograd", "strassen_naive"):
+            assert err(rows_of(name, mmm.Config(strassen_levels=L))) <= TOL_STRASSEN, (name, L)

@@ -415,4 +415,11 @@ def test_thread_count_does_not_change_bits(orc):
         assert np.array_equal(a, b)
     rows = np.array([0, 5, 69, 33])
     assert np.array_equal(orc.naive_rows(A, B, rows), orc.naive(A, B)[rows])
+    assert np.array_equal(orc.kahan_rows(A, B, rows), orc.kahan(A, B)[rows])
+    assert np.array_equal(orc.winograd_rows(A, B, rows), orc.winograd(A, B)[rows])
+    B2 = B * 2.0 ** 9
+    assert np.array_equal(orc.winograd_rows(A, B2, rows, scaled=True), orc.winograd_scaled(A, B2)[rows])
+    Ao = synth.uniform((70, 91), 3)
+    Bo = synth.uniform((91, 60), 4) * 64.0
+    assert np.array_equal(orc.winograd_rows(Ao, Bo, rows, scaled=True), orc.winograd_scaled(Ao, Bo)[rows])
     assert np.array_equal(orc.split_model_rows(A, B, rows, 4, 8), orc.split_model(A, B, 4, 8)[rows])
