@@ -39,6 +39,9 @@ PEAK_FP64_VALU_OPS_T = CUS * SIMDS_PER_CU * LANES_PER_SIMD * CLOCK_GHZ * 1e9 / 1
 #   kahan:   1 mul + 4 add/sub                             -> 5 VALU ops / MAC
 #   winograd: 2 add + 1 mul + 1 add per pair of MACs       -> 2 VALU ops / MAC
 #   dgemm:   2 flop / MAC on FP64 matrix cores
+#   split:   s(s+1)/2 digit-pair products x 2 ops / MAC on the bf16 / int8 matrix cores
+PEAK_BF16_MFMA_TFLOPS = 2516.6
+PEAK_INT8_MFMA_TOPS = 5033.2
 METHODS = [
     ("dgemm", "dgemm", {}, 2.0, "mfma"),
     ("naive", "naive", {}, 2.0, "alu"),
@@ -47,6 +50,14 @@ METHODS = [
     ("winograd_scaled", "winograd_scaled", {}, 2.0, "alu"),
     ("strassen_winograd_L2", "strassen_winograd", {"strassen_levels": 2}, None, None),
     ("strassen_naive_L2", "strassen_naive", {"strassen_levels": 2}, None, None),
+    ("split_int8_s7", "split", {"split_type": "int8", "split_slices": 7}, None, None),
+    ("split_bf16_s6", "split", {"split_type": "bf16", "split_slices": 6}, None, None),
+]
+# the precision comparison at 8192^3 on the wide-range distribution
+PRECISION = [
+    ("dgemm", "dgemm", {}),
+    ("split_int8_s7", "split", {"split_type": "int8", "split_slices": 7}),
+    ("split_bf16_s6", "split", {"split_type": "bf16", "split_slices": 6}),
 ]
 
 
@@ -58,6 +69,8 @@ def parse():
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", default="", help="comma-separated subset of methods (for profiling)")
+    ap.add_argument("--no-precision", action="store_true", help="skip the 8192^3 split-vs-DGEMM comparison")
+    ap.add_argument("--precision-reps", type=int, default=5)
     return ap.parse_args()
 
 
@@ -142,7 +155,7 @@ def main():
         # the host cores this process may use (the GPU machine grants 16 per GPU)
         threads = min(len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS", "16")))
         oracle.set_threads(threads)
-        rows = np.linspace(0, n - 1, 16 * threads).round().astype(np.int64)
+        rows = np.linspace(0, n - 1, 8 * threads).round().astype(np.int64)
         ref = {}
         cpu_t = 0.0
         cpu_flop = 0.0
@@ -168,6 +181,10 @@ def main():
                 e = oracle.norm_inf(oracle.minus(got, ref[P])) / (nrm[P][0] * nrm[P][1])
                 worst = max(worst, e)
             errors[name] = worst
+
+    precision = None
+    if not args.no_precision:
+        precision = precision_section(args, mmm, torch, synth, dev, stream, errors_needed=not args.no_cpu_baseline)
 
     results = {}
     for name, method, kw, cost, bound in methods:
@@ -223,9 +240,64 @@ def main():
         "methods": results,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "precision_8192": precision,
         "device": torch.cuda.get_device_name(0),
     }
     print(json.dumps(out), flush=True)
+
+
+def precision_section(args, mmm, torch, synth, dev, stream, errors_needed):
+    """DGEMM against the split products at N = P = M = 8192 on the
+    wide-range distribution: median time, FP64-grade TFLOP/s (2NPM/t) and
+    relative infinity-norm error on sampled rows against the oracle."""
+    n = 8192
+    A = synth.wide_range((n, n), synth.seed_a(2))
+    B = synth.wide_range((n, n), synth.seed_b(2))
+    Ad = torch.from_numpy(A).to(dev)
+    Bd = torch.from_numpy(B).to(dev)
+    C = torch.empty((n, n), dtype=torch.float64, device=dev)
+    out = {"workload": "N = P = M = 8192, entries +-2^u (u ~ U[-20,20]), rows scaled by 2^v (v ~ U{-10..10}), "
+                       "seeds 2001/2002", "reps": args.precision_reps}
+    rows = np.array([0, 1, 2048, 4095, 6000, 8191])
+    ref = None
+    if errors_needed:
+        import oracle
+
+        ref = oracle.naive_rows(A, B, rows)
+        nrm = oracle.norm_inf(A) * oracle.norm_inf(B)
+    ridx = torch.from_numpy(rows).to(dev)
+    for name, method, kw in PRECISION:
+        cfg = mmm.Config(**kw)
+        ws = torch.empty(max(mmm.workspace_bytes(method, n, n, n, cfg), 1), dtype=torch.uint8, device=dev)
+        mmm.multiply(Ad, Bd, method, cfg, out=C, workspace=ws, stream=stream)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(args.precision_reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            mmm.multiply(Ad, Bd, method, cfg, out=C, workspace=ws, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        med = float(np.median(ms))
+        ent = {"ms_p50": med, "ms_min": float(np.min(ms)), "tflops_fp64_grade": 2.0 * n ** 3 / (med / 1e3) / 1e12}
+        if name == "dgemm":
+            ent["frac_fp64_mfma_peak"] = ent["tflops_fp64_grade"] / PEAK_FP64_MFMA_TFLOPS
+        else:
+            s = kw["split_slices"]
+            pairs = s * (s + 1) // 2
+            peak = PEAK_INT8_MFMA_TOPS if kw["split_type"] == "int8" else PEAK_BF16_MFMA_TFLOPS
+            ent["lowprec_ops_per_s_T"] = pairs * 2.0 * n ** 3 / (med / 1e3) / 1e12
+            ent["frac_lowprec_mfma_peak"] = ent["lowprec_ops_per_s_T"] / peak
+        if ref is not None:
+            import oracle
+
+            got = C[ridx].cpu().numpy()
+            ent["rel_err_inf_sampled"] = oracle.norm_inf(oracle.minus(got, ref)) / nrm
+        out[name] = ent
+        del ws
+    return out
 
 
 def _cpu_model():

@@ -1,12 +1,556 @@
+// FP64 product from exact low-precision digit products ("split" method).
+//
+// Not a method of the paper; it reuses WinogradScaled's infinity-norm
+// scaling (Section 2.3.2) and computes the same result as the CPU model of
+// the oracle, bit for bit:
+//   1. lambda from NormInf(A), NormInf(B) (optional); A' = 2^l A, B' = 2^-l B.
+//   2. e_i = E(max_k |A'_ik|) + 1 per row of A', f_j likewise per column of
+//      B' (E = frexp exponent), so every scaled entry lies in [-1/2, 1/2].
+//   3. s signed digits of beta bits per entry by repeated round-to-nearest:
+//      d_t = rint(2^beta r_{t-1}), r_t = 2^beta r_{t-1} - d_t, |d_t| <= 2^(beta-1).
+//   4. For g = 2..s+1: G_g = sum_{t+u=g} D_A^(t) D_B^(u), an exact integer
+//      matrix formed on the matrix cores (digits are exact in bf16/fp16/int8;
+//      products and partial sums stay below the accumulator's exact range
+//      and are flushed to FP64 before they could exceed it).
+//   5. c = sum_{g = s+1 .. 2} 2^(-beta g) G_g in FP64, in that order; then
+//      C_ij = 2^(e_i + f_j) c.
+//
+// Digit types: BF16 (beta = 8, FP32 accumulation, 16x16x32 MFMA), FP16
+// (beta = 9), INT8 (beta = 7, INT32 accumulation, 16x16x64 MFMA).
+//
+// Layouts (workspace): digits of A as SA[i][kt][t][kk] and of B transposed
+// as SB[j][kt][u][kk] (kt = K tile of 64, kk < 64), so one K tile of every
+// digit of a row is one contiguous run; rows and K padded with zeros to the
+// tile sizes, so the GEMM's loads need no bounds checks.
+#include <string.h>
+
+#include "launch.h"
 #include "split.h"
 
 namespace mmm {
 
-size_t split_workspace_bytes(i64, i64, i64, const mmm_config&) { return 0; }
+namespace {
 
-hipError_t run_split(const double*, const double*, double*, i64, i64, i64, const mmm_config&, char*, hipStream_t)
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+
+constexpr int KT = 64;  // K tile (elements)
+
+enum DType { DT_BF16 = 0, DT_FP16 = 1, DT_INT8 = 2 };
+
+template <int DT>
+struct Digit;
+template <>
+struct Digit<DT_BF16> {
+    static constexpr int beta = 8, esize = 2, mfma_k = 32;
+    static constexpr double budget = 16777216.0;  // 2^24: exact FP32 integers
+};
+template <>
+struct Digit<DT_FP16> {
+    static constexpr int beta = 9, esize = 2, mfma_k = 32;
+    static constexpr double budget = 16777216.0;
+};
+template <>
+struct Digit<DT_INT8> {
+    static constexpr int beta = 7, esize = 1, mfma_k = 64;
+    static constexpr double budget = 2147483647.0;  // int32
+};
+
+// Wave tile (wbm x wbn blocks of 16 x 16, 2 x 2 waves per workgroup) for a
+// digit type, digit count and accumulation scheme, sized so that the group
+// accumulators (s per output, plus 2 s FP64 registers when flushing) and
+// the staging registers fit one wave per SIMD without spills.
+struct TileCfg {
+    int wbm, wbn;
+    constexpr int bm() const { return 32 * wbm; }
+    constexpr int bn() const { return 32 * wbn; }
+};
+__host__ __device__ constexpr TileCfg tile_cfg(int dt, int s, bool flush)
 {
-    return hipErrorNotSupported;
+    return dt == DT_INT8 ? (flush ? TileCfg{2, 2} : TileCfg{4, 2}) : (s >= 7 ? TileCfg{1, 2} : TileCfg{2, 2});
+}
+
+__host__ __device__ inline int beta_of(int dt) { return dt == DT_BF16 ? 8 : (dt == DT_FP16 ? 9 : 7); }
+
+// e = E(mx) + 1 (0 for an all-zero vector)
+__device__ inline int vec_exponent(double mx)
+{
+    if (!(mx > 0.0)) return 0;
+    int e;
+    frexp(mx, &e);
+    return e + 1;
+}
+
+template <int DT>
+__device__ inline void store_digits(char* dst, const double* d)
+{
+    // 8 digits -> 8 elements (16 bytes for 2-byte types, 8 bytes for int8)
+    if (DT == DT_INT8) {
+        unsigned int lo = 0, hi = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) lo |= ((unsigned int)(unsigned char)(signed char)(int)d[q]) << (8 * q);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) hi |= ((unsigned int)(unsigned char)(signed char)(int)d[4 + q]) << (8 * q);
+        *reinterpret_cast<uint2*>(dst) = make_uint2(lo, hi);
+    } else {
+        unsigned short h[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (DT == DT_BF16) {
+                const float f = (float)d[q];  // |d| <= 2^7: exact; bf16 keeps the top 16 bits exactly
+                h[q] = (unsigned short)(__float_as_uint(f) >> 16);
+            } else {
+                const _Float16 x = (_Float16)(float)d[q];  // |d| <= 2^8: exact in fp16
+                h[q] = *reinterpret_cast<const unsigned short*>(&x);
+            }
+        }
+        uint4 v;
+        v.x = h[0] | ((unsigned int)h[1] << 16);
+        v.y = h[2] | ((unsigned int)h[3] << 16);
+        v.z = h[4] | ((unsigned int)h[5] << 16);
+        v.w = h[6] | ((unsigned int)h[7] << 16);
+        *reinterpret_cast<uint4*>(dst) = v;
+    }
+}
+
+// Digits of 8 consecutive entries along k of one row of A (or one column
+// of B).  x[q] are the unscaled entries (0 outside the matrix).
+template <int DT>
+__device__ inline void cut(const double* x, double sc, int e, int s, char* out, i64 slice_stride)
+{
+    constexpr int beta = Digit<DT>::beta;
+    const double up = (double)(1 << beta);
+    double r[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) r[q] = ldexp(x[q] * sc, -e);
+    for (int t = 0; t < s; ++t) {
+        double d[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const double y = r[q] * up;
+            d[q] = rint(y);
+            r[q] = y - d[q];
+        }
+        store_digits<DT>(out + t * slice_stride, d);
+    }
+}
+
+// A: one thread per (row i < Np, 8-entry chunk of the padded K).
+template <int DT>
+__global__ __launch_bounds__(256) void split_a_kernel(const double* __restrict__ A, i64 N, i64 P, i64 Np, i64 Kp,
+                                                      const double* __restrict__ rmax, const int* lam, int s,
+                                                      char* __restrict__ SA, int* __restrict__ ea)
+{
+    constexpr int ES = Digit<DT>::esize;
+    const i64 chunks = Kp / 8;
+    const i64 total = Np * chunks;
+    const double sc = lam ? ldexp(1.0, *lam) : 1.0;
+    const i64 row_bytes = Kp * s * ES;
+    for (i64 c = (i64)blockIdx.x * 256 + threadIdx.x; c < total; c += (i64)gridDim.x * 256) {
+        const i64 i = c / chunks, k0 = (c - i * chunks) * 8;
+        const int e = i < N ? vec_exponent(rmax[i]) : 0;
+        double x[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) x[q] = (i < N && k0 + q < P) ? A[i * P + k0 + q] : 0.0;
+        const i64 kt = k0 / KT, kk = k0 % KT;
+        char* out = SA + i * row_bytes + (kt * s * KT + kk) * ES;
+        cut<DT>(x, sc, e, s, out, (i64)KT * ES);
+        if (k0 == 0) ea[i] = e;
+    }
+}
+
+// B (P x M, row-major) to SB[j][kt][u][kk]: a 64 (k) x 64 (j) tile goes
+// through LDS so both the loads (along j) and the stores (along k) are
+// contiguous.
+template <int DT>
+__global__ __launch_bounds__(256) void split_b_kernel(const double* __restrict__ B, i64 P, i64 M, i64 Mp, i64 Kp,
+                                                      const double* __restrict__ cmax, const int* lam, int s,
+                                                      char* __restrict__ SB, int* __restrict__ fb)
+{
+    constexpr int ES = Digit<DT>::esize;
+    __shared__ double T[64][65];
+    const i64 tiles_j = Mp / 64;
+    const i64 kt = blockIdx.x / tiles_j;
+    const i64 j0 = (blockIdx.x - kt * tiles_j) * 64, k0 = kt * 64;
+    const int tid = threadIdx.x;
+    const double sc = lam ? ldexp(1.0, -*lam) : 1.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int e = q * 256 + tid, kr = e / 64, jc = e % 64;
+        const i64 k = k0 + kr, j = j0 + jc;
+        T[kr][jc] = (k < P && j < M) ? B[k * M + j] : 0.0;
+    }
+    __syncthreads();
+    // 256 threads: 64 columns x 4 chunks of 8 -> two passes cover 64 k
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+        const int jc = tid / 4, ch = (tid % 4) + 4 * pass;
+        const i64 j = j0 + jc;
+        const int e = j < M ? vec_exponent(cmax[j]) : 0;
+        double x[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) x[q] = T[ch * 8 + q][jc];
+        const i64 row_bytes = Kp * s * ES;
+        char* out = SB + j * row_bytes + (kt * s * KT + ch * 8) * ES;
+        cut<DT>(x, sc, e, s, out, (i64)KT * ES);
+        if (kt == 0 && ch == 0) fb[j] = e;
+    }
+}
+
+// ---- the digit-product GEMM -------------------------------------------------
+
+template <int DT>
+struct Mfma;
+template <>
+struct Mfma<DT_BF16> {
+    typedef v4f acc_t;
+    __device__ static acc_t run(uint4 a, uint4 b, acc_t c)
+    {
+        v8bf x, y;
+        __builtin_memcpy(&x, &a, 16);
+        __builtin_memcpy(&y, &b, 16);
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
+    }
+};
+template <>
+struct Mfma<DT_FP16> {
+    typedef v4f acc_t;
+    __device__ static acc_t run(uint4 a, uint4 b, acc_t c)
+    {
+        v8h x, y;
+        __builtin_memcpy(&x, &a, 16);
+        __builtin_memcpy(&y, &b, 16);
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(x, y, c, 0, 0, 0);
+    }
+};
+template <>
+struct Mfma<DT_INT8> {
+    typedef v4i acc_t;
+    __device__ static acc_t run(uint4 a, uint4 b, acc_t c)
+    {
+        v4i x, y;
+        __builtin_memcpy(&x, &a, 16);
+        __builtin_memcpy(&y, &b, 16);
+        return __builtin_amdgcn_mfma_i32_16x16x64_i8(x, y, c, 0, 0, 0);
+    }
+};
+
+// Workgroup of 4 waves (2 x 2); wave tile WBM x WBN blocks of 16 x 16.
+// Per K tile of 64 the workgroup stages the s digit tiles of its BM rows of
+// A and BN columns of B in LDS (row pitch 64*esize + 16 bytes: the 16 rows
+// a lane group reads fall in distinct banks), then every wave runs the
+// s(s+1)/2 kept digit pairs, pair (t, u) accumulating into group t+u.
+// Operand layout of both MFMAs used: lane l holds row (A) / column (B)
+// l % 16 and the 16 bytes of K starting at 16 (l / 16) bytes; result
+// element r of lane l is D[4 (l / 16) + r][l % 16].
+template <int DT, int S, bool FLUSH>
+__global__ __launch_bounds__(256) void split_gemm_kernel(const char* __restrict__ SA, const char* __restrict__ SB,
+                                                         const int* __restrict__ ea, const int* __restrict__ fb,
+                                                         double* __restrict__ C, i64 N, i64 M, i64 Kp,
+                                                         i64 tiles_m, i64 tiles_n, int flush_steps)
+{
+    typedef Digit<DT> D;
+    typedef typename Mfma<DT>::acc_t acc_t;
+    constexpr TileCfg TC = tile_cfg(DT, S, FLUSH);
+    constexpr int ES = D::esize, BM = TC.bm(), BN = TC.bn(), WBM = TC.wbm, WBN = TC.wbn;
+    constexpr int ROWB = KT * ES;         // bytes of one digit row in a K tile
+    constexpr int PITCH = ROWB + 16;      // LDS row pitch
+    constexpr int G = S;                  // groups g = 2 .. S+1 -> index g-2
+    constexpr int STEPS = KT / D::mfma_k; // MFMA k-steps per K tile
+    constexpr int CH_A = BM * S * ROWB / 16, CH_B = BN * S * ROWB / 16;  // 16-byte chunks per tile
+    constexpr int LA = CH_A / 256, LB = CH_B / 256;
+    static_assert(CH_A % 256 == 0 && CH_B % 256 == 0, "chunks");
+    extern __shared__ __align__(16) char lds[];
+    char* la = lds;                       // [S][BM][PITCH]
+    char* lb = lds + S * BM * PITCH;      // [S][BN][PITCH]
+
+    // tile order: XCD-contiguous ranges, 8 tile-rows per group
+    const i64 total = tiles_m * tiles_n;
+    i64 b = blockIdx.x;
+    if (total % 8 == 0) b = (b % 8) * (total / 8) + b / 8;
+    const i64 grp = b / (8 * tiles_n), first = grp * 8;
+    const i64 gs = (tiles_m - first) < 8 ? (tiles_m - first) : 8;
+    const i64 w = b - grp * 8 * tiles_n;
+    const i64 tm = first + w % gs, tn = w / gs;
+    const i64 m0 = tm * BM, n0 = tn * BN;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int li = lane & 15, lq = lane >> 4;
+
+    acc_t acc[G][WBM][WBN];
+    double acc64[FLUSH ? G : 1][FLUSH ? WBM : 1][FLUSH ? WBN : 1][4];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int i = 0; i < WBM; ++i)
+#pragma unroll
+            for (int j = 0; j < WBN; ++j) {
+                acc[g][i][j] = (acc_t){0, 0, 0, 0};
+                if (FLUSH)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc64[g][i][j][r] = 0.0;
+            }
+
+    const i64 row_bytes = Kp * S * ES;
+    const i64 ktiles = Kp / KT;
+    uint4 ra[LA], rb[LB];
+    // chunk c of a tile: row = c / (S*ROWB/16), then digit t and 16-byte piece
+    auto gload = [&](i64 kt) {
+#pragma unroll
+        for (int q = 0; q < LA; ++q) {
+            const int c = q * 256 + tid;
+            const int row = c / (S * ROWB / 16), rem = c % (S * ROWB / 16);
+            ra[q] = *reinterpret_cast<const uint4*>(SA + (m0 + row) * row_bytes + kt * S * ROWB + rem * 16);
+        }
+#pragma unroll
+        for (int q = 0; q < LB; ++q) {
+            const int c = q * 256 + tid;
+            const int row = c / (S * ROWB / 16), rem = c % (S * ROWB / 16);
+            rb[q] = *reinterpret_cast<const uint4*>(SB + (n0 + row) * row_bytes + kt * S * ROWB + rem * 16);
+        }
+    };
+    auto lstore = [&]() {
+#pragma unroll
+        for (int q = 0; q < LA; ++q) {
+            const int c = q * 256 + tid;
+            const int row = c / (S * ROWB / 16), rem = c % (S * ROWB / 16);
+            const int t = rem / (ROWB / 16), piece = rem % (ROWB / 16);
+            *reinterpret_cast<uint4*>(la + (t * BM + row) * PITCH + piece * 16) = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < LB; ++q) {
+            const int c = q * 256 + tid;
+            const int row = c / (S * ROWB / 16), rem = c % (S * ROWB / 16);
+            const int t = rem / (ROWB / 16), piece = rem % (ROWB / 16);
+            *reinterpret_cast<uint4*>(lb + (t * BN + row) * PITCH + piece * 16) = rb[q];
+        }
+    };
+
+    int since_flush = 0;
+    if (ktiles > 0) gload(0);
+    for (i64 kt = 0; kt < ktiles; ++kt) {
+        __syncthreads();  // previous tile fully consumed
+        lstore();
+        __syncthreads();
+        if (kt + 1 < ktiles) gload(kt + 1);
+#pragma unroll
+        for (int st = 0; st < STEPS; ++st) {
+            const int koff = st * D::mfma_k * ES + lq * 16;
+#pragma unroll
+            for (int t = 0; t < S; ++t) {
+                uint4 af[WBM];
+#pragma unroll
+                for (int i = 0; i < WBM; ++i)
+                    af[i] = *reinterpret_cast<const uint4*>(la + (t * BM + wm * WBM * 16 + i * 16 + li) * PITCH + koff);
+#pragma unroll
+                for (int u = 0; u + t + 2 <= S + 1; ++u) {
+                    uint4 bf[WBN];
+#pragma unroll
+                    for (int j = 0; j < WBN; ++j)
+                        bf[j] = *reinterpret_cast<const uint4*>(lb + (u * BN + wn * WBN * 16 + j * 16 + li) * PITCH + koff);
+#pragma unroll
+                    for (int i = 0; i < WBM; ++i)
+#pragma unroll
+                        for (int j = 0; j < WBN; ++j)
+                            acc[t + u][i][j] = Mfma<DT>::run(af[i], bf[j], acc[t + u][i][j]);
+                }
+            }
+            if (FLUSH) {
+                if (++since_flush == flush_steps) {
+                    since_flush = 0;
+#pragma unroll
+                    for (int g = 0; g < G; ++g)
+#pragma unroll
+                        for (int i = 0; i < WBM; ++i)
+#pragma unroll
+                            for (int j = 0; j < WBN; ++j) {
+#pragma unroll
+                                for (int r = 0; r < 4; ++r) acc64[g][i][j][r] += (double)acc[g][i][j][r];
+                                acc[g][i][j] = (acc_t){0, 0, 0, 0};
+                            }
+                }
+            }
+        }
+    }
+
+    // c = sum over g = S+1 .. 2 of 2^(-beta g) G_g, then scale by 2^(e_i + f_j)
+#pragma unroll
+    for (int i = 0; i < WBM; ++i)
+#pragma unroll
+        for (int j = 0; j < WBN; ++j) {
+            const i64 gn = n0 + wn * WBN * 16 + j * 16 + li;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const i64 gm = m0 + wm * WBM * 16 + i * 16 + 4 * lq + r;
+                double c = 0.0;
+#pragma unroll
+                for (int g = G - 1; g >= 0; --g) {
+                    const double Gg = FLUSH ? acc64[g][i][j][r] + (double)acc[g][i][j][r] : (double)acc[g][i][j][r];
+                    const double term = ldexp(Gg, -D::beta * (g + 2));
+                    c = c + term;
+                }
+                if (gm < N && gn < M) C[gm * M + gn] = ldexp(c, ea[gm] + fb[gn]);
+            }
+        }
+}
+
+struct SplitLayout {
+    int dt = 0, s = 0;
+    bool flush = false;
+    i64 Np = 0, Mp = 0, Kp = 0;
+    size_t nA = 0, nB = 0, lam = 0, rmax = 0, cmax = 0, ea = 0, fb = 0, SA = 0, SB = 0, bytes = 0;
+};
+
+size_t al(size_t x) { return (x + 255) / 256 * 256; }
+
+// exact-accumulation budget: digit products are at most 2^(2 beta - 2);
+// a group of at most s pairs over kb entries must stay below the budget.
+// Returns the number of MFMA k-steps between flushes to FP64.
+int flush_steps_for(int dt, int s)
+{
+    const int beta = beta_of(dt);
+    const double prod = ldexp(1.0, 2 * beta - 2);
+    const double budget = dt == DT_INT8 ? Digit<DT_INT8>::budget : Digit<DT_BF16>::budget;
+    const int mk = dt == DT_INT8 ? Digit<DT_INT8>::mfma_k : Digit<DT_BF16>::mfma_k;
+    const double kb = budget / (prod * s);
+    return (int)(kb / mk);
+}
+
+bool split_layout(i64 N, i64 P, i64 M, const mmm_config& c, SplitLayout& L)
+{
+    L.dt = c.split_type;
+    L.s = c.split_slices;
+    const int es = L.dt == DT_INT8 ? 1 : 2;
+    const int mk = L.dt == DT_INT8 ? Digit<DT_INT8>::mfma_k : Digit<DT_BF16>::mfma_k;
+    L.Kp = cdiv(P, KT) * KT;
+    const int fs = flush_steps_for(L.dt, L.s);
+    L.flush = fs < L.Kp / mk;
+    const TileCfg tc = tile_cfg(L.dt, L.s, L.flush);
+    L.Np = cdiv(N, tc.bm()) * tc.bm();
+    L.Mp = cdiv(M, tc.bn()) * tc.bn();
+    const double sa = (double)L.Np * L.Kp * L.s * es, sb = (double)L.Mp * L.Kp * L.s * es;
+    if (sa + sb > 4.0e18) return false;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = al(off + bytes);
+        return at;
+    };
+    L.nA = take(8);
+    L.nB = take(8);
+    L.lam = take(4);
+    L.rmax = take(8 * (size_t)N);
+    L.cmax = take(8 * (size_t)M);
+    L.ea = take(4 * (size_t)L.Np);
+    L.fb = take(4 * (size_t)L.Mp);
+    L.SA = take((size_t)sa);
+    L.SB = take((size_t)sb);
+    L.bytes = off;
+    return true;
+}
+
+template <int DT, int S, bool FLUSH>
+hipError_t launch_split_gemm(const SplitLayout& L, char* ws, double* C, i64 N, i64 M, int flush_steps, hipStream_t st)
+{
+    typedef Digit<DT> D;
+    constexpr TileCfg TC = tile_cfg(DT, S, FLUSH);
+    const i64 tiles_m = L.Np / TC.bm(), tiles_n = L.Mp / TC.bn();
+    const i64 blocks = tiles_m * tiles_n;
+    if (blocks == 0) return hipSuccess;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    const size_t lds = (size_t)S * (TC.bm() + TC.bn()) * (KT * D::esize + 16);
+    auto kern = split_gemm_kernel<DT, S, FLUSH>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), lds, st, (const char*)(ws + L.SA),
+                       (const char*)(ws + L.SB), (const int*)(ws + L.ea), (const int*)(ws + L.fb), C, N, M, L.Kp,
+                       tiles_m, tiles_n, flush_steps);
+    return hipGetLastError();
+}
+
+template <int DT, int S>
+hipError_t dispatch_flush(const SplitLayout& L, char* ws, double* C, i64 N, i64 M, hipStream_t st)
+{
+    const int fs = flush_steps_for(DT, S);
+    if (fs < 1) return hipErrorNotSupported;
+    if (!L.flush) return launch_split_gemm<DT, S, false>(L, ws, C, N, M, fs, st);
+    return launch_split_gemm<DT, S, true>(L, ws, C, N, M, fs, st);
+}
+
+template <int DT>
+hipError_t dispatch_s(const SplitLayout& L, char* ws, double* C, i64 N, i64 M, hipStream_t st)
+{
+    switch (L.s) {
+    case 1: return dispatch_flush<DT, 1>(L, ws, C, N, M, st);
+    case 2: return dispatch_flush<DT, 2>(L, ws, C, N, M, st);
+    case 3: return dispatch_flush<DT, 3>(L, ws, C, N, M, st);
+    case 4: return dispatch_flush<DT, 4>(L, ws, C, N, M, st);
+    case 5: return dispatch_flush<DT, 5>(L, ws, C, N, M, st);
+    case 6: return dispatch_flush<DT, 6>(L, ws, C, N, M, st);
+    case 7: return dispatch_flush<DT, 7>(L, ws, C, N, M, st);
+    case 8: return dispatch_flush<DT, 8>(L, ws, C, N, M, st);
+    default: return hipErrorNotSupported;
+    }
+}
+
+template <int DT>
+hipError_t run_split_dt(const double* A, const double* B, double* C, i64 N, i64 P, i64 M, const SplitLayout& L,
+                        bool scale, char* ws, hipStream_t st)
+{
+    hipError_t e;
+    int* lam = nullptr;
+    if (scale) {
+        lam = (int*)(ws + L.lam);
+        if ((e = launch_norm_inf(A, N, P, (double*)(ws + L.nA), st)) != hipSuccess) return e;
+        if ((e = launch_norm_inf(B, P, M, (double*)(ws + L.nB), st)) != hipSuccess) return e;
+        if ((e = launch_lambda((double*)(ws + L.nA), (double*)(ws + L.nB), lam, st)) != hipSuccess) return e;
+    }
+    double* rmax = (double*)(ws + L.rmax);
+    double* cmax = (double*)(ws + L.cmax);
+    if ((e = launch_vector_reduce(RED_ABS_MAX, false, A, P, N, P, rmax, lam, +1, st)) != hipSuccess) return e;
+    if ((e = launch_vector_reduce(RED_ABS_MAX, true, B, M, M, P, cmax, lam, -1, st)) != hipSuccess) return e;
+    {
+        const i64 total = L.Np * (L.Kp / 8);
+        i64 blocks = cdiv(total, 256);
+        if (blocks > 256 * 64) blocks = 256 * 64;
+        hipLaunchKernelGGL((split_a_kernel<DT>), dim3((unsigned)blocks), dim3(256), 0, st, A, N, P, L.Np, L.Kp, rmax,
+                           lam, L.s, ws + L.SA, (int*)(ws + L.ea));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    {
+        const i64 blocks = (L.Kp / 64) * (L.Mp / 64);
+        hipLaunchKernelGGL((split_b_kernel<DT>), dim3((unsigned)blocks), dim3(256), 0, st, B, P, M, L.Mp, L.Kp, cmax,
+                           lam, L.s, ws + L.SB, (int*)(ws + L.fb));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return dispatch_s<DT>(L, ws, C, N, M, st);
+}
+
+}  // namespace
+
+size_t split_workspace_bytes(i64 N, i64 P, i64 M, const mmm_config& c)
+{
+    SplitLayout L;
+    if (!split_layout(N, P, M, c, L)) return (size_t)-1;
+    if (flush_steps_for(c.split_type, c.split_slices) < 1) return (size_t)-1;
+    return L.bytes;
+}
+
+hipError_t run_split(const double* A, const double* B, double* C, i64 N, i64 P, i64 M, const mmm_config& c,
+                     char* ws, hipStream_t s)
+{
+    SplitLayout L;
+    if (!split_layout(N, P, M, c, L)) return hipErrorNotSupported;
+    const bool scale = c.split_scale_lambda != 0;
+    switch (c.split_type) {
+    case DT_BF16: return run_split_dt<DT_BF16>(A, B, C, N, P, M, L, scale, ws, s);
+    case DT_FP16: return run_split_dt<DT_FP16>(A, B, C, N, P, M, L, scale, ws, s);
+    case DT_INT8: return run_split_dt<DT_INT8>(A, B, C, N, P, M, L, scale, ws, s);
+    default: return hipErrorNotSupported;
+    }
 }
 
 }  // namespace mmm
