@@ -71,6 +71,7 @@ def parse():
     ap.add_argument("--only", default="", help="comma-separated subset of methods (for profiling)")
     ap.add_argument("--no-precision", action="store_true", help="skip the 8192^3 split-vs-DGEMM comparison")
     ap.add_argument("--precision-reps", type=int, default=5)
+    ap.add_argument("--precision-only", action="store_true", help="run only the 8192^3 comparison (profiling)")
     return ap.parse_args()
 
 
@@ -87,6 +88,11 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.precision_only:
+        stream = torch.cuda.current_stream()
+        print(json.dumps({"precision_8192": precision_section(args, mmm, torch, synth, dev, stream,
+                                                              errors_needed=not args.no_cpu_baseline)}), flush=True)
+        return
     n = args.size
     shapes = [(n, n, n), (n, n + 1, n)]
     methods = [m for m in METHODS if not args.only or m[0] in args.only.split(",")]

@@ -35,6 +35,7 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int KT = 64;  // K tile (elements)
 
@@ -69,7 +70,7 @@ struct TileCfg {
 };
 __host__ __device__ constexpr TileCfg tile_cfg(int dt, int s, bool flush)
 {
-    return dt == DT_INT8 ? (flush ? TileCfg{2, 2} : TileCfg{4, 2}) : (s >= 7 ? TileCfg{1, 2} : TileCfg{2, 2});
+    return dt == DT_INT8 ? (flush ? TileCfg{2, 2} : TileCfg{4, 2}) : (s >= 6 ? TileCfg{1, 2} : TileCfg{2, 2});
 }
 
 __host__ __device__ inline int beta_of(int dt) { return dt == DT_BF16 ? 8 : (dt == DT_FP16 ? 9 : 7); }
@@ -206,7 +207,7 @@ struct Mfma;
 template <>
 struct Mfma<DT_BF16> {
     typedef v4f acc_t;
-    __device__ static acc_t run(uint4 a, uint4 b, acc_t c)
+    __device__ static acc_t run(u32x4 a, u32x4 b, acc_t c)
     {
         v8bf x, y;
         __builtin_memcpy(&x, &a, 16);
@@ -217,7 +218,7 @@ struct Mfma<DT_BF16> {
 template <>
 struct Mfma<DT_FP16> {
     typedef v4f acc_t;
-    __device__ static acc_t run(uint4 a, uint4 b, acc_t c)
+    __device__ static acc_t run(u32x4 a, u32x4 b, acc_t c)
     {
         v8h x, y;
         __builtin_memcpy(&x, &a, 16);
@@ -228,7 +229,7 @@ struct Mfma<DT_FP16> {
 template <>
 struct Mfma<DT_INT8> {
     typedef v4i acc_t;
-    __device__ static acc_t run(uint4 a, uint4 b, acc_t c)
+    __device__ static acc_t run(u32x4 a, u32x4 b, acc_t c)
     {
         v4i x, y;
         __builtin_memcpy(&x, &a, 16);
@@ -296,36 +297,36 @@ __global__ __launch_bounds__(256) void split_gemm_kernel(const char* __restrict_
 
     const i64 row_bytes = Kp * S * ES;
     const i64 ktiles = Kp / KT;
-    uint4 ra[LA], rb[LB];
+    u32x4 ra[LA], rb[LB];
     // chunk c of a tile: row = c / (S*ROWB/16), then digit t and 16-byte piece
-    auto gload = [&](i64 kt) {
+    auto gload = [&](i64 kt) __attribute__((always_inline)) {
 #pragma unroll
         for (int q = 0; q < LA; ++q) {
             const int c = q * 256 + tid;
             const int row = c / (S * ROWB / 16), rem = c % (S * ROWB / 16);
-            ra[q] = *reinterpret_cast<const uint4*>(SA + (m0 + row) * row_bytes + kt * S * ROWB + rem * 16);
+            ra[q] = *reinterpret_cast<const u32x4*>(SA + (m0 + row) * row_bytes + kt * S * ROWB + rem * 16);
         }
 #pragma unroll
         for (int q = 0; q < LB; ++q) {
             const int c = q * 256 + tid;
             const int row = c / (S * ROWB / 16), rem = c % (S * ROWB / 16);
-            rb[q] = *reinterpret_cast<const uint4*>(SB + (n0 + row) * row_bytes + kt * S * ROWB + rem * 16);
+            rb[q] = *reinterpret_cast<const u32x4*>(SB + (n0 + row) * row_bytes + kt * S * ROWB + rem * 16);
         }
     };
-    auto lstore = [&]() {
+    auto lstore = [&]() __attribute__((always_inline)) {
 #pragma unroll
         for (int q = 0; q < LA; ++q) {
             const int c = q * 256 + tid;
             const int row = c / (S * ROWB / 16), rem = c % (S * ROWB / 16);
             const int t = rem / (ROWB / 16), piece = rem % (ROWB / 16);
-            *reinterpret_cast<uint4*>(la + (t * BM + row) * PITCH + piece * 16) = ra[q];
+            *reinterpret_cast<u32x4*>(la + (t * BM + row) * PITCH + piece * 16) = ra[q];
         }
 #pragma unroll
         for (int q = 0; q < LB; ++q) {
             const int c = q * 256 + tid;
             const int row = c / (S * ROWB / 16), rem = c % (S * ROWB / 16);
             const int t = rem / (ROWB / 16), piece = rem % (ROWB / 16);
-            *reinterpret_cast<uint4*>(lb + (t * BN + row) * PITCH + piece * 16) = rb[q];
+            *reinterpret_cast<u32x4*>(lb + (t * BN + row) * PITCH + piece * 16) = rb[q];
         }
     };
 
@@ -341,16 +342,16 @@ __global__ __launch_bounds__(256) void split_gemm_kernel(const char* __restrict_
             const int koff = st * D::mfma_k * ES + lq * 16;
 #pragma unroll
             for (int t = 0; t < S; ++t) {
-                uint4 af[WBM];
+                u32x4 af[WBM];
 #pragma unroll
                 for (int i = 0; i < WBM; ++i)
-                    af[i] = *reinterpret_cast<const uint4*>(la + (t * BM + wm * WBM * 16 + i * 16 + li) * PITCH + koff);
+                    af[i] = *reinterpret_cast<const u32x4*>(la + (t * BM + wm * WBM * 16 + i * 16 + li) * PITCH + koff);
 #pragma unroll
                 for (int u = 0; u + t + 2 <= S + 1; ++u) {
-                    uint4 bf[WBN];
+                    u32x4 bf[WBN];
 #pragma unroll
                     for (int j = 0; j < WBN; ++j)
-                        bf[j] = *reinterpret_cast<const uint4*>(lb + (u * BN + wn * WBN * 16 + j * 16 + li) * PITCH + koff);
+                        bf[j] = *reinterpret_cast<const u32x4*>(lb + (u * BN + wn * WBN * 16 + j * 16 + li) * PITCH + koff);
 #pragma unroll
                     for (int i = 0; i < WBM; ++i)
 #pragma unroll
