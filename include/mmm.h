@@ -136,14 +136,20 @@ typedef struct {
     int64_t N, P, M;
     int32_t method;  /* MMM_DGEMM or MMM_SPLIT */
     int32_t slices;  /* split digits (MMM_SPLIT), 0 = the config's default */
+    int32_t tile;    /* DGEMM tile shape: 0 = library's choice, 1 = 128x128, 2 = 64x64, 3 = 128x64 */
+    int32_t reserved;/* must be zero */
 } mmm_problem;
 
 typedef struct mmm_batch mmm_batch;
 
-/* Build a plan for `count` problems: validates them, chooses tile shapes,
- * allocates device tables and workspace (owned by the plan) and uploads the
- * descriptors on `stream`.  Pointers inside the problems are captured; the
- * caller must keep the matrices alive while the plan is launched. */
+/* Build a plan for `count` (1..65535) problems: validates them, chooses
+ * tile shapes, allocates device tables and workspace (owned by the plan),
+ * uploads the descriptors and records the launch sequence into a HIP graph
+ * (FP64 and split halves on parallel branches).  Synchronous with respect
+ * to `stream`.  Pointers inside the problems are captured; the caller must
+ * keep the matrices alive while the plan is launched.  Each product is
+ * computed exactly as a single mmm_multiply call with the same method and
+ * config would compute it (bitwise), whatever else is in the batch. */
 mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mmm_config* cfg, void* stream,
                             mmm_batch** plan_out);
 

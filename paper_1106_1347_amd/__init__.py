@@ -12,6 +12,7 @@ module fails when ``libmmm.so`` is missing.
 """
 from ._lib import (  # noqa: F401
     METHODS,
+    TILES,
     Batch,
     Config,
     MmmError,

@@ -42,7 +42,8 @@ class _CConfig(ctypes.Structure):
 class _CProblem(ctypes.Structure):
     _fields_ = [("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("C", ctypes.c_void_p),
                 ("N", ctypes.c_int64), ("P", ctypes.c_int64), ("M", ctypes.c_int64),
-                ("method", ctypes.c_int32), ("slices", ctypes.c_int32)]
+                ("method", ctypes.c_int32), ("slices", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 _vp, _i64, _i32, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
@@ -208,23 +209,34 @@ def winograd_lambda(normA: torch.Tensor, normB: torch.Tensor, stream=None):
     return out
 
 
+TILES = {"auto": 0, "128x128": 1, "64x64": 2, "128x64": 3}
+
+
 class Batch:
-    """Plan for many independent products launched together (mmm_batch_*)."""
+    """Plan for many independent products launched as one HIP graph (mmm_batch_*).
+
+    problems: sequence of (A, B, C, method[, slices[, tile]]) with CUDA
+    float64 tensors; method is "dgemm" or "split"; slices 0 = the config's
+    digit count; tile a key of TILES (DGEMM only) or an int.
+    """
 
     def __init__(self, problems: Sequence[tuple], config: Optional[Config] = None, stream=None):
-        """problems: (A, B, C, method[, slices]) with CUDA float64 tensors."""
         arr = (_CProblem * len(problems))()
         self._keep = []
         for i, p in enumerate(problems):
             A, B, C, method = p[0], p[1], p[2], p[3]
             slices = p[4] if len(p) > 4 else 0
+            tile = p[5] if len(p) > 5 else 0
             for t, n in ((A, "A"), (B, "B"), (C, "C")):
                 _dev(t, n)
+            if A.shape[1] != B.shape[0] or tuple(C.shape) != (A.shape[0], B.shape[1]):
+                raise ValueError("problem %d: shapes do not match" % i)
             arr[i].A, arr[i].B, arr[i].C = A.data_ptr(), B.data_ptr(), C.data_ptr()
             arr[i].N, arr[i].P = A.shape
             arr[i].M = B.shape[1]
             arr[i].method = METHODS[method]
             arr[i].slices = int(slices)
+            arr[i].tile = TILES[tile] if isinstance(tile, str) else int(tile)
             self._keep.append((A, B, C))
         c = (config or Config())._c()
         h = ctypes.c_void_p()

@@ -13,10 +13,12 @@
 using namespace mmm;
 
 namespace {
-
 thread_local char g_err[512] = "";
+}
 
-mmm_status fail(mmm_status st, const char* fmt, ...)
+namespace mmm {
+
+mmm_status set_error(mmm_status st, const char* fmt, ...)
 {
     va_list ap;
     va_start(ap, fmt);
@@ -24,6 +26,12 @@ mmm_status fail(mmm_status st, const char* fmt, ...)
     va_end(ap);
     return st;
 }
+
+}  // namespace mmm
+
+namespace {
+
+#define fail mmm::set_error
 
 mmm_status from_hip(hipError_t e, const char* what)
 {
@@ -41,7 +49,9 @@ bool overlap(const void* a, size_t abytes, const void* b, size_t bbytes)
     return a0 < b0 + bbytes && b0 < a0 + abytes;
 }
 
-mmm_status check_cfg(const mmm_config& c)
+}  // namespace
+
+mmm_status mmm::check_config(const mmm_config& c)
 {
     for (int i = 0; i < 9; ++i)
         if (c.reserved[i] != 0) return fail(MMM_EINVAL, "config: reserved fields must be zero");
@@ -58,6 +68,10 @@ mmm_status check_cfg(const mmm_config& c)
     if (c.naive_fma != 0 && c.naive_fma != 1) return fail(MMM_EINVAL, "config: bad naive_fma");
     return MMM_OK;
 }
+
+namespace {
+
+mmm_status check_cfg(const mmm_config& c) { return mmm::check_config(c); }
 
 // ---- Strassen planning (Section 2.4) ---------------------------------------
 

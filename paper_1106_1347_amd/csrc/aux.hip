@@ -8,12 +8,11 @@
 // results equal a sequential binary64 evaluation bit for bit.
 #include "common.h"
 #include "launch.h"
+#include "reduce.h"
 
 namespace mmm {
 
 namespace {
-
-__device__ inline double max_s13(double x, double y) { return x >= y ? x : y; }  // Section 1.3
 
 template <int OP>
 __device__ inline double ew(double a, double b, double alpha)
@@ -66,82 +65,12 @@ hipError_t launch_ew(const double* A, const double* B, double alpha, double* C, 
     return hipGetLastError();
 }
 
-// Sequential reduction of 16 vectors per workgroup.  The workgroup streams
-// each vector in chunks of 256 entries through double-buffered LDS with
-// coalesced loads (rows: 2 KiB runs; columns: 128-byte runs of 16
-// neighbouring columns); 16 lanes then fold their vector's chunk in order.
-constexpr int RV = 16, RL = 256, RPER = RV * RL / 256;
-
 template <int OP, bool COLS, bool SCALED, bool FOLD_MAX>
 __global__ __launch_bounds__(256) void vecred_kernel(const double* __restrict__ X, i64 ld, i64 nvec, i64 len,
                                                      double* __restrict__ out, const int* lam, int sign)
 {
     __shared__ double T[2][RV][RL + 1];
-    const int tid = threadIdx.x;
-    const i64 v0 = (i64)blockIdx.x * RV;
-    const i64 lim = (OP == RED_PAIR_SUM) ? 2 * (len / 2) : len;
-    const i64 nchunks = (lim + RL - 1) / RL;
-    const double sc = SCALED ? ldexp(1.0, sign * *lam) : 1.0;
-    double r[RPER];
-    auto load = [&](i64 c) {
-#pragma unroll
-        for (int q = 0; q < RPER; ++q) {
-            const int e = q * 256 + tid;
-            const int v = COLS ? (e % RV) : (e / RL);
-            const int x = COLS ? (e / RV) : (e % RL);
-            const i64 gv = v0 + v, gx = c * RL + x;
-            double val = 0.0;
-            if (gv < nvec && gx < lim) val = COLS ? X[gx * ld + gv] : X[gv * ld + gx];
-            r[q] = val;
-        }
-    };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int q = 0; q < RPER; ++q) {
-            const int e = q * 256 + tid;
-            const int v = COLS ? (e % RV) : (e / RL);
-            const int x = COLS ? (e / RV) : (e % RL);
-            T[buf][v][x] = r[q];
-        }
-    };
-    double acc = 0.0;
-    if (nchunks > 0) {
-        load(0);
-        store(0);
-    }
-    __syncthreads();
-    for (i64 c = 0; c < nchunks; ++c) {
-        const int cur = (int)(c & 1);
-        if (c + 1 < nchunks) load(c + 1);
-        if (tid < RV) {
-            const i64 rem = lim - c * RL;
-            const int cnt = rem < RL ? (int)rem : RL;
-            const double* row = T[cur][tid];
-            if (OP == RED_ABS_SUM) {
-                for (int x = 0; x < cnt; ++x) acc = acc + fabs(SCALED ? row[x] * sc : row[x]);
-            } else if (OP == RED_PAIR_SUM) {
-                for (int x = 0; x < cnt; x += 2) {
-                    const double a = SCALED ? row[x] * sc : row[x];
-                    const double b = SCALED ? row[x + 1] * sc : row[x + 1];
-                    const double p = a * b;
-                    acc = acc + p;
-                }
-            } else {
-                for (int x = 0; x < cnt; ++x) acc = max_s13(acc, fabs(SCALED ? row[x] * sc : row[x]));
-            }
-        }
-        if (c + 1 < nchunks) store(cur ^ 1);
-        __syncthreads();
-    }
-    if (tid < RV && v0 + tid < nvec) {
-        if (FOLD_MAX) {
-            // max over vectors of non-negative values: the order of binary64
-            // bit patterns of non-negative numbers is their numeric order
-            atomicMax(reinterpret_cast<unsigned long long*>(out), (unsigned long long)__double_as_longlong(acc));
-        } else {
-            out[v0 + tid] = acc;
-        }
-    }
+    vecred_body<OP, COLS, SCALED, FOLD_MAX>(X, ld, nvec, len, out, lam, sign, blockIdx.x, T);
 }
 
 template <int OP, bool COLS>

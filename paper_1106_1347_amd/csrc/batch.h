@@ -1,0 +1,57 @@
+// Batches of independent products (internal to libmmm).
+#pragma once
+
+#include "common.h"
+
+namespace mmm {
+
+// DGEMM tile shapes a batch problem may request (mmm_problem.tile).
+enum DgemmTile { DGEMM_TILE_AUTO = 0, DGEMM_TILE_128x128 = 1, DGEMM_TILE_64x64 = 2, DGEMM_TILE_128x64 = 3 };
+
+int dgemm_tile_bm(int tile);
+int dgemm_tile_bn(int tile);
+// Persistent grid of `grid` workgroups over the `total` tiles of `nprob`
+// problems (device tables: probs[nprob], prefix[nprob + 1]).
+hipError_t launch_dgemm_grouped(int tile, const Gemm* probs, const i64* prefix, int nprob, i64 total, int grid,
+                                hipStream_t s);
+
+// One split problem of a batch: operands, output and its workspace slices.
+struct SplitJob {
+    const double* A;
+    const double* B;
+    double* C;
+    i64 N, P, M;
+    i64 Np, Mp, Kp;
+    double* nA;   // norms (device scalars)
+    double* nB;
+    int* lam;
+    double* rmax; // N
+    double* cmax; // M
+    int* ea;      // Np
+    int* fb;      // Mp
+    char* SA;
+    char* SB;
+};
+
+// Split jobs of one digit type and count, sharing one tile shape.
+struct SplitGroup {
+    int dt, s;
+    bool flush;
+    int flush_steps;
+    int bm, bn;
+};
+
+// Workspace bytes for one split job; fills the job's Np/Mp/Kp and returns
+// (size_t)-1 when unsupported.  Offsets of the job's buffers inside its
+// workspace are assigned by split_job_bind.
+size_t split_job_bytes(i64 N, i64 P, i64 M, int dt, int s, SplitGroup& grp, i64& Np, i64& Mp, i64& Kp);
+void split_job_bind(SplitJob& j, char* base, int dt, int s);
+// Host-side set-up of a group's kernels (dynamic LDS size); call once
+// before recording launches into a graph.
+hipError_t split_grouped_prepare(const SplitGroup& grp);
+// Enqueue the grouped split pipeline for `n` jobs (device table `jobs`,
+// host copy `hjobs` for launch sizing), tile prefix table `prefix`.
+hipError_t launch_split_grouped(const SplitGroup& grp, const SplitJob* jobs, const SplitJob* hjobs, int n,
+                                const i64* prefix, i64 total_tiles, bool scale_lambda, int grid, hipStream_t s);
+
+}  // namespace mmm

@@ -1,11 +1,270 @@
+// Batches of independent products (mmm_batch_*): one plan, one HIP graph.
+//
+// The plan groups the FP64 problems by DGEMM tile shape and the split
+// problems by (digit type, digit count, flush scheme); every group runs as
+// one persistent kernel that deals its tiles round robin over a grid sized
+// to the chip, preceded for split groups by batched preprocessing kernels
+// (norms, lambda, row/column maxima, digit extraction) whose blockIdx.y
+// selects the problem.  The FP64 groups and the split groups are recorded
+// on two branches of one HIP graph, so they overlap on the device.  A
+// tile's arithmetic does not depend on the tile shape or on which workgroup
+// runs it, so every result equals the single-call result bit for bit.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <tuple>
+#include <vector>
+
+#include "batch.h"
 #include "common.h"
+#include "split.h"
+
+using namespace mmm;
+
+struct mmm_batch {
+    void* dmem = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t last = nullptr;
+};
+
+namespace {
+
+#define bfail mmm::set_error
+
+size_t al256(size_t x) { return (x + 255) / 256 * 256; }
+
+struct DGroup {
+    int tile;
+    std::vector<Gemm> probs;
+    std::vector<i64> prefix;
+    size_t off_probs = 0, off_prefix = 0;
+};
+
+struct SGroup {
+    SplitGroup g;
+    std::vector<SplitJob> jobs;
+    std::vector<size_t> ws_off;
+    std::vector<i64> prefix;
+    size_t off_jobs = 0, off_prefix = 0;
+};
+
+struct Interval {
+    uintptr_t lo, hi;
+    bool out;
+    int idx;
+};
+
+int pick_tile(const mmm_problem& p)
+{
+    if (p.tile != DGEMM_TILE_AUTO) return p.tile;
+    return (p.N >= 256 && p.M >= 256) ? DGEMM_TILE_128x128 : DGEMM_TILE_64x64;
+}
+
+}  // namespace
 
 extern "C" {
-mmm_status mmm_batch_create(const mmm_problem*, int32_t, const mmm_config*, void*, mmm_batch** out)
+
+mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mmm_config* cfgp, void* stream,
+                            mmm_batch** plan_out)
 {
-    if (out) *out = nullptr;
-    return MMM_EUNSUPPORTED;
+    if (!plan_out) return bfail(MMM_EINVAL, "plan_out is null");
+    *plan_out = nullptr;
+    if (!problems || count < 1 || count > 65535) return bfail(MMM_EINVAL, "count must be 1..65535");
+    const mmm_config c = cfgp ? *cfgp : mmm_config_default();
+    if (check_config(c) != MMM_OK) return MMM_EINVAL;
+
+    // validation and aliasing
+    std::vector<Interval> iv;
+    for (int i = 0; i < count; ++i) {
+        const mmm_problem& p = problems[i];
+        if (p.N < 0 || p.P < 0 || p.M < 0) return bfail(MMM_EINVAL, "problem %d: negative size", i);
+        if (p.method != MMM_DGEMM && p.method != MMM_SPLIT)
+            return bfail(MMM_EINVAL, "problem %d: batches take MMM_DGEMM or MMM_SPLIT", i);
+        if (p.slices < 0 || p.slices > kMaxSlices) return bfail(MMM_EINVAL, "problem %d: slices outside 0..8", i);
+        if (p.tile < 0 || p.tile > 3 || p.reserved != 0) return bfail(MMM_EINVAL, "problem %d: bad tile", i);
+        if (p.N > 0 && p.M > 0 && !p.C) return bfail(MMM_EINVAL, "problem %d: C is null", i);
+        if (p.N > 0 && p.M > 0 && p.P > 0 && (!p.A || !p.B)) return bfail(MMM_EINVAL, "problem %d: A or B is null", i);
+        if (p.N > 0 && p.M > 0) iv.push_back({(uintptr_t)p.C, (uintptr_t)p.C + 8 * (size_t)(p.N * p.M), true, i});
+        if (p.N > 0 && p.P > 0) iv.push_back({(uintptr_t)p.A, (uintptr_t)p.A + 8 * (size_t)(p.N * p.P), false, i});
+        if (p.P > 0 && p.M > 0) iv.push_back({(uintptr_t)p.B, (uintptr_t)p.B + 8 * (size_t)(p.P * p.M), false, i});
+    }
+    std::sort(iv.begin(), iv.end(), [](const Interval& a, const Interval& b) { return a.lo < b.lo; });
+    // sweep: any output interval overlapping anything else is an alias
+    {
+        uintptr_t reach_any = 0, reach_out = 0;
+        for (size_t k = 0; k < iv.size(); ++k) {
+            const Interval& x = iv[k];
+            if (x.lo < reach_out || (x.out && x.lo < reach_any))
+                return bfail(MMM_EALIAS, "problem %d: an output overlaps another operand", x.idx);
+            reach_any = std::max(reach_any, x.hi);
+            if (x.out) reach_out = std::max(reach_out, x.hi);
+        }
+    }
+
+    // grouping
+    std::map<int, DGroup> dg;
+    std::map<std::tuple<int, int, bool>, SGroup> sg;
+    size_t split_ws = 0;
+    for (int i = 0; i < count; ++i) {
+        const mmm_problem& p = problems[i];
+        if (p.N == 0 || p.M == 0) continue;
+        if (p.method == MMM_DGEMM || p.P == 0) {
+            const int tile = pick_tile(p);
+            DGroup& g = dg[tile];
+            g.tile = tile;
+            g.probs.push_back(Gemm{p.A, p.P, p.B, p.M, p.C, p.M, p.N, p.P, p.M});
+        } else {
+            const int s = p.slices ? p.slices : c.split_slices;
+            SplitGroup grp;
+            i64 Np, Mp, Kp;
+            const size_t bytes = split_job_bytes(p.N, p.P, p.M, c.split_type, s, grp, Np, Mp, Kp);
+            if (bytes == (size_t)-1) return bfail(MMM_EUNSUPPORTED, "problem %d: split configuration", i);
+            SGroup& g = sg[std::make_tuple(grp.dt, grp.s, grp.flush)];
+            g.g = grp;
+            SplitJob j;
+            memset(&j, 0, sizeof(j));
+            j.A = p.A;
+            j.B = p.B;
+            j.C = p.C;
+            j.N = p.N;
+            j.P = p.P;
+            j.M = p.M;
+            g.jobs.push_back(j);
+            g.ws_off.push_back(split_ws);
+            split_ws = al256(split_ws + bytes);
+        }
+    }
+
+    // device memory layout: tables first, then the split workspaces
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = al256(off + bytes);
+        return at;
+    };
+    for (auto& kv : dg) {
+        DGroup& g = kv.second;
+        const int bm = dgemm_tile_bm(g.tile), bn = dgemm_tile_bn(g.tile);
+        g.prefix.assign(g.probs.size() + 1, 0);
+        for (size_t k = 0; k < g.probs.size(); ++k)
+            g.prefix[k + 1] = g.prefix[k] + cdiv(g.probs[k].N, bm) * cdiv(g.probs[k].M, bn);
+        g.off_probs = take(sizeof(Gemm) * g.probs.size());
+        g.off_prefix = take(sizeof(i64) * g.prefix.size());
+    }
+    for (auto& kv : sg) {
+        SGroup& g = kv.second;
+        g.prefix.assign(g.jobs.size() + 1, 0);
+        g.off_jobs = take(sizeof(SplitJob) * g.jobs.size());
+        g.off_prefix = take(sizeof(i64) * g.prefix.size());
+    }
+    const size_t off_ws = off;
+    const size_t total = off + split_ws + 256;
+
+    mmm_batch* plan = new mmm_batch();
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMalloc(&plan->dmem, total) != hipSuccess) {
+        delete plan;
+        (void)hipGetLastError();
+        return bfail(MMM_ENOMEM, "batch: cannot allocate %zu bytes", total);
+    }
+    char* base = (char*)plan->dmem;
+    for (auto& kv : sg) {
+        SGroup& g = kv.second;
+        for (size_t k = 0; k < g.jobs.size(); ++k) {
+            split_job_bind(g.jobs[k], base + off_ws + g.ws_off[k], g.g.dt, g.g.s);
+            g.prefix[k + 1] = g.prefix[k] + (g.jobs[k].Np / g.g.bm) * (g.jobs[k].Mp / g.g.bn);
+        }
+    }
+    // upload tables
+    std::vector<char> host(off_ws > 0 ? off_ws : 1, 0);
+    for (auto& kv : dg) {
+        memcpy(host.data() + kv.second.off_probs, kv.second.probs.data(), sizeof(Gemm) * kv.second.probs.size());
+        memcpy(host.data() + kv.second.off_prefix, kv.second.prefix.data(), sizeof(i64) * kv.second.prefix.size());
+    }
+    for (auto& kv : sg) {
+        memcpy(host.data() + kv.second.off_jobs, kv.second.jobs.data(), sizeof(SplitJob) * kv.second.jobs.size());
+        memcpy(host.data() + kv.second.off_prefix, kv.second.prefix.data(), sizeof(i64) * kv.second.prefix.size());
+    }
+    hipError_t e = hipSuccess;
+    if (off_ws > 0) e = hipMemcpyAsync(base, host.data(), off_ws, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+
+    // persistent grid: every CU, as many workgroups as fit
+    int dev = 0, cus = 256;
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    for (auto& kv : sg)
+        if (e == hipSuccess) e = split_grouped_prepare(kv.second.g);
+
+    // record the launch sequence: FP64 groups on the capture stream, split
+    // groups on a forked branch
+    hipStream_t cap = nullptr, side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = hipEventRecord(fork, cap);
+        if (le == hipSuccess) le = hipStreamWaitEvent(side, fork, 0);
+        for (auto& kv : dg) {
+            if (le != hipSuccess) break;
+            DGroup& g = kv.second;
+            const i64 tiles = g.prefix.back();
+            const int grid = (int)std::min<i64>(tiles, (i64)cus * 2);
+            le = launch_dgemm_grouped(g.tile, (const Gemm*)(base + g.off_probs), (const i64*)(base + g.off_prefix),
+                                      (int)g.probs.size(), tiles, grid, cap);
+        }
+        for (auto& kv : sg) {
+            if (le != hipSuccess) break;
+            SGroup& g = kv.second;
+            const i64 tiles = g.prefix.back();
+            const int grid = (int)std::min<i64>(tiles, (i64)cus);
+            le = launch_split_grouped(g.g, (const SplitJob*)(base + g.off_jobs), g.jobs.data(), (int)g.jobs.size(),
+                                      (const i64*)(base + g.off_prefix), tiles, c.split_scale_lambda != 0, grid, side);
+        }
+        if (le == hipSuccess) le = hipEventRecord(join, side);
+        if (le == hipSuccess) le = hipStreamWaitEvent(cap, join, 0);
+        e = hipStreamEndCapture(cap, &plan->graph);
+        if (le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    if (side) (void)hipStreamDestroy(side);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+        const mmm_status st = bfail(MMM_ELAUNCH, "batch create: %s", hipGetErrorString(e));
+        (void)hipGetLastError();
+        mmm_batch_destroy(plan);
+        return st;
+    }
+    *plan_out = plan;
+    return MMM_OK;
 }
-mmm_status mmm_batch_launch(mmm_batch*, void*) { return MMM_EUNSUPPORTED; }
-mmm_status mmm_batch_destroy(mmm_batch*) { return MMM_OK; }
+
+mmm_status mmm_batch_launch(mmm_batch* plan, void* stream)
+{
+    if (!plan || !plan->exec) return bfail(MMM_EINVAL, "plan is null");
+    const hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return bfail(MMM_ELAUNCH, "graph launch: %s", hipGetErrorString(e));
+    plan->last = (hipStream_t)stream;
+    return MMM_OK;
 }
+
+mmm_status mmm_batch_destroy(mmm_batch* plan)
+{
+    if (!plan) return MMM_OK;
+    if (plan->exec) (void)hipStreamSynchronize(plan->last);
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    if (plan->dmem) (void)hipFree(plan->dmem);
+    delete plan;
+    return MMM_OK;
+}
+
+}  // extern "C"

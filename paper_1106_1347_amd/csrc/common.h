@@ -139,4 +139,9 @@ __device__ inline void flat_tile(i64 tiles_m, i64 tiles_n, i64& prob, i64& tm, i
 
 inline i64 cdiv(i64 a, i64 b) { return (a + b - 1) / b; }
 
+// Record a message for mmm_last_error (thread local) and return `st`.
+mmm_status set_error(mmm_status st, const char* fmt, ...);
+// MMM_OK when every field of the config is valid (message set otherwise).
+mmm_status check_config(const mmm_config& c);
+
 }  // namespace mmm

@@ -24,7 +24,9 @@
 // tile sizes, so the GEMM's loads need no bounds checks.
 #include <string.h>
 
+#include "batch.h"
 #include "launch.h"
+#include "reduce.h"
 #include "split.h"
 
 namespace mmm {
@@ -140,16 +142,16 @@ __device__ inline void cut(const double* x, double sc, int e, int s, char* out, 
 
 // A: one thread per (row i < Np, 8-entry chunk of the padded K).
 template <int DT>
-__global__ __launch_bounds__(256) void split_a_kernel(const double* __restrict__ A, i64 N, i64 P, i64 Np, i64 Kp,
-                                                      const double* __restrict__ rmax, const int* lam, int s,
-                                                      char* __restrict__ SA, int* __restrict__ ea)
+__device__ __forceinline__ void split_a_body(const double* __restrict__ A, i64 N, i64 P, i64 Np, i64 Kp,
+                                             const double* __restrict__ rmax, const int* lam, int s,
+                                             char* __restrict__ SA, int* __restrict__ ea, i64 block, i64 nblocks)
 {
     constexpr int ES = Digit<DT>::esize;
     const i64 chunks = Kp / 8;
     const i64 total = Np * chunks;
     const double sc = lam ? ldexp(1.0, *lam) : 1.0;
     const i64 row_bytes = Kp * s * ES;
-    for (i64 c = (i64)blockIdx.x * 256 + threadIdx.x; c < total; c += (i64)gridDim.x * 256) {
+    for (i64 c = block * 256 + threadIdx.x; c < total; c += nblocks * 256) {
         const i64 i = c / chunks, k0 = (c - i * chunks) * 8;
         const int e = i < N ? vec_exponent(rmax[i]) : 0;
         double x[8];
@@ -162,19 +164,26 @@ __global__ __launch_bounds__(256) void split_a_kernel(const double* __restrict__
     }
 }
 
+template <int DT>
+__global__ __launch_bounds__(256) void split_a_kernel(const double* __restrict__ A, i64 N, i64 P, i64 Np, i64 Kp,
+                                                      const double* __restrict__ rmax, const int* lam, int s,
+                                                      char* __restrict__ SA, int* __restrict__ ea)
+{
+    split_a_body<DT>(A, N, P, Np, Kp, rmax, lam, s, SA, ea, blockIdx.x, gridDim.x);
+}
+
 // B (P x M, row-major) to SB[j][kt][u][kk]: a 64 (k) x 64 (j) tile goes
 // through LDS so both the loads (along j) and the stores (along k) are
 // contiguous.
 template <int DT>
-__global__ __launch_bounds__(256) void split_b_kernel(const double* __restrict__ B, i64 P, i64 M, i64 Mp, i64 Kp,
-                                                      const double* __restrict__ cmax, const int* lam, int s,
-                                                      char* __restrict__ SB, int* __restrict__ fb)
+__device__ __forceinline__ void split_b_body(const double* __restrict__ B, i64 P, i64 M, i64 Mp, i64 Kp,
+                                             const double* __restrict__ cmax, const int* lam, int s,
+                                             char* __restrict__ SB, int* __restrict__ fb, i64 block, double (*T)[65])
 {
     constexpr int ES = Digit<DT>::esize;
-    __shared__ double T[64][65];
     const i64 tiles_j = Mp / 64;
-    const i64 kt = blockIdx.x / tiles_j;
-    const i64 j0 = (blockIdx.x - kt * tiles_j) * 64, k0 = kt * 64;
+    const i64 kt = block / tiles_j;
+    const i64 j0 = (block - kt * tiles_j) * 64, k0 = kt * 64;
     const int tid = threadIdx.x;
     const double sc = lam ? ldexp(1.0, -*lam) : 1.0;
 #pragma unroll
@@ -198,6 +207,15 @@ __global__ __launch_bounds__(256) void split_b_kernel(const double* __restrict__
         cut<DT>(x, sc, e, s, out, (i64)KT * ES);
         if (kt == 0 && ch == 0) fb[j] = e;
     }
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void split_b_kernel(const double* __restrict__ B, i64 P, i64 M, i64 Mp, i64 Kp,
+                                                      const double* __restrict__ cmax, const int* lam, int s,
+                                                      char* __restrict__ SB, int* __restrict__ fb)
+{
+    __shared__ double T[64][65];
+    split_b_body<DT>(B, P, M, Mp, Kp, cmax, lam, s, SB, fb, blockIdx.x, T);
 }
 
 // ---- the digit-product GEMM -------------------------------------------------
@@ -247,10 +265,10 @@ struct Mfma<DT_INT8> {
 // l % 16 and the 16 bytes of K starting at 16 (l / 16) bytes; result
 // element r of lane l is D[4 (l / 16) + r][l % 16].
 template <int DT, int S, bool FLUSH>
-__global__ __launch_bounds__(256) void split_gemm_kernel(const char* __restrict__ SA, const char* __restrict__ SB,
-                                                         const int* __restrict__ ea, const int* __restrict__ fb,
-                                                         double* __restrict__ C, i64 N, i64 M, i64 Kp,
-                                                         i64 tiles_m, i64 tiles_n, int flush_steps)
+__device__ __forceinline__ void split_tile(const char* __restrict__ SA, const char* __restrict__ SB,
+                                           const int* __restrict__ ea, const int* __restrict__ fb,
+                                           double* __restrict__ C, i64 N, i64 M, i64 Kp, i64 tm, i64 tn,
+                                           int flush_steps, char* lds)
 {
     typedef Digit<DT> D;
     typedef typename Mfma<DT>::acc_t acc_t;
@@ -263,18 +281,8 @@ __global__ __launch_bounds__(256) void split_gemm_kernel(const char* __restrict_
     constexpr int CH_A = BM * S * ROWB / 16, CH_B = BN * S * ROWB / 16;  // 16-byte chunks per tile
     constexpr int LA = CH_A / 256, LB = CH_B / 256;
     static_assert(CH_A % 256 == 0 && CH_B % 256 == 0, "chunks");
-    extern __shared__ __align__(16) char lds[];
     char* la = lds;                       // [S][BM][PITCH]
     char* lb = lds + S * BM * PITCH;      // [S][BN][PITCH]
-
-    // tile order: XCD-contiguous ranges, 8 tile-rows per group
-    const i64 total = tiles_m * tiles_n;
-    i64 b = blockIdx.x;
-    if (total % 8 == 0) b = (b % 8) * (total / 8) + b / 8;
-    const i64 grp = b / (8 * tiles_n), first = grp * 8;
-    const i64 gs = (tiles_m - first) < 8 ? (tiles_m - first) : 8;
-    const i64 w = b - grp * 8 * tiles_n;
-    const i64 tm = first + w % gs, tn = w / gs;
     const i64 m0 = tm * BM, n0 = tn * BN;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -396,6 +404,127 @@ __global__ __launch_bounds__(256) void split_gemm_kernel(const char* __restrict_
                 if (gm < N && gn < M) C[gm * M + gn] = ldexp(c, ea[gm] + fb[gn]);
             }
         }
+}
+
+template <int DT, int S, bool FLUSH>
+__global__ __launch_bounds__(256) void split_gemm_kernel(const char* __restrict__ SA, const char* __restrict__ SB,
+                                                         const int* __restrict__ ea, const int* __restrict__ fb,
+                                                         double* __restrict__ C, i64 N, i64 M, i64 Kp,
+                                                         i64 tiles_m, i64 tiles_n, int flush_steps)
+{
+    extern __shared__ __align__(16) char lds[];
+    // tile order: XCD-contiguous ranges, 8 tile-rows per group
+    const i64 total = tiles_m * tiles_n;
+    i64 b = blockIdx.x;
+    if (total % 8 == 0) b = (b % 8) * (total / 8) + b / 8;
+    const i64 grp = b / (8 * tiles_n), first = grp * 8;
+    const i64 gs = (tiles_m - first) < 8 ? (tiles_m - first) : 8;
+    const i64 w = b - grp * 8 * tiles_n;
+    split_tile<DT, S, FLUSH>(SA, SB, ea, fb, C, N, M, Kp, first + w % gs, w / gs, flush_steps, lds);
+}
+
+// Persistent grid over the tiles of a group of split jobs (same digit type
+// and count): tile t is job p's (t - prefix[p])-th tile, row-major.
+template <int DT, int S, bool FLUSH>
+__global__ __launch_bounds__(256) void split_gemm_grouped_kernel(const SplitJob* __restrict__ jobs,
+                                                                 const i64* __restrict__ prefix, int njobs, i64 total,
+                                                                 int flush_steps)
+{
+    extern __shared__ __align__(16) char lds[];
+    constexpr TileCfg TC = tile_cfg(DT, S, FLUSH);
+    for (i64 t = blockIdx.x; t < total; t += gridDim.x) {
+        int lo = 0, hi = njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (prefix[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const SplitJob& j = jobs[lo];
+        const i64 local = t - prefix[lo];
+        const i64 tiles_n = j.Mp / TC.bn();
+        split_tile<DT, S, FLUSH>(j.SA, j.SB, j.ea, j.fb, j.C, j.N, j.M, j.Kp, local / tiles_n, local % tiles_n,
+                                 flush_steps, lds);
+        __syncthreads();
+    }
+}
+
+// ---- batched preprocessing: blockIdx.y selects the job -----------------------
+
+__global__ void jobs_zero_norms_kernel(const SplitJob* jobs, int n)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) {
+        *jobs[i].nA = 0.0;
+        *jobs[i].nB = 0.0;
+    }
+}
+
+// which = 0: NormInf of A; 1: NormInf of B (row sums folded by atomic max)
+__global__ __launch_bounds__(256) void jobs_norm_kernel(const SplitJob* __restrict__ jobs, int which)
+{
+    __shared__ double T[2][RV][RL + 1];
+    const SplitJob& j = jobs[blockIdx.y];
+    const double* X = which ? j.B : j.A;
+    const i64 rows = which ? j.P : j.N, cols = which ? j.M : j.P;
+    const i64 blocks = (rows + RV - 1) / RV;
+    for (i64 b = blockIdx.x; b < blocks; b += gridDim.x) {
+        vecred_body<RED_ABS_SUM, false, false, true>(X, cols, rows, cols, which ? j.nB : j.nA, nullptr, 0, b, T);
+        __syncthreads();
+    }
+}
+
+__global__ void jobs_lambda_kernel(const SplitJob* jobs, int n)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) {
+        const double a = *jobs[i].nA, b = *jobs[i].nB;
+        int res = 0;
+        if (a > 0.0 && b > 0.0 && !isinf(a) && !isinf(b)) {
+            int eA, eB;
+            const double fa = frexp(a, &eA);
+            const double fb = frexp(b, &eB);
+            const long long d = (long long)eB - (long long)eA;
+            const long long x = fb >= fa ? d + 1 : d;
+            res = (int)(x >= 0 ? x / 2 : -((-x + 1) / 2));
+        }
+        *jobs[i].lam = res;
+    }
+}
+
+// which = 0: max |2^l A_ik| over each row of A; 1: max |2^-l B_kj| over each column of B
+template <bool SCALED>
+__global__ __launch_bounds__(256) void jobs_absmax_kernel(const SplitJob* __restrict__ jobs, int which)
+{
+    __shared__ double T[2][RV][RL + 1];
+    const SplitJob& j = jobs[blockIdx.y];
+    const i64 nvec = which ? j.M : j.N;
+    const i64 blocks = (nvec + RV - 1) / RV;
+    for (i64 b = blockIdx.x; b < blocks; b += gridDim.x) {
+        if (which)
+            vecred_body<RED_ABS_MAX, true, SCALED, false>(j.B, j.M, j.M, j.P, j.cmax, SCALED ? j.lam : nullptr, -1, b, T);
+        else
+            vecred_body<RED_ABS_MAX, false, SCALED, false>(j.A, j.P, j.N, j.P, j.rmax, SCALED ? j.lam : nullptr, +1, b, T);
+        __syncthreads();
+    }
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void jobs_split_a_kernel(const SplitJob* __restrict__ jobs, int s, bool scaled)
+{
+    const SplitJob& j = jobs[blockIdx.y];
+    split_a_body<DT>(j.A, j.N, j.P, j.Np, j.Kp, j.rmax, scaled ? j.lam : nullptr, s, j.SA, j.ea, blockIdx.x, gridDim.x);
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void jobs_split_b_kernel(const SplitJob* __restrict__ jobs, int s, bool scaled)
+{
+    __shared__ double T[64][65];
+    const SplitJob& j = jobs[blockIdx.y];
+    const i64 blocks = (j.Kp / 64) * (j.Mp / 64);
+    for (i64 b = blockIdx.x; b < blocks; b += gridDim.x) {
+        split_b_body<DT>(j.B, j.P, j.M, j.Mp, j.Kp, j.cmax, scaled ? j.lam : nullptr, s, j.SB, j.fb, b, T);
+        __syncthreads();
+    }
 }
 
 struct SplitLayout {
@@ -530,6 +659,80 @@ hipError_t run_split_dt(const double* A, const double* B, double* C, i64 N, i64 
     return dispatch_s<DT>(L, ws, C, N, M, st);
 }
 
+template <int DT, int S, bool FLUSH>
+hipError_t launch_grouped_gemm(const SplitJob* jobs, const i64* prefix, int n, i64 total, int flush_steps, int grid,
+                               hipStream_t st)
+{
+    typedef Digit<DT> D;
+    constexpr TileCfg TC = tile_cfg(DT, S, FLUSH);
+    const size_t lds = (size_t)S * (TC.bm() + TC.bn()) * (KT * D::esize + 16);
+    auto kern = split_gemm_grouped_kernel<DT, S, FLUSH>;
+    if (!jobs) return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, st, jobs, prefix, n, total, flush_steps);
+    return hipGetLastError();
+}
+
+template <int DT, int S>
+hipError_t grouped_flush(const SplitGroup& g, const SplitJob* jobs, const i64* prefix, int n, i64 total, int grid,
+                         hipStream_t st)
+{
+    if (g.flush) return launch_grouped_gemm<DT, S, true>(jobs, prefix, n, total, g.flush_steps, grid, st);
+    return launch_grouped_gemm<DT, S, false>(jobs, prefix, n, total, g.flush_steps, grid, st);
+}
+
+template <int DT>
+hipError_t grouped_s(const SplitGroup& g, const SplitJob* jobs, const i64* prefix, int n, i64 total, int grid,
+                     hipStream_t st)
+{
+    switch (g.s) {
+    case 1: return grouped_flush<DT, 1>(g, jobs, prefix, n, total, grid, st);
+    case 2: return grouped_flush<DT, 2>(g, jobs, prefix, n, total, grid, st);
+    case 3: return grouped_flush<DT, 3>(g, jobs, prefix, n, total, grid, st);
+    case 4: return grouped_flush<DT, 4>(g, jobs, prefix, n, total, grid, st);
+    case 5: return grouped_flush<DT, 5>(g, jobs, prefix, n, total, grid, st);
+    case 6: return grouped_flush<DT, 6>(g, jobs, prefix, n, total, grid, st);
+    case 7: return grouped_flush<DT, 7>(g, jobs, prefix, n, total, grid, st);
+    case 8: return grouped_flush<DT, 8>(g, jobs, prefix, n, total, grid, st);
+    default: return hipErrorNotSupported;
+    }
+}
+
+template <int DT>
+hipError_t launch_split_grouped_dt(const SplitGroup& g, const SplitJob* jobs, const SplitJob* hjobs, int n,
+                                   const i64* prefix, i64 total, bool scale, int grid, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipError_t e;
+    i64 max_rows_a = 0, max_rows_b = 0, max_cols_b = 0, max_a = 0, max_b = 0;
+    for (int i = 0; i < n; ++i) {
+        const SplitJob& j = hjobs[i];
+        max_rows_a = j.N > max_rows_a ? j.N : max_rows_a;
+        max_rows_b = j.P > max_rows_b ? j.P : max_rows_b;
+        max_cols_b = j.M > max_cols_b ? j.M : max_cols_b;
+        const i64 ba = cdiv(j.Np * (j.Kp / 8), 256), bb = (j.Kp / 64) * (j.Mp / 64);
+        max_a = ba > max_a ? ba : max_a;
+        max_b = bb > max_b ? bb : max_b;
+    }
+    auto cap = [](i64 x) { return (unsigned)(x < 1 ? 1 : (x > 64 ? 64 : x)); };
+    const dim3 blk(256);
+    if (scale) {
+        hipLaunchKernelGGL(jobs_zero_norms_kernel, dim3((unsigned)cdiv(n, 256)), blk, 0, st, jobs, n);
+        hipLaunchKernelGGL(jobs_norm_kernel, dim3(cap(cdiv(max_rows_a, RV)), n), blk, 0, st, jobs, 0);
+        hipLaunchKernelGGL(jobs_norm_kernel, dim3(cap(cdiv(max_rows_b, RV)), n), blk, 0, st, jobs, 1);
+        hipLaunchKernelGGL(jobs_lambda_kernel, dim3((unsigned)cdiv(n, 256)), blk, 0, st, jobs, n);
+        hipLaunchKernelGGL(jobs_absmax_kernel<true>, dim3(cap(cdiv(max_rows_a, RV)), n), blk, 0, st, jobs, 0);
+        hipLaunchKernelGGL(jobs_absmax_kernel<true>, dim3(cap(cdiv(max_cols_b, RV)), n), blk, 0, st, jobs, 1);
+    } else {
+        hipLaunchKernelGGL(jobs_absmax_kernel<false>, dim3(cap(cdiv(max_rows_a, RV)), n), blk, 0, st, jobs, 0);
+        hipLaunchKernelGGL(jobs_absmax_kernel<false>, dim3(cap(cdiv(max_cols_b, RV)), n), blk, 0, st, jobs, 1);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(jobs_split_a_kernel<DT>, dim3(cap(max_a), n), blk, 0, st, jobs, g.s, scale);
+    hipLaunchKernelGGL(jobs_split_b_kernel<DT>, dim3(cap(max_b), n), blk, 0, st, jobs, g.s, scale);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return grouped_s<DT>(g, jobs, prefix, n, total, grid, st);
+}
+
 }  // namespace
 
 size_t split_workspace_bytes(i64 N, i64 P, i64 M, const mmm_config& c)
@@ -550,6 +753,75 @@ hipError_t run_split(const double* A, const double* B, double* C, i64 N, i64 P, 
     case DT_BF16: return run_split_dt<DT_BF16>(A, B, C, N, P, M, L, scale, ws, s);
     case DT_FP16: return run_split_dt<DT_FP16>(A, B, C, N, P, M, L, scale, ws, s);
     case DT_INT8: return run_split_dt<DT_INT8>(A, B, C, N, P, M, L, scale, ws, s);
+    default: return hipErrorNotSupported;
+    }
+}
+
+}  // namespace mmm
+
+namespace mmm {
+
+size_t split_job_bytes(i64 N, i64 P, i64 M, int dt, int s, SplitGroup& grp, i64& Np, i64& Mp, i64& Kp)
+{
+    mmm_config c = mmm_config_default();
+    c.split_type = dt;
+    c.split_slices = s;
+    SplitLayout L;
+    if (!split_layout(N, P, M, c, L)) return (size_t)-1;
+    const int fs = flush_steps_for(dt, s);
+    if (fs < 1) return (size_t)-1;
+    const TileCfg tc = tile_cfg(dt, s, L.flush);
+    grp.dt = dt;
+    grp.s = s;
+    grp.flush = L.flush;
+    grp.flush_steps = fs;
+    grp.bm = tc.bm();
+    grp.bn = tc.bn();
+    Np = L.Np;
+    Mp = L.Mp;
+    Kp = L.Kp;
+    return L.bytes;
+}
+
+void split_job_bind(SplitJob& j, char* base, int dt, int s)
+{
+    mmm_config c = mmm_config_default();
+    c.split_type = dt;
+    c.split_slices = s;
+    SplitLayout L;
+    split_layout(j.N, j.P, j.M, c, L);
+    j.Np = L.Np;
+    j.Mp = L.Mp;
+    j.Kp = L.Kp;
+    j.nA = (double*)(base + L.nA);
+    j.nB = (double*)(base + L.nB);
+    j.lam = (int*)(base + L.lam);
+    j.rmax = (double*)(base + L.rmax);
+    j.cmax = (double*)(base + L.cmax);
+    j.ea = (int*)(base + L.ea);
+    j.fb = (int*)(base + L.fb);
+    j.SA = base + L.SA;
+    j.SB = base + L.SB;
+}
+
+hipError_t split_grouped_prepare(const SplitGroup& g)
+{
+    // a null job table only sets the kernel's dynamic LDS limit
+    switch (g.dt) {
+    case DT_BF16: return grouped_s<DT_BF16>(g, nullptr, nullptr, 0, 0, 0, nullptr);
+    case DT_FP16: return grouped_s<DT_FP16>(g, nullptr, nullptr, 0, 0, 0, nullptr);
+    case DT_INT8: return grouped_s<DT_INT8>(g, nullptr, nullptr, 0, 0, 0, nullptr);
+    default: return hipErrorNotSupported;
+    }
+}
+
+hipError_t launch_split_grouped(const SplitGroup& grp, const SplitJob* jobs, const SplitJob* hjobs, int n,
+                                const i64* prefix, i64 total_tiles, bool scale_lambda, int grid, hipStream_t s)
+{
+    switch (grp.dt) {
+    case DT_BF16: return launch_split_grouped_dt<DT_BF16>(grp, jobs, hjobs, n, prefix, total_tiles, scale_lambda, grid, s);
+    case DT_FP16: return launch_split_grouped_dt<DT_FP16>(grp, jobs, hjobs, n, prefix, total_tiles, scale_lambda, grid, s);
+    case DT_INT8: return launch_split_grouped_dt<DT_INT8>(grp, jobs, hjobs, n, prefix, total_tiles, scale_lambda, grid, s);
     default: return hipErrorNotSupported;
     }
 }

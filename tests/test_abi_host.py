@@ -91,3 +91,30 @@ def test_argument_errors_before_any_launch(lib):
     assert lib._lib.mmm_norm_inf(8, 2, 2, None, None) == 1
     assert lib._lib.mmm_winograd_lambda(None, 8, 8, None) == 1
     assert lib._lib.mmm_status_string(2) == b"output overlaps an input"
+
+
+def test_batch_validation_before_any_allocation(lib):
+    P = lib._CProblem
+    f = lib._lib.mmm_batch_create
+    c = lib._lib.mmm_config_default()
+    h = ctypes.c_void_p()
+    r = ctypes.byref
+
+    def arr(*ps):
+        a = (P * len(ps))()
+        for i, p in enumerate(ps):
+            a[i] = p
+        return a
+
+    ok = P(A=0x10000, B=0x20000, C=0x30000, N=4, P=4, M=4, method=6)
+    assert f(arr(ok), 0, r(c), None, r(h)) == 1            # count 0
+    assert f(arr(P(A=8, B=8, C=8, N=-1, P=1, M=1, method=6)), 1, r(c), None, r(h)) == 1
+    assert f(arr(P(A=8, B=8, C=8, N=1, P=1, M=1, method=2)), 1, r(c), None, r(h)) == 1  # not dgemm/split
+    assert f(arr(P(A=8, B=8, C=8, N=1, P=1, M=1, method=6, tile=9)), 1, r(c), None, r(h)) == 1
+    # C of one problem overlapping A of another
+    bad = P(A=0x40000, B=0x50000, C=0x10008, N=2, P=2, M=2, method=6)
+    assert f(arr(ok, bad), 2, r(c), None, r(h)) == 2
+    # two outputs overlapping
+    bad2 = P(A=0x40000, B=0x50000, C=0x30010, N=2, P=2, M=2, method=7)
+    assert f(arr(ok, bad2), 2, r(c), None, r(h)) == 2
+    assert h.value is None

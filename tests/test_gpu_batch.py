@@ -1,0 +1,103 @@
+"""Batches: one HIP graph over many uneven products, FP64 and split mixed.
+
+Every batched product must equal the single mmm_multiply result with the
+same method and config bit for bit (the tile arithmetic does not depend on
+the tile shape or on the workgroup that runs it), on every replay of the
+graph, with unrelated eager work between replays.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mmm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1106_1347_amd as m
+
+    return m
+
+
+def make_problems(shapes, seed, methods, slices, tiles):
+    out = []
+    for g, (N, P, M) in enumerate(shapes):
+        A = torch.from_numpy(synth.uniform((N, P), seed + 2 * g)).cuda()
+        B = torch.from_numpy(synth.uniform((P, M), seed + 2 * g + 1)).cuda()
+        C = torch.full((N, M), float("nan"), dtype=torch.float64, device="cuda")
+        out.append((A, B, C, methods[g % len(methods)], slices[g % len(slices)], tiles[g % len(tiles)]))
+    return out
+
+
+def single(mmm, A, B, method, s, cfg):
+    c = mmm.Config(**{**cfg.__dict__, "split_slices": s or cfg.split_slices})
+    return mmm.multiply(A, B, method, c)
+
+
+@pytest.mark.parametrize("typ,slices", [("int8", [0, 4, 7]), ("bf16", [0, 3, 6]), ("fp16", [6])])
+def test_batch_equals_single_calls_and_replays(mmm, typ, slices):
+    cfg = mmm.Config(split_type=typ, split_slices=7 if typ == "int8" else 6)
+    shapes = synth.batch_shapes(48, 7, 1, 200) + [(16, 0, 9), (0, 5, 5), (300, 257, 3)]
+    probs = make_problems(shapes, 100, ["dgemm", "split"], slices, ["auto", "128x128", "64x64", "128x64"])
+    want = [single(mmm, A, B, m, s, cfg).cpu() for (A, B, C, m, s, t) in probs]
+    plan = mmm.Batch(probs, cfg)
+    for rep in range(3):
+        for p in probs:
+            p[2].fill_(float("nan"))
+        plan.launch()
+        # unrelated eager work between replays
+        X = torch.rand(300, 300, dtype=torch.float64, device="cuda")
+        mmm.multiply(X, X, "winograd")
+        torch.cuda.synchronize()
+        for k, (p, w) in enumerate(zip(probs, want)):
+            got = p[2].cpu()
+            assert got.shape == w.shape
+            assert np.array_equal(got.numpy().view(np.int64), w.numpy().view(np.int64)), (rep, k, shapes[k], p[3])
+    plan.close()
+
+
+def test_batch_full_workload(mmm, orc):
+    """2048 problems, N, P, M uniform on 16..512, even index FP64 DGEMM, odd
+    index split (bf16, 6 digits): one graph launch; sampled results checked
+    against single calls bitwise and against the oracle."""
+    shapes = synth.batch_shapes(2048, synth.seed_a(3), 16, 512)
+    rng = np.random.default_rng(1)
+    probs = []
+    for g, (N, P, M) in enumerate(shapes):
+        A = torch.rand(N, P, dtype=torch.float64, device="cuda") * 2 - 1
+        B = torch.rand(P, M, dtype=torch.float64, device="cuda") * 2 - 1
+        C = torch.empty(N, M, dtype=torch.float64, device="cuda")
+        probs.append((A, B, C, "dgemm" if g % 2 == 0 else "split"))
+    cfg = mmm.Config()
+    plan = mmm.Batch(probs, cfg)
+    plan.launch()
+    torch.cuda.synchronize()
+    sample = sorted(set(rng.integers(0, 2048, 40).tolist()) | {0, 1, 2046, 2047})
+    for g in sample:
+        A, B, C, m = probs[g]
+        w = mmm.multiply(A, B, m, cfg)
+        assert torch.equal(C.view(torch.int64), w.view(torch.int64)), g
+    for g in sample[:6]:
+        A, B, C, m = probs[g]
+        An, Bn = A.cpu().numpy(), B.cpu().numpy()
+        if m == "dgemm":
+            e = orc.rel_err_inf(C.cpu().numpy(), orc.naive(An, Bn), orc.norm_inf(An), orc.norm_inf(Bn))
+            assert e <= 1e-13
+        else:
+            assert np.array_equal(C.cpu().numpy().view(np.int64), orc.split_model(An, Bn, 6, 8).view(np.int64))
+    plan.close()
+
+
+def test_autotuner_picks_and_persists(mmm, tmp_path):
+    from paper_1106_1347_amd.tune import TileTuner
+
+    t = TileTuner(path=str(tmp_path / "tiles.json"))
+    shapes = [(64, 64, 64)] * 8 + [(512, 300, 512)] * 4
+    table = t.tune(shapes, reps=3)
+    assert len(table) == 2 and all(v in ("128x128", "64x64", "128x64") for v in table.values())
+    t2 = TileTuner(path=str(tmp_path / "tiles.json"))
+    assert t2.tile_for(64, 64, 64) == table[t.key((6, 6))]

@@ -1,0 +1,60 @@
+"""Serving loop on the GPU: continuous admission under a tight HBM budget,
+each result bitwise equal to the same request served alone."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def serve():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1106_1347_amd.serve as s
+
+    return s
+
+
+def make_requests(n, seed):
+    reqs = []
+    for r in synth.serving_requests(n, seed, rate_per_s=1000.0, lo=32, hi=1536):
+        N, P, M = r["shape"]
+        g = torch.Generator(device="cuda").manual_seed(seed * 1000 + r["id"])
+        A = torch.rand((N, P), generator=g, dtype=torch.float64, device="cuda") * 2 - 1
+        B = torch.rand((P, M), generator=g, dtype=torch.float64, device="cuda") * 2 - 1
+        reqs.append((A, B, r["tol"]))
+    torch.cuda.synchronize()
+    return reqs
+
+
+def test_alone_equals_mix(serve, orc):
+    reqs = make_requests(40, 5)
+    # big enough for the split path too
+    g = torch.Generator(device="cuda").manual_seed(9)
+    A = torch.rand((1100, 1030), generator=g, dtype=torch.float64, device="cuda")
+    B = torch.rand((1030, 1050), generator=g, dtype=torch.float64, device="cuda")
+    reqs += [(A, B, 1e-13), (A, B, 1e-10)]
+    torch.cuda.synchronize()
+    alone = []
+    srv = serve.Server(budget_bytes=8 << 30, streams=1)
+    for (A, B, tol) in reqs:
+        alone.append(srv.submit(A, B, tol).result(timeout=60).cpu())
+    srv.close()
+    foot = max(8 * (A.shape[0] * A.shape[1] + B.numel() + A.shape[0] * B.shape[1]) for (A, B, _) in reqs)
+    srv = serve.Server(budget_bytes=3 * foot + (256 << 20), streams=4)
+    futs = [srv.submit(A, B, tol) for (A, B, tol) in reqs]
+    mix = [f.result(timeout=120).cpu() for f in futs]
+    st = srv.stats()
+    srv.close()
+    assert st["requests"] == len(reqs)
+    assert st["peak_budget_used"] <= 3 * foot + (256 << 20)
+    for k, (a, m) in enumerate(zip(alone, mix)):
+        assert torch.equal(a.view(torch.int64), m.view(torch.int64)), k
+    # accuracy against the oracle for two of them, at their tolerance
+    for k in (0, len(reqs) - 2, len(reqs) - 1):
+        An, Bn = reqs[k][0].cpu().numpy(), reqs[k][1].cpu().numpy()
+        e = orc.rel_err_inf(mix[k].numpy(), orc.naive(An, Bn), orc.norm_inf(An), orc.norm_inf(Bn))
+        assert e <= reqs[k][2], (k, e)
