@@ -61,6 +61,31 @@ PRECISION = [
 ]
 
 
+# HBM bytes per launch of a kernel, from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by
+# what the counters read for a plain 512 MiB device copy (FETCH x 2.0, WRITE x 1.0); valid only while the
+# kernel's source is the one measured (sha256 below), otherwise reported as null.
+COUNTED_TRAFFIC = {
+    "kahan": {"bytes": 2.8376e9, "file": "paper_1106_1347_amd/csrc/valu_gemm.hip",
+              "sha256": "2a2ae41d76d6fcdfed7603dd5657b402c609fb2bdd2daec896a2cf6af9f157d7"},
+    "dgemm": {"bytes": 1.7468e9, "file": "paper_1106_1347_amd/csrc/dgemm.hip",
+              "sha256": "a44783d487894e8e06732f018482b3556d1f8717705ad0a94c292c3628775a26"},
+}
+
+
+def counted_traffic(name):
+    import hashlib
+
+    rec = COUNTED_TRAFFIC.get(name)
+    if not rec:
+        return None
+    try:
+        with open(os.path.join(ROOT, rec["file"]), "rb") as f:
+            ok = hashlib.sha256(f.read()).hexdigest() == rec["sha256"]
+    except OSError:
+        return None
+    return rec["bytes"] if ok else None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,13 +97,19 @@ def parse():
     ap.add_argument("--no-precision", action="store_true", help="skip the 8192^3 split-vs-DGEMM comparison")
     ap.add_argument("--precision-reps", type=int, default=5)
     ap.add_argument("--precision-only", action="store_true", help="run only the 8192^3 comparison (profiling)")
+    ap.add_argument("--no-aux", action="store_true", help="skip the auxiliary-kernel bandwidth section")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 2048-problem batch section")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
+    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (the products of the workload "
+        print("bench.py runs on one GPU only: there is no multi-GPU path (the products of the workload "
               "are independent per GPU; see the design notes on sharding). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import torch
@@ -129,6 +160,12 @@ def main():
     for _ in range(args.warmup):
         one_step(None)
     torch.cuda.synchronize()
+    if args.copy_mib:
+        src = torch.ones(args.copy_mib * (1 << 20) // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     timings = []
     step_events = []
@@ -191,6 +228,9 @@ def main():
     precision = None
     if not args.no_precision:
         precision = precision_section(args, mmm, torch, synth, dev, stream, errors_needed=not args.no_cpu_baseline)
+    aux = None if args.no_aux else aux_section(mmm, torch, dev, stream)
+    batch = None if args.no_batch else batch_section(mmm, torch, synth, dev, stream)
+    serving = None if args.no_serve else serve_section(args, mmm, torch, synth, dev)
 
     results = {}
     for name, method, kw, cost, bound in methods:
@@ -217,7 +257,7 @@ def main():
         achieved = dcost * macs / (dms / 1e3) / 1e12
         peak = PEAK_FP64_VALU_OPS_T
     roofline = {"bound": dbound, "kernel": dname, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None,
+                "frac": achieved / peak, "traffic": counted_traffic(dname),
                 "note": "achieved = %g algorithmic FP64 ops per multiply-add x N*P*M / mean launch time; "
                         "alu peak = 256 CU x 4 SIMD x 16 lanes x 2.4 GHz non-fused FP64 ops" % dcost}
 
@@ -247,6 +287,9 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "precision_8192": precision,
+        "aux_8192": aux,
+        "batch_2048": batch,
+        "serving": serving,
         "device": torch.cuda.get_device_name(0),
     }
     print(json.dumps(out), flush=True)
@@ -303,6 +346,121 @@ def precision_section(args, mmm, torch, synth, dev, stream, errors_needed):
             ent["rel_err_inf_sampled"] = oracle.norm_inf(oracle.minus(got, ref)) / nrm
         out[name] = ent
         del ws
+    return out
+
+
+def _time(torch, stream, fn, reps):
+    ms = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    return float(np.median(ms))
+
+
+def aux_section(mmm, torch, dev, stream):
+    """Plus, Minus, MultiplyWithScalar and NormInf on 8192 x 8192 operands
+    (512 MiB each, above the 256 MB Infinity Cache): algorithmic bytes per
+    entry 24, 24, 16 and 8; GB/s against the 8 TB/s HBM peak."""
+    n = 8192
+    X = torch.rand(n, n, dtype=torch.float64, device=dev)
+    Y = torch.rand(n, n, dtype=torch.float64, device=dev)
+    Z = torch.empty_like(X)
+    out = torch.empty((), dtype=torch.float64, device=dev)
+    res = {}
+    for name, fn, bpe in (("plus", lambda: mmm.plus(X, Y, out=Z, stream=stream), 24),
+                          ("minus", lambda: mmm.minus(X, Y, out=Z, stream=stream), 24),
+                          ("multiply_with_scalar", lambda: mmm.multiply_with_scalar(0.5, X, out=Z, stream=stream), 16),
+                          ("norm_inf", lambda: mmm.norm_inf(X, out=out, stream=stream), 8)):
+        fn()
+        ms = _time(torch, stream, fn, 10)
+        gbs = bpe * n * n / (ms / 1e3) / 1e9
+        res[name] = {"ms_p50": ms, "GB_s": gbs, "frac_hbm_peak": gbs / PEAK_HBM_GBS}
+    return res
+
+
+def batch_section(mmm, torch, synth, dev, stream):
+    """2048 independent products, N, P, M uniform on 16..512, entries
+    U[-1,1]; even index FP64 DGEMM, odd index split (int8 digits, 7): one
+    graph launch against 2048 separate calls."""
+    shapes = synth.batch_shapes(2048, synth.seed_a(3), 16, 512)
+    probs = []
+    for g, (N, P, M) in enumerate(shapes):
+        gen = torch.Generator(device=dev).manual_seed(3010 + g)
+        A = torch.rand((N, P), generator=gen, dtype=torch.float64, device=dev) * 2 - 1
+        B = torch.rand((P, M), generator=gen, dtype=torch.float64, device=dev) * 2 - 1
+        probs.append((A, B, torch.empty((N, M), dtype=torch.float64, device=dev), "dgemm" if g % 2 == 0 else "split"))
+    cfg = mmm.Config(split_type="int8", split_slices=7)
+    t0 = time.perf_counter()
+    plan = mmm.Batch(probs, cfg, stream=stream)
+    create_s = time.perf_counter() - t0
+    plan.launch(stream)
+    torch.cuda.synchronize()
+    ms_graph = _time(torch, stream, lambda: plan.launch(stream), 5)
+    def separate():
+        for (A, B, C, m) in probs:
+            mmm.multiply(A, B, m, cfg, out=C, stream=stream)
+
+    separate()
+    ms_sep = _time(torch, stream, separate, 3)
+    plan.close()
+    flop = sum(2.0 * N * P * M for (N, P, M) in shapes)
+    return {"workload": "2048 products, N,P,M ~ U{16..512}, half DGEMM, half split int8 x7, one HIP graph",
+            "plan_create_s": create_s, "ms_graph_p50": ms_graph, "ms_separate_calls_p50": ms_sep,
+            "tflops_fp64_grade_graph": flop / (ms_graph / 1e3) / 1e12, "speedup_vs_separate": ms_sep / ms_graph,
+            "flop": flop}
+
+
+def serve_section(args, mmm, torch, synth, dev):
+    """Poisson request stream, dims log-uniform on 32..4096 (half square),
+    tolerance 1e-13 or 1e-10: capacity measured closed-loop, then p50/p99
+    latency (arrival to completion event) at 50% and 80% of it."""
+    from paper_1106_1347_amd.serve import Server
+
+    n = args.serve_requests
+    reqs = synth.serving_requests(n, synth.seed_a(4), rate_per_s=1.0)
+    data = []
+    for r in reqs:
+        N, P, M = r["shape"]
+        gen = torch.Generator(device=dev).manual_seed(4010 + r["id"])
+        A = torch.rand((N, P), generator=gen, dtype=torch.float64, device=dev) * 2 - 1
+        B = torch.rand((P, M), generator=gen, dtype=torch.float64, device=dev) * 2 - 1
+        data.append((A, B, r["tol"]))
+    torch.cuda.synchronize()
+    budget = 64 << 30
+    # warm-up and closed-loop capacity
+    srv = Server(budget, streams=4)
+    for f in [srv.submit(A, B, tol) for (A, B, tol) in data[: min(40, n)]]:
+        f.result()
+    srv.close()
+    srv = Server(budget, streams=4)
+    for f in [srv.submit(A, B, tol) for (A, B, tol) in data]:
+        f.result()
+    cap = srv.stats()
+    srv.close()
+    out = {"workload": "%d requests, dims log-uniform 32..4096 (half square), tol 1e-13 | 1e-10, HBM budget 64 GiB, "
+                       "4 streams" % n, "capacity_req_per_s": cap["req_per_s"], "closed_loop": cap}
+    for frac in (0.5, 0.8):
+        rate = frac * cap["req_per_s"]
+        arrivals = np.cumsum(np.random.default_rng(4004).exponential(1.0 / rate, size=n))
+        srv = Server(budget, streams=4)
+        t0 = time.perf_counter()
+        futs = []
+        for (A, B, tol), ta in zip(data, arrivals):
+            dt = t0 + ta - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            futs.append(srv.submit(A, B, tol))
+        for f in futs:
+            f.result()
+        st = srv.stats()
+        srv.close()
+        st["offered_req_per_s"] = rate
+        out["load_%d" % int(frac * 100)] = st
     return out
 
 

@@ -44,7 +44,7 @@ typedef enum {
     MMM_EINVAL = 1,      /* bad size, null pointer with nonzero size, bad method or config */
     MMM_EALIAS = 2,      /* C overlaps A or B in mmm_multiply */
     MMM_EWORKSPACE = 3,  /* workspace smaller than mmm_workspace_bytes, or misaligned */
-    MMM_EUNSUPPORTED = 4,/* valid request this build does not implement */
+    MMM_EUNSUPPORTED = 4,/* valid request that is not implemented (e.g. a digit count without exact accumulation) */
     MMM_ELAUNCH = 5,     /* HIP reported an error when enqueuing */
     MMM_ENOMEM = 6       /* batch plan could not allocate its tables */
 } mmm_status;
