@@ -9,14 +9,39 @@
 // results equal bit for bit to a sequential binary64 evaluation.  Only the
 // optional fused variant of the naive method calls fma() explicitly.
 //
-// Tiling: 256 threads (16 x 16) per workgroup own a BM x BN tile of C, each
-// thread a TM x TN register block (rows ty*TM + i, columns h*BN/2 +
+// Tiling: 256 threads (16 x 16) per workgroup own a BM x BN tile of C
+// (128 x 64 for the naive and Winograd loops, 64 x 64 for Kahan, whose state
+// is two doubles per entry), each thread a TM x TN register block (rows ty*TM + i, columns h*BN/2 +
 // tx*TN/2 + j).  K advances in steps of 16 through double-buffered LDS
 // tiles: the A tile is stored k-major so a thread reads its TM rows as one
-// contiguous run, the B tile row-major.  Global loads are issued for step
-// t+1 before the arithmetic of step t and land in the other LDS buffer.
+// contiguous run, the B tile row-major.  With PREFETCH the global loads of
+// step t+1 are issued before the arithmetic of step t and held in registers;
+// without it each step's tile is loaded and stored before the arithmetic
+// (fewer registers, more resident waves to hide the latency).  Tiles that lie
+// inside the matrices take a path without bounds checks.
+#include <type_traits>
+
 #include "common.h"
 #include "launch.h"
+
+// Tile shapes (BM, BN, TM, TN), staging and occupancy hints; overridable at
+// build time.  Defaults (measured on MI355X at 4096^3): two waves per SIMD
+// without register prefetch beat one wave per SIMD with it by 10-20%.
+#ifndef MMM_VALU_NAIVE_TILE
+#define MMM_VALU_NAIVE_TILE 128, 64, 8, 4
+#endif
+#ifndef MMM_VALU_KAHAN_TILE
+#define MMM_VALU_KAHAN_TILE 64, 64, 4, 4
+#endif
+#ifndef MMM_VALU_WINO_TILE
+#define MMM_VALU_WINO_TILE 128, 64, 8, 4
+#endif
+#ifndef MMM_VALU_PREFETCH
+#define MMM_VALU_PREFETCH 0
+#endif
+#ifndef MMM_VALU_MINWAVES
+#define MMM_VALU_MINWAVES 2
+#endif
 
 namespace mmm {
 
@@ -51,195 +76,233 @@ __device__ inline void tile_of(i64 b, i64 tiles_m, i64 tiles_n, i64& prob, i64& 
     tn = w / gs;
 }
 
-template <int BM, int BN, int TM, int TN, int OP, bool SCALED, class Src>
-__global__ __launch_bounds__(NT) void valu_gemm_kernel(Src src, i64 tiles_m, i64 tiles_n, i64 total,
-                                                       const double* __restrict__ yv,
-                                                       const double* __restrict__ zv, const int* lam)
-{
+template <int BM, int BN, int TM, int TN, int OP, bool SCALED>
+struct ValuTile {
     static_assert((BM / TM) * (BN / TN) == NT, "256 threads");
     static_assert(BM / TM == 16 && BN / TN == 16, "16 x 16 thread grid");
-    constexpr int LA = BM * BK / NT;  // A elements each thread moves per step
-    constexpr int LB = BK * BN / NT;
-    constexpr int TH = TN / 2;        // columns per half
-    __shared__ __align__(16) double As[2][BK][BM + 2];
-    __shared__ __align__(16) double Bs[2][BK][BN + 2];
+    static constexpr int LA = BM * BK / NT;  // A elements each thread moves per step
+    static constexpr int LB = BK * BN / NT;
+    static constexpr int TH = TN / 2;        // columns per half
+    static constexpr int KSTEP = (OP == OP_WINOGRAD) ? 2 : 1;
 
-    i64 prob, tm, tn;
-    tile_of(xcd_remap(blockIdx.x, total), tiles_m, tiles_n, prob, tm, tn);
-    const Gemm g = src.get(prob);
-    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
-    const i64 m0 = tm * BM, n0 = tn * BN;
-    const i64 kmax = (OP == OP_WINOGRAD) ? 2 * (g.P / 2) : g.P;
-    const i64 ntiles = (kmax + BK - 1) / BK;
+    static constexpr int NBUF = MMM_VALU_PREFETCH ? 2 : 1;
+    struct Smem {
+        double As[NBUF][BK][BM + 2];
+        double Bs[NBUF][BK][BN + 2];
+    };
 
-    double sa = 1.0, sb = 1.0;
-    if (SCALED) {
-        const int l = *lam;
-        sa = ldexp(1.0, l);
-        sb = ldexp(1.0, -l);
+    // Accumulate the whole K range into acc (and cmp for Kahan).  CHECK:
+    // bounds-check every load (edge tiles); otherwise only the last K step
+    // is checked.
+    template <bool CHECK>
+    __device__ __forceinline__ static void mainloop(const Gemm& g, i64 m0, i64 n0, i64 kmax, double sa, double sb,
+                                                    Smem& sm, double (&acc)[TM][TN], double (&cmp)[TM][TN])
+    {
+        const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+        const i64 ntiles = (kmax + BK - 1) / BK;
+        double ra[LA], rb[LB];
+        auto gload = [&](i64 t, bool check) __attribute__((always_inline)) {
+            const i64 k0 = t * BK;
+#pragma unroll
+            for (int q = 0; q < LA; ++q) {
+                const int e = q * NT + tid, r = e / BK, k = e % BK;
+                const i64 gm = m0 + r, gk = k0 + k;
+                double v;
+                if (check) v = (gm < g.N && gk < kmax) ? g.A[gm * g.lda + gk] : 0.0;
+                else v = g.A[gm * g.lda + gk];
+                ra[q] = SCALED ? v * sa : v;
+            }
+#pragma unroll
+            for (int q = 0; q < LB; ++q) {
+                const int e = q * NT + tid, k = e / BN, n = e % BN;
+                const i64 gk = k0 + k, gn = n0 + n;
+                double v;
+                if (check) v = (gk < kmax && gn < g.M) ? g.B[gk * g.ldb + gn] : 0.0;
+                else v = g.B[gk * g.ldb + gn];
+                rb[q] = SCALED ? v * sb : v;
+            }
+        };
+        auto lstore = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+            for (int q = 0; q < LA; ++q) {
+                const int e = q * NT + tid;
+                sm.As[buf][e % BK][e / BK] = ra[q];
+            }
+#pragma unroll
+            for (int q = 0; q < LB; ++q) {
+                const int e = q * NT + tid;
+                sm.Bs[buf][e / BN][e % BN] = rb[q];
+            }
+        };
+        auto frag_a = [&](int buf, int k, double* a) __attribute__((always_inline)) {
+#pragma unroll
+            for (int i = 0; i < TM; i += 2) {
+                const double2 v = *reinterpret_cast<const double2*>(&sm.As[buf][k][ty * TM + i]);
+                a[i] = v.x;
+                a[i + 1] = v.y;
+            }
+        };
+        auto frag_b = [&](int buf, int k, double* b) __attribute__((always_inline)) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (TH % 2 == 0) {
+#pragma unroll
+                    for (int j = 0; j < TH; j += 2) {
+                        const double2 v =
+                            *reinterpret_cast<const double2*>(&sm.Bs[buf][k][h * (BN / 2) + tx * TH + j]);
+                        b[h * TH + j] = v.x;
+                        b[h * TH + j + 1] = v.y;
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < TH; ++j) b[h * TH + j] = sm.Bs[buf][k][h * (BN / 2) + tx * TH + j];
+                }
+            }
+        };
+        auto step = [&](int buf, int k) __attribute__((always_inline)) {
+            if (OP == OP_WINOGRAD) {
+                // pair (k, k+1): (A_{i,k} + B_{k+1,j}) (A_{i,k+1} + B_{k,j})
+                double a0[TM], a1[TM], b0[TN], b1[TN];
+                frag_a(buf, k, a0);
+                frag_a(buf, k + 1, a1);
+                frag_b(buf, k, b0);
+                frag_b(buf, k + 1, b1);
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) {
+                        const double u = a0[i] + b1[j];
+                        const double v = a1[i] + b0[j];
+                        const double w = u * v;
+                        acc[i][j] = acc[i][j] + w;
+                    }
+            } else {
+                double a[TM], b[TN];
+                frag_a(buf, k, a);
+                frag_b(buf, k, b);
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) {
+                        if (OP == OP_NAIVE) {
+                            const double x = a[i] * b[j];
+                            acc[i][j] = acc[i][j] + x;
+                        } else if (OP == OP_NAIVE_FMA) {
+                            acc[i][j] = fma(a[i], b[j], acc[i][j]);
+                        } else {
+                            // Kahan as printed: err = err + x; t = sum + err;
+                            // err = (sum - t) + err; sum = t.
+                            const double x = a[i] * b[j];
+                            const double e = cmp[i][j] + x;
+                            const double t = acc[i][j] + e;
+                            cmp[i][j] = (acc[i][j] - t) + e;
+                            acc[i][j] = t;
+                        }
+                    }
+            }
+        };
+        auto compute = [&](int buf, i64 t) __attribute__((always_inline)) {
+            const i64 rem = kmax - t * BK;
+            if (rem >= BK) {
+#pragma unroll
+                for (int k = 0; k < BK; k += KSTEP) step(buf, k);
+            } else {
+                const int kc = (int)rem;
+                for (int k = 0; k < kc; k += KSTEP) step(buf, k);
+            }
+        };
+        auto need_check = [&](i64 t) __attribute__((always_inline)) { return CHECK || (t + 1) * BK > kmax; };
+
+        if (MMM_VALU_PREFETCH) {
+            if (ntiles > 0) {
+                gload(0, need_check(0));
+                lstore(0);
+            }
+            __syncthreads();
+            for (i64 t = 0; t < ntiles; ++t) {
+                const int cur = (int)(t & 1);
+                if (t + 1 < ntiles) gload(t + 1, need_check(t + 1));
+                compute(cur, t);
+                if (t + 1 < ntiles) lstore(cur ^ 1);
+                __syncthreads();
+            }
+        } else {
+            for (i64 t = 0; t < ntiles; ++t) {
+                gload(t, need_check(t));
+                __syncthreads();  // the previous step's reads of the buffer are done
+                lstore(0);
+                __syncthreads();
+                compute(0, t);
+            }
+        }
     }
 
-    double acc[TM][TN];
-    double cmp[(OP == OP_KAHAN) ? TM : 1][(OP == OP_KAHAN) ? TN : 1];
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = 0.0;
-    if (OP == OP_KAHAN) {
+    __device__ __forceinline__ static void run(const Gemm& g, i64 tm, i64 tn, const double* __restrict__ yv,
+                                               const double* __restrict__ zv, const int* lam, Smem& sm)
+    {
+        const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+        const i64 m0 = tm * BM, n0 = tn * BN;
+        const i64 kmax = (OP == OP_WINOGRAD) ? 2 * (g.P / 2) : g.P;
+        double sa = 1.0, sb = 1.0;
+        if (SCALED) {
+            const int l = *lam;
+            sa = ldexp(1.0, l);
+            sb = ldexp(1.0, -l);
+        }
+        double acc[TM][TN], cmp[TM][TN];
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
-            for (int j = 0; j < TN; ++j) cmp[i][j] = 0.0;
-    }
-
-    double ra[LA], rb[LB];
-    auto gload = [&](i64 t) {
-        const i64 k0 = t * BK;
-#pragma unroll
-        for (int q = 0; q < LA; ++q) {
-            const int e = q * NT + tid, r = e / BK, k = e % BK;
-            const i64 gm = m0 + r, gk = k0 + k;
-            double v = (gm < g.N && gk < kmax) ? g.A[gm * g.lda + gk] : 0.0;
-            ra[q] = SCALED ? v * sa : v;
-        }
-#pragma unroll
-        for (int q = 0; q < LB; ++q) {
-            const int e = q * NT + tid, k = e / BN, n = e % BN;
-            const i64 gk = k0 + k, gn = n0 + n;
-            double v = (gk < kmax && gn < g.M) ? g.B[gk * g.ldb + gn] : 0.0;
-            rb[q] = SCALED ? v * sb : v;
-        }
-    };
-    auto lstore = [&](int buf) {
-#pragma unroll
-        for (int q = 0; q < LA; ++q) {
-            const int e = q * NT + tid;
-            As[buf][e % BK][e / BK] = ra[q];
-        }
-#pragma unroll
-        for (int q = 0; q < LB; ++q) {
-            const int e = q * NT + tid;
-            Bs[buf][e / BN][e % BN] = rb[q];
-        }
-    };
-    auto frag_a = [&](int buf, int k, double* a) {
-#pragma unroll
-        for (int i = 0; i < TM; i += 2) {
-            const double2 v = *reinterpret_cast<const double2*>(&As[buf][k][ty * TM + i]);
-            a[i] = v.x;
-            a[i + 1] = v.y;
-        }
-    };
-    auto frag_b = [&](int buf, int k, double* b) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            if (TH % 2 == 0) {
-#pragma unroll
-                for (int j = 0; j < TH; j += 2) {
-                    const double2 v =
-                        *reinterpret_cast<const double2*>(&Bs[buf][k][h * (BN / 2) + tx * TH + j]);
-                    b[h * TH + j] = v.x;
-                    b[h * TH + j + 1] = v.y;
-                }
-            } else {
-#pragma unroll
-                for (int j = 0; j < TH; ++j) b[h * TH + j] = Bs[buf][k][h * (BN / 2) + tx * TH + j];
+            for (int j = 0; j < TN; ++j) {
+                acc[i][j] = 0.0;
+                cmp[i][j] = 0.0;
             }
-        }
-    };
-    auto step = [&](int buf, int k) {
-        if (OP == OP_WINOGRAD) {
-            // pair (k, k+1): (A_{i,k} + B_{k+1,j}) (A_{i,k+1} + B_{k,j})
-            double a0[TM], a1[TM], b0[TN], b1[TN];
-            frag_a(buf, k, a0);
-            frag_a(buf, k + 1, a1);
-            frag_b(buf, k, b0);
-            frag_b(buf, k + 1, b1);
-#pragma unroll
-            for (int i = 0; i < TM; ++i)
-#pragma unroll
-                for (int j = 0; j < TN; ++j) {
-                    const double u = a0[i] + b1[j];
-                    const double v = a1[i] + b0[j];
-                    const double w = u * v;
-                    acc[i][j] = acc[i][j] + w;
-                }
-        } else {
-            double a[TM], b[TN];
-            frag_a(buf, k, a);
-            frag_b(buf, k, b);
-#pragma unroll
-            for (int i = 0; i < TM; ++i)
-#pragma unroll
-                for (int j = 0; j < TN; ++j) {
-                    if (OP == OP_NAIVE) {
-                        const double x = a[i] * b[j];
-                        acc[i][j] = acc[i][j] + x;
-                    } else if (OP == OP_NAIVE_FMA) {
-                        acc[i][j] = fma(a[i], b[j], acc[i][j]);
-                    } else {
-                        // Kahan as printed: err = err + x; t = sum + err;
-                        // err = (sum - t) + err; sum = t.
-                        const double x = a[i] * b[j];
-                        const double e = cmp[i][j] + x;
-                        const double t = acc[i][j] + e;
-                        cmp[i][j] = (acc[i][j] - t) + e;
-                        acc[i][j] = t;
-                    }
-                }
-        }
-    };
-    constexpr int KSTEP = (OP == OP_WINOGRAD) ? 2 : 1;
+        if (m0 + BM <= g.N && n0 + BN <= g.M) mainloop<false>(g, m0, n0, kmax, sa, sb, sm, acc, cmp);
+        else mainloop<true>(g, m0, n0, kmax, sa, sb, sm, acc, cmp);
 
-    if (ntiles > 0) {
-        gload(0);
-        lstore(0);
-    }
-    __syncthreads();
-    for (i64 t = 0; t < ntiles; ++t) {
-        const int cur = (int)(t & 1);
-        if (t + 1 < ntiles) gload(t + 1);
-        const i64 rem = kmax - t * BK;
-        if (rem >= BK) {
+        const bool odd = (OP == OP_WINOGRAD) && (g.P % 2 == 1);
 #pragma unroll
-            for (int k = 0; k < BK; k += KSTEP) step(cur, k);
-        } else {
-            const int kc = (int)rem;
-            for (int k = 0; k < kc; k += KSTEP) step(cur, k);
-        }
-        if (t + 1 < ntiles) lstore(cur ^ 1);
-        __syncthreads();
-    }
-
-    // epilogue
-    const bool odd = (OP == OP_WINOGRAD) && (g.P % 2 == 1);
-#pragma unroll
-    for (int i = 0; i < TM; ++i) {
-        const i64 gm = m0 + ty * TM + i;
-        if (gm >= g.N) continue;
-        double yi = 0.0, alast = 0.0;
-        if (OP == OP_WINOGRAD) {
-            yi = yv[gm];
-            if (odd) alast = SCALED ? g.A[gm * g.lda + (g.P - 1)] * sa : g.A[gm * g.lda + (g.P - 1)];
-        }
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int j = 0; j < TH; ++j) {
-                const i64 gn = n0 + h * (BN / 2) + tx * TH + j;
-                if (gn >= g.M) continue;
-                double c = acc[i][h * TH + j];
-                if (OP == OP_WINOGRAD) {
-                    c = (c - yi) - zv[gn];
-                    if (odd) {
-                        const double bl = SCALED ? g.B[(g.P - 1) * g.ldb + gn] * sb : g.B[(g.P - 1) * g.ldb + gn];
-                        const double tail = alast * bl;
-                        c = c + tail;
-                    }
-                }
-                g.C[gm * g.ldc + gn] = c;
+        for (int i = 0; i < TM; ++i) {
+            const i64 gm = m0 + ty * TM + i;
+            if (gm >= g.N) continue;
+            double yi = 0.0, alast = 0.0;
+            if (OP == OP_WINOGRAD) {
+                yi = yv[gm];
+                if (odd) alast = SCALED ? g.A[gm * g.lda + (g.P - 1)] * sa : g.A[gm * g.lda + (g.P - 1)];
             }
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int j = 0; j < TH; ++j) {
+                    const i64 gn = n0 + h * (BN / 2) + tx * TH + j;
+                    if (gn >= g.M) continue;
+                    double c = acc[i][h * TH + j];
+                    if (OP == OP_WINOGRAD) {
+                        c = (c - yi) - zv[gn];
+                        if (odd) {
+                            const double bl =
+                                SCALED ? g.B[(g.P - 1) * g.ldb + gn] * sb : g.B[(g.P - 1) * g.ldb + gn];
+                            const double tail = alast * bl;
+                            c = c + tail;
+                        }
+                    }
+                    g.C[gm * g.ldc + gn] = c;
+                }
+        }
     }
+};
+
+template <int BM, int BN, int TM, int TN, int OP, bool SCALED, class Src>
+__global__ __launch_bounds__(NT, MMM_VALU_MINWAVES) void valu_gemm_kernel(Src src, i64 tiles_m, i64 tiles_n,
+                                                                          i64 total, const double* __restrict__ yv,
+                                                                          const double* __restrict__ zv,
+                                                                          const int* lam)
+{
+    typedef ValuTile<BM, BN, TM, TN, OP, SCALED> T;
+    __shared__ __align__(16) typename T::Smem sm;
+    i64 prob, tm, tn;
+    tile_of(xcd_remap(blockIdx.x, total), tiles_m, tiles_n, prob, tm, tn);
+    T::run(src.get(prob), tm, tn, yv, zv, lam, sm);
 }
 
 template <int BM, int BN, int TM, int TN, int OP, bool SCALED, class Src>
@@ -255,16 +318,22 @@ hipError_t launch_valu(const Src& src, i64 N, i64 M, const double* yv, const dou
     return hipGetLastError();
 }
 
+template <int BM, int BN, int TM, int TN>
+struct Shape {
+    static constexpr int bm = BM, bn = BN, tm = TM, tn = TN;
+};
+typedef Shape<MMM_VALU_NAIVE_TILE> NaiveShape;
+typedef Shape<MMM_VALU_KAHAN_TILE> KahanShape;
+typedef Shape<MMM_VALU_WINO_TILE> WinoShape;
+
 // Small problems (every dimension <= 48, e.g. the m x m leaves of the
 // paper's Strassen embedding) use 32 x 32 tiles.
 template <int OP, class Src>
 hipError_t launch_naive_like(const Src& src, i64 N, i64 M, hipStream_t s)
 {
     if (N <= 48 && M <= 48) return launch_valu<32, 32, 2, 2, OP, false>(src, N, M, nullptr, nullptr, nullptr, s);
-    if constexpr (OP == OP_KAHAN)
-        return launch_valu<128, 64, 8, 4, OP, false>(src, N, M, nullptr, nullptr, nullptr, s);
-    else
-        return launch_valu<128, 128, 8, 8, OP, false>(src, N, M, nullptr, nullptr, nullptr, s);
+    typedef typename std::conditional<OP == OP_KAHAN, KahanShape, NaiveShape>::type S;
+    return launch_valu<S::bm, S::bn, S::tm, S::tn, OP, false>(src, N, M, nullptr, nullptr, nullptr, s);
 }
 
 }  // namespace
@@ -290,8 +359,9 @@ hipError_t launch_kahan(const Gemm& g, hipStream_t s)
 hipError_t launch_winograd_main(const Gemm& g, const double* y, const double* z, const int* lam, hipStream_t s)
 {
     SingleSrc src{g};
-    if (lam) return launch_valu<128, 128, 8, 8, OP_WINOGRAD, true>(src, g.N, g.M, y, z, lam, s);
-    return launch_valu<128, 128, 8, 8, OP_WINOGRAD, false>(src, g.N, g.M, y, z, nullptr, s);
+    typedef WinoShape S;
+    if (lam) return launch_valu<S::bm, S::bn, S::tm, S::tn, OP_WINOGRAD, true>(src, g.N, g.M, y, z, lam, s);
+    return launch_valu<S::bm, S::bn, S::tm, S::tn, OP_WINOGRAD, false>(src, g.N, g.M, y, z, nullptr, s);
 }
 
 }  // namespace mmm

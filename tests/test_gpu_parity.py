@@ -199,3 +199,18 @@ def test_full_size_sampled_rows(mmm, orc, P):
     for L in (2, 3):
         for name in ("strassen_winograd", "strassen_naive"):
             assert err(rows_of(name, mmm.Config(strassen_levels=L))) <= TOL_STRASSEN, (name, L)
+
+
+@pytest.mark.parametrize("shape", [(2048, 2048, 2048), (2048, 512, 4096), (4096, 16, 2048), (1024, 4096, 8192)])
+def test_dgemm_direct_load_path_exact(mmm, shape):
+    """Shapes whose every tile takes the direct global-to-LDS path (N, M
+    multiples of 128 with at least 256 tiles, P a multiple of 16): integer
+    data makes the product exact, so any layout or index error shows."""
+    N, P, M = shape
+    print("case", shape, flush=True)
+    A = synth.integers((N, P), 401)
+    B = synth.integers((P, M), 402)
+    ref = A @ B  # integer-valued doubles below 2^53: exact in any order
+    assert np.array_equal(run(mmm, A, B, "dgemm"), ref)
+    cfg = mmm.Config(strassen_levels=1)
+    assert np.array_equal(run(mmm, A, B, "strassen_winograd", cfg), ref)
