@@ -18,10 +18,13 @@
 // Digit types: BF16 (beta = 8, FP32 accumulation, 16x16x32 MFMA), FP16
 // (beta = 9), INT8 (beta = 7, INT32 accumulation, 16x16x64 MFMA).
 //
-// Layouts (workspace): digits of A as SA[i][kt][t][kk] and of B transposed
-// as SB[j][kt][u][kk] (kt = K tile of 64, kk < 64), so one K tile of every
-// digit of a row is one contiguous run; rows and K padded with zeros to the
-// tile sizes, so the GEMM's loads need no bounds checks.
+// Layouts (workspace): K is padded to a multiple of 64 entries and cut into
+// blocks of 64 bytes (64 int8 or 32 bf16/fp16 digits: one MFMA step of
+// every digit type).  Digits of A are stored as SA[kb][t][i][64 bytes] and
+// digits of B transposed as SB[kb][u][j][64 bytes] (kb = K block, t/u =
+// digit), so the 16 rows x 64 bytes one MFMA operand block needs are one
+// contiguous KiB; rows are padded with zeros to the tile sizes, so the
+// GEMM's loads need no bounds checks.
 #include <string.h>
 
 #include "batch.h"
@@ -39,7 +42,8 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int KT = 64;  // K tile (elements)
+constexpr int KT = 64;  // K padding (entries)
+constexpr int KB = 64;  // bytes of K per MFMA step and per digit block
 
 enum DType { DT_BF16 = 0, DT_FP16 = 1, DT_INT8 = 2 };
 
@@ -61,18 +65,34 @@ struct Digit<DT_INT8> {
     static constexpr double budget = 2147483647.0;  // int32
 };
 
-// Wave tile (wbm x wbn blocks of 16 x 16, 2 x 2 waves per workgroup) for a
-// digit type, digit count and accumulation scheme, sized so that the group
-// accumulators (s per output, plus 2 s FP64 registers when flushing) and
-// the staging registers fit one wave per SIMD without spills.
+// Workgroup tile: 4 waves side by side along N, each owning wbm blocks of
+// 16 rows and one block of 16 columns, so BM = 16 wbm and BN = 64; minw
+// waves per SIMD.  Sized so that the group accumulators (s per output),
+// when flushing the 2 s FP64 registers per output, and the double-buffered
+// B digit fragments fit the register share of minw waves without spills.
+#ifndef MMM_SPLIT_WBM
+#define MMM_SPLIT_WBM 4
+#endif
+#ifndef MMM_SPLIT_MINW
+#define MMM_SPLIT_MINW 2
+#endif
 struct TileCfg {
-    int wbm, wbn;
-    constexpr int bm() const { return 32 * wbm; }
-    constexpr int bn() const { return 32 * wbn; }
+    int wbm, minw;
+    constexpr int bm() const { return 16 * wbm; }
+    constexpr int bn() const { return 64; }
 };
 __host__ __device__ constexpr TileCfg tile_cfg(int dt, int s, bool flush)
 {
-    return dt == DT_INT8 ? (flush ? TileCfg{2, 2} : TileCfg{4, 2}) : (s >= 6 ? TileCfg{1, 2} : TileCfg{2, 2});
+    return (void)dt, !flush ? TileCfg{MMM_SPLIT_WBM, MMM_SPLIT_MINW}
+                            : (s <= 3 ? TileCfg{4, 2} : (s <= 6 ? TileCfg{2, 2} : TileCfg{2, 1}));
+}
+// The persistent batch kernel keeps the job-table walk live as well: one
+// wave per SIMD where the flushing tile is at the two-wave register limit.
+// Its tiles equal the single-product ones, so one workspace layout serves
+// both.
+__host__ __device__ constexpr TileCfg grouped_tile_cfg(int dt, int s, bool flush)
+{
+    return (flush && s >= 4) ? TileCfg{2, 1} : tile_cfg(dt, s, flush);
 }
 
 __host__ __device__ inline int beta_of(int dt) { return dt == DT_BF16 ? 8 : (dt == DT_FP16 ? 9 : 7); }
@@ -140,26 +160,28 @@ __device__ inline void cut(const double* x, double sc, int e, int s, char* out, 
     }
 }
 
-// A: one thread per (row i < Np, 8-entry chunk of the padded K).
+// A: one thread per (row i < Np, 8-entry chunk of the padded K); the
+// threads of one 64-byte digit block are adjacent, then rows, then blocks,
+// so the digit stores of a wave are contiguous.
 template <int DT>
 __device__ __forceinline__ void split_a_body(const double* __restrict__ A, i64 N, i64 P, i64 Np, i64 Kp,
                                              const double* __restrict__ rmax, const int* lam, int s,
                                              char* __restrict__ SA, int* __restrict__ ea, i64 block, i64 nblocks)
 {
     constexpr int ES = Digit<DT>::esize;
-    const i64 chunks = Kp / 8;
-    const i64 total = Np * chunks;
+    constexpr int TB = KB / (8 * ES);  // threads per 64-byte block
+    const i64 total = Np * (Kp / 8);
     const double sc = lam ? ldexp(1.0, *lam) : 1.0;
-    const i64 row_bytes = Kp * s * ES;
     for (i64 c = block * 256 + threadIdx.x; c < total; c += nblocks * 256) {
-        const i64 i = c / chunks, k0 = (c - i * chunks) * 8;
+        const int q = (int)(c % TB);
+        const i64 rest = c / TB, i = rest % Np, kb = rest / Np;
+        const i64 k0 = kb * (KB / ES) + q * 8;
         const int e = i < N ? vec_exponent(rmax[i]) : 0;
         double x[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) x[q] = (i < N && k0 + q < P) ? A[i * P + k0 + q] : 0.0;
-        const i64 kt = k0 / KT, kk = k0 % KT;
-        char* out = SA + i * row_bytes + (kt * s * KT + kk) * ES;
-        cut<DT>(x, sc, e, s, out, (i64)KT * ES);
+        for (int r = 0; r < 8; ++r) x[r] = (i < N && k0 + r < P) ? A[i * P + k0 + r] : 0.0;
+        char* out = SA + (kb * s * Np + i) * KB + q * 8 * ES;
+        cut<DT>(x, sc, e, s, out, Np * KB);
         if (k0 == 0) ea[i] = e;
     }
 }
@@ -172,15 +194,16 @@ __global__ __launch_bounds__(256) void split_a_kernel(const double* __restrict__
     split_a_body<DT>(A, N, P, Np, Kp, rmax, lam, s, SA, ea, blockIdx.x, gridDim.x);
 }
 
-// B (P x M, row-major) to SB[j][kt][u][kk]: a 64 (k) x 64 (j) tile goes
-// through LDS so both the loads (along j) and the stores (along k) are
-// contiguous.
+// B (P x M, row-major) to SB[kb][u][j][64 bytes]: a 64 (k) x 64 (j) tile
+// goes through LDS so both the loads (along j) and the stores (64-byte
+// blocks of neighbouring columns) are contiguous.
 template <int DT>
 __device__ __forceinline__ void split_b_body(const double* __restrict__ B, i64 P, i64 M, i64 Mp, i64 Kp,
                                              const double* __restrict__ cmax, const int* lam, int s,
                                              char* __restrict__ SB, int* __restrict__ fb, i64 block, double (*T)[65])
 {
     constexpr int ES = Digit<DT>::esize;
+    constexpr int TB = KB / (8 * ES);  // threads per 64-byte block
     const i64 tiles_j = Mp / 64;
     const i64 kt = block / tiles_j;
     const i64 j0 = (block - kt * tiles_j) * 64, k0 = kt * 64;
@@ -193,19 +216,21 @@ __device__ __forceinline__ void split_b_body(const double* __restrict__ B, i64 P
         T[kr][jc] = (k < P && j < M) ? B[k * M + j] : 0.0;
     }
     __syncthreads();
-    // 256 threads: 64 columns x 4 chunks of 8 -> two passes cover 64 k
+    // 512 chunks of 8 entries (64 columns x 64 k) over two passes of 256 threads
 #pragma unroll
     for (int pass = 0; pass < 2; ++pass) {
-        const int jc = tid / 4, ch = (tid % 4) + 4 * pass;
+        const int c = pass * 256 + tid;
+        const int q = c % TB, jc = (c / TB) % 64, blk = c / (TB * 64);
+        const int kk = blk * (KB / ES) + q * 8;
         const i64 j = j0 + jc;
         const int e = j < M ? vec_exponent(cmax[j]) : 0;
         double x[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) x[q] = T[ch * 8 + q][jc];
-        const i64 row_bytes = Kp * s * ES;
-        char* out = SB + j * row_bytes + (kt * s * KT + ch * 8) * ES;
-        cut<DT>(x, sc, e, s, out, (i64)KT * ES);
-        if (kt == 0 && ch == 0) fb[j] = e;
+        for (int r = 0; r < 8; ++r) x[r] = T[kk + r][jc];
+        const i64 kb = kt * ES + blk;
+        char* out = SB + (kb * s * Mp + j) * KB + q * 8 * ES;
+        cut<DT>(x, sc, e, s, out, Mp * KB);
+        if (kt == 0 && kk == 0) fb[j] = e;
     }
 }
 
@@ -256,161 +281,148 @@ struct Mfma<DT_INT8> {
     }
 };
 
-// Workgroup of 4 waves (2 x 2); wave tile WBM x WBN blocks of 16 x 16.
-// Per K tile of 64 the workgroup stages the s digit tiles of its BM rows of
-// A and BN columns of B in LDS (row pitch 64*esize + 16 bytes: the 16 rows
-// a lane group reads fall in distinct banks), then every wave runs the
-// s(s+1)/2 kept digit pairs, pair (t, u) accumulating into group t+u.
-// Operand layout of both MFMAs used: lane l holds row (A) / column (B)
-// l % 16 and the 16 bytes of K starting at 16 (l / 16) bytes; result
-// element r of lane l is D[4 (l / 16) + r][l % 16].
-template <int DT, int S, bool FLUSH>
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+typedef __attribute__((address_space(1))) void* gbl_ptr_t;
+
+// Slot of 16-byte chunk c of row r (r < 16) in a 16-row x 64-byte LDS
+// block.  Row r starts at byte 64 r; XOR-ing the chunk with a function of
+// r spreads the 16 rows of one chunk column over all banks, so the MFMA
+// operand reads (lane: row l % 16, chunk l / 16) are free of conflicts.
+__device__ __forceinline__ int swz(int r, int c) { return c ^ (((r >> 1) ^ (r >> 2)) & 3); }
+
+// Workgroup of 4 waves side by side along N; wave w owns columns
+// n0 + 16 w .. n0 + 16 w + 15 and all BM rows (WBM blocks of 16).  Per K
+// block of 64 bytes:
+//   A: the S digit planes of the BM rows (S x BM x 64 bytes, contiguous
+//      KiBs in the workspace) are loaded straight into LDS (16 bytes per
+//      lane, lane l of a wave instruction landing at base + 16 l, rows
+//      swizzled by swz), two stages, no staging registers;
+//   B: each wave loads its own S fragments (16 columns x 64 bytes per
+//      digit: one KiB) into registers, double buffered;
+// then every wave runs the s(s+1)/2 kept digit pairs, pair (t, u)
+// accumulating into group t + u.  Both MFMAs used take lane l's operand
+// as row (A) / column (B) l % 16 and bytes 16 (l / 16) .. 16 (l / 16) + 15
+// of the K block; result element r of lane l is D[4 (l / 16) + r][l % 16].
+template <int DT, int S, bool FLUSH, int WBM>
 __device__ __forceinline__ void split_tile(const char* __restrict__ SA, const char* __restrict__ SB,
                                            const int* __restrict__ ea, const int* __restrict__ fb,
-                                           double* __restrict__ C, i64 N, i64 M, i64 Kp, i64 tm, i64 tn,
-                                           int flush_steps, char* lds)
+                                           double* __restrict__ C, i64 N, i64 M, i64 Np, i64 Mp, i64 Kp, i64 tm,
+                                           i64 tn, int flush_steps, char* lds)
 {
     typedef Digit<DT> D;
     typedef typename Mfma<DT>::acc_t acc_t;
-    constexpr TileCfg TC = tile_cfg(DT, S, FLUSH);
-    constexpr int ES = D::esize, BM = TC.bm(), BN = TC.bn(), WBM = TC.wbm, WBN = TC.wbn;
-    constexpr int ROWB = KT * ES;         // bytes of one digit row in a K tile
-    constexpr int PITCH = ROWB + 16;      // LDS row pitch
+    constexpr TileCfg TC{WBM, 1};
+    constexpr int BM = TC.bm(), BN = TC.bn();
     constexpr int G = S;                  // groups g = 2 .. S+1 -> index g-2
-    constexpr int STEPS = KT / D::mfma_k; // MFMA k-steps per K tile
-    constexpr int CH_A = BM * S * ROWB / 16, CH_B = BN * S * ROWB / 16;  // 16-byte chunks per tile
-    constexpr int LA = CH_A / 256, LB = CH_B / 256;
-    static_assert(CH_A % 256 == 0 && CH_B % 256 == 0, "chunks");
-    char* la = lds;                       // [S][BM][PITCH]
-    char* lb = lds + S * BM * PITCH;      // [S][BN][PITCH]
+    constexpr int NBLK = S * WBM;         // KiB blocks of A per K block
+    constexpr int STAGE = NBLK * 1024;
     const i64 m0 = tm * BM, n0 = tn * BN;
-
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
     const int li = lane & 15, lq = lane >> 4;
+    const i64 steps = Kp * D::esize / KB;
+    const i64 plane_a = Np * KB, plane_b = Mp * KB;  // bytes of one digit plane of one K block
 
-    acc_t acc[G][WBM][WBN];
-    double acc64[FLUSH ? G : 1][FLUSH ? WBM : 1][FLUSH ? WBN : 1][4];
+    acc_t acc[G][WBM];
+    double acc64[FLUSH ? G : 1][FLUSH ? WBM : 1][4];
 #pragma unroll
     for (int g = 0; g < G; ++g)
 #pragma unroll
-        for (int i = 0; i < WBM; ++i)
+        for (int i = 0; i < WBM; ++i) {
+            acc[g][i] = (acc_t){0, 0, 0, 0};
+            if (FLUSH)
 #pragma unroll
-            for (int j = 0; j < WBN; ++j) {
-                acc[g][i][j] = (acc_t){0, 0, 0, 0};
-                if (FLUSH)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) acc64[g][i][j][r] = 0.0;
-            }
-
-    const i64 row_bytes = Kp * S * ES;
-    const i64 ktiles = Kp / KT;
-    u32x4 ra[LA], rb[LB];
-    // chunk c of a tile: row = c / (S*ROWB/16), then digit t and 16-byte piece
-    auto gload = [&](i64 kt) __attribute__((always_inline)) {
-#pragma unroll
-        for (int q = 0; q < LA; ++q) {
-            const int c = q * 256 + tid;
-            const int row = c / (S * ROWB / 16), rem = c % (S * ROWB / 16);
-            ra[q] = *reinterpret_cast<const u32x4*>(SA + (m0 + row) * row_bytes + kt * S * ROWB + rem * 16);
+                for (int r = 0; r < 4; ++r) acc64[g][i][r] = 0.0;
         }
+
+    // this lane's source within a KiB block of A: row lane / 4, swizzled chunk
+    const int dr = lane >> 2;
+    const char* ga = SA + (m0 + dr) * KB + swz(dr, lane & 3) * 16;
+    const char* gb = SB + (n0 + wave * 16 + li) * KB + lq * 16;
+    const int rd = li * KB + swz(li, lq) * 16;  // this lane's fragment within a KiB block
+
+    auto issue_a = [&](i64 kb, int buf) __attribute__((always_inline)) {
 #pragma unroll
-        for (int q = 0; q < LB; ++q) {
-            const int c = q * 256 + tid;
-            const int row = c / (S * ROWB / 16), rem = c % (S * ROWB / 16);
-            rb[q] = *reinterpret_cast<const u32x4*>(SB + (n0 + row) * row_bytes + kt * S * ROWB + rem * 16);
+        for (int q = 0; q < (NBLK + 3) / 4; ++q) {
+            const int blk = q * 4 + wave;  // block = (digit t, 16-row block) written by this wave instruction
+            if (NBLK % 4 == 0 || blk < NBLK) {
+                const int t = blk / WBM, rb = blk % WBM;
+                const char* src = ga + (kb * S + t) * plane_a + rb * 16 * KB;
+                __builtin_amdgcn_global_load_lds((gbl_ptr_t)src, (lds_ptr_t)(lds + buf * STAGE + blk * 1024), 16, 0,
+                                                 0);
+            }
         }
     };
-    auto lstore = [&]() __attribute__((always_inline)) {
+    u32x4 bcur[S], bnxt[S];
+    auto load_b = [&](i64 kb) __attribute__((always_inline)) {
 #pragma unroll
-        for (int q = 0; q < LA; ++q) {
-            const int c = q * 256 + tid;
-            const int row = c / (S * ROWB / 16), rem = c % (S * ROWB / 16);
-            const int t = rem / (ROWB / 16), piece = rem % (ROWB / 16);
-            *reinterpret_cast<u32x4*>(la + (t * BM + row) * PITCH + piece * 16) = ra[q];
-        }
-#pragma unroll
-        for (int q = 0; q < LB; ++q) {
-            const int c = q * 256 + tid;
-            const int row = c / (S * ROWB / 16), rem = c % (S * ROWB / 16);
-            const int t = rem / (ROWB / 16), piece = rem % (ROWB / 16);
-            *reinterpret_cast<u32x4*>(lb + (t * BN + row) * PITCH + piece * 16) = rb[q];
-        }
+        for (int u = 0; u < S; ++u) bnxt[u] = *reinterpret_cast<const u32x4*>(gb + (kb * S + u) * plane_b);
     };
 
     int since_flush = 0;
-    if (ktiles > 0) gload(0);
-    for (i64 kt = 0; kt < ktiles; ++kt) {
-        __syncthreads();  // previous tile fully consumed
-        lstore();
+    if (steps > 0) {
+        issue_a(0, 0);
+        load_b(0);
+    }
+    for (i64 kb = 0; kb < steps; ++kb) {
+        const int buf = (int)(kb & 1);
+        // this block's A has landed in LDS (own loads) and B in registers;
+        // after the barrier every wave's A has landed and every wave is done
+        // with the stage the next block's loads overwrite
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
-        if (kt + 1 < ktiles) gload(kt + 1);
 #pragma unroll
-        for (int st = 0; st < STEPS; ++st) {
-            const int koff = st * D::mfma_k * ES + lq * 16;
+        for (int u = 0; u < S; ++u) bcur[u] = bnxt[u];
+        if (kb + 1 < steps) {
+            issue_a(kb + 1, buf ^ 1);
+            load_b(kb + 1);
+        }
+        const char* la = lds + buf * STAGE + rd;
 #pragma unroll
-            for (int t = 0; t < S; ++t) {
-                u32x4 af[WBM];
+        for (int t = 0; t < S; ++t)
 #pragma unroll
-                for (int i = 0; i < WBM; ++i)
-                    af[i] = *reinterpret_cast<const u32x4*>(la + (t * BM + wm * WBM * 16 + i * 16 + li) * PITCH + koff);
+            for (int i = 0; i < WBM; ++i) {
+                const u32x4 a = *reinterpret_cast<const u32x4*>(la + (t * WBM + i) * 1024);
 #pragma unroll
-                for (int u = 0; u + t + 2 <= S + 1; ++u) {
-                    u32x4 bf[WBN];
-#pragma unroll
-                    for (int j = 0; j < WBN; ++j)
-                        bf[j] = *reinterpret_cast<const u32x4*>(lb + (u * BN + wn * WBN * 16 + j * 16 + li) * PITCH + koff);
-#pragma unroll
-                    for (int i = 0; i < WBM; ++i)
-#pragma unroll
-                        for (int j = 0; j < WBN; ++j)
-                            acc[t + u][i][j] = Mfma<DT>::run(af[i], bf[j], acc[t + u][i][j]);
-                }
+                for (int u = 0; u + t < S; ++u) acc[t + u][i] = Mfma<DT>::run(a, bcur[u], acc[t + u][i]);
             }
-            if (FLUSH) {
-                if (++since_flush == flush_steps) {
-                    since_flush = 0;
+        if (FLUSH) {
+            if (++since_flush == flush_steps) {
+                since_flush = 0;
 #pragma unroll
-                    for (int g = 0; g < G; ++g)
+                for (int g = 0; g < G; ++g)
 #pragma unroll
-                        for (int i = 0; i < WBM; ++i)
+                    for (int i = 0; i < WBM; ++i) {
 #pragma unroll
-                            for (int j = 0; j < WBN; ++j) {
-#pragma unroll
-                                for (int r = 0; r < 4; ++r) acc64[g][i][j][r] += (double)acc[g][i][j][r];
-                                acc[g][i][j] = (acc_t){0, 0, 0, 0};
-                            }
-                }
+                        for (int r = 0; r < 4; ++r) acc64[g][i][r] += (double)acc[g][i][r];
+                        acc[g][i] = (acc_t){0, 0, 0, 0};
+                    }
             }
         }
     }
 
     // c = sum over g = S+1 .. 2 of 2^(-beta g) G_g, then scale by 2^(e_i + f_j)
+    const i64 gn = n0 + wave * 16 + li;
 #pragma unroll
     for (int i = 0; i < WBM; ++i)
 #pragma unroll
-        for (int j = 0; j < WBN; ++j) {
-            const i64 gn = n0 + wn * WBN * 16 + j * 16 + li;
+        for (int r = 0; r < 4; ++r) {
+            const i64 gm = m0 + i * 16 + 4 * lq + r;
+            double c = 0.0;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const i64 gm = m0 + wm * WBM * 16 + i * 16 + 4 * lq + r;
-                double c = 0.0;
-#pragma unroll
-                for (int g = G - 1; g >= 0; --g) {
-                    const double Gg = FLUSH ? acc64[g][i][j][r] + (double)acc[g][i][j][r] : (double)acc[g][i][j][r];
-                    const double term = ldexp(Gg, -D::beta * (g + 2));
-                    c = c + term;
-                }
-                if (gm < N && gn < M) C[gm * M + gn] = ldexp(c, ea[gm] + fb[gn]);
+            for (int g = G - 1; g >= 0; --g) {
+                const double Gg = FLUSH ? acc64[g][i][r] + (double)acc[g][i][r] : (double)acc[g][i][r];
+                const double term = ldexp(Gg, -D::beta * (g + 2));
+                c = c + term;
             }
+            if (gm < N && gn < M) C[gm * M + gn] = ldexp(c, ea[gm] + fb[gn]);
         }
 }
 
 template <int DT, int S, bool FLUSH>
-__global__ __launch_bounds__(256) void split_gemm_kernel(const char* __restrict__ SA, const char* __restrict__ SB,
+__global__ __launch_bounds__(256, tile_cfg(DT, S, FLUSH).minw) void split_gemm_kernel(const char* __restrict__ SA, const char* __restrict__ SB,
                                                          const int* __restrict__ ea, const int* __restrict__ fb,
-                                                         double* __restrict__ C, i64 N, i64 M, i64 Kp,
-                                                         i64 tiles_m, i64 tiles_n, int flush_steps)
+                                                         double* __restrict__ C, i64 N, i64 M, i64 Np, i64 Mp,
+                                                         i64 Kp, i64 tiles_m, i64 tiles_n, int flush_steps)
 {
     extern __shared__ __align__(16) char lds[];
     // tile order: XCD-contiguous ranges, 8 tile-rows per group
@@ -420,18 +432,19 @@ __global__ __launch_bounds__(256) void split_gemm_kernel(const char* __restrict_
     const i64 grp = b / (8 * tiles_n), first = grp * 8;
     const i64 gs = (tiles_m - first) < 8 ? (tiles_m - first) : 8;
     const i64 w = b - grp * 8 * tiles_n;
-    split_tile<DT, S, FLUSH>(SA, SB, ea, fb, C, N, M, Kp, first + w % gs, w / gs, flush_steps, lds);
+    split_tile<DT, S, FLUSH, tile_cfg(DT, S, FLUSH).wbm>(SA, SB, ea, fb, C, N, M, Np, Mp, Kp, first + w % gs, w / gs,
+                                                          flush_steps, lds);
 }
 
 // Persistent grid over the tiles of a group of split jobs (same digit type
 // and count): tile t is job p's (t - prefix[p])-th tile, row-major.
 template <int DT, int S, bool FLUSH>
-__global__ __launch_bounds__(256) void split_gemm_grouped_kernel(const SplitJob* __restrict__ jobs,
+__global__ __launch_bounds__(256, grouped_tile_cfg(DT, S, FLUSH).minw) void split_gemm_grouped_kernel(const SplitJob* __restrict__ jobs,
                                                                  const i64* __restrict__ prefix, int njobs, i64 total,
                                                                  int flush_steps)
 {
     extern __shared__ __align__(16) char lds[];
-    constexpr TileCfg TC = tile_cfg(DT, S, FLUSH);
+    constexpr TileCfg TC = grouped_tile_cfg(DT, S, FLUSH);
     for (i64 t = blockIdx.x; t < total; t += gridDim.x) {
         int lo = 0, hi = njobs - 1;
         while (lo < hi) {
@@ -442,8 +455,8 @@ __global__ __launch_bounds__(256) void split_gemm_grouped_kernel(const SplitJob*
         const SplitJob& j = jobs[lo];
         const i64 local = t - prefix[lo];
         const i64 tiles_n = j.Mp / TC.bn();
-        split_tile<DT, S, FLUSH>(j.SA, j.SB, j.ea, j.fb, j.C, j.N, j.M, j.Kp, local / tiles_n, local % tiles_n,
-                                 flush_steps, lds);
+        split_tile<DT, S, FLUSH, TC.wbm>(j.SA, j.SB, j.ea, j.fb, j.C, j.N, j.M, j.Np, j.Mp, j.Kp, local / tiles_n,
+                                 local % tiles_n, flush_steps, lds);
         __syncthreads();
     }
 }
@@ -536,6 +549,9 @@ struct SplitLayout {
 
 size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
+// two stages of the A digit planes (S x BM rows x 64 bytes)
+size_t split_lds_bytes(const TileCfg& tc, int s) { return (size_t)2 * s * tc.bm() * KB; }
+
 // exact-accumulation budget: digit products are at most 2^(2 beta - 2);
 // a group of at most s pairs over kb entries must stay below the budget.
 // Returns the number of MFMA k-steps between flushes to FP64.
@@ -585,19 +601,18 @@ bool split_layout(i64 N, i64 P, i64 M, const mmm_config& c, SplitLayout& L)
 template <int DT, int S, bool FLUSH>
 hipError_t launch_split_gemm(const SplitLayout& L, char* ws, double* C, i64 N, i64 M, int flush_steps, hipStream_t st)
 {
-    typedef Digit<DT> D;
     constexpr TileCfg TC = tile_cfg(DT, S, FLUSH);
     const i64 tiles_m = L.Np / TC.bm(), tiles_n = L.Mp / TC.bn();
     const i64 blocks = tiles_m * tiles_n;
     if (blocks == 0) return hipSuccess;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    const size_t lds = (size_t)S * (TC.bm() + TC.bn()) * (KT * D::esize + 16);
+    const size_t lds = split_lds_bytes(TC, S);
     auto kern = split_gemm_kernel<DT, S, FLUSH>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), lds, st, (const char*)(ws + L.SA),
-                       (const char*)(ws + L.SB), (const int*)(ws + L.ea), (const int*)(ws + L.fb), C, N, M, L.Kp,
-                       tiles_m, tiles_n, flush_steps);
+                       (const char*)(ws + L.SB), (const int*)(ws + L.ea), (const int*)(ws + L.fb), C, N, M, L.Np, L.Mp,
+                       L.Kp, tiles_m, tiles_n, flush_steps);
     return hipGetLastError();
 }
 
@@ -663,9 +678,8 @@ template <int DT, int S, bool FLUSH>
 hipError_t launch_grouped_gemm(const SplitJob* jobs, const i64* prefix, int n, i64 total, int flush_steps, int grid,
                                hipStream_t st)
 {
-    typedef Digit<DT> D;
-    constexpr TileCfg TC = tile_cfg(DT, S, FLUSH);
-    const size_t lds = (size_t)S * (TC.bm() + TC.bn()) * (KT * D::esize + 16);
+    constexpr TileCfg TC = grouped_tile_cfg(DT, S, FLUSH);
+    const size_t lds = split_lds_bytes(TC, S);
     auto kern = split_gemm_grouped_kernel<DT, S, FLUSH>;
     if (!jobs) return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, st, jobs, prefix, n, total, flush_steps);
@@ -770,7 +784,7 @@ size_t split_job_bytes(i64 N, i64 P, i64 M, int dt, int s, SplitGroup& grp, i64&
     if (!split_layout(N, P, M, c, L)) return (size_t)-1;
     const int fs = flush_steps_for(dt, s);
     if (fs < 1) return (size_t)-1;
-    const TileCfg tc = tile_cfg(dt, s, L.flush);
+    const TileCfg tc = grouped_tile_cfg(dt, s, L.flush);
     grp.dt = dt;
     grp.s = s;
     grp.flush = L.flush;
