@@ -39,6 +39,7 @@ struct SplitGroup {
     bool flush;
     int flush_steps;
     int bm, bn;
+    int per_cu;  // workgroups of the group's kernel resident per CU
 };
 
 // Workspace bytes for one split job; fills the job's Np/Mp/Kp and returns

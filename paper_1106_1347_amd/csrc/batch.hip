@@ -223,7 +223,7 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
             if (le != hipSuccess) break;
             SGroup& g = kv.second;
             const i64 tiles = g.prefix.back();
-            const int grid = (int)std::min<i64>(tiles, (i64)cus);
+            const int grid = (int)std::min<i64>(tiles, (i64)cus * g.g.per_cu);
             le = launch_split_grouped(g.g, (const SplitJob*)(base + g.off_jobs), g.jobs.data(), (int)g.jobs.size(),
                                       (const i64*)(base + g.off_prefix), tiles, c.split_scale_lambda != 0, grid, side);
         }

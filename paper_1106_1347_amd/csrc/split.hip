@@ -27,6 +27,8 @@
 // GEMM's loads need no bounds checks.
 #include <string.h>
 
+#include <type_traits>
+
 #include "batch.h"
 #include "launch.h"
 #include "reduce.h"
@@ -65,34 +67,48 @@ struct Digit<DT_INT8> {
     static constexpr double budget = 2147483647.0;  // int32
 };
 
-// Workgroup tile: 4 waves side by side along N, each owning wbm blocks of
-// 16 rows and one block of 16 columns, so BM = 16 wbm and BN = 64; minw
-// waves per SIMD.  Sized so that the group accumulators (s per output),
-// when flushing the 2 s FP64 registers per output, and the double-buffered
-// B digit fragments fit the register share of minw waves without spills.
+// Workgroup tile: nw waves side by side along N, each owning wbm blocks of
+// 16 rows and one block of 16 columns, so BM = 16 wbm and BN = 16 nw; minw
+// waves per SIMD; `stages` K blocks in flight (LDS stages of A, register
+// sets of B).  Sized so that the group accumulators (s per output), when
+// flushing the 2 s FP64 registers per output, and the B digit fragments
+// fit the register share of minw waves without spills.
 #ifndef MMM_SPLIT_WBM
 #define MMM_SPLIT_WBM 4
 #endif
 #ifndef MMM_SPLIT_MINW
 #define MMM_SPLIT_MINW 2
 #endif
+#ifndef MMM_SPLIT_NW
+#define MMM_SPLIT_NW 4
+#endif
+#ifndef MMM_SPLIT_STAGES
+#define MMM_SPLIT_STAGES 2
+#endif
+#ifndef MMM_SPLIT_SCHED
+#define MMM_SPLIT_SCHED 6  // scheduling hints for digit counts from this value up (0: never)
+#endif
 struct TileCfg {
-    int wbm, minw;
+    int wbm, minw, nw, stages;
     constexpr int bm() const { return 16 * wbm; }
-    constexpr int bn() const { return 64; }
+    constexpr int bn() const { return 16 * nw; }
+    constexpr int threads() const { return 64 * nw; }
 };
 __host__ __device__ constexpr TileCfg tile_cfg(int dt, int s, bool flush)
 {
-    return (void)dt, !flush ? TileCfg{MMM_SPLIT_WBM, MMM_SPLIT_MINW}
-                            : (s <= 3 ? TileCfg{4, 2} : (s <= 6 ? TileCfg{2, 2} : TileCfg{2, 1}));
+    return (void)dt, !flush ? (s <= 7 ? TileCfg{MMM_SPLIT_WBM, MMM_SPLIT_MINW, MMM_SPLIT_NW, MMM_SPLIT_STAGES}
+                                      : TileCfg{2, 2, 4, 2})
+                            : (s <= 3 ? TileCfg{4, 2, 4, 2} : (s <= 6 ? TileCfg{2, 2, 4, 2} : TileCfg{2, 1, 4, 2}));
 }
-// The persistent batch kernel keeps the job-table walk live as well: one
-// wave per SIMD where the flushing tile is at the two-wave register limit.
-// Its tiles equal the single-product ones, so one workspace layout serves
-// both.
+// The persistent batch kernel keeps the job-table walk live as well, so it
+// takes smaller register footprints: 4 waves and two stages without
+// flushing, one wave per SIMD where the flushing tile is at the two-wave
+// limit.  Its tiles divide the single-product ones, so one workspace
+// layout serves both.
 __host__ __device__ constexpr TileCfg grouped_tile_cfg(int dt, int s, bool flush)
 {
-    return (flush && s >= 4) ? TileCfg{2, 1} : tile_cfg(dt, s, flush);
+    return !flush ? (s <= 7 ? TileCfg{4, 2, 4, 2} : TileCfg{2, 2, 4, 2})
+                  : (s >= 4 ? TileCfg{2, 1, 4, 2} : tile_cfg(dt, s, flush));
 }
 
 __host__ __device__ inline int beta_of(int dt) { return dt == DT_BF16 ? 8 : (dt == DT_FP16 ? 9 : 7); }
@@ -290,20 +306,37 @@ typedef __attribute__((address_space(1))) void* gbl_ptr_t;
 // operand reads (lane: row l % 16, chunk l / 16) are free of conflicts.
 __device__ __forceinline__ int swz(int r, int c) { return c ^ (((r >> 1) ^ (r >> 2)) & 3); }
 
-// Workgroup of 4 waves side by side along N; wave w owns columns
+// Issue order of one K block's digit pairs for the instruction scheduler:
+// the A fragments of digits 0 and 1 first, then after the S - t MFMAs of
+// each (t, i) the read of fragment (t + 2, i), so every LDS read is two
+// digit levels ahead of its first use.
+template <int S, int WBM, int T = 0, int I = 0>
+__device__ __forceinline__ void sched_digit_pairs()
+{
+    if constexpr (T == 0 && I == 0) __builtin_amdgcn_sched_group_barrier(0x100, S >= 2 ? 2 * WBM : WBM, 0);
+    if constexpr (T < S) {
+        __builtin_amdgcn_sched_group_barrier(0x008, S - T, 0);
+        if constexpr (T + 2 < S) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        if constexpr (I + 1 < WBM) sched_digit_pairs<S, WBM, T, I + 1>();
+        else sched_digit_pairs<S, WBM, T + 1, 0>();
+    }
+}
+
+// Workgroup of NW waves side by side along N; wave w owns columns
 // n0 + 16 w .. n0 + 16 w + 15 and all BM rows (WBM blocks of 16).  Per K
 // block of 64 bytes:
 //   A: the S digit planes of the BM rows (S x BM x 64 bytes, contiguous
 //      KiBs in the workspace) are loaded straight into LDS (16 bytes per
 //      lane, lane l of a wave instruction landing at base + 16 l, rows
-//      swizzled by swz), two stages, no staging registers;
+//      swizzled by swz), NST stages, no staging registers;
 //   B: each wave loads its own S fragments (16 columns x 64 bytes per
-//      digit: one KiB) into registers, double buffered;
+//      digit: one KiB) into registers, NST sets;
+// the loads of block kb + NST - 1 are issued while block kb computes;
 // then every wave runs the s(s+1)/2 kept digit pairs, pair (t, u)
 // accumulating into group t + u.  Both MFMAs used take lane l's operand
 // as row (A) / column (B) l % 16 and bytes 16 (l / 16) .. 16 (l / 16) + 15
 // of the K block; result element r of lane l is D[4 (l / 16) + r][l % 16].
-template <int DT, int S, bool FLUSH, int WBM>
+template <int DT, int S, bool FLUSH, int WBM, int NW, int NST>
 __device__ __forceinline__ void split_tile(const char* __restrict__ SA, const char* __restrict__ SB,
                                            const int* __restrict__ ea, const int* __restrict__ fb,
                                            double* __restrict__ C, i64 N, i64 M, i64 Np, i64 Mp, i64 Kp, i64 tm,
@@ -311,7 +344,7 @@ __device__ __forceinline__ void split_tile(const char* __restrict__ SA, const ch
 {
     typedef Digit<DT> D;
     typedef typename Mfma<DT>::acc_t acc_t;
-    constexpr TileCfg TC{WBM, 1};
+    constexpr TileCfg TC{WBM, 1, NW, NST};
     constexpr int BM = TC.bm(), BN = TC.bn();
     constexpr int G = S;                  // groups g = 2 .. S+1 -> index g-2
     constexpr int NBLK = S * WBM;         // KiB blocks of A per K block
@@ -334,57 +367,73 @@ __device__ __forceinline__ void split_tile(const char* __restrict__ SA, const ch
                 for (int r = 0; r < 4; ++r) acc64[g][i][r] = 0.0;
         }
 
-    // this lane's source within a KiB block of A: row lane / 4, swizzled chunk
+    // per-lane byte offsets (32 bits) from wave-uniform bases: the loads
+    // take a scalar base plus a vector offset, so no 64-bit per-lane
+    // addresses are kept live.  A: row lane / 4 of a KiB block, swizzled chunk.
     const int dr = lane >> 2;
-    const char* ga = SA + (m0 + dr) * KB + swz(dr, lane & 3) * 16;
-    const char* gb = SB + (n0 + wave * 16 + li) * KB + lq * 16;
+    const unsigned offa = (unsigned)(dr * KB + swz(dr, lane & 3) * 16);
+    const unsigned offb = (unsigned)((wave * 16 + li) * KB + lq * 16);
+    const char* sa0 = SA + m0 * KB;  // row m0 of digit plane 0 of K block 0
+    const char* sb0 = SB + n0 * KB;
     const int rd = li * KB + swz(li, lq) * 16;  // this lane's fragment within a KiB block
 
     auto issue_a = [&](i64 kb, int buf) __attribute__((always_inline)) {
 #pragma unroll
-        for (int q = 0; q < (NBLK + 3) / 4; ++q) {
-            const int blk = q * 4 + wave;  // block = (digit t, 16-row block) written by this wave instruction
-            if (NBLK % 4 == 0 || blk < NBLK) {
+        for (int q = 0; q < (NBLK + NW - 1) / NW; ++q) {
+            const int blk = q * NW + wave;  // block = (digit t, 16-row block) written by this wave instruction
+            if (NBLK % NW == 0 || blk < NBLK) {
                 const int t = blk / WBM, rb = blk % WBM;
-                const char* src = ga + (kb * S + t) * plane_a + rb * 16 * KB;
-                __builtin_amdgcn_global_load_lds((gbl_ptr_t)src, (lds_ptr_t)(lds + buf * STAGE + blk * 1024), 16, 0,
-                                                 0);
+                const char* base = sa0 + (kb * S + t) * plane_a + rb * 16 * KB;
+                __builtin_amdgcn_global_load_lds((gbl_ptr_t)(base + offa), (lds_ptr_t)(lds + buf * STAGE + blk * 1024),
+                                                 16, 0, 0);
             }
         }
     };
-    u32x4 bcur[S], bnxt[S];
-    auto load_b = [&](i64 kb) __attribute__((always_inline)) {
+    // B fragments of NST K blocks: the one in use and the NST - 1 in flight
+    u32x4 bring[NST][S];
+    auto load_b = [&](i64 kb, u32x4(&b)[S]) __attribute__((always_inline)) {
 #pragma unroll
-        for (int u = 0; u < S; ++u) bnxt[u] = *reinterpret_cast<const u32x4*>(gb + (kb * S + u) * plane_b);
+        for (int u = 0; u < S; ++u) b[u] = *reinterpret_cast<const u32x4*>(sb0 + (kb * S + u) * plane_b + offb);
     };
+    // memory instructions this wave issues per K block (fewest over the
+    // waves), so that waiting for "at most n blocks' worth outstanding"
+    // is never too lax
+    constexpr int PER_BLOCK = NBLK / NW + S;
 
     int since_flush = 0;
-    if (steps > 0) {
-        issue_a(0, 0);
-        load_b(0);
-    }
-    for (i64 kb = 0; kb < steps; ++kb) {
-        const int buf = (int)(kb & 1);
-        // this block's A has landed in LDS (own loads) and B in registers;
-        // after the barrier every wave's A has landed and every wave is done
-        // with the stage the next block's loads overwrite
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
 #pragma unroll
-        for (int u = 0; u < S; ++u) bcur[u] = bnxt[u];
-        if (kb + 1 < steps) {
-            issue_a(kb + 1, buf ^ 1);
-            load_b(kb + 1);
+    for (int q = 0; q < NST - 1; ++q)
+        if (q < steps) {
+            issue_a(q, q);
+            load_b(q, bring[q]);
         }
-        const char* la = lds + buf * STAGE + rd;
+    // K block kb uses stage and B slot kb % NST; the loop is unrolled NST
+    // times so both are compile-time constants.
+    auto step = [&](auto slot, i64 kb) __attribute__((always_inline)) {
+        constexpr int J = decltype(slot)::value;
+        // this block's A has landed in LDS (own loads; the later blocks'
+        // loads may still be in flight) and B in registers; after the
+        // barrier every wave's A has landed and every wave is done with the
+        // stage the loads issued next overwrite
+        const i64 ahead = (steps - 1 - kb) < (NST - 2) ? (steps - 1 - kb) : (NST - 2);
+        if (NST >= 4 && ahead >= 2) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * PER_BLOCK) : "memory");
+        else if (NST >= 3 && ahead >= 1) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(PER_BLOCK) : "memory");
+        else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (kb + NST - 1 < steps) {
+            issue_a(kb + NST - 1, (J + NST - 1) % NST);
+            load_b(kb + NST - 1, bring[(J + NST - 1) % NST]);
+        }
+        const char* la = lds + J * STAGE + rd;
 #pragma unroll
         for (int t = 0; t < S; ++t)
 #pragma unroll
             for (int i = 0; i < WBM; ++i) {
                 const u32x4 a = *reinterpret_cast<const u32x4*>(la + (t * WBM + i) * 1024);
 #pragma unroll
-                for (int u = 0; u + t < S; ++u) acc[t + u][i] = Mfma<DT>::run(a, bcur[u], acc[t + u][i]);
+                for (int u = 0; u + t < S; ++u) acc[t + u][i] = Mfma<DT>::run(a, bring[J][u], acc[t + u][i]);
             }
+        if (MMM_SPLIT_SCHED > 0 && S >= MMM_SPLIT_SCHED) sched_digit_pairs<S, WBM>();
         if (FLUSH) {
             if (++since_flush == flush_steps) {
                 since_flush = 0;
@@ -398,6 +447,12 @@ __device__ __forceinline__ void split_tile(const char* __restrict__ SA, const ch
                     }
             }
         }
+    };
+    for (i64 kb = 0; kb < steps; kb += NST) {
+        step(std::integral_constant<int, 0>(), kb);
+        if (kb + 1 < steps) step(std::integral_constant<int, 1>(), kb + 1);
+        if (NST >= 3 && kb + 2 < steps) step(std::integral_constant<int, (NST >= 3 ? 2 : 0)>(), kb + 2);
+        if (NST >= 4 && kb + 3 < steps) step(std::integral_constant<int, (NST >= 4 ? 3 : 0)>(), kb + 3);
     }
 
     // c = sum over g = S+1 .. 2 of 2^(-beta g) G_g, then scale by 2^(e_i + f_j)
@@ -419,7 +474,7 @@ __device__ __forceinline__ void split_tile(const char* __restrict__ SA, const ch
 }
 
 template <int DT, int S, bool FLUSH>
-__global__ __launch_bounds__(256, tile_cfg(DT, S, FLUSH).minw) void split_gemm_kernel(const char* __restrict__ SA, const char* __restrict__ SB,
+__global__ __launch_bounds__(tile_cfg(DT, S, FLUSH).threads(), tile_cfg(DT, S, FLUSH).minw) void split_gemm_kernel(const char* __restrict__ SA, const char* __restrict__ SB,
                                                          const int* __restrict__ ea, const int* __restrict__ fb,
                                                          double* __restrict__ C, i64 N, i64 M, i64 Np, i64 Mp,
                                                          i64 Kp, i64 tiles_m, i64 tiles_n, int flush_steps)
@@ -432,14 +487,14 @@ __global__ __launch_bounds__(256, tile_cfg(DT, S, FLUSH).minw) void split_gemm_k
     const i64 grp = b / (8 * tiles_n), first = grp * 8;
     const i64 gs = (tiles_m - first) < 8 ? (tiles_m - first) : 8;
     const i64 w = b - grp * 8 * tiles_n;
-    split_tile<DT, S, FLUSH, tile_cfg(DT, S, FLUSH).wbm>(SA, SB, ea, fb, C, N, M, Np, Mp, Kp, first + w % gs, w / gs,
+    split_tile<DT, S, FLUSH, tile_cfg(DT, S, FLUSH).wbm, tile_cfg(DT, S, FLUSH).nw, tile_cfg(DT, S, FLUSH).stages>(SA, SB, ea, fb, C, N, M, Np, Mp, Kp, first + w % gs, w / gs,
                                                           flush_steps, lds);
 }
 
 // Persistent grid over the tiles of a group of split jobs (same digit type
 // and count): tile t is job p's (t - prefix[p])-th tile, row-major.
 template <int DT, int S, bool FLUSH>
-__global__ __launch_bounds__(256, grouped_tile_cfg(DT, S, FLUSH).minw) void split_gemm_grouped_kernel(const SplitJob* __restrict__ jobs,
+__global__ __launch_bounds__(grouped_tile_cfg(DT, S, FLUSH).threads(), grouped_tile_cfg(DT, S, FLUSH).minw) void split_gemm_grouped_kernel(const SplitJob* __restrict__ jobs,
                                                                  const i64* __restrict__ prefix, int njobs, i64 total,
                                                                  int flush_steps)
 {
@@ -455,7 +510,7 @@ __global__ __launch_bounds__(256, grouped_tile_cfg(DT, S, FLUSH).minw) void spli
         const SplitJob& j = jobs[lo];
         const i64 local = t - prefix[lo];
         const i64 tiles_n = j.Mp / TC.bn();
-        split_tile<DT, S, FLUSH, TC.wbm>(j.SA, j.SB, j.ea, j.fb, j.C, j.N, j.M, j.Np, j.Mp, j.Kp, local / tiles_n,
+        split_tile<DT, S, FLUSH, TC.wbm, TC.nw, TC.stages>(j.SA, j.SB, j.ea, j.fb, j.C, j.N, j.M, j.Np, j.Mp, j.Kp, local / tiles_n,
                                  local % tiles_n, flush_steps, lds);
         __syncthreads();
     }
@@ -549,8 +604,8 @@ struct SplitLayout {
 
 size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
-// two stages of the A digit planes (S x BM rows x 64 bytes)
-size_t split_lds_bytes(const TileCfg& tc, int s) { return (size_t)2 * s * tc.bm() * KB; }
+// the LDS stages of the A digit planes (S x BM rows x 64 bytes each)
+size_t split_lds_bytes(const TileCfg& tc, int s) { return (size_t)tc.stages * s * tc.bm() * KB; }
 
 // exact-accumulation budget: digit products are at most 2^(2 beta - 2);
 // a group of at most s pairs over kb entries must stay below the budget.
@@ -610,7 +665,7 @@ hipError_t launch_split_gemm(const SplitLayout& L, char* ws, double* C, i64 N, i
     auto kern = split_gemm_kernel<DT, S, FLUSH>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), lds, st, (const char*)(ws + L.SA),
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(TC.threads()), lds, st, (const char*)(ws + L.SA),
                        (const char*)(ws + L.SB), (const int*)(ws + L.ea), (const int*)(ws + L.fb), C, N, M, L.Np, L.Mp,
                        L.Kp, tiles_m, tiles_n, flush_steps);
     return hipGetLastError();
@@ -682,7 +737,7 @@ hipError_t launch_grouped_gemm(const SplitJob* jobs, const i64* prefix, int n, i
     const size_t lds = split_lds_bytes(TC, S);
     auto kern = split_gemm_grouped_kernel<DT, S, FLUSH>;
     if (!jobs) return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, st, jobs, prefix, n, total, flush_steps);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(TC.threads()), lds, st, jobs, prefix, n, total, flush_steps);
     return hipGetLastError();
 }
 
@@ -791,6 +846,7 @@ size_t split_job_bytes(i64 N, i64 P, i64 M, int dt, int s, SplitGroup& grp, i64&
     grp.flush_steps = fs;
     grp.bm = tc.bm();
     grp.bn = tc.bn();
+    grp.per_cu = tc.minw * 4 / tc.nw > 0 ? tc.minw * 4 / tc.nw : 1;
     Np = L.Np;
     Mp = L.Mp;
     Kp = L.Kp;
