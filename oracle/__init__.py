@@ -41,6 +41,8 @@ def _load():
         "oracle_naive": (None, [dp, dp, dp, i64, i64, i64]),
         "oracle_naive_rows": (None, [dp, dp, dp, i64, i64, i64, dp, i64]),
         "oracle_kahan": (None, [dp, dp, dp, i64, i64, i64]),
+        "oracle_naive_on_array": (None, [dp, dp, dp, i64, i64, i64]),
+        "oracle_naive_unroll": (None, [dp, dp, dp, i64, i64, i64, ctypes.c_int]),
         "oracle_kahan_rows": (None, [dp, dp, dp, i64, i64, i64, dp, i64]),
         "oracle_winograd_rows": (None, [dp, dp, dp, i64, i64, i64, dp, i64, ctypes.c_int]),
         "oracle_winograd": (None, [dp, dp, dp, i64, i64, i64, dp, dp]),
@@ -147,6 +149,27 @@ def naive_rows(A, B, rows):
     out = np.empty((r.size, M))
     _load().oracle_naive_rows(_p(A), _p(B), _p(out), N, P, M, _p(r), r.size)
     return out
+
+
+def naive_on_array(A, B):
+    """Section 2.1.2 (NaivOnArray): the naive sum kept in the result entry itself."""
+    A, B = _f64(A), _f64(B)
+    N, P, M = _shape(A, B)
+    C = np.empty((N, M))
+    _load().oracle_naive_on_array(_p(A), _p(B), _p(C), N, P, M)
+    return C
+
+
+def naive_unroll(A, B, q):
+    """Section 2.2 (NaivLoopUnrollingTwo/Three/Four for q = 2/3/4): products
+    summed q at a time, each group sum added to the running sum; the P mod q
+    leftover products added one at a time afterwards."""
+    assert q in (2, 3, 4)
+    A, B = _f64(A), _f64(B)
+    N, P, M = _shape(A, B)
+    C = np.empty((N, M))
+    _load().oracle_naive_unroll(_p(A), _p(B), _p(C), N, P, M, q)
+    return C
 
 
 def kahan(A, B):

@@ -136,6 +136,47 @@ void oracle_naive_rows(const double* A, const double* B, double* out, i64 N, i64
     }
 }
 
+/* Section 2.1.2 (NaivOnArray): the same sum accumulated directly in the
+ * entry of the result array instead of an auxiliary variable: the entry is
+ * set to 0.0 and every product is added to it in place, k ascending.  Each
+ * step rounds exactly as in NaivStandard; only where the running sum lives
+ * differs. */
+void oracle_naive_on_array(const double* A, const double* B, double* C, i64 N, i64 P, i64 M)
+{
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (N * P * M > 32768)
+    for (i64 i = 0; i < N; ++i) {
+        for (i64 j = 0; j < M; ++j) {
+            C[i * M + j] = 0.0;
+            for (i64 k = 0; k < P; ++k) C[i * M + j] = C[i * M + j] + A[i * P + k] * B[k * M + j];
+        }
+    }
+}
+
+/* Section 2.2 (NaivLoopUnrollingTwo, -Three, -Four; q = 2, 3, 4): the k
+ * range is taken q consecutive indices at a time; the q products of a group
+ * are summed left to right, p_1 + p_2 (+ p_3 (+ p_4)), and that group sum
+ * is added to the auxiliary variable.  When q does not divide P the
+ * remaining P mod q products are added to the variable after the grouped
+ * sum, one at a time in ascending k (for q = 2 this is the paper's odd-P
+ * formula; for q = 3, 4 it is the reading of its "correction terms"). */
+void oracle_naive_unroll(const double* A, const double* B, double* C, i64 N, i64 P, i64 M, int q)
+{
+    const i64 full = (P / q) * q;
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (N * P * M > 32768)
+    for (i64 i = 0; i < N; ++i) {
+        for (i64 j = 0; j < M; ++j) {
+            double aux = 0.0;
+            for (i64 k = 0; k < full; k += q) {
+                double grp = A[i * P + k] * B[k * M + j];
+                for (int r = 1; r < q; ++r) grp = grp + A[i * P + k + r] * B[(k + r) * M + j];
+                aux = aux + grp;
+            }
+            for (i64 k = full; k < P; ++k) aux = aux + A[i * P + k] * B[k * M + j];
+            C[i * M + j] = aux;
+        }
+    }
+}
+
 /* Section 2.1.3 (NaivKahan): the naive sum with Kahan's compensation in the
  * form the paper prints: with x = A_ik * B_kj rounded on its own,
  *   err = err + x;  t = sum + err;  err = (sum - t) + err;  sum = t;

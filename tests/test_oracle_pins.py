@@ -39,6 +39,10 @@ def _methods(orc):
         "kahan": orc.kahan,
         "winograd": orc.winograd,
         "winograd_scaled": orc.winograd_scaled,
+        "naive_on_array": orc.naive_on_array,
+        "unroll2": lambda A, B: orc.naive_unroll(A, B, 2),
+        "unroll3": lambda A, B: orc.naive_unroll(A, B, 3),
+        "unroll4": lambda A, B: orc.naive_unroll(A, B, 4),
         "split_bf16_s1": lambda A, B: orc.split_model(A, B, 1, 8),
         "split_bf16_s6": lambda A, B: orc.split_model(A, B, 6, 8),
         "split_fp16_s4": lambda A, B: orc.split_model(A, B, 4, 10),
@@ -290,7 +294,11 @@ def test_paper_error_tables(orc):
     to the printed tenth decimal within a factor 1.5."""
     with open(os.path.join(GOLDEN, "paper_tables.json")) as f:
         tables = json.load(f)["tables"]
-    names = {"NaivStandard": orc.naive, "WinogradOriginal": orc.winograd,
+    names = {"NaivStandard": orc.naive, "NaivOnArray": orc.naive_on_array,
+             "NaivLoopUnrollingTwo": lambda A, B: orc.naive_unroll(A, B, 2),
+             "NaivLoopUnrollingThree": lambda A, B: orc.naive_unroll(A, B, 3),
+             "NaivLoopUnrollingFour": lambda A, B: orc.naive_unroll(A, B, 4),
+             "WinogradOriginal": orc.winograd,
              "WinogradScaled": orc.winograd_scaled,
              "StrassenNaiv": lambda A, B: orc.strassen(A, B, 0, orc.MODE_PAPER),
              "StrassenWinograd": lambda A, B: orc.strassen(A, B, 1, orc.MODE_PAPER)}
@@ -423,3 +431,60 @@ def test_thread_count_does_not_change_bits(orc):
     Bo = synth.uniform((91, 60), 4) * 64.0
     assert np.array_equal(orc.winograd_rows(Ao, Bo, rows, scaled=True), orc.winograd_scaled(Ao, Bo)[rows])
     assert np.array_equal(orc.split_model_rows(A, B, rows, 4, 8), orc.split_model(A, B, 4, 8)[rows])
+
+
+def test_unrolled_sums_worked_examples(orc):
+    """Section 2.2 groupings worked by hand with u = 2^-53 against a column
+    of ones.  1 + u is a tie between 1 and 1 + 2u and rounds to 1 (even).
+      Two,  a = [1,u,u,u]:        (1+u) -> 1;  (u+u) = 2u;  1 + 2u exact
+                                   -> 1 + 2^-52   (NaivStandard: 1)
+      Three, a = [1,u,u,u,u,u]:   ((1+u)+u) -> 1;  (u+u)+u = 3u;  1 + 3u is a
+                                   tie between 1 + 2u and 1 + 4u -> 1 + 4u = 1 + 2^-51
+      Four, a = [1,u,...,u] (P=8): 1;  4u;  1 + 4u exact -> 1 + 2^-51
+    Leftover products go one at a time (reading of the correction terms):
+      Four, a = [1,u,u,u,u,u] (P=6): group -> 1, then 1 + u -> 1 twice -> 1
+      (a grouped tail would give 1 + (u+u) = 1 + 2^-52);
+      Three, a = [1,u,u,u,u] (P=5): group -> 1, then 1 -> 1 -> 1.
+    NaivOnArray rounds exactly like NaivStandard."""
+    def run(f, row):
+        a = np.array([row])
+        return f(a, np.ones((a.shape[1], 1)))[0, 0]
+
+    u = U
+    one_u = [1.0] + [u] * 3
+    assert run(orc.naive, one_u) == 1.0
+    assert run(lambda A, B: orc.naive_unroll(A, B, 2), one_u) == 1.0 + 2.0 ** -52
+    assert run(lambda A, B: orc.naive_unroll(A, B, 3), [1.0] + [u] * 5) == 1.0 + 2.0 ** -51
+    assert run(lambda A, B: orc.naive_unroll(A, B, 4), [1.0] + [u] * 7) == 1.0 + 2.0 ** -51
+    assert run(lambda A, B: orc.naive_unroll(A, B, 4), [1.0] + [u] * 5) == 1.0
+    assert run(lambda A, B: orc.naive_unroll(A, B, 3), [1.0] + [u] * 4) == 1.0
+    for row in (one_u, [u, u, 1.0], [1.0] + [u] * 7):
+        assert run(orc.naive_on_array, row) == run(orc.naive, row)
+
+
+def test_unrolled_sums_bounds_against_rationals(orc):
+    """All N, P, M in 1..6, random doubles: every summation order of Section
+    2.1/2.2 obeys |C^ - C| <= gamma_{P+1} |A||B| elementwise (no term passes
+    through more than P + 1 roundings: its product, at most q - 1 group
+    additions and at most ceil(P/q) + (P mod q) accumulations).  Where no
+    full group exists (P < q) the grouped method is the plain sequential sum,
+    and for P = q it is one group sum added to 0: both equal NaivStandard
+    bit for bit; NaivOnArray always does."""
+    rng = np.random.default_rng(12)
+    for N in range(1, 4):
+        for P in range(1, 7):
+            for M in range(1, 4):
+                A = rng.uniform(-1, 1, (N, P)) * 2.0 ** rng.integers(-3, 4, (N, P))
+                B = rng.uniform(-1, 1, (P, M)) * 2.0 ** rng.integers(-3, 4, (P, M))
+                Cn = orc.naive(A, B)
+                assert np.array_equal(orc.naive_on_array(A, B), Cn)
+                g = Fraction((P + 1) * U) / (1 - Fraction((P + 1) * U))
+                for q in (2, 3, 4):
+                    Cq = orc.naive_unroll(A, B, q)
+                    if P <= q:
+                        assert np.array_equal(Cq, Cn), (P, q)
+                    for i in range(N):
+                        for j in range(M):
+                            ex = sum(Fraction(A[i, k]) * Fraction(B[k, j]) for k in range(P))
+                            ab = sum(abs(Fraction(A[i, k]) * Fraction(B[k, j])) for k in range(P))
+                            assert abs(Fraction(Cq[i, j]) - ex) <= g * ab, (P, q)
