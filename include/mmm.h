@@ -59,7 +59,11 @@ typedef enum {
     MMM_STRASSEN_WINOGRAD = 5, /* 2.4.2 StrassenWinograd: 7 products, 15 additions per level */
     MMM_DGEMM = 6,             /* the definition of 2.1 evaluated on FP64 matrix cores */
     MMM_SPLIT = 7,             /* FP64 product from exact low-precision digit products */
-    MMM_METHOD_COUNT = 8
+    MMM_NAIVE_ON_ARRAY = 8,    /* 2.1.2 NaivOnArray: the naive sum kept in the entry of C itself */
+    MMM_NAIVE_UNROLL2 = 9,     /* 2.2.1 NaivLoopUnrollingTwo: products summed in pairs, pair sums accumulated */
+    MMM_NAIVE_UNROLL3 = 10,    /* 2.2.2 NaivLoopUnrollingThree: in groups of three */
+    MMM_NAIVE_UNROLL4 = 11,    /* 2.2.3 NaivLoopUnrollingFour: in groups of four */
+    MMM_METHOD_COUNT = 12
 } mmm_method;
 
 /* Strassen embedding.  PAPER: the square Y x Y zero embedding of Section

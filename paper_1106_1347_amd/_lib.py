@@ -24,6 +24,10 @@ METHODS = {
     "strassen_winograd": 5,
     "dgemm": 6,
     "split": 7,
+    "naive_on_array": 8,
+    "naive_unroll2": 9,
+    "naive_unroll3": 10,
+    "naive_unroll4": 11,
 }
 PAD_MODES = {"paper": 0, "levels": 1}
 LEAVES = {"dgemm": 0, "naive": 1}

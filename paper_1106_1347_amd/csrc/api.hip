@@ -280,6 +280,10 @@ size_t mmm_workspace_bytes(mmm_method method, int64_t N, int64_t P, int64_t M, c
     case MMM_NAIVE:
     case MMM_KAHAN:
     case MMM_DGEMM:
+    case MMM_NAIVE_ON_ARRAY:
+    case MMM_NAIVE_UNROLL2:
+    case MMM_NAIVE_UNROLL3:
+    case MMM_NAIVE_UNROLL4:
         return 0;
     case MMM_WINOGRAD:
         return wino_layout(N, M, false).bytes;
@@ -333,6 +337,12 @@ mmm_status mmm_multiply(const double* A, const double* B, double* C, int64_t N, 
         return from_hip(launch_naive(g, c.naive_fma != 0, s), "naive");
     case MMM_KAHAN:
         return from_hip(launch_kahan(g, s), "kahan");
+    case MMM_NAIVE_ON_ARRAY:
+        return from_hip(launch_naive_variant(g, 0, s), "naive on array");
+    case MMM_NAIVE_UNROLL2:
+    case MMM_NAIVE_UNROLL3:
+    case MMM_NAIVE_UNROLL4:
+        return from_hip(launch_naive_variant(g, 2 + (int)(method - MMM_NAIVE_UNROLL2), s), "naive unrolled");
     case MMM_DGEMM:
         return from_hip(launch_dgemm(g, s), "dgemm");
     case MMM_WINOGRAD:

@@ -12,13 +12,17 @@
 // Tiling: 256 threads (16 x 16) per workgroup own a BM x BN tile of C
 // (128 x 64 for the naive and Winograd loops, 64 x 64 for Kahan, whose state
 // is two doubles per entry), each thread a TM x TN register block (rows ty*TM + i, columns h*BN/2 +
-// tx*TN/2 + j).  K advances in steps of 16 through double-buffered LDS
-// tiles: the A tile is stored k-major so a thread reads its TM rows as one
+// tx*TN/2 + j).  K advances in steps of 16 (32 for Kahan) through LDS tiles:
+// the A tile is stored k-major so a thread reads its TM rows as one
 // contiguous run, the B tile row-major.  With PREFETCH the global loads of
 // step t+1 are issued before the arithmetic of step t and held in registers;
 // without it each step's tile is loaded and stored before the arithmetic
-// (fewer registers, more resident waves to hide the latency).  Tiles that lie
-// inside the matrices take a path without bounds checks.
+// (fewer registers, more resident waves to hide the latency).  Within a step
+// each operation of the recurrence is issued for a whole row (Winograd) or
+// the whole register block (naive, Kahan) before the next one, so the FP64
+// pipeline sees independent chains; the per-entry order of operations, and
+// hence every rounding, is unchanged.  Tiles that lie inside the matrices
+// take a path without bounds checks.
 #include <type_traits>
 
 #include "common.h"
@@ -42,15 +46,35 @@
 #ifndef MMM_VALU_MINWAVES
 #define MMM_VALU_MINWAVES 2
 #endif
+#ifndef MMM_VALU_BK
+#define MMM_VALU_BK 16
+#endif
+#ifndef MMM_VALU_KAHAN_BK
+#define MMM_VALU_KAHAN_BK 32
+#endif
+// evaluate each operation of a step for a whole row / block of entries
+// before the next (independent chains for the FP64 pipeline)
+#ifndef MMM_VALU_ILP
+#define MMM_VALU_ILP 1
+#endif
 
 namespace mmm {
 
 namespace {
 
-constexpr int BK = 16;
 constexpr int NT = 256;
 
-enum Op { OP_NAIVE = 0, OP_NAIVE_FMA = 1, OP_KAHAN = 2, OP_WINOGRAD = 3 };
+enum Op {
+    OP_NAIVE = 0,
+    OP_NAIVE_FMA = 1,
+    OP_KAHAN = 2,
+    OP_WINOGRAD = 3,
+    OP_UNROLL2 = 4,  // NaivLoopUnrollingTwo / Three / Four
+    OP_UNROLL3 = 5,
+    OP_UNROLL4 = 6,
+    OP_ON_ARRAY = 7  // NaivOnArray
+};
+__host__ __device__ constexpr int unroll_q(int op) { return op == OP_UNROLL2 ? 2 : (op == OP_UNROLL3 ? 3 : (op == OP_UNROLL4 ? 4 : 0)); }
 
 __device__ inline i64 xcd_remap(i64 b, i64 total)
 {
@@ -78,12 +102,15 @@ __device__ inline void tile_of(i64 b, i64 tiles_m, i64 tiles_n, i64& prob, i64& 
 
 template <int BM, int BN, int TM, int TN, int OP, bool SCALED>
 struct ValuTile {
+    // K per LDS step; a multiple of the group length of the unrolled sums
+    static constexpr int BK = OP == OP_KAHAN ? MMM_VALU_KAHAN_BK : (OP == OP_UNROLL3 ? 24 : MMM_VALU_BK);
+    static constexpr int Q = unroll_q(OP);
     static_assert((BM / TM) * (BN / TN) == NT, "256 threads");
     static_assert(BM / TM == 16 && BN / TN == 16, "16 x 16 thread grid");
     static constexpr int LA = BM * BK / NT;  // A elements each thread moves per step
     static constexpr int LB = BK * BN / NT;
     static constexpr int TH = TN / 2;        // columns per half
-    static constexpr int KSTEP = (OP == OP_WINOGRAD) ? 2 : 1;
+    static constexpr int KSTEP = (OP == OP_WINOGRAD) ? 2 : (Q ? Q : 1);
 
     static constexpr int NBUF = MMM_VALU_PREFETCH ? 2 : 1;
     struct Smem {
@@ -167,6 +194,23 @@ struct ValuTile {
                 frag_a(buf, k + 1, a1);
                 frag_b(buf, k, b0);
                 frag_b(buf, k + 1, b1);
+                if (MMM_VALU_ILP) {
+                    // one row of the register block at a time, each
+                    // operation for all its columns before the next
+#pragma unroll
+                    for (int i = 0; i < TM; ++i) {
+                        double u[TN], v[TN], w[TN];
+#pragma unroll
+                        for (int j = 0; j < TN; ++j) u[j] = a0[i] + b1[j];
+#pragma unroll
+                        for (int j = 0; j < TN; ++j) v[j] = a1[i] + b0[j];
+#pragma unroll
+                        for (int j = 0; j < TN; ++j) w[j] = u[j] * v[j];
+#pragma unroll
+                        for (int j = 0; j < TN; ++j) acc[i][j] = acc[i][j] + w[j];
+                    }
+                    return;
+                }
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -176,15 +220,77 @@ struct ValuTile {
                         const double w = u * v;
                         acc[i][j] = acc[i][j] + w;
                     }
+            } else if (Q) {
+                // a group of Q consecutive k: (p_1 + p_2 (+ p_3 (+ p_4))) summed
+                // left to right, then added to the running sum
+                double a[Q ? Q : 1][TM], b[Q ? Q : 1][TN];
+#pragma unroll
+                for (int r = 0; r < Q; ++r) {
+                    frag_a(buf, k + r, a[r]);
+                    frag_b(buf, k + r, b[r]);
+                }
+#pragma unroll
+                for (int i = 0; i < TM; ++i) {
+                    double grp[TN];
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) grp[j] = a[0][i] * b[0][j];
+#pragma unroll
+                    for (int r = 1; r < Q; ++r)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j) {
+                            const double x = a[r][i] * b[r][j];
+                            grp[j] = grp[j] + x;
+                        }
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) acc[i][j] = acc[i][j] + grp[j];
+                }
             } else {
                 double a[TM], b[TN];
                 frag_a(buf, k, a);
                 frag_b(buf, k, b);
+                if (MMM_VALU_ILP && OP == OP_KAHAN) {
+                    // each operation of the recurrence for all entries of
+                    // the register block before the next
+                    double x[TM][TN], e[TM][TN], t[TM][TN];
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j) x[i][j] = a[i] * b[j];
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j) e[i][j] = cmp[i][j] + x[i][j];
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j) t[i][j] = acc[i][j] + e[i][j];
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j) {
+                            cmp[i][j] = (acc[i][j] - t[i][j]) + e[i][j];
+                            acc[i][j] = t[i][j];
+                        }
+                    return;
+                }
+                if (MMM_VALU_ILP && (OP == OP_NAIVE || OP == OP_ON_ARRAY)) {
+                    // all products of the step first, then the sums
+                    double x[TM][TN];
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j) x[i][j] = a[i] * b[j];
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j) acc[i][j] = acc[i][j] + x[i][j];
+                    return;
+                }
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
 #pragma unroll
                     for (int j = 0; j < TN; ++j) {
-                        if (OP == OP_NAIVE) {
+                        if (OP == OP_NAIVE || OP == OP_ON_ARRAY) {
                             const double x = a[i] * b[j];
                             acc[i][j] = acc[i][j] + x;
                         } else if (OP == OP_NAIVE_FMA) {
@@ -212,6 +318,26 @@ struct ValuTile {
             }
         };
         auto need_check = [&](i64 t) __attribute__((always_inline)) { return CHECK || (t + 1) * BK > kmax; };
+        // NaivOnArray: the running sum lives in the entries of C; every K
+        // step reads them and writes them back (the first step starts from
+        // the zeroed entries)
+        auto c_io = [&](bool store) __attribute__((always_inline)) {
+            if (OP != OP_ON_ARRAY) return;
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const i64 gm = m0 + ty * TM + i;
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int j = 0; j < TH; ++j) {
+                        const i64 gn = n0 + h * (BN / 2) + tx * TH + j;
+                        if (CHECK && (gm >= g.N || gn >= g.M)) continue;
+                        if (store) g.C[gm * g.ldc + gn] = acc[i][h * TH + j];
+                        else acc[i][h * TH + j] = g.C[gm * g.ldc + gn];
+                    }
+            }
+        };
+        if (OP == OP_ON_ARRAY) c_io(true);  // C = 0
 
         if (MMM_VALU_PREFETCH) {
             if (ntiles > 0) {
@@ -222,7 +348,9 @@ struct ValuTile {
             for (i64 t = 0; t < ntiles; ++t) {
                 const int cur = (int)(t & 1);
                 if (t + 1 < ntiles) gload(t + 1, need_check(t + 1));
+                c_io(false);
                 compute(cur, t);
+                c_io(true);
                 if (t + 1 < ntiles) lstore(cur ^ 1);
                 __syncthreads();
             }
@@ -232,7 +360,9 @@ struct ValuTile {
                 __syncthreads();  // the previous step's reads of the buffer are done
                 lstore(0);
                 __syncthreads();
+                c_io(false);
                 compute(0, t);
+                c_io(true);
             }
         }
     }
@@ -242,7 +372,8 @@ struct ValuTile {
     {
         const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
         const i64 m0 = tm * BM, n0 = tn * BN;
-        const i64 kmax = (OP == OP_WINOGRAD) ? 2 * (g.P / 2) : g.P;
+        // the grouped part of the k range; the rest is added in the epilogue
+        const i64 kmax = (OP == OP_WINOGRAD) ? 2 * (g.P / 2) : (Q ? Q * (g.P / Q) : g.P);
         double sa = 1.0, sb = 1.0;
         if (SCALED) {
             const int l = *lam;
@@ -277,6 +408,13 @@ struct ValuTile {
                     const i64 gn = n0 + h * (BN / 2) + tx * TH + j;
                     if (gn >= g.M) continue;
                     double c = acc[i][h * TH + j];
+                    if (Q) {
+                        // leftover P mod Q products, one at a time, k ascending
+                        for (i64 k = kmax; k < g.P; ++k) {
+                            const double x = g.A[gm * g.lda + k] * g.B[k * g.ldb + gn];
+                            c = c + x;
+                        }
+                    }
                     if (OP == OP_WINOGRAD) {
                         c = (c - yi) - zv[gn];
                         if (odd) {
@@ -332,7 +470,11 @@ template <int OP, class Src>
 hipError_t launch_naive_like(const Src& src, i64 N, i64 M, hipStream_t s)
 {
     if (N <= 48 && M <= 48) return launch_valu<32, 32, 2, 2, OP, false>(src, N, M, nullptr, nullptr, nullptr, s);
-    typedef typename std::conditional<OP == OP_KAHAN, KahanShape, NaiveShape>::type S;
+    // Kahan keeps two doubles per entry, the longer groups and the on-array
+    // round trips more operands in flight: 64 x 64 tiles for those
+    constexpr bool small = OP == OP_KAHAN || OP == OP_UNROLL3 || OP == OP_UNROLL4 || OP == OP_ON_ARRAY;
+    typedef typename std::conditional<OP == OP_KAHAN, KahanShape,
+                                      typename std::conditional<small, Shape<64, 64, 4, 4>, NaiveShape>::type>::type S;
     return launch_valu<S::bm, S::bn, S::tm, S::tn, OP, false>(src, N, M, nullptr, nullptr, nullptr, s);
 }
 
@@ -348,6 +490,18 @@ hipError_t launch_naive_strassen_leaves(const StrassenLeafSrc& src, hipStream_t 
 {
     const int d = src.T.depth;
     return launch_naive_like<OP_NAIVE>(src, src.T.n[d], src.T.m[d], s);
+}
+
+hipError_t launch_naive_variant(const Gemm& g, int variant, hipStream_t s)
+{
+    SingleSrc src{g};
+    switch (variant) {
+    case 0: return launch_naive_like<OP_ON_ARRAY>(src, g.N, g.M, s);
+    case 2: return launch_naive_like<OP_UNROLL2>(src, g.N, g.M, s);
+    case 3: return launch_naive_like<OP_UNROLL3>(src, g.N, g.M, s);
+    case 4: return launch_naive_like<OP_UNROLL4>(src, g.N, g.M, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_kahan(const Gemm& g, hipStream_t s)

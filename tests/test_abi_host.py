@@ -118,3 +118,23 @@ def test_batch_validation_before_any_allocation(lib):
     bad2 = P(A=0x40000, B=0x50000, C=0x30010, N=2, P=2, M=2, method=7)
     assert f(arr(ok, bad2), 2, r(c), None, r(h)) == 2
     assert h.value is None
+
+
+def test_papertest_inputs_and_layout(lib):
+    """Host side of the paper's test program: its inputs are the shared
+    generator's (A ~ U[0,1), B = 8A exactly) and the table keeps the
+    paper's columns and row order."""
+    import synth
+    from paper_1106_1347_amd import papertest
+
+    A, B = papertest.paper_inputs(17, 3)
+    A2, B2 = synth.paper_test_pair(17, 3)
+    assert (A == A2).all() and (B == B2).all() and (B == 8.0 * A).all()
+    assert [r[0] for r in papertest.PAPER_ROWS] == [
+        "NaivStandard", "NaivOnArray", "NaivLoopUnrollingTwo", "NaivLoopUnrollingThree", "NaivLoopUnrollingFour",
+        "StrassenNaiv", "StrassenWinograd", "WinogradOriginal", "WinogradScaled"]
+    res = {"n": 5, "rows": [{"label": "N := NaivKahan", "seconds": 0.5, "err": None},
+                            {"label": "NaivStandard", "seconds": 0.25, "err": 1e-10}]}
+    lines = papertest.format_table(res).splitlines()
+    assert len({len(l) for l in lines}) == 1  # a rectangular box
+    assert "0.0000000001" in lines[-2] and lines[-3].split("|")[3].strip() == ""

@@ -105,6 +105,7 @@ def test_integer_inputs_exact_every_method(mmm, shape):
     B = synth.integers((P, M), 302)
     ref = (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float64)
     cfgs = {"naive": [None, mmm.Config(naive_fma=True)], "kahan": [None], "winograd": [None],
+            "naive_on_array": [None], "naive_unroll2": [None], "naive_unroll3": [None], "naive_unroll4": [None],
             "winograd_scaled": [None], "dgemm": [None],
             "strassen_naive": [mmm.Config(strassen_levels=L) for L in (1, 2, 3)] + [mmm.Config(pad_mode="paper")],
             "strassen_winograd": [mmm.Config(strassen_levels=L) for L in (1, 2, 3)] + [mmm.Config(pad_mode="paper")]}
@@ -148,8 +149,31 @@ def test_lambda_on_device(mmm, orc):
         assert mmm.winograd_lambda(na, nb).item() == orc.winograd_lambda(a, b), (a, b)
 
 
+VARIANTS = ("naive_on_array", "naive_unroll2", "naive_unroll3", "naive_unroll4")
+
+
+def _variant_ref(orc, name, A, B):
+    if name == "naive_on_array":
+        return orc.naive_on_array(A, B)
+    return orc.naive_unroll(A, B, int(name[-1]))
+
+
+@pytest.mark.parametrize("shape", SHAPES + [(70, 50, 90), (65, 97, 66), (130, 100, 129), (48, 47, 48)])
+def test_naive_variants_bitwise(mmm, orc, shape):
+    """NaivOnArray and NaivLoopUnrollingTwo/Three/Four (Sections 2.1.2, 2.2):
+    bit for bit the oracle's evaluation order, including the leftover P mod q
+    products and tiles that straddle the matrix edges."""
+    N, P, M = shape
+    print("case", shape, flush=True)
+    A = synth.uniform((N, P), 111 + N)
+    B = synth.uniform((P, M), 112 + M)
+    for name in VARIANTS:
+        assert bits_equal(run(mmm, A, B, name), _variant_ref(orc, name, A, B)), name
+
+
 def test_zero_sizes(mmm):
-    for method in ("naive", "kahan", "winograd", "winograd_scaled", "strassen_naive", "strassen_winograd", "dgemm"):
+    for method in ("naive", "kahan", "winograd", "winograd_scaled", "strassen_naive", "strassen_winograd", "dgemm",
+                   *VARIANTS):
         A = torch.zeros((5, 0), dtype=torch.float64, device="cuda")
         B = torch.zeros((0, 4), dtype=torch.float64, device="cuda")
         C = torch.full((5, 4), 7.0, dtype=torch.float64, device="cuda")
@@ -163,7 +187,8 @@ def test_zero_sizes(mmm):
 def test_deterministic_bits(mmm):
     A = dev(synth.uniform((300, 211), 5))
     B = dev(synth.uniform((211, 190), 6))
-    for method in ("naive", "kahan", "winograd", "winograd_scaled", "dgemm", "strassen_winograd", "strassen_naive"):
+    for method in ("naive", "kahan", "winograd", "winograd_scaled", "dgemm", "strassen_winograd", "strassen_naive",
+                   *VARIANTS):
         c1 = mmm.multiply(A, B, method).cpu().numpy()
         c2 = mmm.multiply(A, B, method).cpu().numpy()
         assert bits_equal(c1, c2), method
@@ -196,6 +221,8 @@ def test_full_size_sampled_rows(mmm, orc, P):
     assert bits_equal(rows_of("winograd"), orc.winograd_rows(A, B, rows))
     assert bits_equal(rows_of("winograd_scaled"), orc.winograd_rows(A, B, rows, scaled=True))
     assert err(rows_of("dgemm")) <= TOL_PLAIN
+    for name in VARIANTS:  # rows of C depend only on the same rows of A
+        assert bits_equal(rows_of(name), _variant_ref(orc, name, A[rows], B)), name
     for L in (2, 3):
         for name in ("strassen_winograd", "strassen_naive"):
             assert err(rows_of(name, mmm.Config(strassen_levels=L))) <= TOL_STRASSEN, (name, L)
