@@ -100,6 +100,7 @@ def parse():
     ap.add_argument("--no-aux", action="store_true", help="skip the auxiliary-kernel bandwidth section")
     ap.add_argument("--no-batch", action="store_true", help="skip the 2048-problem batch section")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
+    ap.add_argument("--no-paper-test", action="store_true", help="skip the paper's test table (n = 800)")
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
@@ -231,6 +232,7 @@ def main():
     aux = None if args.no_aux else aux_section(mmm, torch, dev, stream)
     batch = None if args.no_batch else batch_section(mmm, torch, synth, dev, stream)
     serving = None if args.no_serve else serve_section(args, mmm, torch, synth, dev)
+    paper_test = None if args.no_paper_test else paper_test_section()
 
     results = {}
     for name, method, kw, cost, bound in methods:
@@ -290,6 +292,7 @@ def main():
         "aux_8192": aux,
         "batch_2048": batch,
         "serving": serving,
+        "paper_test_800": paper_test,
         "device": torch.cuda.get_device_name(0),
     }
     print(json.dumps(out), flush=True)
@@ -360,6 +363,16 @@ def _time(torch, stream, fn, reps):
         torch.cuda.synchronize()
         ms.append(e0.elapsed_time(e1))
     return float(np.median(ms))
+
+
+def paper_test_section():
+    """The paper's test program at n = 800, R = 10 (C = A (8A), N := NaivKahan):
+    per method the median time of one product and NormInf(N - C)."""
+    from paper_1106_1347_amd import papertest
+
+    res = papertest.run(n=800, repeats=10, seed=500)
+    return {"workload": "C = A (8A), A 800 x 800 ~ U[0,1) (seed 500), N := NaivKahan, R = 10",
+            "rows": {r["label"]: {"ms": 1e3 * r["seconds"], "norm_inf_n_minus_c": r["err"]} for r in res["rows"]}}
 
 
 def aux_section(mmm, torch, dev, stream):
