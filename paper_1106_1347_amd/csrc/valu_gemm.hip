@@ -1,5 +1,6 @@
 // Inner-product methods of Section 2 on the FP64 vector ALUs of gfx950:
-// NaivStandard (2.1.1), NaivKahan (2.1.3) and the main loop of
+// NaivStandard (2.1.1), NaivOnArray (2.1.2), NaivKahan (2.1.3),
+// NaivLoopUnrollingTwo/Three/Four (2.2) and the main loop of
 // WinogradOriginal (2.3.1, also used by WinogradScaled 2.3.2).
 //
 // Every output entry is owned by one lane, which runs the paper's recurrence
@@ -11,26 +12,31 @@
 //
 // Tiling: 256 threads (16 x 16) per workgroup own a BM x BN tile of C
 // (128 x 64 for the naive and Winograd loops, 64 x 64 for Kahan, whose state
-// is two doubles per entry), each thread a TM x TN register block (rows ty*TM + i, columns h*BN/2 +
-// tx*TN/2 + j).  K advances in steps of 16 (32 for Kahan) through LDS tiles:
-// the A tile is stored k-major so a thread reads its TM rows as one
-// contiguous run, the B tile row-major.  With PREFETCH the global loads of
-// step t+1 are issued before the arithmetic of step t and held in registers;
-// without it each step's tile is loaded and stored before the arithmetic
-// (fewer registers, more resident waves to hide the latency).  Within a step
-// each operation of the recurrence is issued for a whole row (Winograd) or
-// the whole register block (naive, Kahan) before the next one, so the FP64
-// pipeline sees independent chains; the per-entry order of operations, and
-// hence every rounding, is unchanged.  Tiles that lie inside the matrices
-// take a path without bounds checks.
+// is two doubles per entry), each thread a TM x TN register block (rows
+// ty*TM + i, columns h*BN/2 + tx*TN/2 + j).  K advances in steps of 16 (32
+// for Kahan, 24 for groups of three) through LDS.  Two ways to fill LDS:
+//   - direct loads (every tile inside the matrices, K a whole number of
+//     steps, 16-byte aligned operands with even leading dimensions): each
+//     step's A and B tiles go global -> LDS by global_load_lds_dwordx4 (no
+//     staging registers) into two stages, the next step's loads in flight
+//     while the current one computes.  The A tile keeps the global row-major
+//     order with its 16-byte chunks XOR-swizzled per row, so one ds_read_b128
+//     returns (A_ik, A_i,k+1) and the rows the 4 thread rows of a wave read
+//     fall in distinct banks; the B tile is row-major.
+//   - register staging (everything else): each step's tiles are loaded into
+//     registers, stored to LDS (A k-major), then used; edge tiles check
+//     bounds.
+// Within a step each operation of the recurrence is issued for a whole row
+// (Winograd) or the whole register block (naive, Kahan) before the next one,
+// so the FP64 pipeline sees independent chains; the per-entry order of
+// operations, and hence every rounding, is unchanged.
 #include <type_traits>
 
 #include "common.h"
 #include "launch.h"
 
-// Tile shapes (BM, BN, TM, TN), staging and occupancy hints; overridable at
-// build time.  Defaults (measured on MI355X at 4096^3): two waves per SIMD
-// without register prefetch beat one wave per SIMD with it by 10-20%.
+// Tile shapes (BM, BN, TM, TN), K steps and occupancy; overridable at build
+// time.  Defaults measured on MI355X at 4096^3 (two waves per SIMD).
 #ifndef MMM_VALU_NAIVE_TILE
 #define MMM_VALU_NAIVE_TILE 128, 64, 8, 4
 #endif
@@ -39,9 +45,6 @@
 #endif
 #ifndef MMM_VALU_WINO_TILE
 #define MMM_VALU_WINO_TILE 128, 64, 8, 4
-#endif
-#ifndef MMM_VALU_PREFETCH
-#define MMM_VALU_PREFETCH 0
 #endif
 #ifndef MMM_VALU_MINWAVES
 #define MMM_VALU_MINWAVES 2
@@ -52,10 +55,8 @@
 #ifndef MMM_VALU_KAHAN_BK
 #define MMM_VALU_KAHAN_BK 32
 #endif
-// evaluate each operation of a step for a whole row / block of entries
-// before the next (independent chains for the FP64 pipeline)
-#ifndef MMM_VALU_ILP
-#define MMM_VALU_ILP 1
+#ifndef MMM_VALU_DMA
+#define MMM_VALU_DMA 1
 #endif
 
 namespace mmm {
@@ -100,6 +101,109 @@ __device__ inline void tile_of(i64 b, i64 tiles_m, i64 tiles_n, i64& prob, i64& 
     tn = w / gs;
 }
 
+// ---- the arithmetic of one k, one Winograd pair or one unrolled group ------
+// for a TM x TN register block.  Each operation is issued for the whole
+// block (row for Winograd) before the next; per entry the recurrence and its
+// roundings are the paper's.
+
+template <int OP, int TM, int TN>
+__device__ __forceinline__ void arith_k(const double (&a)[TM], const double (&b)[TN], double (&acc)[TM][TN],
+                                        double (&cmp)[TM][TN])
+{
+    if constexpr (OP == OP_KAHAN) {
+        // as printed: err = err + x; t = sum + err; err = (sum - t) + err; sum = t
+        double x[TM][TN], e[TM][TN], t[TM][TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) x[i][j] = a[i] * b[j];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) e[i][j] = cmp[i][j] + x[i][j];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) t[i][j] = acc[i][j] + e[i][j];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                cmp[i][j] = (acc[i][j] - t[i][j]) + e[i][j];
+                acc[i][j] = t[i][j];
+            }
+    } else if constexpr (OP == OP_NAIVE_FMA) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    } else if constexpr (OP == OP_NAIVE) {  // aux = aux + a * b, a row of the block at a time
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            double x[TN];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) x[j] = a[i] * b[j];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = acc[i][j] + x[j];
+        }
+    } else {  // NaivOnArray: the same recurrence, the whole block at a time
+        double x[TM][TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) x[i][j] = a[i] * b[j];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = acc[i][j] + x[i][j];
+    }
+}
+
+// Winograd pair (k, k+1): (A_{i,k} + B_{k+1,j}) (A_{i,k+1} + B_{k,j})
+template <int TM, int TN>
+__device__ __forceinline__ void arith_pair(const double (&a0)[TM], const double (&a1)[TM], const double (&b0)[TN],
+                                           const double (&b1)[TN], double (&acc)[TM][TN])
+{
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        double u[TN], v[TN], w[TN];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) u[j] = a0[i] + b1[j];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) v[j] = a1[i] + b0[j];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) w[j] = u[j] * v[j];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = acc[i][j] + w[j];
+    }
+}
+
+// a group of Q consecutive k: (p_1 + p_2 (+ p_3 (+ p_4))) left to right,
+// then added to the running sum
+template <int Q, int TM, int TN>
+__device__ __forceinline__ void arith_group(const double (&a)[Q][TM], const double (&b)[Q][TN],
+                                            double (&acc)[TM][TN])
+{
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        double grp[TN];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) grp[j] = a[0][i] * b[0][j];
+#pragma unroll
+        for (int r = 1; r < Q; ++r)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const double x = a[r][i] * b[r][j];
+                grp[j] = grp[j] + x;
+            }
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = acc[i][j] + grp[j];
+    }
+}
+
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+typedef __attribute__((address_space(1))) void* gbl_ptr_t;
+
 template <int BM, int BN, int TM, int TN, int OP, bool SCALED>
 struct ValuTile {
     // K per LDS step; a multiple of the group length of the unrolled sums
@@ -107,23 +211,59 @@ struct ValuTile {
     static constexpr int Q = unroll_q(OP);
     static_assert((BM / TM) * (BN / TN) == NT, "256 threads");
     static_assert(BM / TM == 16 && BN / TN == 16, "16 x 16 thread grid");
-    static constexpr int LA = BM * BK / NT;  // A elements each thread moves per step
+    static constexpr int LA = BM * BK / NT;  // A elements each thread moves per step (register staging)
     static constexpr int LB = BK * BN / NT;
     static constexpr int TH = TN / 2;        // columns per half
     static constexpr int KSTEP = (OP == OP_WINOGRAD) ? 2 : (Q ? Q : 1);
+    // the grouped part of the k range (the rest is added in the epilogue)
+    __host__ __device__ static i64 kmax_of(i64 P) { return (OP == OP_WINOGRAD) ? 2 * (P / 2) : (Q ? Q * (P / Q) : P); }
 
-    static constexpr int NBUF = MMM_VALU_PREFETCH ? 2 : 1;
-    struct Smem {
-        double As[NBUF][BK][BM + 2];
-        double Bs[NBUF][BK][BN + 2];
+    // direct loads: 16-byte chunks per A row, KiB blocks of A and B per step
+    static constexpr int CH = BK / 2;
+    static constexpr int NA = BM * BK / 128, NB = BK * BN / 128;
+    static constexpr bool DMA_OK = TN == 4 && (CH & (CH - 1)) == 0 && NA % 4 == 0 && NB % 4 == 0 && Q != 3;
+
+    struct SmemReg {
+        double As[BK][BM + 2];
+        double Bs[BK][BN + 2];
+    };
+    struct SmemDma {
+        double A[2][BM * BK];  // row-major, chunk c of row r in slot c ^ swz(r)
+        double B[2][BK * BN];  // row-major
     };
 
-    // Accumulate the whole K range into acc (and cmp for Kahan).  CHECK:
-    // bounds-check every load (edge tiles); otherwise only the last K step
-    // is checked.
+    __device__ __forceinline__ static int swz(int r) { return (r / TM) & (CH - 1); }
+
+    // NaivOnArray: the running sum lives in the entries of C; every K step
+    // reads them and writes them back (the first step starts from the zeroed
+    // entries)
     template <bool CHECK>
-    __device__ __forceinline__ static void mainloop(const Gemm& g, i64 m0, i64 n0, i64 kmax, double sa, double sb,
-                                                    Smem& sm, double (&acc)[TM][TN], double (&cmp)[TM][TN])
+    __device__ __forceinline__ static void c_io(const Gemm& g, i64 m0, i64 n0, bool store, double (&acc)[TM][TN])
+    {
+        if constexpr (OP == OP_ON_ARRAY) {
+            const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const i64 gm = m0 + ty * TM + i;
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int j = 0; j < TH; ++j) {
+                        const i64 gn = n0 + h * (BN / 2) + tx * TH + j;
+                        if (CHECK && (gm >= g.N || gn >= g.M)) continue;
+                        if (store) g.C[gm * g.ldc + gn] = acc[i][h * TH + j];
+                        else acc[i][h * TH + j] = g.C[gm * g.ldc + gn];
+                    }
+            }
+        }
+    }
+
+    // Register staging.  CHECK: bounds-check every load (edge tiles);
+    // otherwise only the last K step is checked.
+    template <bool CHECK>
+    __device__ __forceinline__ static void mainloop_reg(const Gemm& g, i64 m0, i64 n0, i64 kmax, double sa,
+                                                        double sb, SmemReg& sm, double (&acc)[TM][TN],
+                                                        double (&cmp)[TM][TN])
     {
         const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
         const i64 ntiles = (kmax + BK - 1) / BK;
@@ -149,231 +289,199 @@ struct ValuTile {
                 rb[q] = SCALED ? v * sb : v;
             }
         };
-        auto lstore = [&](int buf) __attribute__((always_inline)) {
+        auto lstore = [&]() __attribute__((always_inline)) {
 #pragma unroll
             for (int q = 0; q < LA; ++q) {
                 const int e = q * NT + tid;
-                sm.As[buf][e % BK][e / BK] = ra[q];
+                sm.As[e % BK][e / BK] = ra[q];
             }
 #pragma unroll
             for (int q = 0; q < LB; ++q) {
                 const int e = q * NT + tid;
-                sm.Bs[buf][e / BN][e % BN] = rb[q];
+                sm.Bs[e / BN][e % BN] = rb[q];
             }
         };
-        auto frag_a = [&](int buf, int k, double* a) __attribute__((always_inline)) {
+        auto frag_a = [&](int k, double(&a)[TM]) __attribute__((always_inline)) {
 #pragma unroll
             for (int i = 0; i < TM; i += 2) {
-                const double2 v = *reinterpret_cast<const double2*>(&sm.As[buf][k][ty * TM + i]);
+                const double2 v = *reinterpret_cast<const double2*>(&sm.As[k][ty * TM + i]);
                 a[i] = v.x;
                 a[i + 1] = v.y;
             }
         };
-        auto frag_b = [&](int buf, int k, double* b) __attribute__((always_inline)) {
+        auto frag_b = [&](int k, double(&b)[TN]) __attribute__((always_inline)) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 if (TH % 2 == 0) {
 #pragma unroll
                     for (int j = 0; j < TH; j += 2) {
-                        const double2 v =
-                            *reinterpret_cast<const double2*>(&sm.Bs[buf][k][h * (BN / 2) + tx * TH + j]);
+                        const double2 v = *reinterpret_cast<const double2*>(&sm.Bs[k][h * (BN / 2) + tx * TH + j]);
                         b[h * TH + j] = v.x;
                         b[h * TH + j + 1] = v.y;
                     }
                 } else {
 #pragma unroll
-                    for (int j = 0; j < TH; ++j) b[h * TH + j] = sm.Bs[buf][k][h * (BN / 2) + tx * TH + j];
+                    for (int j = 0; j < TH; ++j) b[h * TH + j] = sm.Bs[k][h * (BN / 2) + tx * TH + j];
                 }
             }
         };
-        auto step = [&](int buf, int k) __attribute__((always_inline)) {
-            if (OP == OP_WINOGRAD) {
-                // pair (k, k+1): (A_{i,k} + B_{k+1,j}) (A_{i,k+1} + B_{k,j})
+        auto step = [&](int k) __attribute__((always_inline)) {
+            if constexpr (OP == OP_WINOGRAD) {
                 double a0[TM], a1[TM], b0[TN], b1[TN];
-                frag_a(buf, k, a0);
-                frag_a(buf, k + 1, a1);
-                frag_b(buf, k, b0);
-                frag_b(buf, k + 1, b1);
-                if (MMM_VALU_ILP) {
-                    // one row of the register block at a time, each
-                    // operation for all its columns before the next
-#pragma unroll
-                    for (int i = 0; i < TM; ++i) {
-                        double u[TN], v[TN], w[TN];
-#pragma unroll
-                        for (int j = 0; j < TN; ++j) u[j] = a0[i] + b1[j];
-#pragma unroll
-                        for (int j = 0; j < TN; ++j) v[j] = a1[i] + b0[j];
-#pragma unroll
-                        for (int j = 0; j < TN; ++j) w[j] = u[j] * v[j];
-#pragma unroll
-                        for (int j = 0; j < TN; ++j) acc[i][j] = acc[i][j] + w[j];
-                    }
-                    return;
-                }
-#pragma unroll
-                for (int i = 0; i < TM; ++i)
-#pragma unroll
-                    for (int j = 0; j < TN; ++j) {
-                        const double u = a0[i] + b1[j];
-                        const double v = a1[i] + b0[j];
-                        const double w = u * v;
-                        acc[i][j] = acc[i][j] + w;
-                    }
-            } else if (Q) {
-                // a group of Q consecutive k: (p_1 + p_2 (+ p_3 (+ p_4))) summed
-                // left to right, then added to the running sum
-                double a[Q ? Q : 1][TM], b[Q ? Q : 1][TN];
+                frag_a(k, a0);
+                frag_a(k + 1, a1);
+                frag_b(k, b0);
+                frag_b(k + 1, b1);
+                arith_pair<TM, TN>(a0, a1, b0, b1, acc);
+            } else if constexpr (Q != 0) {
+                double a[Q][TM], b[Q][TN];
 #pragma unroll
                 for (int r = 0; r < Q; ++r) {
-                    frag_a(buf, k + r, a[r]);
-                    frag_b(buf, k + r, b[r]);
+                    frag_a(k + r, a[r]);
+                    frag_b(k + r, b[r]);
                 }
-#pragma unroll
-                for (int i = 0; i < TM; ++i) {
-                    double grp[TN];
-#pragma unroll
-                    for (int j = 0; j < TN; ++j) grp[j] = a[0][i] * b[0][j];
-#pragma unroll
-                    for (int r = 1; r < Q; ++r)
-#pragma unroll
-                        for (int j = 0; j < TN; ++j) {
-                            const double x = a[r][i] * b[r][j];
-                            grp[j] = grp[j] + x;
-                        }
-#pragma unroll
-                    for (int j = 0; j < TN; ++j) acc[i][j] = acc[i][j] + grp[j];
-                }
+                arith_group<Q, TM, TN>(a, b, acc);
             } else {
                 double a[TM], b[TN];
-                frag_a(buf, k, a);
-                frag_b(buf, k, b);
-                if (MMM_VALU_ILP && OP == OP_KAHAN) {
-                    // each operation of the recurrence for all entries of
-                    // the register block before the next
-                    double x[TM][TN], e[TM][TN], t[TM][TN];
-#pragma unroll
-                    for (int i = 0; i < TM; ++i)
-#pragma unroll
-                        for (int j = 0; j < TN; ++j) x[i][j] = a[i] * b[j];
-#pragma unroll
-                    for (int i = 0; i < TM; ++i)
-#pragma unroll
-                        for (int j = 0; j < TN; ++j) e[i][j] = cmp[i][j] + x[i][j];
-#pragma unroll
-                    for (int i = 0; i < TM; ++i)
-#pragma unroll
-                        for (int j = 0; j < TN; ++j) t[i][j] = acc[i][j] + e[i][j];
-#pragma unroll
-                    for (int i = 0; i < TM; ++i)
-#pragma unroll
-                        for (int j = 0; j < TN; ++j) {
-                            cmp[i][j] = (acc[i][j] - t[i][j]) + e[i][j];
-                            acc[i][j] = t[i][j];
-                        }
-                    return;
-                }
-                if (MMM_VALU_ILP && (OP == OP_NAIVE || OP == OP_ON_ARRAY)) {
-                    // all products of the step first, then the sums
-                    double x[TM][TN];
-#pragma unroll
-                    for (int i = 0; i < TM; ++i)
-#pragma unroll
-                        for (int j = 0; j < TN; ++j) x[i][j] = a[i] * b[j];
-#pragma unroll
-                    for (int i = 0; i < TM; ++i)
-#pragma unroll
-                        for (int j = 0; j < TN; ++j) acc[i][j] = acc[i][j] + x[i][j];
-                    return;
-                }
-#pragma unroll
-                for (int i = 0; i < TM; ++i)
-#pragma unroll
-                    for (int j = 0; j < TN; ++j) {
-                        if (OP == OP_NAIVE || OP == OP_ON_ARRAY) {
-                            const double x = a[i] * b[j];
-                            acc[i][j] = acc[i][j] + x;
-                        } else if (OP == OP_NAIVE_FMA) {
-                            acc[i][j] = fma(a[i], b[j], acc[i][j]);
-                        } else {
-                            // Kahan as printed: err = err + x; t = sum + err;
-                            // err = (sum - t) + err; sum = t.
-                            const double x = a[i] * b[j];
-                            const double e = cmp[i][j] + x;
-                            const double t = acc[i][j] + e;
-                            cmp[i][j] = (acc[i][j] - t) + e;
-                            acc[i][j] = t;
-                        }
-                    }
+                frag_a(k, a);
+                frag_b(k, b);
+                arith_k<OP, TM, TN>(a, b, acc, cmp);
             }
         };
-        auto compute = [&](int buf, i64 t) __attribute__((always_inline)) {
+        auto compute = [&](i64 t) __attribute__((always_inline)) {
             const i64 rem = kmax - t * BK;
             if (rem >= BK) {
 #pragma unroll
-                for (int k = 0; k < BK; k += KSTEP) step(buf, k);
+                for (int k = 0; k < BK; k += KSTEP) step(k);
             } else {
                 const int kc = (int)rem;
-                for (int k = 0; k < kc; k += KSTEP) step(buf, k);
+                for (int k = 0; k < kc; k += KSTEP) step(k);
             }
         };
-        auto need_check = [&](i64 t) __attribute__((always_inline)) { return CHECK || (t + 1) * BK > kmax; };
-        // NaivOnArray: the running sum lives in the entries of C; every K
-        // step reads them and writes them back (the first step starts from
-        // the zeroed entries)
-        auto c_io = [&](bool store) __attribute__((always_inline)) {
-            if (OP != OP_ON_ARRAY) return;
-#pragma unroll
-            for (int i = 0; i < TM; ++i) {
-                const i64 gm = m0 + ty * TM + i;
-#pragma unroll
-                for (int h = 0; h < 2; ++h)
-#pragma unroll
-                    for (int j = 0; j < TH; ++j) {
-                        const i64 gn = n0 + h * (BN / 2) + tx * TH + j;
-                        if (CHECK && (gm >= g.N || gn >= g.M)) continue;
-                        if (store) g.C[gm * g.ldc + gn] = acc[i][h * TH + j];
-                        else acc[i][h * TH + j] = g.C[gm * g.ldc + gn];
-                    }
-            }
-        };
-        if (OP == OP_ON_ARRAY) c_io(true);  // C = 0
-
-        if (MMM_VALU_PREFETCH) {
-            if (ntiles > 0) {
-                gload(0, need_check(0));
-                lstore(0);
-            }
+        if (OP == OP_ON_ARRAY) c_io<CHECK>(g, m0, n0, true, acc);  // C = 0
+        for (i64 t = 0; t < ntiles; ++t) {
+            gload(t, CHECK || (t + 1) * BK > kmax);
+            __syncthreads();  // the previous step's reads of the buffer are done
+            lstore();
             __syncthreads();
-            for (i64 t = 0; t < ntiles; ++t) {
-                const int cur = (int)(t & 1);
-                if (t + 1 < ntiles) gload(t + 1, need_check(t + 1));
-                c_io(false);
-                compute(cur, t);
-                c_io(true);
-                if (t + 1 < ntiles) lstore(cur ^ 1);
-                __syncthreads();
-            }
-        } else {
-            for (i64 t = 0; t < ntiles; ++t) {
-                gload(t, need_check(t));
-                __syncthreads();  // the previous step's reads of the buffer are done
-                lstore(0);
-                __syncthreads();
-                c_io(false);
-                compute(0, t);
-                c_io(true);
-            }
+            c_io<CHECK>(g, m0, n0, false, acc);
+            compute(t);
+            c_io<CHECK>(g, m0, n0, true, acc);
         }
     }
 
+    // Direct loads (host has checked: tile inside the matrices, kmax a
+    // multiple of BK, aligned operands with even leading dimensions).
+    __device__ __forceinline__ static void mainloop_dma(const Gemm& g, i64 m0, i64 n0, i64 kmax, double sa,
+                                                        double sb, SmemDma& sm, double (&acc)[TM][TN],
+                                                        double (&cmp)[TM][TN])
+    {
+        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, tx = tid % 16, ty = tid / 16;
+        const i64 nt = kmax / BK;
+        // lane l of a wave instruction writes LDS bytes 16 l .. 16 l + 15 of
+        // its KiB block; it fetches the global chunk that belongs there
+        auto issue = [&](i64 t, int buf) __attribute__((always_inline)) {
+            const i64 k0 = t * BK;
+#pragma unroll
+            for (int q = 0; q < NA / 4; ++q) {
+                const int blk = q * 4 + wave, p = blk * 64 + lane;
+                const int r = p / CH, c = (p % CH) ^ swz(r);
+                const double* src = g.A + (m0 + r) * g.lda + k0 + 2 * c;
+                __builtin_amdgcn_global_load_lds((gbl_ptr_t)src, (lds_ptr_t)&sm.A[buf][blk * 128], 16, 0, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < NB / 4; ++q) {
+                const int blk = q * 4 + wave, p = blk * 64 + lane;
+                const int r = p / (BN / 2), c = p % (BN / 2);
+                const double* src = g.B + (k0 + r) * g.ldb + n0 + 2 * c;
+                __builtin_amdgcn_global_load_lds((gbl_ptr_t)src, (lds_ptr_t)&sm.B[buf][blk * 128], 16, 0, 0);
+            }
+        };
+        // WinogradScaled: each lane scales the 16 bytes it loaded (exact)
+        auto rescale = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+            for (int q = 0; q < NA / 4; ++q) {
+                double2* v = reinterpret_cast<double2*>(&sm.A[buf][(q * 4 + wave) * 128 + 2 * lane]);
+                v->x = v->x * sa;
+                v->y = v->y * sa;
+            }
+#pragma unroll
+            for (int q = 0; q < NB / 4; ++q) {
+                double2* v = reinterpret_cast<double2*>(&sm.B[buf][(q * 4 + wave) * 128 + 2 * lane]);
+                v->x = v->x * sb;
+                v->y = v->y * sb;
+            }
+        };
+        // operands of k = 2 kp and 2 kp + 1
+        auto frag_pair = [&](int buf, int kp, double(&a0)[TM], double(&a1)[TM], double(&b0)[TN],
+                             double(&b1)[TN]) __attribute__((always_inline)) {
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const int r = ty * TM + i;
+                const double2 v = *reinterpret_cast<const double2*>(&sm.A[buf][r * BK + 2 * (kp ^ swz(r))]);
+                a0[i] = v.x;
+                a1[i] = v.y;
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int col = h * (BN / 2) + tx * TH;
+                const double2 v0 = *reinterpret_cast<const double2*>(&sm.B[buf][(2 * kp) * BN + col]);
+                const double2 v1 = *reinterpret_cast<const double2*>(&sm.B[buf][(2 * kp + 1) * BN + col]);
+                b0[h * TH] = v0.x;
+                b0[h * TH + 1] = v0.y;
+                b1[h * TH] = v1.x;
+                b1[h * TH + 1] = v1.y;
+            }
+        };
+        auto compute = [&](int buf) __attribute__((always_inline)) {
+            if constexpr (Q == 4) {
+#pragma unroll
+                for (int kp = 0; kp < BK / 2; kp += 2) {
+                    double a[4][TM], b[4][TN];
+                    frag_pair(buf, kp, a[0], a[1], b[0], b[1]);
+                    frag_pair(buf, kp + 1, a[2], a[3], b[2], b[3]);
+                    arith_group<4, TM, TN>(a, b, acc);
+                }
+            } else {
+#pragma unroll
+                for (int kp = 0; kp < BK / 2; ++kp) {
+                    double a[2][TM], b[2][TN];
+                    frag_pair(buf, kp, a[0], a[1], b[0], b[1]);
+                    if constexpr (OP == OP_WINOGRAD) {
+                        arith_pair<TM, TN>(a[0], a[1], b[0], b[1], acc);
+                    } else if constexpr (Q == 2) {
+                        arith_group<2, TM, TN>(a, b, acc);
+                    } else {
+                        arith_k<OP, TM, TN>(a[0], b[0], acc, cmp);
+                        arith_k<OP, TM, TN>(a[1], b[1], acc, cmp);
+                    }
+                }
+            }
+        };
+        if (OP == OP_ON_ARRAY) c_io<false>(g, m0, n0, true, acc);  // C = 0
+        if (nt > 0) issue(0, 0);
+        for (i64 t = 0; t < nt; ++t) {
+            const int cur = (int)(t & 1);
+            // own loads of this step have landed; after the barrier every
+            // wave's have, and every wave is done with the other stage
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            if (SCALED) rescale(cur);
+            __syncthreads();
+            if (t + 1 < nt) issue(t + 1, cur ^ 1);
+            c_io<false>(g, m0, n0, false, acc);
+            compute(cur);
+            c_io<false>(g, m0, n0, true, acc);
+        }
+    }
+
+    template <bool DMA>
     __device__ __forceinline__ static void run(const Gemm& g, i64 tm, i64 tn, const double* __restrict__ yv,
-                                               const double* __restrict__ zv, const int* lam, Smem& sm)
+                                               const double* __restrict__ zv, const int* lam,
+                                               typename std::conditional<DMA, SmemDma, SmemReg>::type& sm)
     {
         const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
         const i64 m0 = tm * BM, n0 = tn * BN;
-        // the grouped part of the k range; the rest is added in the epilogue
-        const i64 kmax = (OP == OP_WINOGRAD) ? 2 * (g.P / 2) : (Q ? Q * (g.P / Q) : g.P);
+        const i64 kmax = kmax_of(g.P);
         double sa = 1.0, sb = 1.0;
         if (SCALED) {
             const int l = *lam;
@@ -388,8 +496,12 @@ struct ValuTile {
                 acc[i][j] = 0.0;
                 cmp[i][j] = 0.0;
             }
-        if (m0 + BM <= g.N && n0 + BN <= g.M) mainloop<false>(g, m0, n0, kmax, sa, sb, sm, acc, cmp);
-        else mainloop<true>(g, m0, n0, kmax, sa, sb, sm, acc, cmp);
+        if constexpr (DMA) {
+            mainloop_dma(g, m0, n0, kmax, sa, sb, sm, acc, cmp);
+        } else {
+            if (m0 + BM <= g.N && n0 + BN <= g.M) mainloop_reg<false>(g, m0, n0, kmax, sa, sb, sm, acc, cmp);
+            else mainloop_reg<true>(g, m0, n0, kmax, sa, sb, sm, acc, cmp);
+        }
 
         const bool odd = (OP == OP_WINOGRAD) && (g.P % 2 == 1);
 #pragma unroll
@@ -430,29 +542,55 @@ struct ValuTile {
     }
 };
 
-template <int BM, int BN, int TM, int TN, int OP, bool SCALED, class Src>
+template <int BM, int BN, int TM, int TN, int OP, bool SCALED, bool DMA, class Src>
 __global__ __launch_bounds__(NT, MMM_VALU_MINWAVES) void valu_gemm_kernel(Src src, i64 tiles_m, i64 tiles_n,
                                                                           i64 total, const double* __restrict__ yv,
                                                                           const double* __restrict__ zv,
                                                                           const int* lam)
 {
     typedef ValuTile<BM, BN, TM, TN, OP, SCALED> T;
-    __shared__ __align__(16) typename T::Smem sm;
+    __shared__ __align__(16) typename std::conditional<DMA, typename T::SmemDma, typename T::SmemReg>::type sm;
     i64 prob, tm, tn;
     tile_of(xcd_remap(blockIdx.x, total), tiles_m, tiles_n, prob, tm, tn);
-    T::run(src.get(prob), tm, tn, yv, zv, lam, sm);
+    T::template run<DMA>(src.get(prob), tm, tn, yv, zv, lam, sm);
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+// Direct loads need every tile inside the matrices, the grouped K range a
+// whole number of steps and 16-byte aligned rows of A and B.
+template <class T>
+bool direct_ok(const SingleSrc& src, i64 bm, i64 bn)
+{
+    const Gemm& g = src.g;
+    const i64 kmax = T::kmax_of(g.P);
+    return MMM_VALU_DMA && T::DMA_OK && g.N % bm == 0 && g.M % bn == 0 && kmax > 0 && kmax % T::BK == 0 &&
+           g.lda % 2 == 0 && g.ldb % 2 == 0 && aligned16(g.A) && aligned16(g.B);
+}
+template <class T>
+bool direct_ok(const StrassenLeafSrc&, i64, i64)
+{
+    return false;
 }
 
 template <int BM, int BN, int TM, int TN, int OP, bool SCALED, class Src>
 hipError_t launch_valu(const Src& src, i64 N, i64 M, const double* yv, const double* zv, const int* lam,
                        hipStream_t s)
 {
+    typedef ValuTile<BM, BN, TM, TN, OP, SCALED> T;
     const i64 tiles_m = cdiv(N, BM), tiles_n = cdiv(M, BN);
     const i64 total = tiles_m * tiles_n * src.count();
     if (total == 0) return hipSuccess;
     if (total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((valu_gemm_kernel<BM, BN, TM, TN, OP, SCALED, Src>), dim3((unsigned)total), dim3(NT), 0, s,
-                       src, tiles_m, tiles_n, total, yv, zv, lam);
+    if constexpr (T::DMA_OK) {
+        if (direct_ok<T>(src, BM, BN)) {
+            hipLaunchKernelGGL((valu_gemm_kernel<BM, BN, TM, TN, OP, SCALED, true, Src>), dim3((unsigned)total),
+                               dim3(NT), 0, s, src, tiles_m, tiles_n, total, yv, zv, lam);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((valu_gemm_kernel<BM, BN, TM, TN, OP, SCALED, false, Src>), dim3((unsigned)total), dim3(NT), 0,
+                       s, src, tiles_m, tiles_n, total, yv, zv, lam);
     return hipGetLastError();
 }
 
