@@ -70,7 +70,8 @@ typedef enum {
  * 2.4.1 (X = max{N,P,M}, k = floor(log2 X) - 4, m = floor(X 2^-k) + 1,
  * Y = m 2^k, k clamped at 0), k levels, naive m x m leaf.  LEVELS:
  * `strassen_levels` levels, each dimension padded to a multiple of
- * 2^levels. */
+ * 2^levels (with the DGEMM leaf and P >= 64 2^levels, P to a multiple of
+ * 16 2^levels, so that the leaf depth suits the matrix cores' K step). */
 typedef enum { MMM_PAD_PAPER = 0, MMM_PAD_LEVELS = 1 } mmm_pad_mode;
 
 /* Leaf product of the Strassen recursion (the algorithm alpha_{m,0}). */

@@ -117,10 +117,15 @@ bool plan_strassen(i64 N, i64 P, i64 M, const mmm_config& c, StrassenPlan& pl)
     } else {
         pl.depth = c.strassen_levels;
         const i64 q = (i64)1 << pl.depth;
-        pl.Np = cdiv(N, q) * q;
-        pl.Pp = cdiv(P, q) * q;
-        pl.Mp = cdiv(M, q) * q;
         pl.naive_leaf = c.strassen_leaf == MMM_LEAF_NAIVE;
+        // the DGEMM leaf takes its direct-load path when the leaf depth is a
+        // multiple of 16: pad P to a multiple of 16 2^L for it (zero columns
+        // of A and rows of B); the naive leaf keeps the 2^L rule, whose block
+        // split defines its rounding
+        const i64 qp = (!pl.naive_leaf && P >= 64 * q) ? 16 * q : q;
+        pl.Np = cdiv(N, q) * q;
+        pl.Pp = cdiv(P, qp) * qp;
+        pl.Mp = cdiv(M, q) * q;
     }
     pl.pad = pl.Np != N || pl.Pp != P || pl.Mp != M;
     size_t off = 0;

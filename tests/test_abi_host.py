@@ -53,6 +53,20 @@ def test_workspace_arithmetic(lib):
     b = ws("strassen_winograd", 4096, 4097, 4096, cfg)
     assert b > 3 * (7 * n1 + 49 * n2)
     assert ws("strassen_naive", 0, 5, 5) == 0
+    # DGEMM leaf: P = 4097 is padded to a multiple of 16 * 2^L = 64 (4160), the
+    # naive leaf only to a multiple of 2^L (4100); both pad copies of A, B, C
+    def plan_bytes(Np, Pp, Mp, L):
+        al = lambda x: (x + 255) // 256 * 256
+        tot = al(8 * Np * Pp) + al(8 * Pp * Mp) + al(8 * Np * Mp)
+        for d in range(1, L + 1):
+            n, p_, m = Np >> d, Pp >> d, Mp >> d
+            tot += al(8 * 7 ** d * n * p_) + al(8 * 7 ** d * p_ * m) + al(8 * 7 ** d * n * m)
+        return tot
+    assert b == plan_bytes(4096, 4160, 4096, 2)
+    assert ws("strassen_winograd", 4096, 4097, 4096, lib.Config(strassen_levels=2, strassen_leaf="naive")) == \
+        plan_bytes(4096, 4100, 4096, 2)
+    # small P keeps the 2^L rule for both leaves
+    assert ws("strassen_winograd", 64, 33, 64, lib.Config(strassen_levels=2)) == plan_bytes(64, 36, 64, 2)
     with pytest.raises(ValueError):
         ws("dgemm", -1, 2, 2)
     # paper mode at X < 32 is a single naive product (no workspace)

@@ -241,3 +241,28 @@ def test_dgemm_direct_load_path_exact(mmm, shape):
     assert np.array_equal(run(mmm, A, B, "dgemm"), ref)
     cfg = mmm.Config(strassen_levels=1)
     assert np.array_equal(run(mmm, A, B, "strassen_winograd", cfg), ref)
+
+
+def test_misaligned_views_take_the_staged_path(mmm, orc):
+    """256^3 qualifies for the direct global-to-LDS paths; operands that are
+    views 8 bytes into a buffer (rows no longer 16-byte aligned) must take
+    the register-staged path and give the same bits."""
+    N = P = M = 256
+    A = synth.uniform((N, P), 21)
+    B = synth.uniform((P, M), 22)
+
+    def shifted(X):
+        flat = dev(np.concatenate([[0.0], X.ravel()]))
+        return flat[1:].view(*X.shape)
+
+    Ad, Bd, Au, Bu = dev(A), dev(B), shifted(A), shifted(B)
+    for method, ref in (("naive", orc.naive(A, B)), ("kahan", orc.kahan(A, B)), ("winograd", orc.winograd(A, B)),
+                        ("naive_unroll4", orc.naive_unroll(A, B, 4))):
+        for X, Y in ((Ad, Bd), (Au, Bd), (Ad, Bu), (Au, Bu)):
+            C = mmm.multiply(X, Y, method)
+            torch.cuda.synchronize()
+            assert bits_equal(C.cpu().numpy(), ref), method
+    base = mmm.multiply(Ad, Bd, "dgemm").cpu().numpy()
+    assert relerr(orc, base, orc.naive(A, B), A, B) <= TOL_PLAIN
+    for X, Y in ((Au, Bd), (Ad, Bu)):
+        assert relerr(orc, mmm.multiply(X, Y, "dgemm").cpu().numpy(), orc.naive(A, B), A, B) <= TOL_PLAIN
