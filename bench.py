@@ -58,6 +58,8 @@ PRECISION = [
     ("dgemm", "dgemm", {}),
     ("split_int8_s7", "split", {"split_type": "int8", "split_slices": 7}),
     ("split_bf16_s6", "split", {"split_type": "bf16", "split_slices": 6}),
+    ("strassen_winograd_L1", "strassen_winograd", {"strassen_levels": 1}),
+    ("strassen_winograd_L2", "strassen_winograd", {"strassen_levels": 2}),
 ]
 
 
@@ -299,9 +301,10 @@ def main():
 
 
 def precision_section(args, mmm, torch, synth, dev, stream, errors_needed):
-    """DGEMM against the split products at N = P = M = 8192 on the
-    wide-range distribution: median time, FP64-grade TFLOP/s (2NPM/t) and
-    relative infinity-norm error on sampled rows against the oracle."""
+    """DGEMM against the split products and Strassen-Winograd (DGEMM leaf, 1
+    and 2 levels) at N = P = M = 8192 on the wide-range distribution: median
+    time, FP64-grade TFLOP/s (2NPM/t) and relative infinity-norm error on
+    sampled rows against the oracle."""
     n = 8192
     A = synth.wide_range((n, n), synth.seed_a(2))
     B = synth.wide_range((n, n), synth.seed_b(2))
@@ -336,6 +339,9 @@ def precision_section(args, mmm, torch, synth, dev, stream, errors_needed):
         ent = {"ms_p50": med, "ms_min": float(np.min(ms)), "tflops_fp64_grade": 2.0 * n ** 3 / (med / 1e3) / 1e12}
         if name == "dgemm":
             ent["frac_fp64_mfma_peak"] = ent["tflops_fp64_grade"] / PEAK_FP64_MFMA_TFLOPS
+        elif method == "strassen_winograd":
+            L = kw["strassen_levels"]
+            ent["leaf_flop_share"] = (7.0 / 8.0) ** L  # of 2NPM, on the FP64 matrix cores
         else:
             s = kw["split_slices"]
             pairs = s * (s + 1) // 2
