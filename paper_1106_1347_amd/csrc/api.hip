@@ -169,6 +169,9 @@ mmm_status run_strassen(int variant, const double* A, const double* B, double* C
     memset(&T, 0, sizeof(T));
     T.variant = variant;
     T.depth = pl.depth;
+    // the deepest two levels run as one pass each way (level depth - 1 is
+    // never written)
+    T.fused = pl.depth >= 2 ? pl.depth - 1 : 0;
     double* Croot = C;
     i64 ldc = M;
     if (pl.pad) {
@@ -199,13 +202,25 @@ mmm_status run_strassen(int variant, const double* A, const double* B, double* C
         }
     }
     T.H[0] = Croot;  // the depth-0 "leaf" is the whole product
-    for (int d = 1; d <= pl.depth; ++d)
-        if ((e = launch_strassen_pre(T, d, s)) != hipSuccess) return from_hip(e, "strassen pre");
+    for (int d = 1; d <= pl.depth; ++d) {
+        if (d == T.fused) {
+            if ((e = launch_strassen_pre2(T, d, s)) != hipSuccess) return from_hip(e, "strassen pre");
+            ++d;
+        } else if ((e = launch_strassen_pre(T, d, s)) != hipSuccess) {
+            return from_hip(e, "strassen pre");
+        }
+    }
     StrassenLeafSrc leaves{T, pow7(pl.depth)};
     e = pl.naive_leaf ? launch_naive_strassen_leaves(leaves, s) : launch_dgemm_strassen_leaves(leaves, s);
     if (e != hipSuccess) return from_hip(e, "strassen leaves");
-    for (int d = pl.depth; d >= 1; --d)
-        if ((e = launch_strassen_post(T, d, Croot, ldc, s)) != hipSuccess) return from_hip(e, "strassen post");
+    for (int d = pl.depth; d >= 1; --d) {
+        if (T.fused && d == T.fused + 1) {
+            if ((e = launch_strassen_post2(T, T.fused, Croot, ldc, s)) != hipSuccess) return from_hip(e, "strassen post");
+            --d;
+        } else if ((e = launch_strassen_post(T, d, Croot, ldc, s)) != hipSuccess) {
+            return from_hip(e, "strassen post");
+        }
+    }
     if (pl.pad && (e = launch_pad_copy(Croot, ldc, N, M, C, M, N, M, s)) != hipSuccess) return from_hip(e, "extract C");
     return MMM_OK;
 }

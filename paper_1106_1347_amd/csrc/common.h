@@ -46,6 +46,8 @@ constexpr int kMaxDepth = 12;
 struct StrassenTree {
     int variant;  // 0 StrassenNaiv, 1 StrassenWinograd
     int depth;
+    int fused;    // level whose sums and products are never written (0 = none): formed in registers by the
+                  // two-level kernels of levels fused and fused + 1
     const double* A;
     i64 lda;
     const double* B;
@@ -76,7 +78,10 @@ struct View {
     i64 ld;
 };
 
-// Operand of node q at level d (A side when is_b is false).
+// Operand of node q at level d (A side when is_b is false).  A child takes
+// a view of its parent's operand only when that operand exists in memory;
+// below the fused level (whose sums live only in registers) every child is
+// materialised.  Never called for the fused level itself.
 __device__ inline View strassen_operand(const StrassenTree& T, int d, i64 q, bool is_b)
 {
     View v{is_b ? T.B : T.A, is_b ? T.ldb : T.lda};
@@ -84,17 +89,21 @@ __device__ inline View strassen_operand(const StrassenTree& T, int d, i64 q, boo
     i64 pw = 1;
     for (int e = 1; e < d; ++e) pw *= 7;
     i64 prefix = 0;
+    bool virt = false;  // the operand so far exists only in registers
     for (int e = 1; e <= d; ++e) {
         const int c = (int)((q / pw) % 7);
         pw /= 7;
         const int quad = is_b ? view_quadrant_b(T.variant, c) : view_quadrant_a(T.variant, c);
         const i64 rows = is_b ? T.p[e] : T.n[e];
         const i64 cols = is_b ? T.m[e] : T.p[e];
-        if (quad >= 0) {
+        if (quad >= 0 && !virt) {
             v.p += (quad >> 1) * rows * v.ld + (quad & 1) * cols;
+        } else if (e == T.fused) {
+            virt = true;
         } else {
             v.p = (is_b ? T.WB[e] : T.WA[e]) + (prefix * 7 + c) * rows * cols;
             v.ld = cols;
+            virt = false;
         }
         prefix = prefix * 7 + c;
     }

@@ -45,5 +45,10 @@ hipError_t launch_fill_zero(double* dst, i64 n, hipStream_t s);
 // strassen.hip
 hipError_t launch_strassen_pre(const StrassenTree& T, int level, hipStream_t s);
 hipError_t launch_strassen_post(const StrassenTree& T, int level, double* C, i64 ldc, hipStream_t s);
+// Levels f and f + 1 of the recursion in one pass each way (level f is never
+// written): operand sums of levels f and f + 1 from the operands of level
+// f - 1, and the products of level f - 1 from those of level f + 1.
+hipError_t launch_strassen_pre2(const StrassenTree& T, int f, hipStream_t s);
+hipError_t launch_strassen_post2(const StrassenTree& T, int f, double* C, i64 ldc, hipStream_t s);
 
 }  // namespace mmm

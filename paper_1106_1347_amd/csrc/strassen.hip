@@ -126,6 +126,181 @@ __global__ __launch_bounds__(256) void strassen_post_kernel(StrassenTree T, int 
     }
 }
 
+// Operand of child c (0..6, i.e. H_{c+1}) from the four quadrant entries
+// of its parent's operand, exactly as the single-level kernel forms it (a
+// view child returns its quadrant entry).
+template <int VARIANT, bool IS_B>
+__device__ __forceinline__ double child_value(int c, double x11, double x12, double x21, double x22)
+{
+    if (VARIANT == 0) {
+        if (!IS_B) {
+            switch (c) {
+            case 0: return x11 + x22;
+            case 1: return x21 + x22;
+            case 2: return x11;
+            case 3: return x22;
+            case 4: return x11 + x12;
+            case 5: return x21 - x11;
+            default: return x12 - x22;
+            }
+        }
+        switch (c) {
+        case 0: return x11 + x22;
+        case 1: return x11;
+        case 2: return x12 - x22;
+        case 3: return x21 - x11;
+        case 4: return x22;
+        case 5: return x11 + x12;
+        default: return x21 + x22;
+        }
+    }
+    if (!IS_B) {
+        const double a1 = x11 - x21;
+        const double a2 = x22 - a1;
+        switch (c) {
+        case 0: return x11;
+        case 1: return x12;
+        case 2: return a2;
+        case 3: return x21 + x22;
+        case 4: return a1;
+        case 5: return x12 - a2;
+        default: return x22;
+        }
+    }
+    const double b1 = x22 - x12;
+    const double b2 = b1 + x11;
+    switch (c) {
+    case 0: return x11;
+    case 1: return x21;
+    case 2: return b2;
+    case 3: return x12 - x11;
+    case 4: return b1;
+    case 5: return x22;
+    default: return x21 - b2;
+    }
+}
+
+// The four result quadrants of a node from its seven child products, as
+// the single-level post-kernel forms them.
+template <int VARIANT>
+__device__ __forceinline__ void fold_products(const double (&h)[7], double& c11, double& c12, double& c21,
+                                              double& c22)
+{
+    if (VARIANT == 0) {
+        c11 = ((h[0] + h[3]) - h[4]) + h[6];
+        c12 = h[2] + h[4];
+        c21 = h[1] + h[3];
+        c22 = ((h[0] + h[2]) - h[1]) + h[5];
+    } else {
+        const double h8 = h[0] + h[2];
+        const double h9 = h8 + h[3];
+        c11 = h[0] + h[1];
+        c12 = h9 + h[5];
+        c21 = (h8 + h[4]) + h[6];
+        c22 = h9 + h[4];
+    }
+}
+
+// Levels f and f + 1 in one pass: for every node of level f - 1, each
+// thread reads the 16 entries of the node's operand that one position of a
+// level-(f+1) block touches, forms the 7 x 4 level-f operand entries in
+// registers (level f is never written) and writes the level-(f+1)
+// operands that are not views of the node's own operand.
+template <int VARIANT, bool IS_B>
+__global__ __launch_bounds__(256) void strassen_pre2_kernel(StrassenTree T, int f, i64 bpp)
+{
+    const i64 parent = blockIdx.x / bpp;
+    const i64 chunk = blockIdx.x - parent * bpp;
+    const View par = strassen_operand(T, f - 1, parent, IS_B);
+    const i64 rows = IS_B ? T.p[f + 1] : T.n[f + 1];
+    const i64 cols = IS_B ? T.m[f + 1] : T.p[f + 1];
+    const i64 sz = rows * cols;
+    double* W = (IS_B ? T.WB[f + 1] : T.WA[f + 1]) + parent * 49 * sz;
+    const i64 base = chunk * 256 * EPT + threadIdx.x;
+#pragma unroll 1
+    for (int u = 0; u < EPT; ++u) {
+        const i64 e = base + u * 256;
+        if (e >= sz) break;
+        const i64 r = e / cols, c = e - r * cols;
+        const double* q = par.p + r * par.ld + c;
+        double x[4][4];  // x[i][j]: block (i, j) of the 4 x 4 grid of level-(f+1) blocks
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) x[i][j] = q[i * rows * par.ld + j * cols];
+#pragma unroll
+        for (int c1 = 0; c1 < 7; ++c1) {
+            double y[2][2];  // level-f operand of child c1, its quadrant (qi, qj)
+#pragma unroll
+            for (int qi = 0; qi < 2; ++qi)
+#pragma unroll
+                for (int qj = 0; qj < 2; ++qj)
+                    y[qi][qj] = child_value<VARIANT, IS_B>(c1, x[qi][qj], x[qi][2 + qj], x[2 + qi][qj],
+                                                           x[2 + qi][2 + qj]);
+            const bool v1 = (IS_B ? view_quadrant_b(VARIANT, c1) : view_quadrant_a(VARIANT, c1)) >= 0;
+#pragma unroll
+            for (int c2 = 0; c2 < 7; ++c2) {
+                const bool v2 = (IS_B ? view_quadrant_b(VARIANT, c2) : view_quadrant_a(VARIANT, c2)) >= 0;
+                if (v1 && v2) continue;  // a view of the node's own operand
+                W[(c1 * 7 + c2) * sz + e] = child_value<VARIANT, IS_B>(c2, y[0][0], y[0][1], y[1][0], y[1][1]);
+            }
+        }
+    }
+}
+
+// Levels f + 1 and f folded in one pass: for every node of level f - 1,
+// each thread reads its 49 grandchild products at one position, forms the
+// 7 x 4 level-f product entries in registers (level f is never written)
+// and writes the 16 entries of the node's product that position feeds.
+template <int VARIANT>
+__global__ __launch_bounds__(256) void strassen_post2_kernel(StrassenTree T, int f, i64 bpp, double* C, i64 ldc)
+{
+    const i64 parent = blockIdx.x / bpp;
+    const i64 chunk = blockIdx.x - parent * bpp;
+    const i64 rows = T.n[f + 1], cols = T.m[f + 1];
+    const i64 sz = rows * cols;
+    const double* H = T.H[f + 1] + parent * 49 * sz;
+    double* out;
+    i64 ld;
+    if (f - 1 >= 1) {
+        out = T.H[f - 1] + parent * T.n[f - 1] * T.m[f - 1];
+        ld = T.m[f - 1];
+    } else {
+        out = C;
+        ld = ldc;
+    }
+    const i64 base = chunk * 256 * EPT + threadIdx.x;
+#pragma unroll 1
+    for (int u = 0; u < EPT; ++u) {
+        const i64 e = base + u * 256;
+        if (e >= sz) break;
+        const i64 r = e / cols, c = e - r * cols;
+        double z[7][2][2];  // level-f product of child c1, its quadrant (qi, qj)
+#pragma unroll
+        for (int c1 = 0; c1 < 7; ++c1) {
+            double h[7];
+#pragma unroll
+            for (int c2 = 0; c2 < 7; ++c2) h[c2] = H[(c1 * 7 + c2) * sz + e];
+            fold_products<VARIANT>(h, z[c1][0][0], z[c1][0][1], z[c1][1][0], z[c1][1][1]);
+        }
+        double* o = out + r * ld + c;
+#pragma unroll
+        for (int qi = 0; qi < 2; ++qi)
+#pragma unroll
+            for (int qj = 0; qj < 2; ++qj) {
+                double h[7];
+#pragma unroll
+                for (int c1 = 0; c1 < 7; ++c1) h[c1] = z[c1][qi][qj];
+                double c11, c12, c21, c22;
+                fold_products<VARIANT>(h, c11, c12, c21, c22);
+                o[qi * rows * ld + qj * cols] = c11;
+                o[qi * rows * ld + (2 + qj) * cols] = c12;
+                o[(2 + qi) * rows * ld + qj * cols] = c21;
+                o[(2 + qi) * rows * ld + (2 + qj) * cols] = c22;
+            }
+    }
+}
+
 i64 pow7(int e)
 {
     i64 r = 1;
@@ -173,6 +348,48 @@ hipError_t launch_strassen_post(const StrassenTree& T, int level, double* C, i64
         hipLaunchKernelGGL((strassen_post_kernel<0>), dim3((unsigned)blocks), dim3(256), 0, s, T, level, bpp, C, ldc);
     else
         hipLaunchKernelGGL((strassen_post_kernel<1>), dim3((unsigned)blocks), dim3(256), 0, s, T, level, bpp, C, ldc);
+    return hipGetLastError();
+}
+
+}  // namespace mmm
+
+namespace mmm {
+
+hipError_t launch_strassen_pre2(const StrassenTree& T, int f, hipStream_t s)
+{
+    const i64 parents = pow7(f - 1);
+    for (int side = 0; side < 2; ++side) {
+        const i64 sz = side ? T.p[f + 1] * T.m[f + 1] : T.n[f + 1] * T.p[f + 1];
+        const i64 bpp = cdiv(sz, 256 * EPT);
+        const i64 blocks = parents * bpp;
+        if (blocks == 0) continue;
+        if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+        const dim3 g((unsigned)blocks), b(256);
+        if (T.variant == 0) {
+            if (side) hipLaunchKernelGGL((strassen_pre2_kernel<0, true>), g, b, 0, s, T, f, bpp);
+            else hipLaunchKernelGGL((strassen_pre2_kernel<0, false>), g, b, 0, s, T, f, bpp);
+        } else {
+            if (side) hipLaunchKernelGGL((strassen_pre2_kernel<1, true>), g, b, 0, s, T, f, bpp);
+            else hipLaunchKernelGGL((strassen_pre2_kernel<1, false>), g, b, 0, s, T, f, bpp);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_strassen_post2(const StrassenTree& T, int f, double* C, i64 ldc, hipStream_t s)
+{
+    const i64 parents = pow7(f - 1);
+    const i64 sz = T.n[f + 1] * T.m[f + 1];
+    const i64 bpp = cdiv(sz, 256 * EPT);
+    const i64 blocks = parents * bpp;
+    if (blocks == 0) return hipSuccess;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    if (T.variant == 0)
+        hipLaunchKernelGGL((strassen_post2_kernel<0>), dim3((unsigned)blocks), dim3(256), 0, s, T, f, bpp, C, ldc);
+    else
+        hipLaunchKernelGGL((strassen_post2_kernel<1>), dim3((unsigned)blocks), dim3(256), 0, s, T, f, bpp, C, ldc);
     return hipGetLastError();
 }
 

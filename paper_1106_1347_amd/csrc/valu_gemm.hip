@@ -58,6 +58,11 @@
 #ifndef MMM_VALU_DMA
 #define MMM_VALU_DMA 1
 #endif
+// waves per SIMD of the direct-load kernels (Kahan: its 64 KiB of LDS per
+// workgroup allow two)
+#ifndef MMM_VALU_DMA_MINWAVES
+#define MMM_VALU_DMA_MINWAVES 2
+#endif
 
 namespace mmm {
 
@@ -543,7 +548,7 @@ struct ValuTile {
 };
 
 template <int BM, int BN, int TM, int TN, int OP, bool SCALED, bool DMA, class Src>
-__global__ __launch_bounds__(NT, MMM_VALU_MINWAVES) void valu_gemm_kernel(Src src, i64 tiles_m, i64 tiles_n,
+__global__ __launch_bounds__(NT, (DMA && OP != OP_KAHAN) ? MMM_VALU_DMA_MINWAVES : MMM_VALU_MINWAVES) void valu_gemm_kernel(Src src, i64 tiles_m, i64 tiles_n,
                                                                           i64 total, const double* __restrict__ yv,
                                                                           const double* __restrict__ zv,
                                                                           const int* lam)
