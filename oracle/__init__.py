@@ -42,6 +42,7 @@ def _load():
         "oracle_naive_rows": (None, [dp, dp, dp, i64, i64, i64, dp, i64]),
         "oracle_kahan": (None, [dp, dp, dp, i64, i64, i64]),
         "oracle_naive_on_array": (None, [dp, dp, dp, i64, i64, i64]),
+        "oracle_dot2": (None, [dp, dp, dp, i64, i64, i64]),
         "oracle_naive_unroll": (None, [dp, dp, dp, i64, i64, i64, ctypes.c_int]),
         "oracle_kahan_rows": (None, [dp, dp, dp, i64, i64, i64, dp, i64]),
         "oracle_winograd_rows": (None, [dp, dp, dp, i64, i64, i64, dp, i64, ctypes.c_int]),
@@ -157,6 +158,16 @@ def naive_on_array(A, B):
     N, P, M = _shape(A, B)
     C = np.empty((N, M))
     _load().oracle_naive_on_array(_p(A), _p(B), _p(C), N, P, M)
+    return C
+
+
+def dot2(A, B):
+    """Compensated dot products (TwoProduct with FMA + TwoSum, Ogita-Rump-Oishi
+    Dot2); beyond the paper."""
+    A, B = _f64(A), _f64(B)
+    N, P, M = _shape(A, B)
+    C = np.empty((N, M))
+    _load().oracle_dot2(_p(A), _p(B), _p(C), N, P, M)
     return C
 
 

@@ -223,6 +223,37 @@ void oracle_kahan_rows(const double* A, const double* B, double* out, i64 N, i64
     }
 }
 
+/* Not a method of the paper (it extends the compensated sum of Section
+ * 2.1.3 to the products): the dot product of Ogita, Rump and Oishi
+ * ("Accurate sum and dot product", SIAM J. Sci. Comput. 26(6), 2005,
+ * Algorithm Dot2).  Every product is split exactly into x + y with
+ * x = fl(a b), y = fma(a, b, -x) (TwoProduct); the running sum p and each x
+ * are split exactly by TwoSum (s = fl(p + x), z = fl(s - p),
+ * e = fl(fl(p - fl(s - z)) + fl(x - z))); the error terms accumulate in q as
+ * q = fl(q + fl(e + y)); the entry is fl(p + q).  Starting from p = q = 0
+ * and running over every k equals the published initialisation with the
+ * first TwoProduct. */
+void oracle_dot2(const double* A, const double* B, double* C, i64 N, i64 P, i64 M)
+{
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (N * P * M > 32768)
+    for (i64 i = 0; i < N; ++i) {
+        for (i64 j = 0; j < M; ++j) {
+            double p = 0.0, q = 0.0;
+            for (i64 k = 0; k < P; ++k) {
+                const double a = A[i * P + k], b = B[k * M + j];
+                const double x = a * b;
+                const double y = fma(a, b, -x);
+                const double s = p + x;
+                const double z = s - p;
+                const double e = (p - (s - z)) + (x - z);
+                p = s;
+                q = q + (e + y);
+            }
+            C[i * M + j] = p + q;
+        }
+    }
+}
+
 /* ---------------------------------------------------------------------- */
 /* Winograd's algorithm, Section 2.3                                      */
 /* ---------------------------------------------------------------------- */

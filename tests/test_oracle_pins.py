@@ -40,6 +40,7 @@ def _methods(orc):
         "winograd": orc.winograd,
         "winograd_scaled": orc.winograd_scaled,
         "naive_on_array": orc.naive_on_array,
+        "dot2": orc.dot2,
         "unroll2": lambda A, B: orc.naive_unroll(A, B, 2),
         "unroll3": lambda A, B: orc.naive_unroll(A, B, 3),
         "unroll4": lambda A, B: orc.naive_unroll(A, B, 4),
@@ -488,3 +489,40 @@ def test_unrolled_sums_bounds_against_rationals(orc):
                             ex = sum(Fraction(A[i, k]) * Fraction(B[k, j]) for k in range(P))
                             ab = sum(abs(Fraction(A[i, k]) * Fraction(B[k, j])) for k in range(P))
                             assert abs(Fraction(Cq[i, j]) - ex) <= g * ab, (P, q)
+
+
+def test_dot2_cancellation_worked_by_hand(orc):
+    """[1e16, 1, -1e16] . [1, 1, 1] = 1: the naive sum and the paper's Kahan
+    loop both lose the 1 (1e16 + 1 rounds to 1e16; Kahan's err then absorbs
+    -1e16 and rounds the 1 away), TwoSum keeps it exactly in the error term.
+    [2^60, 1, -2^60, 1] = 2 likewise."""
+    A = np.array([[1e16, 1.0, -1e16], [2.0 ** 60, 1.0, -(2.0 ** 60)]])
+    B = np.ones((3, 1))
+    assert orc.dot2(A, B)[:, 0].tolist() == [1.0, 1.0]
+    assert orc.naive(A, B)[0, 0] == 0.0 and orc.kahan(A, B)[0, 0] == 0.0
+    A4 = np.array([[2.0 ** 60, 1.0, -(2.0 ** 60), 1.0]])
+    assert orc.dot2(A4, np.ones((4, 1)))[0, 0] == 2.0
+
+
+def test_dot2_bound_against_rationals(orc):
+    """Ogita-Rump-Oishi (2005), bound for Dot2:
+    |res - x^T y| <= u |x^T y| + gamma_n^2 |x|^T |y|, gamma_n = n u / (1 - n u).
+    Checked against exact rationals on random entries over 40 binades and on
+    ill-conditioned rows (a random row followed by its negation plus a small
+    remainder, so the exact result is tiny next to |x|^T|y|)."""
+    rng = np.random.default_rng(21)
+    u = Fraction(U)
+    for trial in range(300):
+        n = int(rng.integers(1, 24))
+        a = rng.uniform(-1, 1, n) * 2.0 ** rng.integers(-20, 21, n)
+        b = rng.uniform(-1, 1, n) * 2.0 ** rng.integers(-20, 21, n)
+        if trial % 2 and n >= 3:
+            h = n // 2
+            a[h:2 * h] = -a[:h]
+            b[h:2 * h] = b[:h]
+            a[-1] = a[-1] * 2.0 ** -30
+        res = orc.dot2(a[None, :], b[:, None])[0, 0]
+        ex = sum(Fraction(x) * Fraction(y) for x, y in zip(a, b))
+        ab = sum(abs(Fraction(x) * Fraction(y)) for x, y in zip(a, b))
+        g = n * u / (1 - n * u)
+        assert abs(Fraction(res) - ex) <= u * abs(ex) + g * g * ab, (trial, n)
