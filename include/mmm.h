@@ -63,7 +63,9 @@ typedef enum {
     MMM_NAIVE_UNROLL2 = 9,     /* 2.2.1 NaivLoopUnrollingTwo: products summed in pairs, pair sums accumulated */
     MMM_NAIVE_UNROLL3 = 10,    /* 2.2.2 NaivLoopUnrollingThree: in groups of three */
     MMM_NAIVE_UNROLL4 = 11,    /* 2.2.3 NaivLoopUnrollingFour: in groups of four */
-    MMM_METHOD_COUNT = 12
+    MMM_DOT2 = 12,             /* beyond the paper: 2.1.3's compensation extended to the products (TwoProduct by
+                                  FMA + TwoSum, Ogita-Rump-Oishi Dot2), about twice the working precision */
+    MMM_METHOD_COUNT = 13
 } mmm_method;
 
 /* Strassen embedding.  PAPER: the square Y x Y zero embedding of Section

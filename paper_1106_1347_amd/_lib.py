@@ -28,6 +28,7 @@ METHODS = {
     "naive_unroll2": 9,
     "naive_unroll3": 10,
     "naive_unroll4": 11,
+    "dot2": 12,
 }
 PAD_MODES = {"paper": 0, "levels": 1}
 LEAVES = {"dgemm": 0, "naive": 1}

@@ -304,6 +304,7 @@ size_t mmm_workspace_bytes(mmm_method method, int64_t N, int64_t P, int64_t M, c
     case MMM_NAIVE_UNROLL2:
     case MMM_NAIVE_UNROLL3:
     case MMM_NAIVE_UNROLL4:
+    case MMM_DOT2:
         return 0;
     case MMM_WINOGRAD:
         return wino_layout(N, M, false).bytes;
@@ -363,6 +364,8 @@ mmm_status mmm_multiply(const double* A, const double* B, double* C, int64_t N, 
     case MMM_NAIVE_UNROLL3:
     case MMM_NAIVE_UNROLL4:
         return from_hip(launch_naive_variant(g, 2 + (int)(method - MMM_NAIVE_UNROLL2), s), "naive unrolled");
+    case MMM_DOT2:
+        return from_hip(launch_naive_variant(g, 5, s), "dot2");
     case MMM_DGEMM:
         return from_hip(launch_dgemm(g, s), "dgemm");
     case MMM_WINOGRAD:

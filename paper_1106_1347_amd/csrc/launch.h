@@ -9,7 +9,8 @@ namespace mmm {
 hipError_t launch_naive(const Gemm& g, bool fused, hipStream_t s);
 hipError_t launch_naive_strassen_leaves(const StrassenLeafSrc& src, hipStream_t s);
 hipError_t launch_kahan(const Gemm& g, hipStream_t s);
-// NaivOnArray (variant 0) or NaivLoopUnrollingTwo/Three/Four (variant 2/3/4)
+// NaivOnArray (variant 0), NaivLoopUnrollingTwo/Three/Four (variant 2/3/4) or
+// compensated dot products (variant 5)
 hipError_t launch_naive_variant(const Gemm& g, int variant, hipStream_t s);
 hipError_t launch_winograd_main(const Gemm& g, const double* y, const double* z, const int* lam, hipStream_t s);
 

@@ -1,7 +1,8 @@
 // Inner-product methods of Section 2 on the FP64 vector ALUs of gfx950:
 // NaivStandard (2.1.1), NaivOnArray (2.1.2), NaivKahan (2.1.3),
 // NaivLoopUnrollingTwo/Three/Four (2.2) and the main loop of
-// WinogradOriginal (2.3.1, also used by WinogradScaled 2.3.2).
+// WinogradOriginal (2.3.1, also used by WinogradScaled 2.3.2); beyond the
+// paper, compensated dot products (Ogita, Rump and Oishi's Dot2).
 //
 // Every output entry is owned by one lane, which runs the paper's recurrence
 // over k (or over the index pairs) in ascending order.  The file is built
@@ -78,7 +79,8 @@ enum Op {
     OP_UNROLL2 = 4,  // NaivLoopUnrollingTwo / Three / Four
     OP_UNROLL3 = 5,
     OP_UNROLL4 = 6,
-    OP_ON_ARRAY = 7  // NaivOnArray
+    OP_ON_ARRAY = 7,  // NaivOnArray
+    OP_DOT2 = 8       // compensated dot products (TwoProduct + TwoSum), beyond the paper
 };
 __host__ __device__ constexpr int unroll_q(int op) { return op == OP_UNROLL2 ? 2 : (op == OP_UNROLL3 ? 3 : (op == OP_UNROLL4 ? 4 : 0)); }
 
@@ -136,6 +138,28 @@ __device__ __forceinline__ void arith_k(const double (&a)[TM], const double (&b)
             for (int j = 0; j < TN; ++j) {
                 cmp[i][j] = (acc[i][j] - t[i][j]) + e[i][j];
                 acc[i][j] = t[i][j];
+            }
+    } else if constexpr (OP == OP_DOT2) {
+        // Ogita-Rump-Oishi Dot2: x + y = a b exactly (TwoProduct), s + e =
+        // p + x exactly (TwoSum), p = s, q = q + (e + y); the entry is p + q
+        double x[TM][TN], s[TM][TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) x[i][j] = a[i] * b[j];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) s[i][j] = acc[i][j] + x[i][j];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const double y = fma(a[i], b[j], -x[i][j]);
+                const double z = s[i][j] - acc[i][j];
+                const double e = (acc[i][j] - (s[i][j] - z)) + (x[i][j] - z);
+                acc[i][j] = s[i][j];
+                cmp[i][j] = cmp[i][j] + (e + y);
             }
     } else if constexpr (OP == OP_NAIVE_FMA) {
 #pragma unroll
@@ -212,7 +236,8 @@ typedef __attribute__((address_space(1))) void* gbl_ptr_t;
 template <int BM, int BN, int TM, int TN, int OP, bool SCALED>
 struct ValuTile {
     // K per LDS step; a multiple of the group length of the unrolled sums
-    static constexpr int BK = OP == OP_KAHAN ? MMM_VALU_KAHAN_BK : (OP == OP_UNROLL3 ? 24 : MMM_VALU_BK);
+    static constexpr int BK =
+        OP == OP_KAHAN ? MMM_VALU_KAHAN_BK : (OP == OP_UNROLL3 ? 24 : MMM_VALU_BK);
     static constexpr int Q = unroll_q(OP);
     static_assert((BM / TM) * (BN / TN) == NT, "256 threads");
     static_assert(BM / TM == 16 && BN / TN == 16, "16 x 16 thread grid");
@@ -525,6 +550,7 @@ struct ValuTile {
                     const i64 gn = n0 + h * (BN / 2) + tx * TH + j;
                     if (gn >= g.M) continue;
                     double c = acc[i][h * TH + j];
+                    if (OP == OP_DOT2) c = c + cmp[i][h * TH + j];
                     if (Q) {
                         // leftover P mod Q products, one at a time, k ascending
                         for (i64 k = kmax; k < g.P; ++k) {
@@ -548,7 +574,7 @@ struct ValuTile {
 };
 
 template <int BM, int BN, int TM, int TN, int OP, bool SCALED, bool DMA, class Src>
-__global__ __launch_bounds__(NT, (DMA && OP != OP_KAHAN) ? MMM_VALU_DMA_MINWAVES : MMM_VALU_MINWAVES) void valu_gemm_kernel(Src src, i64 tiles_m, i64 tiles_n,
+__global__ __launch_bounds__(NT, (DMA && OP != OP_KAHAN && OP != OP_DOT2) ? MMM_VALU_DMA_MINWAVES : MMM_VALU_MINWAVES) void valu_gemm_kernel(Src src, i64 tiles_m, i64 tiles_n,
                                                                           i64 total, const double* __restrict__ yv,
                                                                           const double* __restrict__ zv,
                                                                           const int* lam)
@@ -615,8 +641,8 @@ hipError_t launch_naive_like(const Src& src, i64 N, i64 M, hipStream_t s)
     if (N <= 48 && M <= 48) return launch_valu<32, 32, 2, 2, OP, false>(src, N, M, nullptr, nullptr, nullptr, s);
     // Kahan keeps two doubles per entry, the longer groups and the on-array
     // round trips more operands in flight: 64 x 64 tiles for those
-    constexpr bool small = OP == OP_KAHAN || OP == OP_UNROLL3 || OP == OP_UNROLL4 || OP == OP_ON_ARRAY;
-    typedef typename std::conditional<OP == OP_KAHAN, KahanShape,
+    constexpr bool small = OP == OP_KAHAN || OP == OP_UNROLL3 || OP == OP_UNROLL4 || OP == OP_ON_ARRAY || OP == OP_DOT2;
+    typedef typename std::conditional<OP == OP_KAHAN || OP == OP_DOT2, KahanShape,
                                       typename std::conditional<small, Shape<64, 64, 4, 4>, NaiveShape>::type>::type S;
     return launch_valu<S::bm, S::bn, S::tm, S::tn, OP, false>(src, N, M, nullptr, nullptr, nullptr, s);
 }
@@ -643,6 +669,7 @@ hipError_t launch_naive_variant(const Gemm& g, int variant, hipStream_t s)
     case 2: return launch_naive_like<OP_UNROLL2>(src, g.N, g.M, s);
     case 3: return launch_naive_like<OP_UNROLL3>(src, g.N, g.M, s);
     case 4: return launch_naive_like<OP_UNROLL4>(src, g.N, g.M, s);
+    case 5: return launch_naive_like<OP_DOT2>(src, g.N, g.M, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -40,6 +40,7 @@ EXTRA_ROWS = [
     ("DGEMM (FP64 matrix cores)", "dgemm", Config()),
     ("StrassenWinograd L=2, DGEMM", "strassen_winograd", Config(strassen_levels=2)),
     ("Split int8 x7", "split", Config(split_type="int8", split_slices=7)),
+    ("Dot2 (compensated, FMA)", "dot2", Config()),
 ]
 REFERENCE = ("N := NaivKahan", "kahan", Config())
 

@@ -106,6 +106,7 @@ def test_integer_inputs_exact_every_method(mmm, shape):
     ref = (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float64)
     cfgs = {"naive": [None, mmm.Config(naive_fma=True)], "kahan": [None], "winograd": [None],
             "naive_on_array": [None], "naive_unroll2": [None], "naive_unroll3": [None], "naive_unroll4": [None],
+            "dot2": [None],
             "winograd_scaled": [None], "dgemm": [None],
             "strassen_naive": [mmm.Config(strassen_levels=L) for L in (1, 2, 3)] + [mmm.Config(pad_mode="paper")],
             "strassen_winograd": [mmm.Config(strassen_levels=L) for L in (1, 2, 3)] + [mmm.Config(pad_mode="paper")]}
@@ -149,20 +150,23 @@ def test_lambda_on_device(mmm, orc):
         assert mmm.winograd_lambda(na, nb).item() == orc.winograd_lambda(a, b), (a, b)
 
 
-VARIANTS = ("naive_on_array", "naive_unroll2", "naive_unroll3", "naive_unroll4")
+VARIANTS = ("naive_on_array", "naive_unroll2", "naive_unroll3", "naive_unroll4", "dot2")
 
 
 def _variant_ref(orc, name, A, B):
     if name == "naive_on_array":
         return orc.naive_on_array(A, B)
+    if name == "dot2":
+        return orc.dot2(A, B)
     return orc.naive_unroll(A, B, int(name[-1]))
 
 
 @pytest.mark.parametrize("shape", SHAPES + [(70, 50, 90), (65, 97, 66), (130, 100, 129), (48, 47, 48)])
 def test_naive_variants_bitwise(mmm, orc, shape):
-    """NaivOnArray and NaivLoopUnrollingTwo/Three/Four (Sections 2.1.2, 2.2):
-    bit for bit the oracle's evaluation order, including the leftover P mod q
-    products and tiles that straddle the matrix edges."""
+    """NaivOnArray and NaivLoopUnrollingTwo/Three/Four (Sections 2.1.2, 2.2)
+    and the compensated dot products (beyond the paper): bit for bit the
+    oracle's evaluation order, including the leftover P mod q products and
+    tiles that straddle the matrix edges."""
     N, P, M = shape
     print("case", shape, flush=True)
     A = synth.uniform((N, P), 111 + N)
@@ -257,7 +261,7 @@ def test_misaligned_views_take_the_staged_path(mmm, orc):
 
     Ad, Bd, Au, Bu = dev(A), dev(B), shifted(A), shifted(B)
     for method, ref in (("naive", orc.naive(A, B)), ("kahan", orc.kahan(A, B)), ("winograd", orc.winograd(A, B)),
-                        ("naive_unroll4", orc.naive_unroll(A, B, 4))):
+                        ("naive_unroll4", orc.naive_unroll(A, B, 4)), ("dot2", orc.dot2(A, B))):
         for X, Y in ((Ad, Bd), (Au, Bd), (Ad, Bu), (Au, Bu)):
             C = mmm.multiply(X, Y, method)
             torch.cuda.synchronize()
@@ -266,3 +270,15 @@ def test_misaligned_views_take_the_staged_path(mmm, orc):
     assert relerr(orc, base, orc.naive(A, B), A, B) <= TOL_PLAIN
     for X, Y in ((Au, Bd), (Ad, Bu)):
         assert relerr(orc, mmm.multiply(X, Y, "dgemm").cpu().numpy(), orc.naive(A, B), A, B) <= TOL_PLAIN
+
+
+def test_dot2_recovers_cancellation(mmm, orc):
+    """Rows [1e16, 1, -1e16] against columns of ones: the compensated dot
+    products return the exact 1 (the naive sum and Kahan's loop give 0), bit
+    for bit the oracle, on a tile of 300 x 3 x 70."""
+    A = np.tile(np.array([[1e16, 1.0, -1e16]]), (300, 1))
+    A[::2] *= -1.0
+    B = np.ones((3, 70))
+    C = run(mmm, A, B, "dot2")
+    assert bits_equal(C, orc.dot2(A, B))
+    assert (C[1::2] == 1.0).all() and (C[::2] == -1.0).all()
