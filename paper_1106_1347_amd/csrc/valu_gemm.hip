@@ -47,6 +47,11 @@
 #ifndef MMM_VALU_WINO_TILE
 #define MMM_VALU_WINO_TILE 128, 64, 8, 4
 #endif
+// NaivStandard on the direct-load path: no staging registers, room for an
+// 8 x 8 block per thread
+#ifndef MMM_VALU_NAIVE_DMA_TILE
+#define MMM_VALU_NAIVE_DMA_TILE 128, 128, 8, 8
+#endif
 #ifndef MMM_VALU_MINWAVES
 #define MMM_VALU_MINWAVES 2
 #endif
@@ -251,7 +256,7 @@ struct ValuTile {
     // direct loads: 16-byte chunks per A row, KiB blocks of A and B per step
     static constexpr int CH = BK / 2;
     static constexpr int NA = BM * BK / 128, NB = BK * BN / 128;
-    static constexpr bool DMA_OK = TN == 4 && (CH & (CH - 1)) == 0 && NA % 4 == 0 && NB % 4 == 0 && Q != 3;
+    static constexpr bool DMA_OK = TN % 4 == 0 && (CH & (CH - 1)) == 0 && NA % 4 == 0 && NB % 4 == 0 && Q != 3;
 
     struct SmemReg {
         double As[BK][BM + 2];
@@ -453,15 +458,17 @@ struct ValuTile {
                 a1[i] = v.y;
             }
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int col = h * (BN / 2) + tx * TH;
-                const double2 v0 = *reinterpret_cast<const double2*>(&sm.B[buf][(2 * kp) * BN + col]);
-                const double2 v1 = *reinterpret_cast<const double2*>(&sm.B[buf][(2 * kp + 1) * BN + col]);
-                b0[h * TH] = v0.x;
-                b0[h * TH + 1] = v0.y;
-                b1[h * TH] = v1.x;
-                b1[h * TH + 1] = v1.y;
-            }
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int j = 0; j < TH; j += 2) {
+                    const int col = h * (BN / 2) + tx * TH + j;
+                    const double2 v0 = *reinterpret_cast<const double2*>(&sm.B[buf][(2 * kp) * BN + col]);
+                    const double2 v1 = *reinterpret_cast<const double2*>(&sm.B[buf][(2 * kp + 1) * BN + col]);
+                    b0[h * TH + j] = v0.x;
+                    b0[h * TH + j + 1] = v0.y;
+                    b1[h * TH + j] = v1.x;
+                    b1[h * TH + j + 1] = v1.y;
+                }
         };
         auto compute = [&](int buf) __attribute__((always_inline)) {
             if constexpr (Q == 4) {
@@ -625,6 +632,27 @@ hipError_t launch_valu(const Src& src, i64 N, i64 M, const double* yv, const dou
     return hipGetLastError();
 }
 
+// Launch the direct-load kernel of this tile shape when the problem
+// qualifies; false otherwise (nothing launched, the register-staged
+// kernel of this shape is not instantiated).
+template <int BM, int BN, int TM, int TN, int OP, bool SCALED, class Src>
+bool try_launch_direct(const Src& src, i64 N, i64 M, hipStream_t s, hipError_t& err)
+{
+    typedef ValuTile<BM, BN, TM, TN, OP, SCALED> T;
+    if constexpr (!T::DMA_OK) {
+        return false;
+    } else {
+        if (!direct_ok<T>(src, BM, BN)) return false;
+        const i64 tiles_m = cdiv(N, BM), tiles_n = cdiv(M, BN);
+        const i64 total = tiles_m * tiles_n * src.count();
+        if (total == 0 || total > 0x7fffffffLL) return false;
+        hipLaunchKernelGGL((valu_gemm_kernel<BM, BN, TM, TN, OP, SCALED, true, Src>), dim3((unsigned)total), dim3(NT), 0,
+                           s, src, tiles_m, tiles_n, total, nullptr, nullptr, nullptr);
+        err = hipGetLastError();
+        return true;
+    }
+}
+
 template <int BM, int BN, int TM, int TN>
 struct Shape {
     static constexpr int bm = BM, bn = BN, tm = TM, tn = TN;
@@ -639,6 +667,11 @@ template <int OP, class Src>
 hipError_t launch_naive_like(const Src& src, i64 N, i64 M, hipStream_t s)
 {
     if (N <= 48 && M <= 48) return launch_valu<32, 32, 2, 2, OP, false>(src, N, M, nullptr, nullptr, nullptr, s);
+    if constexpr (OP == OP_NAIVE || OP == OP_NAIVE_FMA) {
+        typedef Shape<MMM_VALU_NAIVE_DMA_TILE> D;
+        hipError_t err = hipSuccess;
+        if (try_launch_direct<D::bm, D::bn, D::tm, D::tn, OP, false>(src, N, M, s, err)) return err;
+    }
     // Kahan keeps two doubles per entry, the longer groups and the on-array
     // round trips more operands in flight: 64 x 64 tiles for those
     constexpr bool small = OP == OP_KAHAN || OP == OP_UNROLL3 || OP == OP_UNROLL4 || OP == OP_ON_ARRAY || OP == OP_DOT2;
