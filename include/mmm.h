@@ -99,7 +99,14 @@ mmm_config mmm_config_default(void);
 
 /* Bytes of workspace mmm_multiply needs for this method, shape and config
  * (0 for methods that need none).  Returns (size_t)-1 for invalid
- * arguments. */
+ * arguments.  The inner-product methods (NAIVE ... DOT2) and DGEMM need none
+ * except for large products (N P M >= 2^32) whose N and M are multiples of
+ * the kernel tile but whose P gives A rows that are not 16-byte aligned or a
+ * K range that is not a whole number of kernel steps (P = 4097, say): those
+ * run on zero-padded copies of A (N x kp) and, when K is ragged, B (kp x M),
+ * kp = P rounded up to at most the next multiple of 32.  The result is the
+ * same as without the copies (bit for bit for the methods defined by a
+ * summation order). */
 size_t mmm_workspace_bytes(mmm_method method, int64_t N, int64_t P, int64_t M, const mmm_config* cfg);
 
 /* C = A B by `method`.  A: N x P, B: P x M, C: N x M, device, row-major.

@@ -251,9 +251,11 @@ WinoLayout wino_layout(i64 N, i64 M, bool scaled)
     return w;
 }
 
-mmm_status run_winograd(const double* A, const double* B, double* C, i64 N, i64 P, i64 M, bool scaled, char* ws,
-                        hipStream_t s)
+// y and z from the caller's A and B; the main loop reads g, which may point
+// at padded copies of them.
+mmm_status run_winograd(const double* A, const double* B, const Gemm& g, bool scaled, char* ws, hipStream_t s)
 {
+    const i64 N = g.N, P = g.P, M = g.M;
     const WinoLayout w = wino_layout(N, M, scaled);
     double* y = (double*)(ws + w.y);
     double* z = (double*)(ws + w.z);
@@ -270,7 +272,56 @@ mmm_status run_winograd(const double* A, const double* B, double* C, i64 N, i64 
     // y_i over the rows of 2^lambda A, z_k over the columns of 2^-lambda B
     if ((e = launch_vector_reduce(RED_PAIR_SUM, false, A, P, N, P, y, lam, +1, s)) != hipSuccess) return from_hip(e, "y");
     if ((e = launch_vector_reduce(RED_PAIR_SUM, true, B, M, M, P, z, lam, -1, s)) != hipSuccess) return from_hip(e, "z");
-    return from_hip(launch_winograd_main(Gemm{A, P, B, M, C, M, N, P, M}, y, z, lam, s), "winograd");
+    return from_hip(launch_winograd_main(g, y, z, lam, s), "winograd");
+}
+
+// ---- zero-padded operand copies (direct loads at a ragged P) ----------------
+
+ValuPad pad_plan(mmm_method method, i64 N, i64 P, i64 M, const mmm_config& c)
+{
+    switch (method) {
+    case MMM_NAIVE: return valu_pad_plan(c.naive_fma ? VK_NAIVE_FMA : VK_NAIVE, N, P, M);
+    case MMM_KAHAN: return valu_pad_plan(VK_KAHAN, N, P, M);
+    case MMM_NAIVE_ON_ARRAY: return valu_pad_plan(VK_ON_ARRAY, N, P, M);
+    case MMM_NAIVE_UNROLL2: return valu_pad_plan(VK_UNROLL2, N, P, M);
+    case MMM_NAIVE_UNROLL3: return valu_pad_plan(VK_UNROLL3, N, P, M);
+    case MMM_NAIVE_UNROLL4: return valu_pad_plan(VK_UNROLL4, N, P, M);
+    case MMM_DOT2: return valu_pad_plan(VK_DOT2, N, P, M);
+    case MMM_DGEMM: return dgemm_pad_plan(N, P, M);
+    case MMM_WINOGRAD: return valu_pad_plan(VK_WINOGRAD, N, P, M);
+    case MMM_WINOGRAD_SCALED: return valu_pad_plan(VK_WINOGRAD_SCALED, N, P, M);
+    default: return ValuPad{0, false, false};
+    }
+}
+
+size_t pad_a_bytes(const ValuPad& p, i64 N) { return align_up(sizeof(double) * (size_t)N * (size_t)p.kp); }
+
+// (size_t)-1 when the copies could not be addressed
+size_t pad_bytes(const ValuPad& p, i64 N, i64 M)
+{
+    if (!p.kp) return 0;
+    if (8.0 * (double)p.kp * ((double)N + (double)M) > 9.0e18) return (size_t)-1;
+    return pad_a_bytes(p, N) + (p.copy_b ? align_up(sizeof(double) * (size_t)p.kp * (size_t)M) : 0);
+}
+
+// Writes the copies to ws and points g at them.
+hipError_t apply_pad(const ValuPad& p, Gemm& g, char* ws, hipStream_t s)
+{
+    if (!p.kp) return hipSuccess;
+    double* Ap = (double*)ws;
+    hipError_t e = launch_pad_copy(g.A, g.lda, g.N, g.P, Ap, p.kp, g.N, p.kp, s);
+    if (e != hipSuccess) return e;
+    if (p.copy_b) {
+        double* Bp = (double*)(ws + pad_a_bytes(p, g.N));
+        if ((e = launch_pad_copy(g.B, g.ldb, g.P, g.M, Bp, g.M, p.kp, g.M, s)) != hipSuccess) return e;
+        g.B = Bp;
+        g.ldb = g.M;
+    }
+    g.A = Ap;
+    g.lda = p.kp;
+    if (p.zero_k) g.P = p.kp;
+    else g.kcap = p.kp;
+    return hipSuccess;
 }
 
 }  // namespace
@@ -305,11 +356,13 @@ size_t mmm_workspace_bytes(mmm_method method, int64_t N, int64_t P, int64_t M, c
     case MMM_NAIVE_UNROLL3:
     case MMM_NAIVE_UNROLL4:
     case MMM_DOT2:
-        return 0;
+        return pad_bytes(pad_plan(method, N, P, M, c), N, M);
     case MMM_WINOGRAD:
-        return wino_layout(N, M, false).bytes;
-    case MMM_WINOGRAD_SCALED:
-        return wino_layout(N, M, true).bytes;
+    case MMM_WINOGRAD_SCALED: {
+        const size_t pb = pad_bytes(pad_plan(method, N, P, M, c), N, M);
+        if (pb == (size_t)-1) return pb;
+        return wino_layout(N, M, method == MMM_WINOGRAD_SCALED).bytes + pb;
+    }
     case MMM_STRASSEN_NAIVE:
     case MMM_STRASSEN_WINOGRAD: {
         StrassenPlan pl;
@@ -352,7 +405,13 @@ mmm_status mmm_multiply(const double* A, const double* B, double* C, int64_t N, 
             return fail(MMM_EALIAS, "workspace overlaps an operand");
     }
     char* ws = (char*)workspace;
-    const Gemm g{A, P, B, M, C, M, N, P, M};
+    Gemm g{A, P, B, M, C, M, N, P, M};
+    // the Winograd vectors sit before the copies
+    const size_t pad_at = method == MMM_WINOGRAD || method == MMM_WINOGRAD_SCALED
+                              ? wino_layout(N, M, method == MMM_WINOGRAD_SCALED).bytes
+                              : 0;
+    hipError_t pe = apply_pad(pad_plan(method, N, P, M, c), g, ws + pad_at, s);
+    if (pe != hipSuccess) return from_hip(pe, "pad operands");
     switch (method) {
     case MMM_NAIVE:
         return from_hip(launch_naive(g, c.naive_fma != 0, s), "naive");
@@ -369,9 +428,9 @@ mmm_status mmm_multiply(const double* A, const double* B, double* C, int64_t N, 
     case MMM_DGEMM:
         return from_hip(launch_dgemm(g, s), "dgemm");
     case MMM_WINOGRAD:
-        return run_winograd(A, B, C, N, P, M, false, ws, s);
+        return run_winograd(A, B, g, false, ws, s);
     case MMM_WINOGRAD_SCALED:
-        return run_winograd(A, B, C, N, P, M, true, ws, s);
+        return run_winograd(A, B, g, true, ws, s);
     case MMM_STRASSEN_NAIVE:
     case MMM_STRASSEN_WINOGRAD: {
         StrassenPlan pl;

@@ -24,6 +24,10 @@ struct Gemm {
     double* C;
     i64 ldc;
     i64 N, P, M;
+    // columns of A (and rows of B) that may be read, >= P: larger when the
+    // operands are zero-padded copies, which lets the direct-load kernels
+    // load a whole last K step (0 means P)
+    i64 kcap;
 };
 
 // A single product: every workgroup works on the same problem.

@@ -369,6 +369,19 @@ hipError_t launch_dgemm_auto(const Src& src, i64 N, i64 M, hipStream_t s)
 
 }  // namespace
 
+// P not a multiple of 16 keeps a large product off the direct-load kernel;
+// zero-padding K to the next multiple adds exact zeros to every sum.
+ValuPad dgemm_pad_plan(i64 N, i64 P, i64 M)
+{
+    ValuPad p{0, false, false};
+    if (!MMM_DGEMM_DMA || N % 128 != 0 || M % 128 != 0 || (N / 128) * (M / 128) < 256 || P % 16 == 0) return p;
+    if ((double)N * (double)P * (double)M < kPadMinWork) return p;
+    p.kp = cdiv(P, 16) * 16;
+    p.copy_b = true;
+    p.zero_k = true;
+    return p;
+}
+
 hipError_t launch_dgemm(const Gemm& g, hipStream_t s)
 {
     SingleSrc src{g};

@@ -5,7 +5,37 @@
 
 namespace mmm {
 
+// Zero-padded operand copies for a large product whose tiles fit N and M
+// but whose P keeps it off the direct-load kernels (rows of A not 16-byte
+// aligned, or K not a whole number of steps): A' is N x kp (leading
+// dimension kp, zero beyond column P), B' is kp x M (zero beyond row P) when
+// copy_b.  zero_k: the product runs over all kp columns, which only adds
+// exact zeros to naive sums; otherwise it stops at P and kp bounds the
+// columns a last partial step may load (Gemm::kcap).  kp == 0: no copies.
+struct ValuPad {
+    i64 kp;
+    bool copy_b;
+    bool zero_k;
+};
+// Problems below this many multiply-adds (N P M) are not worth the copies.
+constexpr double kPadMinWork = 4294967296.0;
+enum ValuKind {
+    VK_NAIVE = 0,
+    VK_NAIVE_FMA,
+    VK_KAHAN,
+    VK_WINOGRAD,
+    VK_WINOGRAD_SCALED,
+    VK_ON_ARRAY,
+    VK_UNROLL2,
+    VK_UNROLL3,
+    VK_UNROLL4,
+    VK_DOT2,
+};
+
 // valu_gemm.hip
+// The copies a product of this kind and shape takes (shape only: pointers
+// are unknown when the workspace is sized).
+ValuPad valu_pad_plan(ValuKind kind, i64 N, i64 P, i64 M);
 hipError_t launch_naive(const Gemm& g, bool fused, hipStream_t s);
 hipError_t launch_naive_strassen_leaves(const StrassenLeafSrc& src, hipStream_t s);
 hipError_t launch_kahan(const Gemm& g, hipStream_t s);
@@ -15,6 +45,7 @@ hipError_t launch_naive_variant(const Gemm& g, int variant, hipStream_t s);
 hipError_t launch_winograd_main(const Gemm& g, const double* y, const double* z, const int* lam, hipStream_t s);
 
 // dgemm.hip
+ValuPad dgemm_pad_plan(i64 N, i64 P, i64 M);
 hipError_t launch_dgemm(const Gemm& g, hipStream_t s);
 hipError_t launch_dgemm_strassen_leaves(const StrassenLeafSrc& src, hipStream_t s);
 

@@ -407,12 +407,15 @@ struct ValuTile {
 
     // Direct loads (host has checked: tile inside the matrices, kmax a
     // multiple of BK, aligned operands with even leading dimensions).
+    template <bool PART>
     __device__ __forceinline__ static void mainloop_dma(const Gemm& g, i64 m0, i64 n0, i64 kmax, double sa,
                                                         double sb, SmemDma& sm, double (&acc)[TM][TN],
                                                         double (&cmp)[TM][TN])
     {
         const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, tx = tid % 16, ty = tid / 16;
-        const i64 nt = kmax / BK;
+        // PART: a partial last step, whose loads read zero-padded operands
+        // (host-checked); otherwise kmax is a whole number of steps
+        const i64 nt = PART ? (kmax + BK - 1) / BK : kmax / BK;
         // lane l of a wave instruction writes LDS bytes 16 l .. 16 l + 15 of
         // its KiB block; it fetches the global chunk that belongs there
         auto issue = [&](i64 t, int buf) __attribute__((always_inline)) {
@@ -495,6 +498,38 @@ struct ValuTile {
                 }
             }
         };
+        // the last step when K is not a whole number of steps: kc < BK
+        // entries (a multiple of the group length; Winograd: even)
+        auto compute_part = [&](int buf, int kc) __attribute__((always_inline)) {
+            if constexpr (Q == 4) {
+                for (int kp = 0; kp < kc / 2; kp += 2) {
+                    double a[4][TM], b[4][TN];
+                    frag_pair(buf, kp, a[0], a[1], b[0], b[1]);
+                    frag_pair(buf, kp + 1, a[2], a[3], b[2], b[3]);
+                    arith_group<4, TM, TN>(a, b, acc);
+                }
+            } else {
+                for (int kp = 0; kp < kc / 2; ++kp) {
+                    double a[2][TM], b[2][TN];
+                    frag_pair(buf, kp, a[0], a[1], b[0], b[1]);
+                    if constexpr (OP == OP_WINOGRAD) {
+                        arith_pair<TM, TN>(a[0], a[1], b[0], b[1], acc);
+                    } else if constexpr (Q == 2) {
+                        arith_group<2, TM, TN>(a, b, acc);
+                    } else {
+                        arith_k<OP, TM, TN>(a[0], b[0], acc, cmp);
+                        arith_k<OP, TM, TN>(a[1], b[1], acc, cmp);
+                    }
+                }
+                if constexpr (OP != OP_WINOGRAD && Q == 0) {
+                    if (kc & 1) {
+                        double a[2][TM], b[2][TN];
+                        frag_pair(buf, kc / 2, a[0], a[1], b[0], b[1]);
+                        arith_k<OP, TM, TN>(a[0], b[0], acc, cmp);
+                    }
+                }
+            }
+        };
         if (OP == OP_ON_ARRAY) c_io<false>(g, m0, n0, true, acc);  // C = 0
         if (nt > 0) issue(0, 0);
         for (i64 t = 0; t < nt; ++t) {
@@ -506,15 +541,23 @@ struct ValuTile {
             __syncthreads();
             if (t + 1 < nt) issue(t + 1, cur ^ 1);
             c_io<false>(g, m0, n0, false, acc);
-            compute(cur);
+            if constexpr (PART) {
+                const i64 rem = kmax - t * BK;
+                if (rem >= BK) compute(cur);
+                else compute_part(cur, (int)rem);
+            } else {
+                compute(cur);
+            }
             c_io<false>(g, m0, n0, true, acc);
         }
     }
 
-    template <bool DMA>
+    // MODE 0: register staging; 1: direct loads, whole K steps; 2: direct
+    // loads with a partial last step
+    template <int MODE>
     __device__ __forceinline__ static void run(const Gemm& g, i64 tm, i64 tn, const double* __restrict__ yv,
                                                const double* __restrict__ zv, const int* lam,
-                                               typename std::conditional<DMA, SmemDma, SmemReg>::type& sm)
+                                               typename std::conditional<MODE != 0, SmemDma, SmemReg>::type& sm)
     {
         const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
         const i64 m0 = tm * BM, n0 = tn * BN;
@@ -533,8 +576,8 @@ struct ValuTile {
                 acc[i][j] = 0.0;
                 cmp[i][j] = 0.0;
             }
-        if constexpr (DMA) {
-            mainloop_dma(g, m0, n0, kmax, sa, sb, sm, acc, cmp);
+        if constexpr (MODE != 0) {
+            mainloop_dma<MODE == 2>(g, m0, n0, kmax, sa, sb, sm, acc, cmp);
         } else {
             if (m0 + BM <= g.N && n0 + BN <= g.M) mainloop_reg<false>(g, m0, n0, kmax, sa, sb, sm, acc, cmp);
             else mainloop_reg<true>(g, m0, n0, kmax, sa, sb, sm, acc, cmp);
@@ -580,35 +623,50 @@ struct ValuTile {
     }
 };
 
-template <int BM, int BN, int TM, int TN, int OP, bool SCALED, bool DMA, class Src>
-__global__ __launch_bounds__(NT, (DMA && OP != OP_KAHAN && OP != OP_DOT2) ? MMM_VALU_DMA_MINWAVES : MMM_VALU_MINWAVES) void valu_gemm_kernel(Src src, i64 tiles_m, i64 tiles_n,
-                                                                          i64 total, const double* __restrict__ yv,
-                                                                          const double* __restrict__ zv,
-                                                                          const int* lam)
+template <int BM, int BN, int TM, int TN, int OP, bool SCALED, int MODE, class Src>
+__global__ __launch_bounds__(NT, (MODE != 0 && OP != OP_KAHAN && OP != OP_DOT2) ? MMM_VALU_DMA_MINWAVES
+                                                                                : MMM_VALU_MINWAVES) void
+valu_gemm_kernel(Src src, i64 tiles_m, i64 tiles_n, i64 total, const double* __restrict__ yv,
+                 const double* __restrict__ zv, const int* lam)
 {
     typedef ValuTile<BM, BN, TM, TN, OP, SCALED> T;
-    __shared__ __align__(16) typename std::conditional<DMA, typename T::SmemDma, typename T::SmemReg>::type sm;
+    __shared__ __align__(16) typename std::conditional<MODE != 0, typename T::SmemDma, typename T::SmemReg>::type sm;
     i64 prob, tm, tn;
     tile_of(xcd_remap(blockIdx.x, total), tiles_m, tiles_n, prob, tm, tn);
-    T::template run<DMA>(src.get(prob), tm, tn, yv, zv, lam, sm);
+    T::template run<MODE>(src.get(prob), tm, tn, yv, zv, lam, sm);
 }
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
-// Direct loads need every tile inside the matrices, the grouped K range a
-// whole number of steps and 16-byte aligned rows of A and B.
+// Direct loads need every tile inside the matrices and 16-byte aligned rows
+// of A and B; the grouped K range a whole number of steps (mode 1) or
+// operands readable up to the next whole step (mode 2, zero-padded copies).
+// Returns the mode, 0 when the problem takes register staging.
 template <class T>
-bool direct_ok(const SingleSrc& src, i64 bm, i64 bn)
+int direct_mode(const SingleSrc& src, i64 bm, i64 bn)
 {
     const Gemm& g = src.g;
     const i64 kmax = T::kmax_of(g.P);
-    return MMM_VALU_DMA && T::DMA_OK && g.N % bm == 0 && g.M % bn == 0 && kmax > 0 && kmax % T::BK == 0 &&
-           g.lda % 2 == 0 && g.ldb % 2 == 0 && aligned16(g.A) && aligned16(g.B);
+    const i64 kcap = g.kcap > g.P ? g.kcap : g.P;
+    if (!(MMM_VALU_DMA && T::DMA_OK && g.N % bm == 0 && g.M % bn == 0 && kmax > 0 && g.lda % 2 == 0 &&
+          g.ldb % 2 == 0 && aligned16(g.A) && aligned16(g.B)))
+        return 0;
+    if (kmax % T::BK == 0) return 1;
+    return kcap >= (kmax + T::BK - 1) / T::BK * T::BK ? 2 : 0;
 }
 template <class T>
-bool direct_ok(const StrassenLeafSrc&, i64, i64)
+int direct_mode(const StrassenLeafSrc&, i64, i64)
 {
-    return false;
+    return 0;
+}
+
+template <int BM, int BN, int TM, int TN, int OP, bool SCALED, int MODE, class Src>
+hipError_t launch_valu_mode(const Src& src, i64 tiles_m, i64 tiles_n, i64 total, const double* yv, const double* zv,
+                            const int* lam, hipStream_t s)
+{
+    hipLaunchKernelGGL((valu_gemm_kernel<BM, BN, TM, TN, OP, SCALED, MODE, Src>), dim3((unsigned)total), dim3(NT), 0, s,
+                       src, tiles_m, tiles_n, total, yv, zv, lam);
+    return hipGetLastError();
 }
 
 template <int BM, int BN, int TM, int TN, int OP, bool SCALED, class Src>
@@ -621,20 +679,16 @@ hipError_t launch_valu(const Src& src, i64 N, i64 M, const double* yv, const dou
     if (total == 0) return hipSuccess;
     if (total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     if constexpr (T::DMA_OK) {
-        if (direct_ok<T>(src, BM, BN)) {
-            hipLaunchKernelGGL((valu_gemm_kernel<BM, BN, TM, TN, OP, SCALED, true, Src>), dim3((unsigned)total),
-                               dim3(NT), 0, s, src, tiles_m, tiles_n, total, yv, zv, lam);
-            return hipGetLastError();
-        }
+        const int mode = direct_mode<T>(src, BM, BN);
+        if (mode == 1) return launch_valu_mode<BM, BN, TM, TN, OP, SCALED, 1>(src, tiles_m, tiles_n, total, yv, zv, lam, s);
+        if (mode == 2) return launch_valu_mode<BM, BN, TM, TN, OP, SCALED, 2>(src, tiles_m, tiles_n, total, yv, zv, lam, s);
     }
-    hipLaunchKernelGGL((valu_gemm_kernel<BM, BN, TM, TN, OP, SCALED, false, Src>), dim3((unsigned)total), dim3(NT), 0,
-                       s, src, tiles_m, tiles_n, total, yv, zv, lam);
-    return hipGetLastError();
+    return launch_valu_mode<BM, BN, TM, TN, OP, SCALED, 0>(src, tiles_m, tiles_n, total, yv, zv, lam, s);
 }
 
-// Launch the direct-load kernel of this tile shape when the problem
-// qualifies; false otherwise (nothing launched, the register-staged
-// kernel of this shape is not instantiated).
+// Launch the whole-step direct-load kernel of this tile shape when the
+// problem qualifies; false otherwise (nothing launched, and no other
+// kernel of this shape is instantiated).
 template <int BM, int BN, int TM, int TN, int OP, bool SCALED, class Src>
 bool try_launch_direct(const Src& src, i64 N, i64 M, hipStream_t s, hipError_t& err)
 {
@@ -642,13 +696,11 @@ bool try_launch_direct(const Src& src, i64 N, i64 M, hipStream_t s, hipError_t& 
     if constexpr (!T::DMA_OK) {
         return false;
     } else {
-        if (!direct_ok<T>(src, BM, BN)) return false;
+        if (direct_mode<T>(src, BM, BN) != 1) return false;
         const i64 tiles_m = cdiv(N, BM), tiles_n = cdiv(M, BN);
         const i64 total = tiles_m * tiles_n * src.count();
         if (total == 0 || total > 0x7fffffffLL) return false;
-        hipLaunchKernelGGL((valu_gemm_kernel<BM, BN, TM, TN, OP, SCALED, true, Src>), dim3((unsigned)total), dim3(NT), 0,
-                           s, src, tiles_m, tiles_n, total, nullptr, nullptr, nullptr);
-        err = hipGetLastError();
+        err = launch_valu_mode<BM, BN, TM, TN, OP, SCALED, 1>(src, tiles_m, tiles_n, total, nullptr, nullptr, nullptr, s);
         return true;
     }
 }
@@ -661,6 +713,20 @@ typedef Shape<MMM_VALU_NAIVE_TILE> NaiveShape;
 typedef Shape<MMM_VALU_KAHAN_TILE> KahanShape;
 typedef Shape<MMM_VALU_WINO_TILE> WinoShape;
 
+// Tile of the inner-product methods for problems past the small case.
+// Kahan keeps two doubles per entry, the longer groups and the on-array
+// round trips more operands in flight: 64 x 64 tiles for those.
+template <int OP>
+struct ShapeOf {
+    static constexpr bool small =
+        OP == OP_KAHAN || OP == OP_UNROLL3 || OP == OP_UNROLL4 || OP == OP_ON_ARRAY || OP == OP_DOT2;
+    typedef typename std::conditional<
+        OP == OP_WINOGRAD, WinoShape,
+        typename std::conditional<OP == OP_KAHAN || OP == OP_DOT2, KahanShape,
+                                  typename std::conditional<small, Shape<64, 64, 4, 4>, NaiveShape>::type>::type>::type
+        type;
+};
+
 // Small problems (every dimension <= 48, e.g. the m x m leaves of the
 // paper's Strassen embedding) use 32 x 32 tiles.
 template <int OP, class Src>
@@ -672,15 +738,53 @@ hipError_t launch_naive_like(const Src& src, i64 N, i64 M, hipStream_t s)
         hipError_t err = hipSuccess;
         if (try_launch_direct<D::bm, D::bn, D::tm, D::tn, OP, false>(src, N, M, s, err)) return err;
     }
-    // Kahan keeps two doubles per entry, the longer groups and the on-array
-    // round trips more operands in flight: 64 x 64 tiles for those
-    constexpr bool small = OP == OP_KAHAN || OP == OP_UNROLL3 || OP == OP_UNROLL4 || OP == OP_ON_ARRAY || OP == OP_DOT2;
-    typedef typename std::conditional<OP == OP_KAHAN || OP == OP_DOT2, KahanShape,
-                                      typename std::conditional<small, Shape<64, 64, 4, 4>, NaiveShape>::type>::type S;
+    typedef typename ShapeOf<OP>::type S;
     return launch_valu<S::bm, S::bn, S::tm, S::tn, OP, false>(src, N, M, nullptr, nullptr, nullptr, s);
 }
 
+// Copies for the tile the launcher takes at this shape (the 128 x 64 naive
+// tile's conditions also admit the 128 x 128 one when M allows it: both take
+// whole steps over the zero-padded K).
+template <int OP, bool SCALED>
+ValuPad pad_plan_op(i64 N, i64 P, i64 M, bool zero_k)
+{
+    typedef typename ShapeOf<OP>::type S;
+    typedef ValuTile<S::bm, S::bn, S::tm, S::tn, OP, SCALED> T;
+    ValuPad p{0, false, false};
+    if (!MMM_VALU_DMA || !T::DMA_OK || (N <= 48 && M <= 48) || N % S::bm != 0 || M % S::bn != 0) return p;
+    if ((double)N * (double)P * (double)M < kPadMinWork) return p;
+    const i64 kmax = T::kmax_of(P);
+    if (kmax <= 0 || (P % 2 == 0 && kmax % T::BK == 0)) return p;  // direct loads as it is
+    const i64 kw = cdiv(kmax, T::BK) * T::BK;                      // K the last step loads
+    if (zero_k) {
+        p.kp = cdiv(P, T::BK) * T::BK;
+        p.copy_b = p.kp > P;
+        p.zero_k = true;
+    } else {
+        p.kp = kw > P + (P & 1) ? kw : P + (P & 1);
+        p.copy_b = kw > P;
+    }
+    return p;
+}
+
 }  // namespace
+
+ValuPad valu_pad_plan(ValuKind kind, i64 N, i64 P, i64 M)
+{
+    switch (kind) {
+    case VK_NAIVE: return pad_plan_op<OP_NAIVE, false>(N, P, M, true);
+    case VK_NAIVE_FMA: return pad_plan_op<OP_NAIVE_FMA, false>(N, P, M, true);
+    case VK_KAHAN: return pad_plan_op<OP_KAHAN, false>(N, P, M, false);
+    case VK_WINOGRAD: return pad_plan_op<OP_WINOGRAD, false>(N, P, M, false);
+    case VK_WINOGRAD_SCALED: return pad_plan_op<OP_WINOGRAD, true>(N, P, M, false);
+    case VK_ON_ARRAY: return pad_plan_op<OP_ON_ARRAY, false>(N, P, M, false);
+    case VK_UNROLL2: return pad_plan_op<OP_UNROLL2, false>(N, P, M, false);
+    case VK_UNROLL3: return pad_plan_op<OP_UNROLL3, false>(N, P, M, false);
+    case VK_UNROLL4: return pad_plan_op<OP_UNROLL4, false>(N, P, M, false);
+    case VK_DOT2: return pad_plan_op<OP_DOT2, false>(N, P, M, false);
+    }
+    return ValuPad{0, false, false};
+}
 
 hipError_t launch_naive(const Gemm& g, bool fused, hipStream_t s)
 {
@@ -716,7 +820,7 @@ hipError_t launch_kahan(const Gemm& g, hipStream_t s)
 hipError_t launch_winograd_main(const Gemm& g, const double* y, const double* z, const int* lam, hipStream_t s)
 {
     SingleSrc src{g};
-    typedef WinoShape S;
+    typedef typename ShapeOf<OP_WINOGRAD>::type S;
     if (lam) return launch_valu<S::bm, S::bn, S::tm, S::tn, OP_WINOGRAD, true>(src, g.N, g.M, y, z, lam, s);
     return launch_valu<S::bm, S::bn, S::tm, S::tn, OP_WINOGRAD, false>(src, g.N, g.M, y, z, nullptr, s);
 }

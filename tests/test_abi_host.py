@@ -41,8 +41,25 @@ def test_config_default_and_version(lib):
 
 def test_workspace_arithmetic(lib):
     ws = lib.workspace_bytes
-    for m in ("naive", "kahan", "dgemm"):
-        assert ws(m, 4096, 4097, 4096) == 0
+    # dense-K shapes, small products and tiles that do not fit N or M run on
+    # the caller's operands
+    for m in ("naive", "kahan", "dgemm", "naive_unroll3", "dot2"):
+        assert ws(m, 4096, 4096, 4096) == 0
+        assert ws(m, 1024, 1025, 1024) == 0          # N P M < 2^32
+        assert ws(m, 4000, 4097, 4096) == 0          # 4000 is no multiple of the tile rows
+    assert ws("naive_unroll3", 4096, 4097, 4096) == 0  # no direct-load kernel for groups of three
+    # P = 4097 on 4096 x 4096: zero-padded A (N x kp) and B (kp x M), kp the
+    # next multiple of the K step (16; 32 for Kahan)
+    assert ws("naive", 4096, 4097, 4096) == 2 * 4096 * 4112 * 8
+    assert ws("dgemm", 4096, 4097, 4096) == 2 * 4096 * 4112 * 8
+    assert ws("kahan", 4096, 4097, 4096) == 2 * 4096 * 4128 * 8
+    assert ws("dot2", 4096, 4097, 4096) == 2 * 4096 * 4112 * 8
+    # Winograd's pairs end at 4096 (a whole step): only A is copied, to an
+    # even row length, after y and z
+    assert ws("winograd", 4096, 4097, 4096) == 2 * 32768 + 4096 * 4098 * 8
+    assert ws("winograd_scaled", 4096, 4097, 4096) == 2 * 32768 + 3 * 256 + 4096 * 4098 * 8
+    # P even but not a multiple of the step: the same copies
+    assert ws("naive", 4096, 4100, 4096) == 2 * 4096 * 4112 * 8
     assert ws("winograd", 100, 7, 300) == 1024 + 2560  # y: 800 B -> 1024, z: 2400 B -> 2560
     assert ws("winograd_scaled", 100, 7, 300) == 1024 + 2560 + 3 * 256
     cfg = lib.Config(strassen_levels=2)

@@ -232,6 +232,41 @@ def test_full_size_sampled_rows(mmm, orc, P):
             assert err(rows_of(name, mmm.Config(strassen_levels=L))) <= TOL_STRASSEN, (name, L)
 
 
+@pytest.mark.parametrize("P", [1025, 1030, 1040, 1047])
+def test_padded_operand_copies_sampled_rows(mmm, orc, P):
+    """N = M = 2048 with P whose rows of A are not 16-byte aligned (odd P)
+    or whose K range ends in a partial step (P mod 16 or 32 != 0): large
+    products run on zero-padded copies of A and B (whole padded steps for the
+    naive sums and DGEMM, a partial last step for the other recurrences).
+    Same bits as the oracle on sampled rows; DGEMM within tolerance."""
+    N = M = 2048
+    print("case padded copies P =", P, flush=True)
+    A = synth.uniform((N, P), synth.seed_a(7))
+    B = synth.uniform((P, M), synth.seed_b(7))
+    rows = np.array([0, 1, 63, 64, 1023, 1500, 2046, 2047])
+    Ad, Bd = dev(A), dev(B)
+    padded = [m for m in ("naive", "kahan", "winograd", "winograd_scaled", "dgemm") + tuple(VARIANTS)
+              if mmm.workspace_bytes(m, N, P, M) > (2 * 16384 + 3 * 256 if m.startswith("winograd") else 0)]
+    # every residue here sends some method through the copies
+    assert padded, P
+    if P % 2:
+        assert {"naive", "kahan", "winograd", "dgemm", "dot2"} <= set(padded)
+
+    def rows_of(method):
+        C = mmm.multiply(Ad, Bd, method)
+        torch.cuda.synchronize()
+        return C[torch.from_numpy(rows).cuda()].cpu().numpy()
+
+    ref = orc.naive_rows(A, B, rows)
+    assert bits_equal(rows_of("naive"), ref)
+    assert bits_equal(rows_of("kahan"), orc.kahan_rows(A, B, rows))
+    assert bits_equal(rows_of("winograd"), orc.winograd_rows(A, B, rows))
+    assert bits_equal(rows_of("winograd_scaled"), orc.winograd_rows(A, B, rows, scaled=True))
+    assert orc.norm_inf(orc.minus(rows_of("dgemm"), ref)) / (orc.norm_inf(A) * orc.norm_inf(B)) <= TOL_PLAIN
+    for name in VARIANTS:
+        assert bits_equal(rows_of(name), _variant_ref(orc, name, A[rows], B)), name
+
+
 @pytest.mark.parametrize("shape", [(2048, 2048, 2048), (2048, 512, 4096), (4096, 16, 2048), (1024, 4096, 8192)])
 def test_dgemm_direct_load_path_exact(mmm, shape):
     """Shapes whose every tile takes the direct global-to-LDS path (N, M
