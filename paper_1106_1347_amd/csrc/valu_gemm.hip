@@ -49,6 +49,9 @@
 #endif
 // NaivStandard on the direct-load path: no staging registers, room for an
 // 8 x 8 block per thread
+#ifndef MMM_VALU_WINO_DMA_TILE
+#define MMM_VALU_WINO_DMA_TILE 128, 128, 8, 8
+#endif
 #ifndef MMM_VALU_NAIVE_DMA_TILE
 #define MMM_VALU_NAIVE_DMA_TILE 128, 128, 8, 8
 #endif
@@ -268,6 +271,11 @@ struct ValuTile {
     };
 
     __device__ __forceinline__ static int swz(int r) { return (r / TM) & (CH - 1); }
+    // Slot of 16-byte chunk c in a B row (direct loads).  At 4 columns per
+    // thread and half, the 16 threads of a row read every other chunk, 32
+    // bytes apart; flipping the low bit of the chunks in odd blocks of 16
+    // puts those reads on all 16 bank groups.
+    __device__ __forceinline__ static int bslot(int c) { return TH % 4 == 0 ? c ^ ((c >> 4) & 1) : c; }
 
     // NaivOnArray: the running sum lives in the entries of C; every K step
     // reads them and writes them back (the first step starts from the zeroed
@@ -430,7 +438,7 @@ struct ValuTile {
 #pragma unroll
             for (int q = 0; q < NB / 4; ++q) {
                 const int blk = q * 4 + wave, p = blk * 64 + lane;
-                const int r = p / (BN / 2), c = p % (BN / 2);
+                const int r = p / (BN / 2), c = bslot(p % (BN / 2));
                 const double* src = g.B + (k0 + r) * g.ldb + n0 + 2 * c;
                 __builtin_amdgcn_global_load_lds((gbl_ptr_t)src, (lds_ptr_t)&sm.B[buf][blk * 128], 16, 0, 0);
             }
@@ -464,7 +472,7 @@ struct ValuTile {
             for (int h = 0; h < 2; ++h)
 #pragma unroll
                 for (int j = 0; j < TH; j += 2) {
-                    const int col = h * (BN / 2) + tx * TH + j;
+                    const int col = 2 * bslot((h * (BN / 2) + tx * TH + j) / 2);
                     const double2 v0 = *reinterpret_cast<const double2*>(&sm.B[buf][(2 * kp) * BN + col]);
                     const double2 v1 = *reinterpret_cast<const double2*>(&sm.B[buf][(2 * kp + 1) * BN + col]);
                     b0[h * TH + j] = v0.x;
@@ -654,11 +662,6 @@ int direct_mode(const SingleSrc& src, i64 bm, i64 bn)
     if (kmax % T::BK == 0) return 1;
     return kcap >= (kmax + T::BK - 1) / T::BK * T::BK ? 2 : 0;
 }
-template <class T>
-int direct_mode(const StrassenLeafSrc&, i64, i64)
-{
-    return 0;
-}
 
 template <int BM, int BN, int TM, int TN, int OP, bool SCALED, int MODE, class Src>
 hipError_t launch_valu_mode(const Src& src, i64 tiles_m, i64 tiles_n, i64 total, const double* yv, const double* zv,
@@ -678,7 +681,8 @@ hipError_t launch_valu(const Src& src, i64 N, i64 M, const double* yv, const dou
     const i64 total = tiles_m * tiles_n * src.count();
     if (total == 0) return hipSuccess;
     if (total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    if constexpr (T::DMA_OK) {
+    // Strassen leaves never take direct loads (their operands are views)
+    if constexpr (T::DMA_OK && std::is_same<Src, SingleSrc>::value) {
         const int mode = direct_mode<T>(src, BM, BN);
         if (mode == 1) return launch_valu_mode<BM, BN, TM, TN, OP, SCALED, 1>(src, tiles_m, tiles_n, total, yv, zv, lam, s);
         if (mode == 2) return launch_valu_mode<BM, BN, TM, TN, OP, SCALED, 2>(src, tiles_m, tiles_n, total, yv, zv, lam, s);
@@ -690,17 +694,18 @@ hipError_t launch_valu(const Src& src, i64 N, i64 M, const double* yv, const dou
 // problem qualifies; false otherwise (nothing launched, and no other
 // kernel of this shape is instantiated).
 template <int BM, int BN, int TM, int TN, int OP, bool SCALED, class Src>
-bool try_launch_direct(const Src& src, i64 N, i64 M, hipStream_t s, hipError_t& err)
+bool try_launch_direct(const Src& src, i64 N, i64 M, const double* yv, const double* zv, const int* lam,
+                       hipStream_t s, hipError_t& err)
 {
     typedef ValuTile<BM, BN, TM, TN, OP, SCALED> T;
-    if constexpr (!T::DMA_OK) {
+    if constexpr (!T::DMA_OK || !std::is_same<Src, SingleSrc>::value) {
         return false;
     } else {
         if (direct_mode<T>(src, BM, BN) != 1) return false;
         const i64 tiles_m = cdiv(N, BM), tiles_n = cdiv(M, BN);
         const i64 total = tiles_m * tiles_n * src.count();
         if (total == 0 || total > 0x7fffffffLL) return false;
-        err = launch_valu_mode<BM, BN, TM, TN, OP, SCALED, 1>(src, tiles_m, tiles_n, total, nullptr, nullptr, nullptr, s);
+        err = launch_valu_mode<BM, BN, TM, TN, OP, SCALED, 1>(src, tiles_m, tiles_n, total, yv, zv, lam, s);
         return true;
     }
 }
@@ -736,7 +741,8 @@ hipError_t launch_naive_like(const Src& src, i64 N, i64 M, hipStream_t s)
     if constexpr (OP == OP_NAIVE || OP == OP_NAIVE_FMA) {
         typedef Shape<MMM_VALU_NAIVE_DMA_TILE> D;
         hipError_t err = hipSuccess;
-        if (try_launch_direct<D::bm, D::bn, D::tm, D::tn, OP, false>(src, N, M, s, err)) return err;
+        if (try_launch_direct<D::bm, D::bn, D::tm, D::tn, OP, false>(src, N, M, nullptr, nullptr, nullptr, s, err))
+            return err;
     }
     typedef typename ShapeOf<OP>::type S;
     return launch_valu<S::bm, S::bn, S::tm, S::tn, OP, false>(src, N, M, nullptr, nullptr, nullptr, s);
@@ -821,6 +827,11 @@ hipError_t launch_winograd_main(const Gemm& g, const double* y, const double* z,
 {
     SingleSrc src{g};
     typedef typename ShapeOf<OP_WINOGRAD>::type S;
+    typedef Shape<MMM_VALU_WINO_DMA_TILE> D;
+    hipError_t err = hipSuccess;
+    if (lam ? try_launch_direct<D::bm, D::bn, D::tm, D::tn, OP_WINOGRAD, true>(src, g.N, g.M, y, z, lam, s, err)
+            : try_launch_direct<D::bm, D::bn, D::tm, D::tn, OP_WINOGRAD, false>(src, g.N, g.M, y, z, nullptr, s, err))
+        return err;
     if (lam) return launch_valu<S::bm, S::bn, S::tm, S::tn, OP_WINOGRAD, true>(src, g.N, g.M, y, z, lam, s);
     return launch_valu<S::bm, S::bn, S::tm, S::tn, OP_WINOGRAD, false>(src, g.N, g.M, y, z, nullptr, s);
 }
