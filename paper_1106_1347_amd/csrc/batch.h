@@ -42,6 +42,15 @@ struct SplitGroup {
     int per_cu;  // workgroups of the group's kernel resident per CU
 };
 
+// A strip of 64 rows of one job's A (side 0) or B (side 1) for the
+// statistics pass of a split group.
+struct StatStrip {
+    int job;
+    int side;
+    i64 row0;
+};
+constexpr int kStatRows = 64;
+
 // Workspace bytes for one split job; fills the job's Np/Mp/Kp and returns
 // (size_t)-1 when unsupported.  Offsets of the job's buffers inside its
 // workspace are assigned by split_job_bind.
@@ -51,8 +60,10 @@ void split_job_bind(SplitJob& j, char* base, int dt, int s);
 // before recording launches into a graph.
 hipError_t split_grouped_prepare(const SplitGroup& grp);
 // Enqueue the grouped split pipeline for `n` jobs (device table `jobs`,
-// host copy `hjobs` for launch sizing), tile prefix table `prefix`.
+// host copy `hjobs` for launch sizing), tile prefix table `prefix`, and
+// `nstrips` statistics strips covering every row of every job's A and B.
 hipError_t launch_split_grouped(const SplitGroup& grp, const SplitJob* jobs, const SplitJob* hjobs, int n,
-                                const i64* prefix, i64 total_tiles, bool scale_lambda, int grid, hipStream_t s);
+                                const i64* prefix, i64 total_tiles, const StatStrip* strips, int nstrips,
+                                bool scale_lambda, int grid, hipStream_t s);
 
 }  // namespace mmm

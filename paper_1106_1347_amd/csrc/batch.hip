@@ -3,9 +3,10 @@
 // The plan groups the FP64 problems by DGEMM tile shape and the split
 // problems by (digit type, digit count, flush scheme); every group runs as
 // one persistent kernel that deals its tiles round robin over a grid sized
-// to the chip, preceded for split groups by batched preprocessing kernels
-// (norms, lambda, row/column maxima, digit extraction) whose blockIdx.y
-// selects the problem.  The FP64 groups and the split groups are recorded
+// to the chip, preceded for split groups by batched preprocessing kernels:
+// one pass over every 64-row strip of every problem's A and B for the
+// norms and row/column maxima (a strip table built here), lambda, and digit
+// extraction (blockIdx.y selects the problem).  The FP64 groups and the split groups are recorded
 // on two branches of one HIP graph, so they overlap on the device.  A
 // tile's arithmetic does not depend on the tile shape or on which workgroup
 // runs it, so every result equals the single-call result bit for bit.
@@ -48,7 +49,8 @@ struct SGroup {
     std::vector<SplitJob> jobs;
     std::vector<size_t> ws_off;
     std::vector<i64> prefix;
-    size_t off_jobs = 0, off_prefix = 0;
+    std::vector<StatStrip> strips;
+    size_t off_jobs = 0, off_prefix = 0, off_strips = 0;
 };
 
 struct Interval {
@@ -157,8 +159,15 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
     for (auto& kv : sg) {
         SGroup& g = kv.second;
         g.prefix.assign(g.jobs.size() + 1, 0);
+        // statistics strips: every 64 rows of every job's A, then of its B
+        for (size_t k = 0; k < g.jobs.size(); ++k) {
+            for (i64 r = 0; r < g.jobs[k].N; r += kStatRows) g.strips.push_back(StatStrip{(int)k, 0, r});
+            for (i64 r = 0; r < g.jobs[k].P; r += kStatRows) g.strips.push_back(StatStrip{(int)k, 1, r});
+        }
+        if (g.strips.size() > 0x7fffffffu) return bfail(MMM_EUNSUPPORTED, "batch: too many rows in split problems");
         g.off_jobs = take(sizeof(SplitJob) * g.jobs.size());
         g.off_prefix = take(sizeof(i64) * g.prefix.size());
+        g.off_strips = take(sizeof(StatStrip) * g.strips.size());
     }
     const size_t off_ws = off;
     const size_t total = off + split_ws + 256;
@@ -187,6 +196,7 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
     for (auto& kv : sg) {
         memcpy(host.data() + kv.second.off_jobs, kv.second.jobs.data(), sizeof(SplitJob) * kv.second.jobs.size());
         memcpy(host.data() + kv.second.off_prefix, kv.second.prefix.data(), sizeof(i64) * kv.second.prefix.size());
+        memcpy(host.data() + kv.second.off_strips, kv.second.strips.data(), sizeof(StatStrip) * kv.second.strips.size());
     }
     hipError_t e = hipSuccess;
     if (off_ws > 0) e = hipMemcpyAsync(base, host.data(), off_ws, hipMemcpyHostToDevice, s);
@@ -225,7 +235,8 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
             const i64 tiles = g.prefix.back();
             const int grid = (int)std::min<i64>(tiles, (i64)cus * g.g.per_cu);
             le = launch_split_grouped(g.g, (const SplitJob*)(base + g.off_jobs), g.jobs.data(), (int)g.jobs.size(),
-                                      (const i64*)(base + g.off_prefix), tiles, c.split_scale_lambda != 0, grid, side);
+                                      (const i64*)(base + g.off_prefix), tiles, (const StatStrip*)(base + g.off_strips),
+                                      (int)g.strips.size(), c.split_scale_lambda != 0, grid, side);
         }
         if (le == hipSuccess) le = hipEventRecord(join, side);
         if (le == hipSuccess) le = hipStreamWaitEvent(cap, join, 0);

@@ -180,9 +180,12 @@ __device__ inline void cut(const double* x, double sc, int e, int s, char* out, 
 // threads of one 64-byte digit block are adjacent, then rows, then blocks,
 // so the digit stores of a wave are contiguous.
 template <int DT>
+// rmax_raw: rmax holds max_k |A_ik| before the 2^lambda scaling (exact to
+// scale afterwards: x -> fl(2^lambda x) is monotone, so it commutes with max).
 __device__ __forceinline__ void split_a_body(const double* __restrict__ A, i64 N, i64 P, i64 Np, i64 Kp,
                                              const double* __restrict__ rmax, const int* lam, int s,
-                                             char* __restrict__ SA, int* __restrict__ ea, i64 block, i64 nblocks)
+                                             char* __restrict__ SA, int* __restrict__ ea, i64 block, i64 nblocks,
+                                             bool rmax_raw = false)
 {
     constexpr int ES = Digit<DT>::esize;
     constexpr int TB = KB / (8 * ES);  // threads per 64-byte block
@@ -192,7 +195,7 @@ __device__ __forceinline__ void split_a_body(const double* __restrict__ A, i64 N
         const int q = (int)(c % TB);
         const i64 rest = c / TB, i = rest % Np, kb = rest / Np;
         const i64 k0 = kb * (KB / ES) + q * 8;
-        const int e = i < N ? vec_exponent(rmax[i]) : 0;
+        const int e = i < N ? vec_exponent(rmax_raw ? rmax[i] * sc : rmax[i]) : 0;
         double x[8];
 #pragma unroll
         for (int r = 0; r < 8; ++r) x[r] = (i < N && k0 + r < P) ? A[i * P + k0 + r] : 0.0;
@@ -216,7 +219,8 @@ __global__ __launch_bounds__(256) void split_a_kernel(const double* __restrict__
 template <int DT>
 __device__ __forceinline__ void split_b_body(const double* __restrict__ B, i64 P, i64 M, i64 Mp, i64 Kp,
                                              const double* __restrict__ cmax, const int* lam, int s,
-                                             char* __restrict__ SB, int* __restrict__ fb, i64 block, double (*T)[65])
+                                             char* __restrict__ SB, int* __restrict__ fb, i64 block, double (*T)[65],
+                                             bool cmax_raw = false)
 {
     constexpr int ES = Digit<DT>::esize;
     constexpr int TB = KB / (8 * ES);  // threads per 64-byte block
@@ -239,7 +243,7 @@ __device__ __forceinline__ void split_b_body(const double* __restrict__ B, i64 P
         const int q = c % TB, jc = (c / TB) % 64, blk = c / (TB * 64);
         const int kk = blk * (KB / ES) + q * 8;
         const i64 j = j0 + jc;
-        const int e = j < M ? vec_exponent(cmax[j]) : 0;
+        const int e = j < M ? vec_exponent(cmax_raw ? cmax[j] * sc : cmax[j]) : 0;
         double x[8];
 #pragma unroll
         for (int r = 0; r < 8; ++r) x[r] = T[kk + r][jc];
@@ -518,26 +522,79 @@ __global__ __launch_bounds__(grouped_tile_cfg(DT, S, FLUSH).threads(), grouped_t
 
 // ---- batched preprocessing: blockIdx.y selects the job -----------------------
 
-__global__ void jobs_zero_norms_kernel(const SplitJob* jobs, int n)
+// Clears the atomic-max targets of every job (one workgroup per job): the
+// two norms and the column maxima of B.
+__global__ __launch_bounds__(256) void jobs_zero_stats_kernel(const SplitJob* __restrict__ jobs)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i < n) {
-        *jobs[i].nA = 0.0;
-        *jobs[i].nB = 0.0;
+    const SplitJob& j = jobs[blockIdx.x];
+    if (threadIdx.x == 0) {
+        *j.nA = 0.0;
+        *j.nB = 0.0;
     }
+    for (i64 c = threadIdx.x; c < j.M; c += 256) j.cmax[c] = 0.0;
 }
 
-// which = 0: NormInf of A; 1: NormInf of B (row sums folded by atomic max)
-__global__ __launch_bounds__(256) void jobs_norm_kernel(const SplitJob* __restrict__ jobs, int which)
+// Largest of non-negative doubles by their bit patterns (which order them
+// as numbers), over the lanes of a wave.
+__device__ inline unsigned long long wave_max_bits(unsigned long long u, int from)
 {
-    __shared__ double T[2][RV][RL + 1];
-    const SplitJob& j = jobs[blockIdx.y];
-    const double* X = which ? j.B : j.A;
-    const i64 rows = which ? j.P : j.N, cols = which ? j.M : j.P;
-    const i64 blocks = (rows + RV - 1) / RV;
-    for (i64 b = blockIdx.x; b < blocks; b += gridDim.x) {
-        vecred_body<RED_ABS_SUM, false, false, true>(X, cols, rows, cols, which ? j.nB : j.nA, nullptr, 0, b, T);
+    for (int o = from; o < 64; o *= 2) {
+        const unsigned long long v = __shfl_xor(u, o);
+        u = v > u ? v : u;
+    }
+    return u;
+}
+
+// One pass over a strip of 64 rows of A or B (one wave, one row per lane):
+//   - NormInf (Section 1.4): each lane sums |x| along its row in order from
+//     0.0, as the sequential definition does; the largest row sum of the
+//     wave goes to the job's norm by an atomic max (NORMS only);
+//   - A: max_k |A_ik| of each row to rmax (before any 2^lambda scaling);
+//   - B: max_k |B_kj| of each column over the strip's rows, folded into
+//     cmax by an atomic max (cleared beforehand).
+// Rows are staged through LDS 16 columns at a time so the loads are
+// contiguous 128-byte runs.
+template <bool NORMS>
+__global__ __launch_bounds__(64) void jobs_stats_kernel(const SplitJob* __restrict__ jobs,
+                                                        const StatStrip* __restrict__ strips)
+{
+    __shared__ double T[kStatRows][17];
+    const StatStrip st = strips[blockIdx.x];
+    const SplitJob& j = jobs[st.job];
+    const int lane = threadIdx.x;
+    const bool side_b = st.side != 0;
+    const double* X = side_b ? j.B : j.A;
+    const i64 rows = side_b ? j.P : j.N, len = side_b ? j.M : j.P, r0 = st.row0;
+    double sum = 0.0, mx = 0.0;
+    for (i64 c0 = 0; c0 < len; c0 += 16) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int rr = q * 4 + lane / 16, cc = lane % 16;
+            const i64 gr = r0 + rr, gc = c0 + cc;
+            T[rr][cc] = (gr < rows && gc < len) ? fabs(X[gr * len + gc]) : 0.0;
+        }
         __syncthreads();
+        const int cnt = len - c0 < 16 ? (int)(len - c0) : 16;
+        for (int x = 0; x < cnt; ++x) {
+            const double v = T[lane][x];
+            if (NORMS) sum = sum + v;
+            mx = max_s13(mx, v);
+        }
+        if (side_b) {
+            const int cc = lane % 16, g = lane / 16;
+            double m = 0.0;
+#pragma unroll
+            for (int rr = 0; rr < 16; ++rr) m = max_s13(m, T[g * 16 + rr][cc]);
+            const unsigned long long u = wave_max_bits((unsigned long long)__double_as_longlong(m), 16);
+            if (lane < 16 && c0 + lane < len) atomicMax(reinterpret_cast<unsigned long long*>(&j.cmax[c0 + lane]), u);
+        }
+        __syncthreads();
+    }
+    const bool live = r0 + lane < rows;
+    if (!side_b && live) j.rmax[r0 + lane] = mx;
+    if (NORMS) {
+        const unsigned long long u = wave_max_bits(live ? (unsigned long long)__double_as_longlong(sum) : 0ull, 1);
+        if (lane == 0) atomicMax(reinterpret_cast<unsigned long long*>(side_b ? j.nB : j.nA), u);
     }
 }
 
@@ -559,28 +616,12 @@ __global__ void jobs_lambda_kernel(const SplitJob* jobs, int n)
     }
 }
 
-// which = 0: max |2^l A_ik| over each row of A; 1: max |2^-l B_kj| over each column of B
-template <bool SCALED>
-__global__ __launch_bounds__(256) void jobs_absmax_kernel(const SplitJob* __restrict__ jobs, int which)
-{
-    __shared__ double T[2][RV][RL + 1];
-    const SplitJob& j = jobs[blockIdx.y];
-    const i64 nvec = which ? j.M : j.N;
-    const i64 blocks = (nvec + RV - 1) / RV;
-    for (i64 b = blockIdx.x; b < blocks; b += gridDim.x) {
-        if (which)
-            vecred_body<RED_ABS_MAX, true, SCALED, false>(j.B, j.M, j.M, j.P, j.cmax, SCALED ? j.lam : nullptr, -1, b, T);
-        else
-            vecred_body<RED_ABS_MAX, false, SCALED, false>(j.A, j.P, j.N, j.P, j.rmax, SCALED ? j.lam : nullptr, +1, b, T);
-        __syncthreads();
-    }
-}
-
 template <int DT>
 __global__ __launch_bounds__(256) void jobs_split_a_kernel(const SplitJob* __restrict__ jobs, int s, bool scaled)
 {
     const SplitJob& j = jobs[blockIdx.y];
-    split_a_body<DT>(j.A, j.N, j.P, j.Np, j.Kp, j.rmax, scaled ? j.lam : nullptr, s, j.SA, j.ea, blockIdx.x, gridDim.x);
+    split_a_body<DT>(j.A, j.N, j.P, j.Np, j.Kp, j.rmax, scaled ? j.lam : nullptr, s, j.SA, j.ea, blockIdx.x, gridDim.x,
+                     true);
 }
 
 template <int DT>
@@ -590,7 +631,7 @@ __global__ __launch_bounds__(256) void jobs_split_b_kernel(const SplitJob* __res
     const SplitJob& j = jobs[blockIdx.y];
     const i64 blocks = (j.Kp / 64) * (j.Mp / 64);
     for (i64 b = blockIdx.x; b < blocks; b += gridDim.x) {
-        split_b_body<DT>(j.B, j.P, j.M, j.Mp, j.Kp, j.cmax, scaled ? j.lam : nullptr, s, j.SB, j.fb, b, T);
+        split_b_body<DT>(j.B, j.P, j.M, j.Mp, j.Kp, j.cmax, scaled ? j.lam : nullptr, s, j.SB, j.fb, b, T, true);
         __syncthreads();
     }
 }
@@ -768,33 +809,26 @@ hipError_t grouped_s(const SplitGroup& g, const SplitJob* jobs, const i64* prefi
 
 template <int DT>
 hipError_t launch_split_grouped_dt(const SplitGroup& g, const SplitJob* jobs, const SplitJob* hjobs, int n,
-                                   const i64* prefix, i64 total, bool scale, int grid, hipStream_t st)
+                                   const i64* prefix, i64 total, const StatStrip* strips, int nstrips, bool scale,
+                                   int grid, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     hipError_t e;
-    i64 max_rows_a = 0, max_rows_b = 0, max_cols_b = 0, max_a = 0, max_b = 0;
+    i64 max_a = 0, max_b = 0;
     for (int i = 0; i < n; ++i) {
         const SplitJob& j = hjobs[i];
-        max_rows_a = j.N > max_rows_a ? j.N : max_rows_a;
-        max_rows_b = j.P > max_rows_b ? j.P : max_rows_b;
-        max_cols_b = j.M > max_cols_b ? j.M : max_cols_b;
         const i64 ba = cdiv(j.Np * (j.Kp / 8), 256), bb = (j.Kp / 64) * (j.Mp / 64);
         max_a = ba > max_a ? ba : max_a;
         max_b = bb > max_b ? bb : max_b;
     }
     auto cap = [](i64 x) { return (unsigned)(x < 1 ? 1 : (x > 64 ? 64 : x)); };
     const dim3 blk(256);
-    if (scale) {
-        hipLaunchKernelGGL(jobs_zero_norms_kernel, dim3((unsigned)cdiv(n, 256)), blk, 0, st, jobs, n);
-        hipLaunchKernelGGL(jobs_norm_kernel, dim3(cap(cdiv(max_rows_a, RV)), n), blk, 0, st, jobs, 0);
-        hipLaunchKernelGGL(jobs_norm_kernel, dim3(cap(cdiv(max_rows_b, RV)), n), blk, 0, st, jobs, 1);
-        hipLaunchKernelGGL(jobs_lambda_kernel, dim3((unsigned)cdiv(n, 256)), blk, 0, st, jobs, n);
-        hipLaunchKernelGGL(jobs_absmax_kernel<true>, dim3(cap(cdiv(max_rows_a, RV)), n), blk, 0, st, jobs, 0);
-        hipLaunchKernelGGL(jobs_absmax_kernel<true>, dim3(cap(cdiv(max_cols_b, RV)), n), blk, 0, st, jobs, 1);
-    } else {
-        hipLaunchKernelGGL(jobs_absmax_kernel<false>, dim3(cap(cdiv(max_rows_a, RV)), n), blk, 0, st, jobs, 0);
-        hipLaunchKernelGGL(jobs_absmax_kernel<false>, dim3(cap(cdiv(max_cols_b, RV)), n), blk, 0, st, jobs, 1);
+    hipLaunchKernelGGL(jobs_zero_stats_kernel, dim3((unsigned)n), blk, 0, st, jobs);
+    if (nstrips > 0) {
+        if (scale) hipLaunchKernelGGL(jobs_stats_kernel<true>, dim3((unsigned)nstrips), dim3(64), 0, st, jobs, strips);
+        else hipLaunchKernelGGL(jobs_stats_kernel<false>, dim3((unsigned)nstrips), dim3(64), 0, st, jobs, strips);
     }
+    if (scale) hipLaunchKernelGGL(jobs_lambda_kernel, dim3((unsigned)cdiv(n, 256)), blk, 0, st, jobs, n);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(jobs_split_a_kernel<DT>, dim3(cap(max_a), n), blk, 0, st, jobs, g.s, scale);
     hipLaunchKernelGGL(jobs_split_b_kernel<DT>, dim3(cap(max_b), n), blk, 0, st, jobs, g.s, scale);
@@ -886,12 +920,19 @@ hipError_t split_grouped_prepare(const SplitGroup& g)
 }
 
 hipError_t launch_split_grouped(const SplitGroup& grp, const SplitJob* jobs, const SplitJob* hjobs, int n,
-                                const i64* prefix, i64 total_tiles, bool scale_lambda, int grid, hipStream_t s)
+                                const i64* prefix, i64 total_tiles, const StatStrip* strips, int nstrips,
+                                bool scale_lambda, int grid, hipStream_t s)
 {
     switch (grp.dt) {
-    case DT_BF16: return launch_split_grouped_dt<DT_BF16>(grp, jobs, hjobs, n, prefix, total_tiles, scale_lambda, grid, s);
-    case DT_FP16: return launch_split_grouped_dt<DT_FP16>(grp, jobs, hjobs, n, prefix, total_tiles, scale_lambda, grid, s);
-    case DT_INT8: return launch_split_grouped_dt<DT_INT8>(grp, jobs, hjobs, n, prefix, total_tiles, scale_lambda, grid, s);
+    case DT_BF16:
+        return launch_split_grouped_dt<DT_BF16>(grp, jobs, hjobs, n, prefix, total_tiles, strips, nstrips, scale_lambda,
+                                                grid, s);
+    case DT_FP16:
+        return launch_split_grouped_dt<DT_FP16>(grp, jobs, hjobs, n, prefix, total_tiles, strips, nstrips, scale_lambda,
+                                                grid, s);
+    case DT_INT8:
+        return launch_split_grouped_dt<DT_INT8>(grp, jobs, hjobs, n, prefix, total_tiles, strips, nstrips, scale_lambda,
+                                                grid, s);
     default: return hipErrorNotSupported;
     }
 }
