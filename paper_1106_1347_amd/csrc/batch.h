@@ -42,14 +42,29 @@ struct SplitGroup {
     int per_cu;  // workgroups of the group's kernel resident per CU
 };
 
-// A strip of 64 rows of one job's A (side 0) or B (side 1) for the
-// statistics pass of a split group.
-struct StatStrip {
+// One workgroup's share of a split group's preprocessing, from tables
+// built with the plan (so no workgroup is launched without work):
+//   statistics: 64 rows of job `job`'s A (side 0) or B (side 1) from row
+//               `index`;
+//   digits of A: the `index`-th 256 groups of 8 entries of the job's A;
+//   digits of B: the `index`-th 64 x 64 tile of the job's B.
+struct JobBlock {
     int job;
     int side;
-    i64 row0;
+    i64 index;
 };
 constexpr int kStatRows = 64;
+struct SplitTables {
+    const JobBlock* strips;
+    int nstrips;
+    const JobBlock* ablocks;
+    int nablocks;
+    const JobBlock* bblocks;
+    int nbblocks;
+};
+// Workgroups of the digit passes for one job (host and device agree).
+__host__ __device__ inline i64 split_a_blocks(const SplitJob& j) { return (j.Np * (j.Kp / 8) + 255) / 256; }
+__host__ __device__ inline i64 split_b_blocks(const SplitJob& j) { return (j.Kp / 64) * (j.Mp / 64); }
 
 // Workspace bytes for one split job; fills the job's Np/Mp/Kp and returns
 // (size_t)-1 when unsupported.  Offsets of the job's buffers inside its
@@ -59,11 +74,9 @@ void split_job_bind(SplitJob& j, char* base, int dt, int s);
 // Host-side set-up of a group's kernels (dynamic LDS size); call once
 // before recording launches into a graph.
 hipError_t split_grouped_prepare(const SplitGroup& grp);
-// Enqueue the grouped split pipeline for `n` jobs (device table `jobs`,
-// host copy `hjobs` for launch sizing), tile prefix table `prefix`, and
-// `nstrips` statistics strips covering every row of every job's A and B.
-hipError_t launch_split_grouped(const SplitGroup& grp, const SplitJob* jobs, const SplitJob* hjobs, int n,
-                                const i64* prefix, i64 total_tiles, const StatStrip* strips, int nstrips,
-                                bool scale_lambda, int grid, hipStream_t s);
+// Enqueue the grouped split pipeline for `n` jobs (device table `jobs`),
+// tile prefix table `prefix` and the preprocessing work tables `tab`.
+hipError_t launch_split_grouped(const SplitGroup& grp, const SplitJob* jobs, int n, const i64* prefix,
+                                i64 total_tiles, const SplitTables& tab, bool scale_lambda, int grid, hipStream_t s);
 
 }  // namespace mmm

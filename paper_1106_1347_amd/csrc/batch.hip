@@ -49,8 +49,8 @@ struct SGroup {
     std::vector<SplitJob> jobs;
     std::vector<size_t> ws_off;
     std::vector<i64> prefix;
-    std::vector<StatStrip> strips;
-    size_t off_jobs = 0, off_prefix = 0, off_strips = 0;
+    std::vector<JobBlock> strips, ablocks, bblocks;
+    size_t off_jobs = 0, off_prefix = 0, off_strips = 0, off_ablocks = 0, off_bblocks = 0;
 };
 
 struct Interval {
@@ -134,6 +134,9 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
             j.N = p.N;
             j.P = p.P;
             j.M = p.M;
+            j.Np = Np;  // padded sizes, needed for the work tables (split_job_bind sets the same)
+            j.Mp = Mp;
+            j.Kp = Kp;
             g.jobs.push_back(j);
             g.ws_off.push_back(split_ws);
             split_ws = al256(split_ws + bytes);
@@ -159,15 +162,22 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
     for (auto& kv : sg) {
         SGroup& g = kv.second;
         g.prefix.assign(g.jobs.size() + 1, 0);
-        // statistics strips: every 64 rows of every job's A, then of its B
+        // preprocessing work: statistics strips of 64 rows of every job's A
+        // and B, then the digit passes' workgroups
         for (size_t k = 0; k < g.jobs.size(); ++k) {
-            for (i64 r = 0; r < g.jobs[k].N; r += kStatRows) g.strips.push_back(StatStrip{(int)k, 0, r});
-            for (i64 r = 0; r < g.jobs[k].P; r += kStatRows) g.strips.push_back(StatStrip{(int)k, 1, r});
+            const SplitJob& j = g.jobs[k];
+            for (i64 r = 0; r < j.N; r += kStatRows) g.strips.push_back(JobBlock{(int)k, 0, r});
+            for (i64 r = 0; r < j.P; r += kStatRows) g.strips.push_back(JobBlock{(int)k, 1, r});
+            for (i64 b = 0, nb = split_a_blocks(j); b < nb; ++b) g.ablocks.push_back(JobBlock{(int)k, 0, b});
+            for (i64 b = 0, nb = split_b_blocks(j); b < nb; ++b) g.bblocks.push_back(JobBlock{(int)k, 1, b});
         }
-        if (g.strips.size() > 0x7fffffffu) return bfail(MMM_EUNSUPPORTED, "batch: too many rows in split problems");
+        if (g.strips.size() > 0x7fffffffu || g.ablocks.size() > 0x7fffffffu || g.bblocks.size() > 0x7fffffffu)
+            return bfail(MMM_EUNSUPPORTED, "batch: split problems too large for one plan");
         g.off_jobs = take(sizeof(SplitJob) * g.jobs.size());
         g.off_prefix = take(sizeof(i64) * g.prefix.size());
-        g.off_strips = take(sizeof(StatStrip) * g.strips.size());
+        g.off_strips = take(sizeof(JobBlock) * g.strips.size());
+        g.off_ablocks = take(sizeof(JobBlock) * g.ablocks.size());
+        g.off_bblocks = take(sizeof(JobBlock) * g.bblocks.size());
     }
     const size_t off_ws = off;
     const size_t total = off + split_ws + 256;
@@ -196,7 +206,9 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
     for (auto& kv : sg) {
         memcpy(host.data() + kv.second.off_jobs, kv.second.jobs.data(), sizeof(SplitJob) * kv.second.jobs.size());
         memcpy(host.data() + kv.second.off_prefix, kv.second.prefix.data(), sizeof(i64) * kv.second.prefix.size());
-        memcpy(host.data() + kv.second.off_strips, kv.second.strips.data(), sizeof(StatStrip) * kv.second.strips.size());
+        memcpy(host.data() + kv.second.off_strips, kv.second.strips.data(), sizeof(JobBlock) * kv.second.strips.size());
+        memcpy(host.data() + kv.second.off_ablocks, kv.second.ablocks.data(), sizeof(JobBlock) * kv.second.ablocks.size());
+        memcpy(host.data() + kv.second.off_bblocks, kv.second.bblocks.data(), sizeof(JobBlock) * kv.second.bblocks.size());
     }
     hipError_t e = hipSuccess;
     if (off_ws > 0) e = hipMemcpyAsync(base, host.data(), off_ws, hipMemcpyHostToDevice, s);
@@ -234,9 +246,12 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
             SGroup& g = kv.second;
             const i64 tiles = g.prefix.back();
             const int grid = (int)std::min<i64>(tiles, (i64)cus * g.g.per_cu);
-            le = launch_split_grouped(g.g, (const SplitJob*)(base + g.off_jobs), g.jobs.data(), (int)g.jobs.size(),
-                                      (const i64*)(base + g.off_prefix), tiles, (const StatStrip*)(base + g.off_strips),
-                                      (int)g.strips.size(), c.split_scale_lambda != 0, grid, side);
+            const SplitTables tab{(const JobBlock*)(base + g.off_strips),  (int)g.strips.size(),
+                                  (const JobBlock*)(base + g.off_ablocks), (int)g.ablocks.size(),
+                                  (const JobBlock*)(base + g.off_bblocks), (int)g.bblocks.size()};
+            le = launch_split_grouped(g.g, (const SplitJob*)(base + g.off_jobs), (int)g.jobs.size(),
+                                      (const i64*)(base + g.off_prefix), tiles, tab, c.split_scale_lambda != 0, grid,
+                                      side);
         }
         if (le == hipSuccess) le = hipEventRecord(join, side);
         if (le == hipSuccess) le = hipStreamWaitEvent(cap, join, 0);

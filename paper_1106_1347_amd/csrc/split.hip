@@ -208,9 +208,9 @@ __device__ __forceinline__ void split_a_body(const double* __restrict__ A, i64 N
 template <int DT>
 __global__ __launch_bounds__(256) void split_a_kernel(const double* __restrict__ A, i64 N, i64 P, i64 Np, i64 Kp,
                                                       const double* __restrict__ rmax, const int* lam, int s,
-                                                      char* __restrict__ SA, int* __restrict__ ea)
+                                                      char* __restrict__ SA, int* __restrict__ ea, bool rmax_raw)
 {
-    split_a_body<DT>(A, N, P, Np, Kp, rmax, lam, s, SA, ea, blockIdx.x, gridDim.x);
+    split_a_body<DT>(A, N, P, Np, Kp, rmax, lam, s, SA, ea, blockIdx.x, gridDim.x, rmax_raw);
 }
 
 // B (P x M, row-major) to SB[kb][u][j][64 bytes]: a 64 (k) x 64 (j) tile
@@ -257,10 +257,10 @@ __device__ __forceinline__ void split_b_body(const double* __restrict__ B, i64 P
 template <int DT>
 __global__ __launch_bounds__(256) void split_b_kernel(const double* __restrict__ B, i64 P, i64 M, i64 Mp, i64 Kp,
                                                       const double* __restrict__ cmax, const int* lam, int s,
-                                                      char* __restrict__ SB, int* __restrict__ fb)
+                                                      char* __restrict__ SB, int* __restrict__ fb, bool cmax_raw)
 {
     __shared__ double T[64][65];
-    split_b_body<DT>(B, P, M, Mp, Kp, cmax, lam, s, SB, fb, blockIdx.x, T);
+    split_b_body<DT>(B, P, M, Mp, Kp, cmax, lam, s, SB, fb, blockIdx.x, T, cmax_raw);
 }
 
 // ---- the digit-product GEMM -------------------------------------------------
@@ -522,6 +522,111 @@ __global__ __launch_bounds__(grouped_tile_cfg(DT, S, FLUSH).threads(), grouped_t
 
 // ---- batched preprocessing: blockIdx.y selects the job -----------------------
 
+// One pass over a row-major rows x len matrix (a single product's A or B),
+// 16 rows per workgroup streamed through LDS in chunks of 256 columns:
+//   NORMS:  each of 16 lanes folds its row's NormInf sum (Section 1.4) in
+//           order from 0.0; the largest goes to *norm by an atomic max;
+//   ROWMAX: 16 threads per row take the max |x| of 16 columns each and
+//           fold them by shuffles (to rmax, unscaled);
+//   COLMAX: each thread takes one column's max |x| over the workgroup's
+//           rows, stored to cpart[workgroup][column] (colmax_kernel folds
+//           the workgroups).
+// Only the sums are bound to an order; the maxima use every thread.
+// *norm is cleared beforehand.
+template <bool NORMS, bool ROWMAX, bool COLMAX>
+__global__ __launch_bounds__(256) void stats_kernel(const double* __restrict__ X, i64 rows, i64 len,
+                                                    double* __restrict__ norm, double* __restrict__ rmax,
+                                                    double* __restrict__ cpart)
+{
+    __shared__ double T[2][RV][RL + 1];
+    const int tid = threadIdx.x;
+    const i64 v0 = (i64)blockIdx.x * RV;
+    const i64 nchunks = (len + RL - 1) / RL;
+    double r[RPER];
+    auto load = [&](i64 c) {
+#pragma unroll
+        for (int q = 0; q < RPER; ++q) {
+            const int e = q * 256 + tid, v = e / RL, x = e % RL;
+            const i64 gv = v0 + v, gx = c * RL + x;
+            r[q] = (gv < rows && gx < len) ? X[gv * len + gx] : 0.0;
+        }
+    };
+    // |x| at the store, so the loads of the next chunk stay in flight while
+    // this one is folded
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < RPER; ++q) {
+            const int e = q * 256 + tid;
+            T[buf][e / RL][e % RL] = fabs(r[q]);
+        }
+    };
+    double acc = 0.0, mx = 0.0;
+    if (nchunks > 0) {
+        load(0);
+        store(0);
+    }
+    __syncthreads();
+    for (i64 c = 0; c < nchunks; ++c) {
+        const int cur = (int)(c & 1);
+        if (c + 1 < nchunks) load(c + 1);
+        if (NORMS && tid < RV) {
+            const i64 rem = len - c * RL;
+            const int cnt = rem < RL ? (int)rem : RL;
+            const double* row = T[cur][tid];
+            for (int x = 0; x < cnt; ++x) acc = acc + row[x];
+        }
+        if (ROWMAX) {
+            // entries past the end were stored as 0.0, below every |x|
+            const double* row = T[cur][tid / 16];
+            double m = 0.0;
+#pragma unroll
+            for (int x = 0; x < RL / 16; ++x) m = max_s13(m, row[x * 16 + tid % 16]);
+            mx = max_s13(mx, m);
+        }
+        if (COLMAX) {
+            double m = 0.0;
+#pragma unroll
+            for (int v = 0; v < RV; ++v) m = max_s13(m, T[cur][v][tid]);
+            const i64 gx = c * RL + tid;
+            if (gx < len) cpart[(i64)blockIdx.x * len + gx] = m;
+        }
+        if (c + 1 < nchunks) store(cur ^ 1);
+        __syncthreads();
+    }
+    if (NORMS && tid < RV && v0 + tid < rows)
+        atomicMax(reinterpret_cast<unsigned long long*>(norm), (unsigned long long)__double_as_longlong(acc));
+    if (ROWMAX) {
+        // the 16 partial maxima of a row sit in 16 neighbouring lanes
+        unsigned long long u = (unsigned long long)__double_as_longlong(mx);
+        for (int o = 1; o < 16; o *= 2) {
+            const unsigned long long w = __shfl_xor(u, o);
+            u = w > u ? w : u;
+        }
+        if (tid % 16 == 0 && v0 + tid / 16 < rows) rmax[v0 + tid / 16] = __longlong_as_double((long long)u);
+    }
+}
+
+// cmax[j] = max over the nparts rows of cpart (nparts x M) of column j:
+// 32 columns per workgroup, 8 threads per column striding the parts, then
+// folded through LDS.
+__global__ __launch_bounds__(256) void colmax_kernel(const double* __restrict__ cpart, i64 nparts, i64 M,
+                                                     double* __restrict__ cmax)
+{
+    __shared__ double T[8][32];
+    const int tid = threadIdx.x, cc = tid % 32, ps = tid / 32;
+    const i64 j = (i64)blockIdx.x * 32 + cc;
+    double m = 0.0;
+    if (j < M)
+        for (i64 p = ps; p < nparts; p += 8) m = max_s13(m, cpart[p * M + j]);
+    T[ps][cc] = m;
+    __syncthreads();
+    if (ps == 0 && j < M) {
+#pragma unroll
+        for (int q = 1; q < 8; ++q) m = max_s13(m, T[q][cc]);
+        cmax[j] = m;
+    }
+}
+
 // Clears the atomic-max targets of every job (one workgroup per job): the
 // two norms and the column maxima of B.
 __global__ __launch_bounds__(256) void jobs_zero_stats_kernel(const SplitJob* __restrict__ jobs)
@@ -553,27 +658,34 @@ __device__ inline unsigned long long wave_max_bits(unsigned long long u, int fro
 //   - B: max_k |B_kj| of each column over the strip's rows, folded into
 //     cmax by an atomic max (cleared beforehand).
 // Rows are staged through LDS 16 columns at a time so the loads are
-// contiguous 128-byte runs.
+// contiguous 128-byte runs; the next 16 columns are in flight meanwhile.
 template <bool NORMS>
 __global__ __launch_bounds__(64) void jobs_stats_kernel(const SplitJob* __restrict__ jobs,
-                                                        const StatStrip* __restrict__ strips)
+                                                        const JobBlock* __restrict__ strips)
 {
     __shared__ double T[kStatRows][17];
-    const StatStrip st = strips[blockIdx.x];
+    const JobBlock st = strips[blockIdx.x];
     const SplitJob& j = jobs[st.job];
     const int lane = threadIdx.x;
     const bool side_b = st.side != 0;
     const double* X = side_b ? j.B : j.A;
-    const i64 rows = side_b ? j.P : j.N, len = side_b ? j.M : j.P, r0 = st.row0;
-    double sum = 0.0, mx = 0.0;
-    for (i64 c0 = 0; c0 < len; c0 += 16) {
+    const i64 rows = side_b ? j.P : j.N, len = side_b ? j.M : j.P, r0 = st.index;
+    double sum = 0.0, mx = 0.0, r[16];
+    // the next 16 columns are loaded while this block of them is folded
+    auto load = [&](i64 c0) {
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int rr = q * 4 + lane / 16, cc = lane % 16;
             const i64 gr = r0 + rr, gc = c0 + cc;
-            T[rr][cc] = (gr < rows && gc < len) ? fabs(X[gr * len + gc]) : 0.0;
+            r[q] = (gr < rows && gc < len) ? X[gr * len + gc] : 0.0;
         }
+    };
+    load(0);
+    for (i64 c0 = 0; c0 < len; c0 += 16) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) T[q * 4 + lane / 16][lane % 16] = fabs(r[q]);
         __syncthreads();
+        if (c0 + 16 < len) load(c0 + 16);
         const int cnt = len - c0 < 16 ? (int)(len - c0) : 16;
         for (int x = 0; x < cnt; ++x) {
             const double v = T[lane][x];
@@ -617,23 +729,23 @@ __global__ void jobs_lambda_kernel(const SplitJob* jobs, int n)
 }
 
 template <int DT>
-__global__ __launch_bounds__(256) void jobs_split_a_kernel(const SplitJob* __restrict__ jobs, int s, bool scaled)
+__global__ __launch_bounds__(256) void jobs_split_a_kernel(const SplitJob* __restrict__ jobs,
+                                                           const JobBlock* __restrict__ blocks, int s, bool scaled)
 {
-    const SplitJob& j = jobs[blockIdx.y];
-    split_a_body<DT>(j.A, j.N, j.P, j.Np, j.Kp, j.rmax, scaled ? j.lam : nullptr, s, j.SA, j.ea, blockIdx.x, gridDim.x,
-                     true);
+    const JobBlock b = blocks[blockIdx.x];
+    const SplitJob& j = jobs[b.job];
+    split_a_body<DT>(j.A, j.N, j.P, j.Np, j.Kp, j.rmax, scaled ? j.lam : nullptr, s, j.SA, j.ea, b.index,
+                     split_a_blocks(j), true);
 }
 
 template <int DT>
-__global__ __launch_bounds__(256) void jobs_split_b_kernel(const SplitJob* __restrict__ jobs, int s, bool scaled)
+__global__ __launch_bounds__(256) void jobs_split_b_kernel(const SplitJob* __restrict__ jobs,
+                                                           const JobBlock* __restrict__ blocks, int s, bool scaled)
 {
     __shared__ double T[64][65];
-    const SplitJob& j = jobs[blockIdx.y];
-    const i64 blocks = (j.Kp / 64) * (j.Mp / 64);
-    for (i64 b = blockIdx.x; b < blocks; b += gridDim.x) {
-        split_b_body<DT>(j.B, j.P, j.M, j.Mp, j.Kp, j.cmax, scaled ? j.lam : nullptr, s, j.SB, j.fb, b, T, true);
-        __syncthreads();
-    }
+    const JobBlock b = blocks[blockIdx.x];
+    const SplitJob& j = jobs[b.job];
+    split_b_body<DT>(j.B, j.P, j.M, j.Mp, j.Kp, j.cmax, scaled ? j.lam : nullptr, s, j.SB, j.fb, b.index, T, true);
 }
 
 struct SplitLayout {
@@ -742,29 +854,46 @@ hipError_t run_split_dt(const double* A, const double* B, double* C, i64 N, i64 
                         bool scale, char* ws, hipStream_t st)
 {
     hipError_t e;
-    int* lam = nullptr;
-    if (scale) {
-        lam = (int*)(ws + L.lam);
-        if ((e = launch_norm_inf(A, N, P, (double*)(ws + L.nA), st)) != hipSuccess) return e;
-        if ((e = launch_norm_inf(B, P, M, (double*)(ws + L.nB), st)) != hipSuccess) return e;
-        if ((e = launch_lambda((double*)(ws + L.nA), (double*)(ws + L.nB), lam, st)) != hipSuccess) return e;
-    }
+    int* lam = scale ? (int*)(ws + L.lam) : nullptr;
+    double* nA = (double*)(ws + L.nA);
+    double* nB = (double*)(ws + L.nB);
     double* rmax = (double*)(ws + L.rmax);
     double* cmax = (double*)(ws + L.cmax);
-    if ((e = launch_vector_reduce(RED_ABS_MAX, false, A, P, N, P, rmax, lam, +1, st)) != hipSuccess) return e;
-    if ((e = launch_vector_reduce(RED_ABS_MAX, true, B, M, M, P, cmax, lam, -1, st)) != hipSuccess) return e;
+    // one pass per operand: A's norm and row maxima, B's norm and column
+    // maxima (the maxima before the 2^lambda scaling, which split_a/split_b
+    // apply when they form the exponents).  B's per-workgroup column maxima
+    // (cdiv(P, 16) x M doubles, at most half of B's digit planes) are staged
+    // in the digit-plane region, which split_b overwrites only afterwards.
+    const i64 nparts = cdiv(P, RV);
+    double* cpart = (double*)(ws + L.SB);
+    if (scale && (e = launch_fill_zero(nA, 1, st)) != hipSuccess) return e;
+    if (scale && (e = launch_fill_zero(nB, 1, st)) != hipSuccess) return e;
+    if (scale) {
+        hipLaunchKernelGGL((stats_kernel<true, true, false>), dim3((unsigned)cdiv(N, RV)), dim3(256), 0, st, A, N, P, nA,
+                           rmax, nullptr);
+        hipLaunchKernelGGL((stats_kernel<true, false, true>), dim3((unsigned)nparts), dim3(256), 0, st, B, P, M, nB,
+                           nullptr, cpart);
+    } else {
+        hipLaunchKernelGGL((stats_kernel<false, true, false>), dim3((unsigned)cdiv(N, RV)), dim3(256), 0, st, A, N, P,
+                           nullptr, rmax, nullptr);
+        hipLaunchKernelGGL((stats_kernel<false, false, true>), dim3((unsigned)nparts), dim3(256), 0, st, B, P, M,
+                           nullptr, nullptr, cpart);
+    }
+    hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)cdiv(M, 32)), dim3(256), 0, st, cpart, nparts, M, cmax);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (scale && (e = launch_lambda(nA, nB, lam, st)) != hipSuccess) return e;
     {
         const i64 total = L.Np * (L.Kp / 8);
         i64 blocks = cdiv(total, 256);
         if (blocks > 256 * 64) blocks = 256 * 64;
         hipLaunchKernelGGL((split_a_kernel<DT>), dim3((unsigned)blocks), dim3(256), 0, st, A, N, P, L.Np, L.Kp, rmax,
-                           lam, L.s, ws + L.SA, (int*)(ws + L.ea));
+                           lam, L.s, ws + L.SA, (int*)(ws + L.ea), true);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     {
         const i64 blocks = (L.Kp / 64) * (L.Mp / 64);
         hipLaunchKernelGGL((split_b_kernel<DT>), dim3((unsigned)blocks), dim3(256), 0, st, B, P, M, L.Mp, L.Kp, cmax,
-                           lam, L.s, ws + L.SB, (int*)(ws + L.fb));
+                           lam, L.s, ws + L.SB, (int*)(ws + L.fb), true);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return dispatch_s<DT>(L, ws, C, N, M, st);
@@ -808,30 +937,27 @@ hipError_t grouped_s(const SplitGroup& g, const SplitJob* jobs, const i64* prefi
 }
 
 template <int DT>
-hipError_t launch_split_grouped_dt(const SplitGroup& g, const SplitJob* jobs, const SplitJob* hjobs, int n,
-                                   const i64* prefix, i64 total, const StatStrip* strips, int nstrips, bool scale,
-                                   int grid, hipStream_t st)
+hipError_t launch_split_grouped_dt(const SplitGroup& g, const SplitJob* jobs, int n, const i64* prefix, i64 total,
+                                   const SplitTables& tab, bool scale, int grid, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     hipError_t e;
-    i64 max_a = 0, max_b = 0;
-    for (int i = 0; i < n; ++i) {
-        const SplitJob& j = hjobs[i];
-        const i64 ba = cdiv(j.Np * (j.Kp / 8), 256), bb = (j.Kp / 64) * (j.Mp / 64);
-        max_a = ba > max_a ? ba : max_a;
-        max_b = bb > max_b ? bb : max_b;
-    }
-    auto cap = [](i64 x) { return (unsigned)(x < 1 ? 1 : (x > 64 ? 64 : x)); };
     const dim3 blk(256);
     hipLaunchKernelGGL(jobs_zero_stats_kernel, dim3((unsigned)n), blk, 0, st, jobs);
-    if (nstrips > 0) {
-        if (scale) hipLaunchKernelGGL(jobs_stats_kernel<true>, dim3((unsigned)nstrips), dim3(64), 0, st, jobs, strips);
-        else hipLaunchKernelGGL(jobs_stats_kernel<false>, dim3((unsigned)nstrips), dim3(64), 0, st, jobs, strips);
+    if (tab.nstrips > 0) {
+        if (scale)
+            hipLaunchKernelGGL(jobs_stats_kernel<true>, dim3((unsigned)tab.nstrips), dim3(64), 0, st, jobs, tab.strips);
+        else
+            hipLaunchKernelGGL(jobs_stats_kernel<false>, dim3((unsigned)tab.nstrips), dim3(64), 0, st, jobs, tab.strips);
     }
     if (scale) hipLaunchKernelGGL(jobs_lambda_kernel, dim3((unsigned)cdiv(n, 256)), blk, 0, st, jobs, n);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(jobs_split_a_kernel<DT>, dim3(cap(max_a), n), blk, 0, st, jobs, g.s, scale);
-    hipLaunchKernelGGL(jobs_split_b_kernel<DT>, dim3(cap(max_b), n), blk, 0, st, jobs, g.s, scale);
+    if (tab.nablocks > 0)
+        hipLaunchKernelGGL(jobs_split_a_kernel<DT>, dim3((unsigned)tab.nablocks), blk, 0, st, jobs, tab.ablocks, g.s,
+                           scale);
+    if (tab.nbblocks > 0)
+        hipLaunchKernelGGL(jobs_split_b_kernel<DT>, dim3((unsigned)tab.nbblocks), blk, 0, st, jobs, tab.bblocks, g.s,
+                           scale);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return grouped_s<DT>(g, jobs, prefix, n, total, grid, st);
 }
@@ -919,20 +1045,13 @@ hipError_t split_grouped_prepare(const SplitGroup& g)
     }
 }
 
-hipError_t launch_split_grouped(const SplitGroup& grp, const SplitJob* jobs, const SplitJob* hjobs, int n,
-                                const i64* prefix, i64 total_tiles, const StatStrip* strips, int nstrips,
-                                bool scale_lambda, int grid, hipStream_t s)
+hipError_t launch_split_grouped(const SplitGroup& grp, const SplitJob* jobs, int n, const i64* prefix,
+                                i64 total_tiles, const SplitTables& tab, bool scale_lambda, int grid, hipStream_t s)
 {
     switch (grp.dt) {
-    case DT_BF16:
-        return launch_split_grouped_dt<DT_BF16>(grp, jobs, hjobs, n, prefix, total_tiles, strips, nstrips, scale_lambda,
-                                                grid, s);
-    case DT_FP16:
-        return launch_split_grouped_dt<DT_FP16>(grp, jobs, hjobs, n, prefix, total_tiles, strips, nstrips, scale_lambda,
-                                                grid, s);
-    case DT_INT8:
-        return launch_split_grouped_dt<DT_INT8>(grp, jobs, hjobs, n, prefix, total_tiles, strips, nstrips, scale_lambda,
-                                                grid, s);
+    case DT_BF16: return launch_split_grouped_dt<DT_BF16>(grp, jobs, n, prefix, total_tiles, tab, scale_lambda, grid, s);
+    case DT_FP16: return launch_split_grouped_dt<DT_FP16>(grp, jobs, n, prefix, total_tiles, tab, scale_lambda, grid, s);
+    case DT_INT8: return launch_split_grouped_dt<DT_INT8>(grp, jobs, n, prefix, total_tiles, tab, scale_lambda, grid, s);
     default: return hipErrorNotSupported;
     }
 }
