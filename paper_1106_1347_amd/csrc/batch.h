@@ -10,10 +10,18 @@ enum DgemmTile { DGEMM_TILE_AUTO = 0, DGEMM_TILE_128x128 = 1, DGEMM_TILE_64x64 =
 
 int dgemm_tile_bm(int tile);
 int dgemm_tile_bn(int tile);
+// Tiles of a persistent grouped kernel per workgroup: workgroup w runs the
+// global tile indices list[off[w]] .. list[off[w + 1] - 1] (device arrays
+// of grid + 1 and total ints), a schedule balanced on the host.
+struct TileSchedule {
+    const int* off;
+    const int* list;
+};
+
 // Persistent grid of `grid` workgroups over the `total` tiles of `nprob`
 // problems (device tables: probs[nprob], prefix[nprob + 1]).
 hipError_t launch_dgemm_grouped(int tile, const Gemm* probs, const i64* prefix, int nprob, i64 total, int grid,
-                                hipStream_t s);
+                                TileSchedule sch, hipStream_t s);
 
 // One split problem of a batch: operands, output and its workspace slices.
 struct SplitJob {
@@ -61,6 +69,7 @@ struct SplitTables {
     int nablocks;
     const JobBlock* bblocks;
     int nbblocks;
+    TileSchedule sched;  // of the digit GEMM's tiles
 };
 // Workgroups of the digit passes for one job (host and device agree).
 __host__ __device__ inline i64 split_a_blocks(const SplitJob& j) { return (j.Np * (j.Kp / 8) + 255) / 256; }

@@ -2,8 +2,9 @@
 //
 // The plan groups the FP64 problems by DGEMM tile shape and the split
 // problems by (digit type, digit count, flush scheme); every group runs as
-// one persistent kernel that deals its tiles round robin over a grid sized
-// to the chip, preceded for split groups by batched preprocessing kernels:
+// one persistent kernel over a grid sized to the chip, each workgroup
+// walking a tile list balanced here (longest tiles first, each to the
+// least-loaded workgroup), preceded for split groups by batched preprocessing kernels:
 // one pass over every 64-row strip of every problem's A and B for the
 // norms and row/column maxima (a strip table built here), lambda, and digit
 // extraction (blockIdx.y selects the problem).  The FP64 groups and the split groups are recorded
@@ -15,6 +16,7 @@
 
 #include <algorithm>
 #include <map>
+#include <queue>
 #include <tuple>
 #include <vector>
 
@@ -41,7 +43,9 @@ struct DGroup {
     int tile;
     std::vector<Gemm> probs;
     std::vector<i64> prefix;
-    size_t off_probs = 0, off_prefix = 0;
+    std::vector<int> soff, slist;
+    int grid = 0;
+    size_t off_probs = 0, off_prefix = 0, off_soff = 0, off_slist = 0;
 };
 
 struct SGroup {
@@ -50,7 +54,9 @@ struct SGroup {
     std::vector<size_t> ws_off;
     std::vector<i64> prefix;
     std::vector<JobBlock> strips, ablocks, bblocks;
-    size_t off_jobs = 0, off_prefix = 0, off_strips = 0, off_ablocks = 0, off_bblocks = 0;
+    std::vector<int> soff, slist;
+    int grid = 0;
+    size_t off_jobs = 0, off_prefix = 0, off_strips = 0, off_ablocks = 0, off_bblocks = 0, off_soff = 0, off_slist = 0;
 };
 
 struct Interval {
@@ -58,6 +64,32 @@ struct Interval {
     bool out;
     int idx;
 };
+
+// Longest first: tiles sorted by estimated cost (stable, descending), each
+// given to the workgroup with the least work so far (ties: lowest index).
+// off[w] .. off[w + 1] - 1 index workgroup w's tiles in list.
+void balance(const std::vector<i64>& cost, int grid, std::vector<int>& off, std::vector<int>& list)
+{
+    std::vector<int> order(cost.size());
+    for (size_t t = 0; t < order.size(); ++t) order[t] = (int)t;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    typedef std::pair<i64, int> Load;
+    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+    for (int w = 0; w < grid; ++w) heap.push(Load{0, w});
+    std::vector<std::vector<int>> per(grid);
+    for (int t : order) {
+        const Load l = heap.top();
+        heap.pop();
+        per[l.second].push_back(t);
+        heap.push(Load{l.first + cost[t], l.second});
+    }
+    off.assign(grid + 1, 0);
+    list.clear();
+    for (int w = 0; w < grid; ++w) {
+        list.insert(list.end(), per[w].begin(), per[w].end());
+        off[w + 1] = (int)list.size();
+    }
+}
 
 int pick_tile(const mmm_problem& p)
 {
@@ -143,6 +175,13 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
         }
     }
 
+    // persistent grids: every CU, as many workgroups as fit
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return bfail(MMM_ELAUNCH, "batch: cannot query the device");
+    }
+
     // device memory layout: tables first, then the split workspaces
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -154,10 +193,19 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
         DGroup& g = kv.second;
         const int bm = dgemm_tile_bm(g.tile), bn = dgemm_tile_bn(g.tile);
         g.prefix.assign(g.probs.size() + 1, 0);
-        for (size_t k = 0; k < g.probs.size(); ++k)
-            g.prefix[k + 1] = g.prefix[k] + cdiv(g.probs[k].N, bm) * cdiv(g.probs[k].M, bn);
+        std::vector<i64> cost;  // K steps of 16 plus the fixed cost of a tile
+        for (size_t k = 0; k < g.probs.size(); ++k) {
+            const i64 nt = cdiv(g.probs[k].N, bm) * cdiv(g.probs[k].M, bn);
+            g.prefix[k + 1] = g.prefix[k] + nt;
+            cost.insert(cost.end(), (size_t)nt, cdiv(g.probs[k].P, 16) + 4);
+        }
+        if (g.prefix.back() > 0x7fffffff) return bfail(MMM_EUNSUPPORTED, "batch: too many DGEMM tiles in one plan");
+        g.grid = (int)std::min<i64>(g.prefix.back(), (i64)cus * 2);
+        balance(cost, g.grid, g.soff, g.slist);
         g.off_probs = take(sizeof(Gemm) * g.probs.size());
         g.off_prefix = take(sizeof(i64) * g.prefix.size());
+        g.off_soff = take(sizeof(int) * g.soff.size());
+        g.off_slist = take(sizeof(int) * (g.slist.size() ? g.slist.size() : 1));
     }
     for (auto& kv : sg) {
         SGroup& g = kv.second;
@@ -178,6 +226,17 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
         g.off_strips = take(sizeof(JobBlock) * g.strips.size());
         g.off_ablocks = take(sizeof(JobBlock) * g.ablocks.size());
         g.off_bblocks = take(sizeof(JobBlock) * g.bblocks.size());
+        std::vector<i64> cost;  // K blocks of 64 plus the fixed cost of a tile
+        for (size_t k = 0; k < g.jobs.size(); ++k) {
+            const i64 nt = (g.jobs[k].Np / g.g.bm) * (g.jobs[k].Mp / g.g.bn);
+            g.prefix[k + 1] = g.prefix[k] + nt;
+            cost.insert(cost.end(), (size_t)nt, g.jobs[k].Kp / 64 + 2);
+        }
+        if (g.prefix.back() > 0x7fffffff) return bfail(MMM_EUNSUPPORTED, "batch: too many split tiles in one plan");
+        g.grid = (int)std::min<i64>(g.prefix.back(), (i64)cus * g.g.per_cu);
+        balance(cost, g.grid, g.soff, g.slist);
+        g.off_soff = take(sizeof(int) * g.soff.size());
+        g.off_slist = take(sizeof(int) * (g.slist.size() ? g.slist.size() : 1));
     }
     const size_t off_ws = off;
     const size_t total = off + split_ws + 256;
@@ -192,16 +251,15 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
     char* base = (char*)plan->dmem;
     for (auto& kv : sg) {
         SGroup& g = kv.second;
-        for (size_t k = 0; k < g.jobs.size(); ++k) {
-            split_job_bind(g.jobs[k], base + off_ws + g.ws_off[k], g.g.dt, g.g.s);
-            g.prefix[k + 1] = g.prefix[k] + (g.jobs[k].Np / g.g.bm) * (g.jobs[k].Mp / g.g.bn);
-        }
+        for (size_t k = 0; k < g.jobs.size(); ++k) split_job_bind(g.jobs[k], base + off_ws + g.ws_off[k], g.g.dt, g.g.s);
     }
     // upload tables
     std::vector<char> host(off_ws > 0 ? off_ws : 1, 0);
     for (auto& kv : dg) {
         memcpy(host.data() + kv.second.off_probs, kv.second.probs.data(), sizeof(Gemm) * kv.second.probs.size());
         memcpy(host.data() + kv.second.off_prefix, kv.second.prefix.data(), sizeof(i64) * kv.second.prefix.size());
+        memcpy(host.data() + kv.second.off_soff, kv.second.soff.data(), sizeof(int) * kv.second.soff.size());
+        memcpy(host.data() + kv.second.off_slist, kv.second.slist.data(), sizeof(int) * kv.second.slist.size());
     }
     for (auto& kv : sg) {
         memcpy(host.data() + kv.second.off_jobs, kv.second.jobs.data(), sizeof(SplitJob) * kv.second.jobs.size());
@@ -209,15 +267,13 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
         memcpy(host.data() + kv.second.off_strips, kv.second.strips.data(), sizeof(JobBlock) * kv.second.strips.size());
         memcpy(host.data() + kv.second.off_ablocks, kv.second.ablocks.data(), sizeof(JobBlock) * kv.second.ablocks.size());
         memcpy(host.data() + kv.second.off_bblocks, kv.second.bblocks.data(), sizeof(JobBlock) * kv.second.bblocks.size());
+        memcpy(host.data() + kv.second.off_soff, kv.second.soff.data(), sizeof(int) * kv.second.soff.size());
+        memcpy(host.data() + kv.second.off_slist, kv.second.slist.data(), sizeof(int) * kv.second.slist.size());
     }
     hipError_t e = hipSuccess;
     if (off_ws > 0) e = hipMemcpyAsync(base, host.data(), off_ws, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
 
-    // persistent grid: every CU, as many workgroups as fit
-    int dev = 0, cus = 256;
-    if (e == hipSuccess) e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     for (auto& kv : sg)
         if (e == hipSuccess) e = split_grouped_prepare(kv.second.g);
 
@@ -236,22 +292,23 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
         for (auto& kv : dg) {
             if (le != hipSuccess) break;
             DGroup& g = kv.second;
-            const i64 tiles = g.prefix.back();
-            const int grid = (int)std::min<i64>(tiles, (i64)cus * 2);
+            const TileSchedule sch{(const int*)(base + g.off_soff), (const int*)(base + g.off_slist)};
             le = launch_dgemm_grouped(g.tile, (const Gemm*)(base + g.off_probs), (const i64*)(base + g.off_prefix),
-                                      (int)g.probs.size(), tiles, grid, cap);
+                                      (int)g.probs.size(), g.prefix.back(), g.grid, sch, cap);
         }
         for (auto& kv : sg) {
             if (le != hipSuccess) break;
             SGroup& g = kv.second;
-            const i64 tiles = g.prefix.back();
-            const int grid = (int)std::min<i64>(tiles, (i64)cus * g.g.per_cu);
-            const SplitTables tab{(const JobBlock*)(base + g.off_strips),  (int)g.strips.size(),
-                                  (const JobBlock*)(base + g.off_ablocks), (int)g.ablocks.size(),
-                                  (const JobBlock*)(base + g.off_bblocks), (int)g.bblocks.size()};
+            const SplitTables tab{(const JobBlock*)(base + g.off_strips),
+                                  (int)g.strips.size(),
+                                  (const JobBlock*)(base + g.off_ablocks),
+                                  (int)g.ablocks.size(),
+                                  (const JobBlock*)(base + g.off_bblocks),
+                                  (int)g.bblocks.size(),
+                                  TileSchedule{(const int*)(base + g.off_soff), (const int*)(base + g.off_slist)}};
             le = launch_split_grouped(g.g, (const SplitJob*)(base + g.off_jobs), (int)g.jobs.size(),
-                                      (const i64*)(base + g.off_prefix), tiles, tab, c.split_scale_lambda != 0, grid,
-                                      side);
+                                      (const i64*)(base + g.off_prefix), g.prefix.back(), tab,
+                                      c.split_scale_lambda != 0, g.grid, side);
         }
         if (le == hipSuccess) le = hipEventRecord(join, side);
         if (le == hipSuccess) le = hipStreamWaitEvent(cap, join, 0);

@@ -313,11 +313,14 @@ __global__ __launch_bounds__(NT, MMM_DGEMM_MINWAVES) void dgemm_dma_kernel(Src s
 // tile in row-major tile order.  Workgroup b takes tiles b, b + grid, ...
 template <int WMB, int WNB>
 __global__ __launch_bounds__(NT, MMM_DGEMM_MINWAVES) void dgemm_grouped_kernel(const Gemm* __restrict__ probs,
-                                                           const i64* __restrict__ prefix, int nprob, i64 total)
+                                                           const i64* __restrict__ prefix, int nprob,
+                                                           const int* __restrict__ soff,
+                                                           const int* __restrict__ slist)
 {
     typedef DTile<WMB, WNB> T;
     __shared__ __align__(16) typename T::Smem sm;
-    for (i64 t = blockIdx.x; t < total; t += gridDim.x) {
+    for (int q = soff[blockIdx.x]; q < soff[blockIdx.x + 1]; ++q) {
+        const i64 t = slist[q];
         int lo = 0, hi = nprob - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -409,15 +412,18 @@ int dgemm_tile_bm(int tile) { return tile == DGEMM_TILE_64x64 ? 64 : 128; }
 int dgemm_tile_bn(int tile) { return tile == DGEMM_TILE_128x128 ? 128 : 64; }
 
 hipError_t launch_dgemm_grouped(int tile, const Gemm* probs, const i64* prefix, int nprob, i64 total, int grid,
-                                hipStream_t s)
+                                TileSchedule sch, hipStream_t s)
 {
     if (total == 0 || nprob == 0) return hipSuccess;
     if (tile == DGEMM_TILE_128x128)
-        hipLaunchKernelGGL((dgemm_grouped_kernel<4, 4>), dim3(grid), dim3(NT), 0, s, probs, prefix, nprob, total);
+        hipLaunchKernelGGL((dgemm_grouped_kernel<4, 4>), dim3(grid), dim3(NT), 0, s, probs, prefix, nprob, sch.off,
+                           sch.list);
     else if (tile == DGEMM_TILE_64x64)
-        hipLaunchKernelGGL((dgemm_grouped_kernel<2, 2>), dim3(grid), dim3(NT), 0, s, probs, prefix, nprob, total);
+        hipLaunchKernelGGL((dgemm_grouped_kernel<2, 2>), dim3(grid), dim3(NT), 0, s, probs, prefix, nprob, sch.off,
+                           sch.list);
     else
-        hipLaunchKernelGGL((dgemm_grouped_kernel<4, 2>), dim3(grid), dim3(NT), 0, s, probs, prefix, nprob, total);
+        hipLaunchKernelGGL((dgemm_grouped_kernel<4, 2>), dim3(grid), dim3(NT), 0, s, probs, prefix, nprob, sch.off,
+                           sch.list);
     return hipGetLastError();
 }
 

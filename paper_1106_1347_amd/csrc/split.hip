@@ -499,12 +499,14 @@ __global__ __launch_bounds__(tile_cfg(DT, S, FLUSH).threads(), tile_cfg(DT, S, F
 // and count): tile t is job p's (t - prefix[p])-th tile, row-major.
 template <int DT, int S, bool FLUSH>
 __global__ __launch_bounds__(grouped_tile_cfg(DT, S, FLUSH).threads(), grouped_tile_cfg(DT, S, FLUSH).minw) void split_gemm_grouped_kernel(const SplitJob* __restrict__ jobs,
-                                                                 const i64* __restrict__ prefix, int njobs, i64 total,
-                                                                 int flush_steps)
+                                                                 const i64* __restrict__ prefix, int njobs,
+                                                                 int flush_steps, const int* __restrict__ soff,
+                                                                 const int* __restrict__ slist)
 {
     extern __shared__ __align__(16) char lds[];
     constexpr TileCfg TC = grouped_tile_cfg(DT, S, FLUSH);
-    for (i64 t = blockIdx.x; t < total; t += gridDim.x) {
+    for (int q = soff[blockIdx.x]; q < soff[blockIdx.x + 1]; ++q) {
+        const i64 t = slist[q];
         int lo = 0, hi = njobs - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -900,38 +902,38 @@ hipError_t run_split_dt(const double* A, const double* B, double* C, i64 N, i64 
 }
 
 template <int DT, int S, bool FLUSH>
-hipError_t launch_grouped_gemm(const SplitJob* jobs, const i64* prefix, int n, i64 total, int flush_steps, int grid,
-                               hipStream_t st)
+hipError_t launch_grouped_gemm(const SplitJob* jobs, const i64* prefix, int n, int flush_steps, int grid,
+                               TileSchedule sch, hipStream_t st)
 {
     constexpr TileCfg TC = grouped_tile_cfg(DT, S, FLUSH);
     const size_t lds = split_lds_bytes(TC, S);
     auto kern = split_gemm_grouped_kernel<DT, S, FLUSH>;
     if (!jobs) return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(TC.threads()), lds, st, jobs, prefix, n, total, flush_steps);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(TC.threads()), lds, st, jobs, prefix, n, flush_steps, sch.off, sch.list);
     return hipGetLastError();
 }
 
 template <int DT, int S>
-hipError_t grouped_flush(const SplitGroup& g, const SplitJob* jobs, const i64* prefix, int n, i64 total, int grid,
-                         hipStream_t st)
+hipError_t grouped_flush(const SplitGroup& g, const SplitJob* jobs, const i64* prefix, int n, int grid,
+                         TileSchedule sch, hipStream_t st)
 {
-    if (g.flush) return launch_grouped_gemm<DT, S, true>(jobs, prefix, n, total, g.flush_steps, grid, st);
-    return launch_grouped_gemm<DT, S, false>(jobs, prefix, n, total, g.flush_steps, grid, st);
+    if (g.flush) return launch_grouped_gemm<DT, S, true>(jobs, prefix, n, g.flush_steps, grid, sch, st);
+    return launch_grouped_gemm<DT, S, false>(jobs, prefix, n, g.flush_steps, grid, sch, st);
 }
 
 template <int DT>
-hipError_t grouped_s(const SplitGroup& g, const SplitJob* jobs, const i64* prefix, int n, i64 total, int grid,
+hipError_t grouped_s(const SplitGroup& g, const SplitJob* jobs, const i64* prefix, int n, int grid, TileSchedule sch,
                      hipStream_t st)
 {
     switch (g.s) {
-    case 1: return grouped_flush<DT, 1>(g, jobs, prefix, n, total, grid, st);
-    case 2: return grouped_flush<DT, 2>(g, jobs, prefix, n, total, grid, st);
-    case 3: return grouped_flush<DT, 3>(g, jobs, prefix, n, total, grid, st);
-    case 4: return grouped_flush<DT, 4>(g, jobs, prefix, n, total, grid, st);
-    case 5: return grouped_flush<DT, 5>(g, jobs, prefix, n, total, grid, st);
-    case 6: return grouped_flush<DT, 6>(g, jobs, prefix, n, total, grid, st);
-    case 7: return grouped_flush<DT, 7>(g, jobs, prefix, n, total, grid, st);
-    case 8: return grouped_flush<DT, 8>(g, jobs, prefix, n, total, grid, st);
+    case 1: return grouped_flush<DT, 1>(g, jobs, prefix, n, grid, sch, st);
+    case 2: return grouped_flush<DT, 2>(g, jobs, prefix, n, grid, sch, st);
+    case 3: return grouped_flush<DT, 3>(g, jobs, prefix, n, grid, sch, st);
+    case 4: return grouped_flush<DT, 4>(g, jobs, prefix, n, grid, sch, st);
+    case 5: return grouped_flush<DT, 5>(g, jobs, prefix, n, grid, sch, st);
+    case 6: return grouped_flush<DT, 6>(g, jobs, prefix, n, grid, sch, st);
+    case 7: return grouped_flush<DT, 7>(g, jobs, prefix, n, grid, sch, st);
+    case 8: return grouped_flush<DT, 8>(g, jobs, prefix, n, grid, sch, st);
     default: return hipErrorNotSupported;
     }
 }
@@ -959,7 +961,7 @@ hipError_t launch_split_grouped_dt(const SplitGroup& g, const SplitJob* jobs, in
         hipLaunchKernelGGL(jobs_split_b_kernel<DT>, dim3((unsigned)tab.nbblocks), blk, 0, st, jobs, tab.bblocks, g.s,
                            scale);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    return grouped_s<DT>(g, jobs, prefix, n, total, grid, st);
+    return total > 0 ? grouped_s<DT>(g, jobs, prefix, n, grid, tab.sched, st) : hipSuccess;
 }
 
 }  // namespace
@@ -1038,9 +1040,9 @@ hipError_t split_grouped_prepare(const SplitGroup& g)
 {
     // a null job table only sets the kernel's dynamic LDS limit
     switch (g.dt) {
-    case DT_BF16: return grouped_s<DT_BF16>(g, nullptr, nullptr, 0, 0, 0, nullptr);
-    case DT_FP16: return grouped_s<DT_FP16>(g, nullptr, nullptr, 0, 0, 0, nullptr);
-    case DT_INT8: return grouped_s<DT_INT8>(g, nullptr, nullptr, 0, 0, 0, nullptr);
+    case DT_BF16: return grouped_s<DT_BF16>(g, nullptr, nullptr, 0, 0, TileSchedule{nullptr, nullptr}, nullptr);
+    case DT_FP16: return grouped_s<DT_FP16>(g, nullptr, nullptr, 0, 0, TileSchedule{nullptr, nullptr}, nullptr);
+    case DT_INT8: return grouped_s<DT_INT8>(g, nullptr, nullptr, 0, 0, TileSchedule{nullptr, nullptr}, nullptr);
     default: return hipErrorNotSupported;
     }
 }
