@@ -267,6 +267,27 @@ def test_padded_operand_copies_sampled_rows(mmm, orc, P):
         assert bits_equal(rows_of(name), _variant_ref(orc, name, A[rows], B)), name
 
 
+def test_padded_operand_copies_integer_inputs_exact(mmm):
+    """2048 x 1031 x 2048 (odd, ragged P: every method takes zero-padded
+    copies) on integer-valued inputs in [-8, 8]: every partial sum is an
+    integer below 2^53, so every method, the fused naive variant included,
+    must return the exact product."""
+    N, P, M = 2048, 1031, 2048
+    print("case padded integers", (N, P, M), flush=True)
+    A = synth.integers((N, P), 411)
+    B = synth.integers((P, M), 412)
+    rows = np.array([0, 5, 64, 1000, 2047])
+    ref = (A[rows].astype(np.int64) @ B.astype(np.int64)).astype(np.float64)
+    Ad, Bd = dev(A), dev(B)
+    cases = [("naive", None), ("naive", mmm.Config(naive_fma=True)), ("kahan", None), ("winograd", None),
+             ("winograd_scaled", None), ("dgemm", None)] + [(v, None) for v in VARIANTS]
+    for method, cfg in cases:
+        assert mmm.workspace_bytes(method, N, P, M, cfg) > 0 or method == "naive_unroll3", method
+        C = mmm.multiply(Ad, Bd, method, cfg)
+        torch.cuda.synchronize()
+        assert np.array_equal(C[torch.from_numpy(rows).cuda()].cpu().numpy(), ref), (method, cfg)
+
+
 @pytest.mark.parametrize("shape", [(2048, 2048, 2048), (2048, 512, 4096), (4096, 16, 2048), (1024, 4096, 8192)])
 def test_dgemm_direct_load_path_exact(mmm, shape):
     """Shapes whose every tile takes the direct global-to-LDS path (N, M
