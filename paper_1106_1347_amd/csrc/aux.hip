@@ -96,20 +96,6 @@ hipError_t launch_vr1(bool cols, const double* X, i64 ld, i64 nvec, i64 len, dou
                 : launch_vr2<OP, false>(X, ld, nvec, len, out, lam, sign, s);
 }
 
-__global__ __launch_bounds__(256) void max_kernel(const double* v, i64 n, double* out)
-{
-    __shared__ double red[256];
-    double m = 0.0;
-    for (i64 i = threadIdx.x; i < n; i += 256) m = max_s13(m, v[i]);
-    red[threadIdx.x] = m;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] = max_s13(red[threadIdx.x], red[threadIdx.x + w]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *out = red[0];
-}
-
 __device__ inline long long floor_half(long long x) { return x >= 0 ? x / 2 : -((-x + 1) / 2); }
 
 // Section 2.3.2: largest integer lambda with 1/2 <= 2^(2 lambda) nA/nB <= 2.
@@ -161,8 +147,7 @@ hipError_t launch_vector_reduce(RedOp op, bool cols, const double* X, i64 ld, i6
                                 const int* lam, int sign, hipStream_t s)
 {
     if (op == RED_ABS_SUM) return launch_vr1<RED_ABS_SUM>(cols, X, ld, nvec, len, out, lam, sign, s);
-    if (op == RED_PAIR_SUM) return launch_vr1<RED_PAIR_SUM>(cols, X, ld, nvec, len, out, lam, sign, s);
-    return launch_vr1<RED_ABS_MAX>(cols, X, ld, nvec, len, out, lam, sign, s);
+    return launch_vr1<RED_PAIR_SUM>(cols, X, ld, nvec, len, out, lam, sign, s);
 }
 
 hipError_t launch_norm_inf(const double* X, i64 rows, i64 cols, double* out, hipStream_t s)
@@ -171,12 +156,6 @@ hipError_t launch_norm_inf(const double* X, i64 rows, i64 cols, double* out, hip
     if (e != hipSuccess || rows <= 0) return e;
     hipLaunchKernelGGL((vecred_kernel<RED_ABS_SUM, false, false, true>), dim3((unsigned)cdiv(rows, RV)), dim3(256), 0,
                        s, X, cols, rows, cols, out, nullptr, 0);
-    return hipGetLastError();
-}
-
-hipError_t launch_max_reduce(const double* v, i64 n, double* out, hipStream_t s)
-{
-    hipLaunchKernelGGL(max_kernel, dim3(1), dim3(256), 0, s, v, n, out);
     return hipGetLastError();
 }
 

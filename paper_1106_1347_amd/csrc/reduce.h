@@ -69,8 +69,6 @@ __device__ __forceinline__ void vecred_body(const double* __restrict__ X, i64 ld
                     const double p = a * b;
                     acc = acc + p;
                 }
-            } else {
-                for (int x = 0; x < cnt; ++x) acc = max_s13(acc, fabs(SCALED ? row[x] * sc : row[x]));
             }
         }
         if (c + 1 < nchunks) store(cur ^ 1);
