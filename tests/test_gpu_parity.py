@@ -115,6 +115,48 @@ def test_integer_inputs_exact_every_method(mmm, shape):
             assert np.array_equal(run(mmm, A, B, method, cfg), ref), (method, cfg)
 
 
+def _sweep_shapes():
+    """24 seeded shapes: dimensions from 1 to 600 (half of them near
+    multiples of the 16 / 64 / 128 tile sizes, so interior and edge tiles,
+    ragged K steps and odd P all occur)."""
+    rng = np.random.default_rng(5150)
+    out = []
+    for k in range(24):
+        if k % 2:
+            N, P, M = (int(rng.integers(1, 5)) * 128 + int(rng.integers(-2, 3)) for _ in range(3))
+        else:
+            N, P, M = (int(x) for x in rng.integers(1, 601, size=3))
+        out.append((max(N, 1), max(P, 1), max(M, 1)))
+    return out
+
+
+@pytest.mark.parametrize("shape", _sweep_shapes())
+def test_random_shape_sweep(mmm, orc, shape):
+    """Every method on a seeded sweep of shapes: the orders the paper fixes
+    bit for bit against the oracle, the matrix-core paths and the split
+    product within their tolerances."""
+    N, P, M = shape
+    print("case sweep", shape, flush=True)
+    A = synth.uniform((N, P), 600 + N + P)
+    B = synth.uniform((P, M), 700 + P + M)
+    ref = orc.naive(A, B)
+    assert bits_equal(run(mmm, A, B, "naive"), ref)
+    assert bits_equal(run(mmm, A, B, "kahan"), orc.kahan(A, B))
+    assert bits_equal(run(mmm, A, B, "winograd"), orc.winograd(A, B))
+    assert bits_equal(run(mmm, A, B, "winograd_scaled"), orc.winograd_scaled(A, B))
+    for name in VARIANTS:
+        assert bits_equal(run(mmm, A, B, name), _variant_ref(orc, name, A, B)), name
+    cfg2 = mmm.Config(strassen_levels=2, strassen_leaf="naive")
+    assert bits_equal(run(mmm, A, B, "strassen_winograd", cfg2), orc.strassen(A, B, 1, orc.MODE_LEVELS, 2))
+    assert relerr(orc, run(mmm, A, B, "dgemm"), ref, A, B) <= TOL_PLAIN
+    assert relerr(orc, run(mmm, A, B, "strassen_winograd", mmm.Config(strassen_levels=2)), ref, A, B) <= TOL_STRASSEN
+    cfg = mmm.Config(split_type="int8", split_slices=7)
+    C = run(mmm, A, B, "split", cfg)
+    assert relerr(orc, C, ref, A, B) <= TOL_PLAIN
+    rows = np.unique(np.linspace(0, N - 1, 8).astype(np.int64))  # the model row by row
+    assert bits_equal(C[rows], orc.split_model_rows(A, B, rows, 7, 7))
+
+
 def test_auxiliaries_bitwise(mmm, orc):
     for rows, cols in ((1, 1), (7, 13), (255, 257), (1024, 1023)):
         print("case", rows, cols, flush=True)
