@@ -54,7 +54,8 @@ typedef enum {
     MMM_NAIVE = 0,             /* 2.1.1 NaivStandard: sum_k a_ik b_kj, k ascending, register accumulator */
     MMM_KAHAN = 1,             /* 2.1.3 NaivKahan: the same sum with Kahan's compensation */
     MMM_WINOGRAD = 2,          /* 2.3.1 WinogradOriginal: pair products minus y_i, z_k, odd-P tail */
-    MMM_WINOGRAD_SCALED = 3,   /* 2.3.2 WinogradScaled: WinogradOriginal on (2^l A, 2^-l B) */
+    MMM_WINOGRAD_SCALED = 3,   /* 2.3.2 WinogradScaled: WinogradOriginal on (2^l A, 2^-l B),
+                                  both materialised in the workspace */
     MMM_STRASSEN_NAIVE = 4,    /* 2.4.1 StrassenNaiv: 7 products, 18 additions per level */
     MMM_STRASSEN_WINOGRAD = 5, /* 2.4.2 StrassenWinograd: 7 products, 15 additions per level */
     MMM_DGEMM = 6,             /* the definition of 2.1 evaluated on FP64 matrix cores */
@@ -106,7 +107,8 @@ mmm_config mmm_config_default(void);
  * run on zero-padded copies of A (N x kp) and, when K is ragged, B (kp x M),
  * kp = P rounded up to at most the next multiple of 32.  The result is the
  * same as without the copies (bit for bit for the methods defined by a
- * summation order). */
+ * summation order).  WinogradScaled also holds 2^l A and 2^-l B (in the
+ * padded copies where those exist, else N x P and P x M doubles). */
 size_t mmm_workspace_bytes(mmm_method method, int64_t N, int64_t P, int64_t M, const mmm_config* cfg);
 
 /* C = A B by `method`.  A: N x P, B: P x M, C: N x M, device, row-major.

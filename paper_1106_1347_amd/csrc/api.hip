@@ -251,28 +251,54 @@ WinoLayout wino_layout(i64 N, i64 M, bool scaled)
     return w;
 }
 
-// y and z from the caller's A and B; the main loop reads g, which may point
-// at padded copies of them.
-mmm_status run_winograd(const double* A, const double* B, const Gemm& g, bool scaled, char* ws, hipStream_t s)
+// g may point at zero-padded copies of A and B (then g.A != A, g.B != B).
+// WinogradScaled materialises 2^lambda A and 2^-lambda B, as the paper does:
+// in place in those copies, else at sws (N x P, then P x M); y, z and the
+// main loop then run on the scaled operands.
+mmm_status run_winograd(const double* A, const double* B, const Gemm& g, bool scaled, char* ws, char* sws,
+                        hipStream_t s)
 {
     const i64 N = g.N, P = g.P, M = g.M;
     const WinoLayout w = wino_layout(N, M, scaled);
     double* y = (double*)(ws + w.y);
     double* z = (double*)(ws + w.z);
-    int* lam = nullptr;
+    Gemm gs = g;
     hipError_t e;
     if (scaled) {
         double* nA = (double*)(ws + w.nA);
         double* nB = (double*)(ws + w.nB);
-        lam = (int*)(ws + w.lam);
+        int* lam = (int*)(ws + w.lam);
         if ((e = launch_norm_inf(A, N, P, nA, s)) != hipSuccess) return from_hip(e, "norm A");
         if ((e = launch_norm_inf(B, P, M, nB, s)) != hipSuccess) return from_hip(e, "norm B");
         if ((e = launch_lambda(nA, nB, lam, s)) != hipSuccess) return from_hip(e, "lambda");
+        double* As = g.A != A ? (double*)g.A : (double*)sws;
+        if (g.A == A) {
+            gs.A = As;
+            gs.lda = P;
+            sws += align_up(sizeof(double) * (size_t)N * (size_t)P);
+        }
+        if ((e = launch_scale_pow2(g.A, g.lda, N, P, As, gs.lda, lam, +1, s)) != hipSuccess) return from_hip(e, "scale A");
+        double* Bs = g.B != B ? (double*)g.B : (double*)sws;
+        if (g.B == B) {
+            gs.B = Bs;
+            gs.ldb = M;
+        }
+        if ((e = launch_scale_pow2(g.B, g.ldb, P, M, Bs, gs.ldb, lam, -1, s)) != hipSuccess) return from_hip(e, "scale B");
     }
-    // y_i over the rows of 2^lambda A, z_k over the columns of 2^-lambda B
-    if ((e = launch_vector_reduce(RED_PAIR_SUM, false, A, P, N, P, y, lam, +1, s)) != hipSuccess) return from_hip(e, "y");
-    if ((e = launch_vector_reduce(RED_PAIR_SUM, true, B, M, M, P, z, lam, -1, s)) != hipSuccess) return from_hip(e, "z");
-    return from_hip(launch_winograd_main(g, y, z, lam, s), "winograd");
+    // y_i over the rows of (scaled) A, z_k over the columns of (scaled) B
+    if ((e = launch_vector_reduce(RED_PAIR_SUM, false, gs.A, gs.lda, N, P, y, nullptr, +1, s)) != hipSuccess)
+        return from_hip(e, "y");
+    if ((e = launch_vector_reduce(RED_PAIR_SUM, true, gs.B, gs.ldb, M, P, z, nullptr, -1, s)) != hipSuccess)
+        return from_hip(e, "z");
+    return from_hip(launch_winograd_main(gs, y, z, s), "winograd");
+}
+
+// Bytes of WinogradScaled's scaled operands beyond the padded copies.
+size_t scaled_bytes(const ValuPad& p, i64 N, i64 P, i64 M)
+{
+    if (8.0 * ((double)N * P + (double)P * M) > 9.0e18) return (size_t)-1;
+    return (p.kp ? 0 : align_up(sizeof(double) * (size_t)N * (size_t)P)) +
+           (p.copy_b ? 0 : align_up(sizeof(double) * (size_t)P * (size_t)M));
 }
 
 // ---- zero-padded operand copies (direct loads at a ragged P) ----------------
@@ -289,7 +315,7 @@ ValuPad pad_plan(mmm_method method, i64 N, i64 P, i64 M, const mmm_config& c)
     case MMM_DOT2: return valu_pad_plan(VK_DOT2, N, P, M);
     case MMM_DGEMM: return dgemm_pad_plan(N, P, M);
     case MMM_WINOGRAD: return valu_pad_plan(VK_WINOGRAD, N, P, M);
-    case MMM_WINOGRAD_SCALED: return valu_pad_plan(VK_WINOGRAD_SCALED, N, P, M);
+    case MMM_WINOGRAD_SCALED: return valu_pad_plan(VK_WINOGRAD, N, P, M);  // the main loop runs unscaled
     default: return ValuPad{0, false, false};
     }
 }
@@ -359,9 +385,11 @@ size_t mmm_workspace_bytes(mmm_method method, int64_t N, int64_t P, int64_t M, c
         return pad_bytes(pad_plan(method, N, P, M, c), N, M);
     case MMM_WINOGRAD:
     case MMM_WINOGRAD_SCALED: {
-        const size_t pb = pad_bytes(pad_plan(method, N, P, M, c), N, M);
-        if (pb == (size_t)-1) return pb;
-        return wino_layout(N, M, method == MMM_WINOGRAD_SCALED).bytes + pb;
+        const ValuPad pl = pad_plan(method, N, P, M, c);
+        const size_t pb = pad_bytes(pl, N, M);
+        const size_t sb = method == MMM_WINOGRAD_SCALED ? scaled_bytes(pl, N, P, M) : 0;
+        if (pb == (size_t)-1 || sb == (size_t)-1) return (size_t)-1;
+        return wino_layout(N, M, method == MMM_WINOGRAD_SCALED).bytes + pb + sb;
     }
     case MMM_STRASSEN_NAIVE:
     case MMM_STRASSEN_WINOGRAD: {
@@ -406,12 +434,15 @@ mmm_status mmm_multiply(const double* A, const double* B, double* C, int64_t N, 
     }
     char* ws = (char*)workspace;
     Gemm g{A, P, B, M, C, M, N, P, M};
-    // the Winograd vectors sit before the copies
+    // the Winograd vectors sit before the copies, WinogradScaled's scaled
+    // operands after them
     const size_t pad_at = method == MMM_WINOGRAD || method == MMM_WINOGRAD_SCALED
                               ? wino_layout(N, M, method == MMM_WINOGRAD_SCALED).bytes
                               : 0;
-    hipError_t pe = apply_pad(pad_plan(method, N, P, M, c), g, ws + pad_at, s);
+    const ValuPad plan = pad_plan(method, N, P, M, c);
+    hipError_t pe = apply_pad(plan, g, ws + pad_at, s);
     if (pe != hipSuccess) return from_hip(pe, "pad operands");
+    char* sws = ws ? ws + pad_at + pad_bytes(plan, N, M) : nullptr;
     switch (method) {
     case MMM_NAIVE:
         return from_hip(launch_naive(g, c.naive_fma != 0, s), "naive");
@@ -428,9 +459,9 @@ mmm_status mmm_multiply(const double* A, const double* B, double* C, int64_t N, 
     case MMM_DGEMM:
         return from_hip(launch_dgemm(g, s), "dgemm");
     case MMM_WINOGRAD:
-        return run_winograd(A, B, g, false, ws, s);
+        return run_winograd(A, B, g, false, ws, sws, s);
     case MMM_WINOGRAD_SCALED:
-        return run_winograd(A, B, g, true, ws, s);
+        return run_winograd(A, B, g, true, ws, sws, s);
     case MMM_STRASSEN_NAIVE:
     case MMM_STRASSEN_WINOGRAD: {
         StrassenPlan pl;

@@ -128,6 +128,22 @@ __global__ __launch_bounds__(256) void pad_kernel(const double* src, i64 lds, i6
     }
 }
 
+// dst = 2^(sign * lambda) src for a rows x cols block (Section 2.3.2's
+// scaled operands): one row per blockIdx.y, 4 entries per thread.  The
+// factor is a power of two, so every entry is the exact product (the same
+// value whichever kernel applies it).  dst may equal src.
+__global__ __launch_bounds__(256) void scale_kernel(const double* src, i64 lds, i64 cols, double* dst, i64 ldd,
+                                                     const int* lam, int sign)
+{
+    const double sc = ldexp(1.0, sign * *lam);
+    const i64 i = blockIdx.y;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const i64 j = ((i64)blockIdx.x * 4 + q) * 256 + threadIdx.x;
+        if (j < cols) dst[i * ldd + j] = src[i * lds + j] * sc;
+    }
+}
+
 __global__ __launch_bounds__(256) void zero_kernel(double* dst, i64 n)
 {
     for (i64 e = (i64)blockIdx.x * 256 + threadIdx.x; e < n; e += (i64)gridDim.x * 256) dst[e] = 0.0;
@@ -173,6 +189,16 @@ hipError_t launch_pad_copy(const double* src, i64 lds, i64 r, i64 c, double* dst
     i64 blocks = cdiv(total, 256 * 4);
     if (blocks > 256 * 16) blocks = 256 * 16;
     hipLaunchKernelGGL(pad_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, lds, r, c, dst, ldd, R, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_pow2(const double* src, i64 lds, i64 rows, i64 cols, double* dst, i64 ldd, const int* lam,
+                             int sign, hipStream_t s)
+{
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    if (rows > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(scale_kernel, dim3((unsigned)cdiv(cols, 1024), (unsigned)rows), dim3(256), 0, s, src, lds, cols,
+                       dst, ldd, lam, sign);
     return hipGetLastError();
 }
 

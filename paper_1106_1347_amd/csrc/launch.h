@@ -24,7 +24,6 @@ enum ValuKind {
     VK_NAIVE_FMA,
     VK_KAHAN,
     VK_WINOGRAD,
-    VK_WINOGRAD_SCALED,
     VK_ON_ARRAY,
     VK_UNROLL2,
     VK_UNROLL3,
@@ -42,7 +41,9 @@ hipError_t launch_kahan(const Gemm& g, hipStream_t s);
 // NaivOnArray (variant 0), NaivLoopUnrollingTwo/Three/Four (variant 2/3/4) or
 // compensated dot products (variant 5)
 hipError_t launch_naive_variant(const Gemm& g, int variant, hipStream_t s);
-hipError_t launch_winograd_main(const Gemm& g, const double* y, const double* z, const int* lam, hipStream_t s);
+// WinogradOriginal's main loop and odd-P tail on operands g (WinogradScaled
+// passes its materialised 2^lambda A, 2^-lambda B): C = pairs - y - z (+ tail).
+hipError_t launch_winograd_main(const Gemm& g, const double* y, const double* z, hipStream_t s);
 
 // dgemm.hip
 ValuPad dgemm_pad_plan(i64 N, i64 P, i64 M);
@@ -70,6 +71,10 @@ hipError_t launch_lambda(const double* nA, const double* nB, int* lam, hipStream
 hipError_t launch_pad_copy(const double* src, i64 lds, i64 r, i64 c, double* dst, i64 ldd, i64 R, i64 C,
                            hipStream_t s);
 hipError_t launch_fill_zero(double* dst, i64 n, hipStream_t s);
+// dst = 2^(sign * *lam) src, rows x cols (leading dims lds / ldd; lam on
+// the device); dst may equal src.
+hipError_t launch_scale_pow2(const double* src, i64 lds, i64 rows, i64 cols, double* dst, i64 ldd, const int* lam,
+                             int sign, hipStream_t s);
 
 // strassen.hip
 hipError_t launch_strassen_pre(const StrassenTree& T, int level, hipStream_t s);

@@ -241,7 +241,7 @@ __device__ __forceinline__ void arith_group(const double (&a)[Q][TM], const doub
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 typedef __attribute__((address_space(1))) void* gbl_ptr_t;
 
-template <int BM, int BN, int TM, int TN, int OP, bool SCALED>
+template <int BM, int BN, int TM, int TN, int OP>
 struct ValuTile {
     // K per LDS step; a multiple of the group length of the unrolled sums
     static constexpr int BK =
@@ -304,9 +304,8 @@ struct ValuTile {
     // Register staging.  CHECK: bounds-check every load (edge tiles);
     // otherwise only the last K step is checked.
     template <bool CHECK>
-    __device__ __forceinline__ static void mainloop_reg(const Gemm& g, i64 m0, i64 n0, i64 kmax, double sa,
-                                                        double sb, SmemReg& sm, double (&acc)[TM][TN],
-                                                        double (&cmp)[TM][TN])
+    __device__ __forceinline__ static void mainloop_reg(const Gemm& g, i64 m0, i64 n0, i64 kmax, SmemReg& sm,
+                                                        double (&acc)[TM][TN], double (&cmp)[TM][TN])
     {
         const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
         const i64 ntiles = (kmax + BK - 1) / BK;
@@ -317,19 +316,15 @@ struct ValuTile {
             for (int q = 0; q < LA; ++q) {
                 const int e = q * NT + tid, r = e / BK, k = e % BK;
                 const i64 gm = m0 + r, gk = k0 + k;
-                double v;
-                if (check) v = (gm < g.N && gk < kmax) ? g.A[gm * g.lda + gk] : 0.0;
-                else v = g.A[gm * g.lda + gk];
-                ra[q] = SCALED ? v * sa : v;
+                if (check) ra[q] = (gm < g.N && gk < kmax) ? g.A[gm * g.lda + gk] : 0.0;
+                else ra[q] = g.A[gm * g.lda + gk];
             }
 #pragma unroll
             for (int q = 0; q < LB; ++q) {
                 const int e = q * NT + tid, k = e / BN, n = e % BN;
                 const i64 gk = k0 + k, gn = n0 + n;
-                double v;
-                if (check) v = (gk < kmax && gn < g.M) ? g.B[gk * g.ldb + gn] : 0.0;
-                else v = g.B[gk * g.ldb + gn];
-                rb[q] = SCALED ? v * sb : v;
+                if (check) rb[q] = (gk < kmax && gn < g.M) ? g.B[gk * g.ldb + gn] : 0.0;
+                else rb[q] = g.B[gk * g.ldb + gn];
             }
         };
         auto lstore = [&]() __attribute__((always_inline)) {
@@ -416,9 +411,8 @@ struct ValuTile {
     // Direct loads (host has checked: tile inside the matrices, kmax a
     // multiple of BK, aligned operands with even leading dimensions).
     template <bool PART>
-    __device__ __forceinline__ static void mainloop_dma(const Gemm& g, i64 m0, i64 n0, i64 kmax, double sa,
-                                                        double sb, SmemDma& sm, double (&acc)[TM][TN],
-                                                        double (&cmp)[TM][TN])
+    __device__ __forceinline__ static void mainloop_dma(const Gemm& g, i64 m0, i64 n0, i64 kmax, SmemDma& sm,
+                                                        double (&acc)[TM][TN], double (&cmp)[TM][TN])
     {
         const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, tx = tid % 16, ty = tid / 16;
         // PART: a partial last step, whose loads read zero-padded operands
@@ -441,21 +435,6 @@ struct ValuTile {
                 const int r = p / (BN / 2), c = bslot(p % (BN / 2));
                 const double* src = g.B + (k0 + r) * g.ldb + n0 + 2 * c;
                 __builtin_amdgcn_global_load_lds((gbl_ptr_t)src, (lds_ptr_t)&sm.B[buf][blk * 128], 16, 0, 0);
-            }
-        };
-        // WinogradScaled: each lane scales the 16 bytes it loaded (exact)
-        auto rescale = [&](int buf) __attribute__((always_inline)) {
-#pragma unroll
-            for (int q = 0; q < NA / 4; ++q) {
-                double2* v = reinterpret_cast<double2*>(&sm.A[buf][(q * 4 + wave) * 128 + 2 * lane]);
-                v->x = v->x * sa;
-                v->y = v->y * sa;
-            }
-#pragma unroll
-            for (int q = 0; q < NB / 4; ++q) {
-                double2* v = reinterpret_cast<double2*>(&sm.B[buf][(q * 4 + wave) * 128 + 2 * lane]);
-                v->x = v->x * sb;
-                v->y = v->y * sb;
             }
         };
         // operands of k = 2 kp and 2 kp + 1
@@ -545,7 +524,6 @@ struct ValuTile {
             // own loads of this step have landed; after the barrier every
             // wave's have, and every wave is done with the other stage
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-            if (SCALED) rescale(cur);
             __syncthreads();
             if (t + 1 < nt) issue(t + 1, cur ^ 1);
             c_io<false>(g, m0, n0, false, acc);
@@ -564,18 +542,12 @@ struct ValuTile {
     // loads with a partial last step
     template <int MODE>
     __device__ __forceinline__ static void run(const Gemm& g, i64 tm, i64 tn, const double* __restrict__ yv,
-                                               const double* __restrict__ zv, const int* lam,
+                                               const double* __restrict__ zv,
                                                typename std::conditional<MODE != 0, SmemDma, SmemReg>::type& sm)
     {
         const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
         const i64 m0 = tm * BM, n0 = tn * BN;
         const i64 kmax = kmax_of(g.P);
-        double sa = 1.0, sb = 1.0;
-        if (SCALED) {
-            const int l = *lam;
-            sa = ldexp(1.0, l);
-            sb = ldexp(1.0, -l);
-        }
         double acc[TM][TN], cmp[TM][TN];
 #pragma unroll
         for (int i = 0; i < TM; ++i)
@@ -585,10 +557,10 @@ struct ValuTile {
                 cmp[i][j] = 0.0;
             }
         if constexpr (MODE != 0) {
-            mainloop_dma<MODE == 2>(g, m0, n0, kmax, sa, sb, sm, acc, cmp);
+            mainloop_dma<MODE == 2>(g, m0, n0, kmax, sm, acc, cmp);
         } else {
-            if (m0 + BM <= g.N && n0 + BN <= g.M) mainloop_reg<false>(g, m0, n0, kmax, sa, sb, sm, acc, cmp);
-            else mainloop_reg<true>(g, m0, n0, kmax, sa, sb, sm, acc, cmp);
+            if (m0 + BM <= g.N && n0 + BN <= g.M) mainloop_reg<false>(g, m0, n0, kmax, sm, acc, cmp);
+            else mainloop_reg<true>(g, m0, n0, kmax, sm, acc, cmp);
         }
 
         const bool odd = (OP == OP_WINOGRAD) && (g.P % 2 == 1);
@@ -599,7 +571,7 @@ struct ValuTile {
             double yi = 0.0, alast = 0.0;
             if (OP == OP_WINOGRAD) {
                 yi = yv[gm];
-                if (odd) alast = SCALED ? g.A[gm * g.lda + (g.P - 1)] * sa : g.A[gm * g.lda + (g.P - 1)];
+                if (odd) alast = g.A[gm * g.lda + (g.P - 1)];
             }
 #pragma unroll
             for (int h = 0; h < 2; ++h)
@@ -619,9 +591,7 @@ struct ValuTile {
                     if (OP == OP_WINOGRAD) {
                         c = (c - yi) - zv[gn];
                         if (odd) {
-                            const double bl =
-                                SCALED ? g.B[(g.P - 1) * g.ldb + gn] * sb : g.B[(g.P - 1) * g.ldb + gn];
-                            const double tail = alast * bl;
+                            const double tail = alast * g.B[(g.P - 1) * g.ldb + gn];
                             c = c + tail;
                         }
                     }
@@ -631,17 +601,17 @@ struct ValuTile {
     }
 };
 
-template <int BM, int BN, int TM, int TN, int OP, bool SCALED, int MODE, class Src>
+template <int BM, int BN, int TM, int TN, int OP, int MODE, class Src>
 __global__ __launch_bounds__(NT, (MODE != 0 && OP != OP_KAHAN && OP != OP_DOT2) ? MMM_VALU_DMA_MINWAVES
                                                                                 : MMM_VALU_MINWAVES) void
 valu_gemm_kernel(Src src, i64 tiles_m, i64 tiles_n, i64 total, const double* __restrict__ yv,
-                 const double* __restrict__ zv, const int* lam)
+                 const double* __restrict__ zv)
 {
-    typedef ValuTile<BM, BN, TM, TN, OP, SCALED> T;
+    typedef ValuTile<BM, BN, TM, TN, OP> T;
     __shared__ __align__(16) typename std::conditional<MODE != 0, typename T::SmemDma, typename T::SmemReg>::type sm;
     i64 prob, tm, tn;
     tile_of(xcd_remap(blockIdx.x, total), tiles_m, tiles_n, prob, tm, tn);
-    T::template run<MODE>(src.get(prob), tm, tn, yv, zv, lam, sm);
+    T::template run<MODE>(src.get(prob), tm, tn, yv, zv, sm);
 }
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
@@ -663,20 +633,20 @@ int direct_mode(const SingleSrc& src, i64 bm, i64 bn)
     return kcap >= (kmax + T::BK - 1) / T::BK * T::BK ? 2 : 0;
 }
 
-template <int BM, int BN, int TM, int TN, int OP, bool SCALED, int MODE, class Src>
+template <int BM, int BN, int TM, int TN, int OP, int MODE, class Src>
 hipError_t launch_valu_mode(const Src& src, i64 tiles_m, i64 tiles_n, i64 total, const double* yv, const double* zv,
-                            const int* lam, hipStream_t s)
+                            hipStream_t s)
 {
-    hipLaunchKernelGGL((valu_gemm_kernel<BM, BN, TM, TN, OP, SCALED, MODE, Src>), dim3((unsigned)total), dim3(NT), 0, s,
-                       src, tiles_m, tiles_n, total, yv, zv, lam);
+    hipLaunchKernelGGL((valu_gemm_kernel<BM, BN, TM, TN, OP, MODE, Src>), dim3((unsigned)total), dim3(NT), 0, s,
+                       src, tiles_m, tiles_n, total, yv, zv);
     return hipGetLastError();
 }
 
-template <int BM, int BN, int TM, int TN, int OP, bool SCALED, class Src>
-hipError_t launch_valu(const Src& src, i64 N, i64 M, const double* yv, const double* zv, const int* lam,
+template <int BM, int BN, int TM, int TN, int OP, class Src>
+hipError_t launch_valu(const Src& src, i64 N, i64 M, const double* yv, const double* zv,
                        hipStream_t s)
 {
-    typedef ValuTile<BM, BN, TM, TN, OP, SCALED> T;
+    typedef ValuTile<BM, BN, TM, TN, OP> T;
     const i64 tiles_m = cdiv(N, BM), tiles_n = cdiv(M, BN);
     const i64 total = tiles_m * tiles_n * src.count();
     if (total == 0) return hipSuccess;
@@ -684,20 +654,20 @@ hipError_t launch_valu(const Src& src, i64 N, i64 M, const double* yv, const dou
     // Strassen leaves never take direct loads (their operands are views)
     if constexpr (T::DMA_OK && std::is_same<Src, SingleSrc>::value) {
         const int mode = direct_mode<T>(src, BM, BN);
-        if (mode == 1) return launch_valu_mode<BM, BN, TM, TN, OP, SCALED, 1>(src, tiles_m, tiles_n, total, yv, zv, lam, s);
-        if (mode == 2) return launch_valu_mode<BM, BN, TM, TN, OP, SCALED, 2>(src, tiles_m, tiles_n, total, yv, zv, lam, s);
+        if (mode == 1) return launch_valu_mode<BM, BN, TM, TN, OP, 1>(src, tiles_m, tiles_n, total, yv, zv, s);
+        if (mode == 2) return launch_valu_mode<BM, BN, TM, TN, OP, 2>(src, tiles_m, tiles_n, total, yv, zv, s);
     }
-    return launch_valu_mode<BM, BN, TM, TN, OP, SCALED, 0>(src, tiles_m, tiles_n, total, yv, zv, lam, s);
+    return launch_valu_mode<BM, BN, TM, TN, OP, 0>(src, tiles_m, tiles_n, total, yv, zv, s);
 }
 
 // Launch the whole-step direct-load kernel of this tile shape when the
 // problem qualifies; false otherwise (nothing launched, and no other
 // kernel of this shape is instantiated).
-template <int BM, int BN, int TM, int TN, int OP, bool SCALED, class Src>
-bool try_launch_direct(const Src& src, i64 N, i64 M, const double* yv, const double* zv, const int* lam,
+template <int BM, int BN, int TM, int TN, int OP, class Src>
+bool try_launch_direct(const Src& src, i64 N, i64 M, const double* yv, const double* zv,
                        hipStream_t s, hipError_t& err)
 {
-    typedef ValuTile<BM, BN, TM, TN, OP, SCALED> T;
+    typedef ValuTile<BM, BN, TM, TN, OP> T;
     if constexpr (!T::DMA_OK || !std::is_same<Src, SingleSrc>::value) {
         return false;
     } else {
@@ -705,7 +675,7 @@ bool try_launch_direct(const Src& src, i64 N, i64 M, const double* yv, const dou
         const i64 tiles_m = cdiv(N, BM), tiles_n = cdiv(M, BN);
         const i64 total = tiles_m * tiles_n * src.count();
         if (total == 0 || total > 0x7fffffffLL) return false;
-        err = launch_valu_mode<BM, BN, TM, TN, OP, SCALED, 1>(src, tiles_m, tiles_n, total, yv, zv, lam, s);
+        err = launch_valu_mode<BM, BN, TM, TN, OP, 1>(src, tiles_m, tiles_n, total, yv, zv, s);
         return true;
     }
 }
@@ -737,25 +707,25 @@ struct ShapeOf {
 template <int OP, class Src>
 hipError_t launch_naive_like(const Src& src, i64 N, i64 M, hipStream_t s)
 {
-    if (N <= 48 && M <= 48) return launch_valu<32, 32, 2, 2, OP, false>(src, N, M, nullptr, nullptr, nullptr, s);
+    if (N <= 48 && M <= 48) return launch_valu<32, 32, 2, 2, OP>(src, N, M, nullptr, nullptr, s);
     if constexpr (OP == OP_NAIVE || OP == OP_NAIVE_FMA) {
         typedef Shape<MMM_VALU_NAIVE_DMA_TILE> D;
         hipError_t err = hipSuccess;
-        if (try_launch_direct<D::bm, D::bn, D::tm, D::tn, OP, false>(src, N, M, nullptr, nullptr, nullptr, s, err))
+        if (try_launch_direct<D::bm, D::bn, D::tm, D::tn, OP>(src, N, M, nullptr, nullptr, s, err))
             return err;
     }
     typedef typename ShapeOf<OP>::type S;
-    return launch_valu<S::bm, S::bn, S::tm, S::tn, OP, false>(src, N, M, nullptr, nullptr, nullptr, s);
+    return launch_valu<S::bm, S::bn, S::tm, S::tn, OP>(src, N, M, nullptr, nullptr, s);
 }
 
 // Copies for the tile the launcher takes at this shape (the 128 x 64 naive
 // tile's conditions also admit the 128 x 128 one when M allows it: both take
 // whole steps over the zero-padded K).
-template <int OP, bool SCALED>
+template <int OP>
 ValuPad pad_plan_op(i64 N, i64 P, i64 M, bool zero_k)
 {
     typedef typename ShapeOf<OP>::type S;
-    typedef ValuTile<S::bm, S::bn, S::tm, S::tn, OP, SCALED> T;
+    typedef ValuTile<S::bm, S::bn, S::tm, S::tn, OP> T;
     ValuPad p{0, false, false};
     if (!MMM_VALU_DMA || !T::DMA_OK || (N <= 48 && M <= 48) || N % S::bm != 0 || M % S::bn != 0) return p;
     if ((double)N * (double)P * (double)M < kPadMinWork) return p;
@@ -778,16 +748,15 @@ ValuPad pad_plan_op(i64 N, i64 P, i64 M, bool zero_k)
 ValuPad valu_pad_plan(ValuKind kind, i64 N, i64 P, i64 M)
 {
     switch (kind) {
-    case VK_NAIVE: return pad_plan_op<OP_NAIVE, false>(N, P, M, true);
-    case VK_NAIVE_FMA: return pad_plan_op<OP_NAIVE_FMA, false>(N, P, M, true);
-    case VK_KAHAN: return pad_plan_op<OP_KAHAN, false>(N, P, M, false);
-    case VK_WINOGRAD: return pad_plan_op<OP_WINOGRAD, false>(N, P, M, false);
-    case VK_WINOGRAD_SCALED: return pad_plan_op<OP_WINOGRAD, true>(N, P, M, false);
-    case VK_ON_ARRAY: return pad_plan_op<OP_ON_ARRAY, false>(N, P, M, false);
-    case VK_UNROLL2: return pad_plan_op<OP_UNROLL2, false>(N, P, M, false);
-    case VK_UNROLL3: return pad_plan_op<OP_UNROLL3, false>(N, P, M, false);
-    case VK_UNROLL4: return pad_plan_op<OP_UNROLL4, false>(N, P, M, false);
-    case VK_DOT2: return pad_plan_op<OP_DOT2, false>(N, P, M, false);
+    case VK_NAIVE: return pad_plan_op<OP_NAIVE>(N, P, M, true);
+    case VK_NAIVE_FMA: return pad_plan_op<OP_NAIVE_FMA>(N, P, M, true);
+    case VK_KAHAN: return pad_plan_op<OP_KAHAN>(N, P, M, false);
+    case VK_WINOGRAD: return pad_plan_op<OP_WINOGRAD>(N, P, M, false);
+    case VK_ON_ARRAY: return pad_plan_op<OP_ON_ARRAY>(N, P, M, false);
+    case VK_UNROLL2: return pad_plan_op<OP_UNROLL2>(N, P, M, false);
+    case VK_UNROLL3: return pad_plan_op<OP_UNROLL3>(N, P, M, false);
+    case VK_UNROLL4: return pad_plan_op<OP_UNROLL4>(N, P, M, false);
+    case VK_DOT2: return pad_plan_op<OP_DOT2>(N, P, M, false);
     }
     return ValuPad{0, false, false};
 }
@@ -823,17 +792,15 @@ hipError_t launch_kahan(const Gemm& g, hipStream_t s)
     return launch_naive_like<OP_KAHAN>(src, g.N, g.M, s);
 }
 
-hipError_t launch_winograd_main(const Gemm& g, const double* y, const double* z, const int* lam, hipStream_t s)
+hipError_t launch_winograd_main(const Gemm& g, const double* y, const double* z, hipStream_t s)
 {
     SingleSrc src{g};
     typedef typename ShapeOf<OP_WINOGRAD>::type S;
     typedef Shape<MMM_VALU_WINO_DMA_TILE> D;
     hipError_t err = hipSuccess;
-    if (lam ? try_launch_direct<D::bm, D::bn, D::tm, D::tn, OP_WINOGRAD, true>(src, g.N, g.M, y, z, lam, s, err)
-            : try_launch_direct<D::bm, D::bn, D::tm, D::tn, OP_WINOGRAD, false>(src, g.N, g.M, y, z, nullptr, s, err))
+    if (try_launch_direct<D::bm, D::bn, D::tm, D::tn, OP_WINOGRAD>(src, g.N, g.M, y, z, s, err))
         return err;
-    if (lam) return launch_valu<S::bm, S::bn, S::tm, S::tn, OP_WINOGRAD, true>(src, g.N, g.M, y, z, lam, s);
-    return launch_valu<S::bm, S::bn, S::tm, S::tn, OP_WINOGRAD, false>(src, g.N, g.M, y, z, nullptr, s);
+    return launch_valu<S::bm, S::bn, S::tm, S::tn, OP_WINOGRAD>(src, g.N, g.M, y, z, s);
 }
 
 }  // namespace mmm
