@@ -109,6 +109,12 @@ def test_argument_errors_before_any_launch(lib):
     assert f(0x1000, 0x90000, 0x200000, 64, 64, 64, 2, r(c), None, 0, None) == 3
     assert f(0x1000, 0x90000, 0x200000, 64, 64, 64, 2, r(c), 0x400000, 16, None) == 3
     assert f(0x1000, 0x90000, 0x200000, 64, 64, 64, 2, r(c), 0x400008, 1 << 20, None) == 3
+    # a large product with a ragged P needs its zero-padded copies (naive,
+    # DGEMM), WinogradScaled its scaled operands: refused without them
+    big = 1 << 40
+    for method in (0, 6, 3):
+        assert f(big, 2 * big, 3 * big, 4096, 4097, 4096, method, r(c), None, 0, None) == 3
+    assert f(big, 2 * big, 3 * big, 4096, 4096, 4096, 3, r(c), None, 0, None) == 3
     # bad config fields
     bad = lib._lib.mmm_config_default()
     bad.strassen_levels = 40
