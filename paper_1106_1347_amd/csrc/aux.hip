@@ -1,7 +1,8 @@
 // Auxiliary routines of Section 1 (Plus, Minus, MultiplyWithScalar,
-// NormInf) and the sequential vector reductions used by WinogradOriginal's
-// precompute (y_i, z_k), WinogradScaled's norms and the split product's
-// row and column exponents.  All are bound by HBM bandwidth.
+// NormInf), the sequential vector reductions of WinogradOriginal's
+// precompute (y_i, z_k) and WinogradScaled's norms, and the copies of the
+// direct-load paths (zero-padded operands, WinogradScaled's scaled
+// operands).  All are bound by HBM bandwidth.
 //
 // Built with -ffp-contract=off: every sum and product is rounded on its
 // own, and each reduction runs over its vector in ascending order, so the
@@ -22,31 +23,56 @@ __device__ inline double ew(double a, double b, double alpha)
     return alpha * a;
 }
 
-// Plus / Minus / MultiplyWithScalar: 16-byte loads and stores when every
-// pointer is 16-byte aligned, otherwise 8-byte ones; grid-stride loops.
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
+// Plus / Minus / MultiplyWithScalar.  Aligned operands: each thread takes 4
+// pairs of doubles 256 pairs apart, issues the four 16-byte loads of each
+// operand before any arithmetic, and loads and stores non-temporally (every
+// byte is touched once): 6.4 TB/s on 8192^2 Plus against 4.6 TB/s for a
+// grid-stride loop of single pairs.  Otherwise 8-byte accesses.
 template <int OP, bool VEC>
 __global__ __launch_bounds__(256) void ew_kernel(const double* A, const double* B, double alpha, double* C, i64 n)
 {
-    const i64 stride = (i64)gridDim.x * 256;
-    const i64 t = (i64)blockIdx.x * 256 + threadIdx.x;
     if (VEC) {
         const i64 n2 = n / 2;
-        const double2* A2 = reinterpret_cast<const double2*>(A);
-        const double2* B2 = reinterpret_cast<const double2*>(B);
-        double2* C2 = reinterpret_cast<double2*>(C);
-        for (i64 i = t; i < n2; i += stride) {
-            const double2 a = A2[i];
-            double2 b = make_double2(0.0, 0.0);
-            if (OP != EW_SCALE) b = B2[i];
-            double2 c;
-            c.x = ew<OP>(a.x, b.x, alpha);
-            c.y = ew<OP>(a.y, b.y, alpha);
-            C2[i] = c;
+        const dbl2* A2 = reinterpret_cast<const dbl2*>(A);
+        const dbl2* B2 = reinterpret_cast<const dbl2*>(B);
+        dbl2* C2 = reinterpret_cast<dbl2*>(C);
+        for (i64 i0 = (i64)blockIdx.x * 1024 + threadIdx.x; i0 < n2; i0 += (i64)gridDim.x * 1024) {
+            dbl2 a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const i64 i = i0 + u * 256;
+                if (i < n2) {
+                    a[u] = __builtin_nontemporal_load(A2 + i);
+                    if (OP != EW_SCALE) b[u] = __builtin_nontemporal_load(B2 + i);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const i64 i = i0 + u * 256;
+                if (i < n2) {
+                    dbl2 c;
+                    c.x = ew<OP>(a[u].x, OP != EW_SCALE ? b[u].x : 0.0, alpha);
+                    c.y = ew<OP>(a[u].y, OP != EW_SCALE ? b[u].y : 0.0, alpha);
+                    __builtin_nontemporal_store(c, C2 + i);
+                }
+            }
         }
-        if ((n & 1) && t == 0) C[n - 1] = ew<OP>(A[n - 1], OP != EW_SCALE ? B[n - 1] : 0.0, alpha);
+        if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0)
+            C[n - 1] = ew<OP>(A[n - 1], OP != EW_SCALE ? B[n - 1] : 0.0, alpha);
     } else {
-        for (i64 i = t; i < n; i += stride) C[i] = ew<OP>(A[i], OP != EW_SCALE ? B[i] : 0.0, alpha);
+        for (i64 i = (i64)blockIdx.x * 256 + threadIdx.x; i < n; i += (i64)gridDim.x * 256)
+            C[i] = ew<OP>(A[i], OP != EW_SCALE ? B[i] : 0.0, alpha);
     }
+}
+
+// workgroups covering `work` items at `per` items per thread, at most 2^31 - 1
+// (the kernels loop when capped)
+unsigned grid_for(i64 work, i64 per)
+{
+    const i64 b = cdiv(work, 256 * per);
+    return (unsigned)(b < 1 ? 1 : (b > 0x7fffffffLL ? 0x7fffffffLL : b));
 }
 
 template <int OP>
@@ -54,14 +80,10 @@ hipError_t launch_ew(const double* A, const double* B, double alpha, double* C, 
 {
     if (n <= 0) return hipSuccess;
     const bool vec = ((uintptr_t)A % 16 == 0) && ((uintptr_t)C % 16 == 0) && (OP == EW_SCALE || (uintptr_t)B % 16 == 0);
-    const i64 work = vec ? (n + 1) / 2 : n;
-    i64 blocks = cdiv(work, 256 * 4);
-    if (blocks > 256 * 16) blocks = 256 * 16;
-    if (blocks < 1) blocks = 1;
     if (vec)
-        hipLaunchKernelGGL((ew_kernel<OP, true>), dim3((unsigned)blocks), dim3(256), 0, s, A, B, alpha, C, n);
+        hipLaunchKernelGGL((ew_kernel<OP, true>), dim3(grid_for(n / 2, 4)), dim3(256), 0, s, A, B, alpha, C, n);
     else
-        hipLaunchKernelGGL((ew_kernel<OP, false>), dim3((unsigned)blocks), dim3(256), 0, s, A, B, alpha, C, n);
+        hipLaunchKernelGGL((ew_kernel<OP, false>), dim3(grid_for(n, 4)), dim3(256), 0, s, A, B, alpha, C, n);
     return hipGetLastError();
 }
 
@@ -118,29 +140,47 @@ __global__ void lambda_kernel(const double* nA, const double* nB, int* lam)
     *lam = res;
 }
 
+// Row-block copies: workgroup b takes row b / chunks, columns
+// 1024 (b % chunks) .. + 1023, 4 entries per thread, loads first; the grid
+// loops when rows x chunks exceeds it.
 __global__ __launch_bounds__(256) void pad_kernel(const double* src, i64 lds, i64 r, i64 c, double* dst, i64 ldd,
                                                    i64 R, i64 C)
 {
-    const i64 total = R * C;
-    for (i64 e = (i64)blockIdx.x * 256 + threadIdx.x; e < total; e += (i64)gridDim.x * 256) {
-        const i64 i = e / C, j = e - i * C;
-        dst[i * ldd + j] = (i < r && j < c) ? src[i * lds + j] : 0.0;
+    const i64 chunks = (C + 1023) / 1024;
+    for (i64 vb = blockIdx.x; vb < R * chunks; vb += gridDim.x) {
+        const i64 i = vb / chunks, j0 = (vb - i * chunks) * 1024 + threadIdx.x;
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const i64 j = j0 + u * 256;
+            v[u] = (i < r && j < c) ? src[i * lds + j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (j0 + u * 256 < C) dst[i * ldd + j0 + u * 256] = v[u];
     }
 }
 
 // dst = 2^(sign * lambda) src for a rows x cols block (Section 2.3.2's
-// scaled operands): one row per blockIdx.y, 4 entries per thread.  The
-// factor is a power of two, so every entry is the exact product (the same
-// value whichever kernel applies it).  dst may equal src.
-__global__ __launch_bounds__(256) void scale_kernel(const double* src, i64 lds, i64 cols, double* dst, i64 ldd,
-                                                     const int* lam, int sign)
+// scaled operands), laid out as pad_kernel.  The factor is a power of two,
+// so every entry is the exact product (the same value whichever kernel
+// applies it).  dst may equal src.
+__global__ __launch_bounds__(256) void scale_kernel(const double* src, i64 lds, i64 rows, i64 cols, double* dst,
+                                                     i64 ldd, const int* lam, int sign)
 {
     const double sc = ldexp(1.0, sign * *lam);
-    const i64 i = blockIdx.y;
+    const i64 chunks = (cols + 1023) / 1024;
+    for (i64 vb = blockIdx.x; vb < rows * chunks; vb += gridDim.x) {
+        const i64 i = vb / chunks, j0 = (vb - i * chunks) * 1024 + threadIdx.x;
+        double v[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const i64 j = ((i64)blockIdx.x * 4 + q) * 256 + threadIdx.x;
-        if (j < cols) dst[i * ldd + j] = src[i * lds + j] * sc;
+        for (int u = 0; u < 4; ++u) {
+            const i64 j = j0 + u * 256;
+            v[u] = j < cols ? src[i * lds + j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (j0 + u * 256 < cols) dst[i * ldd + j0 + u * 256] = v[u] * sc;
     }
 }
 
@@ -184,11 +224,9 @@ hipError_t launch_lambda(const double* nA, const double* nB, int* lam, hipStream
 hipError_t launch_pad_copy(const double* src, i64 lds, i64 r, i64 c, double* dst, i64 ldd, i64 R, i64 C,
                            hipStream_t s)
 {
-    const i64 total = R * C;
-    if (total <= 0) return hipSuccess;
-    i64 blocks = cdiv(total, 256 * 4);
-    if (blocks > 256 * 16) blocks = 256 * 16;
-    hipLaunchKernelGGL(pad_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, lds, r, c, dst, ldd, R, C);
+    if (R <= 0 || C <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pad_kernel, dim3(grid_for(R * cdiv(C, 1024) * 256, 1)), dim3(256), 0, s, src, lds, r, c, dst, ldd,
+                       R, C);
     return hipGetLastError();
 }
 
@@ -196,9 +234,8 @@ hipError_t launch_scale_pow2(const double* src, i64 lds, i64 rows, i64 cols, dou
                              int sign, hipStream_t s)
 {
     if (rows <= 0 || cols <= 0) return hipSuccess;
-    if (rows > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(scale_kernel, dim3((unsigned)cdiv(cols, 1024), (unsigned)rows), dim3(256), 0, s, src, lds, cols,
-                       dst, ldd, lam, sign);
+    hipLaunchKernelGGL(scale_kernel, dim3(grid_for(rows * cdiv(cols, 1024) * 256, 1)), dim3(256), 0, s, src, lds, rows,
+                       cols, dst, ldd, lam, sign);
     return hipGetLastError();
 }
 
