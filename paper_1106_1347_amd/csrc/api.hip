@@ -286,9 +286,9 @@ mmm_status run_winograd(const double* A, const double* B, const Gemm& g, bool sc
         if ((e = launch_scale_pow2(g.B, g.ldb, P, M, Bs, gs.ldb, lam, -1, s)) != hipSuccess) return from_hip(e, "scale B");
     }
     // y_i over the rows of (scaled) A, z_k over the columns of (scaled) B
-    if ((e = launch_vector_reduce(RED_PAIR_SUM, false, gs.A, gs.lda, N, P, y, nullptr, +1, s)) != hipSuccess)
+    if ((e = launch_vector_reduce(RED_PAIR_SUM, false, gs.A, gs.lda, N, P, y, s)) != hipSuccess)
         return from_hip(e, "y");
-    if ((e = launch_vector_reduce(RED_PAIR_SUM, true, gs.B, gs.ldb, M, P, z, nullptr, -1, s)) != hipSuccess)
+    if ((e = launch_vector_reduce(RED_PAIR_SUM, true, gs.B, gs.ldb, M, P, z, s)) != hipSuccess)
         return from_hip(e, "z");
     return from_hip(launch_winograd_main(gs, y, z, s), "winograd");
 }

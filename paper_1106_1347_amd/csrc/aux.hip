@@ -87,35 +87,27 @@ hipError_t launch_ew(const double* A, const double* B, double alpha, double* C, 
     return hipGetLastError();
 }
 
-template <int OP, bool COLS, bool SCALED, bool FOLD_MAX>
+template <int OP, bool COLS, bool FOLD_MAX>
 __global__ __launch_bounds__(256) void vecred_kernel(const double* __restrict__ X, i64 ld, i64 nvec, i64 len,
-                                                     double* __restrict__ out, const int* lam, int sign)
+                                                     double* __restrict__ out)
 {
     __shared__ double T[2][RV][RL + 1];
-    vecred_body<OP, COLS, SCALED, FOLD_MAX>(X, ld, nvec, len, out, lam, sign, blockIdx.x, T);
+    vecred_body<OP, COLS, FOLD_MAX>(X, ld, nvec, len, out, blockIdx.x, T);
 }
 
 template <int OP, bool COLS>
-hipError_t launch_vr2(const double* X, i64 ld, i64 nvec, i64 len, double* out, const int* lam, int sign,
-                      hipStream_t s)
+hipError_t launch_vr2(const double* X, i64 ld, i64 nvec, i64 len, double* out, hipStream_t s)
 {
     const i64 blocks = cdiv(nvec, RV);
     if (blocks == 0) return hipSuccess;
-    if (lam)
-        hipLaunchKernelGGL((vecred_kernel<OP, COLS, true, false>), dim3((unsigned)blocks), dim3(256), 0, s, X, ld, nvec,
-                           len, out, lam, sign);
-    else
-        hipLaunchKernelGGL((vecred_kernel<OP, COLS, false, false>), dim3((unsigned)blocks), dim3(256), 0, s, X, ld,
-                           nvec, len, out, lam, sign);
+    hipLaunchKernelGGL((vecred_kernel<OP, COLS, false>), dim3((unsigned)blocks), dim3(256), 0, s, X, ld, nvec, len, out);
     return hipGetLastError();
 }
 
 template <int OP>
-hipError_t launch_vr1(bool cols, const double* X, i64 ld, i64 nvec, i64 len, double* out, const int* lam, int sign,
-                      hipStream_t s)
+hipError_t launch_vr1(bool cols, const double* X, i64 ld, i64 nvec, i64 len, double* out, hipStream_t s)
 {
-    return cols ? launch_vr2<OP, true>(X, ld, nvec, len, out, lam, sign, s)
-                : launch_vr2<OP, false>(X, ld, nvec, len, out, lam, sign, s);
+    return cols ? launch_vr2<OP, true>(X, ld, nvec, len, out, s) : launch_vr2<OP, false>(X, ld, nvec, len, out, s);
 }
 
 __device__ inline long long floor_half(long long x) { return x >= 0 ? x / 2 : -((-x + 1) / 2); }
@@ -200,18 +192,18 @@ hipError_t launch_elementwise(EwOp op, const double* A, const double* B, double 
 }
 
 hipError_t launch_vector_reduce(RedOp op, bool cols, const double* X, i64 ld, i64 nvec, i64 len, double* out,
-                                const int* lam, int sign, hipStream_t s)
+                                hipStream_t s)
 {
-    if (op == RED_ABS_SUM) return launch_vr1<RED_ABS_SUM>(cols, X, ld, nvec, len, out, lam, sign, s);
-    return launch_vr1<RED_PAIR_SUM>(cols, X, ld, nvec, len, out, lam, sign, s);
+    if (op == RED_ABS_SUM) return launch_vr1<RED_ABS_SUM>(cols, X, ld, nvec, len, out, s);
+    return launch_vr1<RED_PAIR_SUM>(cols, X, ld, nvec, len, out, s);
 }
 
 hipError_t launch_norm_inf(const double* X, i64 rows, i64 cols, double* out, hipStream_t s)
 {
     hipError_t e = launch_fill_zero(out, 1, s);
     if (e != hipSuccess || rows <= 0) return e;
-    hipLaunchKernelGGL((vecred_kernel<RED_ABS_SUM, false, false, true>), dim3((unsigned)cdiv(rows, RV)), dim3(256), 0,
-                       s, X, cols, rows, cols, out, nullptr, 0);
+    hipLaunchKernelGGL((vecred_kernel<RED_ABS_SUM, false, true>), dim3((unsigned)cdiv(rows, RV)), dim3(256), 0, s, X,
+                       cols, rows, cols, out);
     return hipGetLastError();
 }
 

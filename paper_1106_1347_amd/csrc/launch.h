@@ -59,10 +59,9 @@ hipError_t launch_elementwise(EwOp op, const double* A, const double* B, double 
 // of a row-major rows x cols matrix with leading dimension ld:
 //   RED_ABS_SUM   out[v] = sum_q |x_q|            (q ascending, from 0.0)
 //   RED_PAIR_SUM  out[v] = sum_p x_{2p} x_{2p+1}  (p ascending, from 0.0)
-// x is first multiplied by 2^(sign * *lam) when lam is not null.
 enum RedOp { RED_ABS_SUM = 0, RED_PAIR_SUM = 1 };
 hipError_t launch_vector_reduce(RedOp op, bool cols, const double* X, i64 ld, i64 nvec, i64 len, double* out,
-                                const int* lam, int sign, hipStream_t s);
+                                hipStream_t s);
 // Section 1.4: *out = max_i sum_j |X_ij| (row sums sequential in j).
 hipError_t launch_norm_inf(const double* X, i64 rows, i64 cols, double* out, hipStream_t s);
 hipError_t launch_lambda(const double* nA, const double* nB, int* lam, hipStream_t s);

@@ -1,5 +1,6 @@
-// Sequential vector reductions shared by the auxiliary kernels and the
-// split product's preprocessing (device code, internal to libmmm).
+// Sequential vector reductions of the auxiliary kernels; the split
+// product's statistics pass uses the same layout (device code, internal to
+// libmmm).
 #pragma once
 
 #include "common.h"
@@ -15,16 +16,14 @@ __device__ inline double max_s13(double x, double y) { return x >= y ? x : y; } 
 // neighbouring columns); 16 lanes then fold their vector's chunk in order.
 constexpr int RV = 16, RL = 256, RPER = RV * RL / 256;
 
-template <int OP, bool COLS, bool SCALED, bool FOLD_MAX>
+template <int OP, bool COLS, bool FOLD_MAX>
 __device__ __forceinline__ void vecred_body(const double* __restrict__ X, i64 ld, i64 nvec, i64 len,
-                                            double* __restrict__ out, const int* lam, int sign, i64 block,
-                                            double (*T)[RV][RL + 1])
+                                            double* __restrict__ out, i64 block, double (*T)[RV][RL + 1])
 {
     const int tid = threadIdx.x;
     const i64 v0 = block * RV;
     const i64 lim = (OP == RED_PAIR_SUM) ? 2 * (len / 2) : len;
     const i64 nchunks = (lim + RL - 1) / RL;
-    const double sc = SCALED ? ldexp(1.0, sign * *lam) : 1.0;
     double r[RPER];
     auto load = [&](i64 c) {
 #pragma unroll
@@ -61,11 +60,11 @@ __device__ __forceinline__ void vecred_body(const double* __restrict__ X, i64 ld
             const int cnt = rem < RL ? (int)rem : RL;
             const double* row = T[cur][tid];
             if (OP == RED_ABS_SUM) {
-                for (int x = 0; x < cnt; ++x) acc = acc + fabs(SCALED ? row[x] * sc : row[x]);
+                for (int x = 0; x < cnt; ++x) acc = acc + fabs(row[x]);
             } else if (OP == RED_PAIR_SUM) {
                 for (int x = 0; x < cnt; x += 2) {
-                    const double a = SCALED ? row[x] * sc : row[x];
-                    const double b = SCALED ? row[x + 1] * sc : row[x + 1];
+                    const double a = row[x];
+                    const double b = row[x + 1];
                     const double p = a * b;
                     acc = acc + p;
                 }

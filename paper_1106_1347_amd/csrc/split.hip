@@ -540,6 +540,7 @@ __global__ __launch_bounds__(256) void stats_kernel(const double* __restrict__ X
                                                     double* __restrict__ norm, double* __restrict__ rmax,
                                                     double* __restrict__ cpart)
 {
+    static_assert(RL == 256, "one column of the chunk per thread");
     __shared__ double T[2][RV][RL + 1];
     const int tid = threadIdx.x;
     const i64 v0 = (i64)blockIdx.x * RV;
