@@ -313,7 +313,11 @@ def precision_section(args, mmm, torch, synth, dev, stream, errors_needed):
     C = torch.empty((n, n), dtype=torch.float64, device=dev)
     out = {"workload": "N = P = M = 8192, entries +-2^u (u ~ U[-20,20]), rows scaled by 2^v (v ~ U{-10..10}), "
                        "seeds 2001/2002", "reps": args.precision_reps}
-    rows = np.array([0, 1, 2048, 4095, 6000, 8191])
+    # fixed rows plus the two rows of A with the largest absolute row sums:
+    # every row of this workload has its own 2^v scale, and the normwise
+    # error is set by the largest rows
+    big = np.argsort(np.abs(A).sum(axis=1))[-2:]
+    rows = np.unique(np.concatenate([np.array([0, 1, 2048, 4095, 6000, 8191]), big]))
     ref = None
     if errors_needed:
         import oracle
