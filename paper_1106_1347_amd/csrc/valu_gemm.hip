@@ -518,8 +518,11 @@ struct ValuTile {
             }
         };
         if (OP == OP_ON_ARRAY) c_io<false>(g, m0, n0, true, acc);  // C = 0
+        // whole steps first (the same loop as without a partial step), then
+        // the partial one
+        const i64 nfull = kmax / BK;
         if (nt > 0) issue(0, 0);
-        for (i64 t = 0; t < nt; ++t) {
+        for (i64 t = 0; t < nfull; ++t) {
             const int cur = (int)(t & 1);
             // own loads of this step have landed; after the barrier every
             // wave's have, and every wave is done with the other stage
@@ -527,14 +530,18 @@ struct ValuTile {
             __syncthreads();
             if (t + 1 < nt) issue(t + 1, cur ^ 1);
             c_io<false>(g, m0, n0, false, acc);
-            if constexpr (PART) {
-                const i64 rem = kmax - t * BK;
-                if (rem >= BK) compute(cur);
-                else compute_part(cur, (int)rem);
-            } else {
-                compute(cur);
-            }
+            compute(cur);
             c_io<false>(g, m0, n0, true, acc);
+        }
+        if constexpr (PART) {
+            if (nfull < nt) {
+                const int cur = (int)(nfull & 1);
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                __syncthreads();
+                c_io<false>(g, m0, n0, false, acc);
+                compute_part(cur, (int)(kmax - nfull * BK));
+                c_io<false>(g, m0, n0, true, acc);
+            }
         }
     }
 
