@@ -201,18 +201,23 @@ template <int TM, int TN>
 __device__ __forceinline__ void arith_pair(const double (&a0)[TM], const double (&a1)[TM], const double (&b0)[TN],
                                            const double (&b1)[TN], double (&acc)[TM][TN])
 {
+    // half a row of 8 at a time: 8 independent sums per stage, with half the
+    // temporaries live (room for the 8 x 8 block's loop without spills)
+    constexpr int H = TN > 4 ? TN / 2 : TN;
 #pragma unroll
-    for (int i = 0; i < TM; ++i) {
-        double u[TN], v[TN], w[TN];
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) u[j] = a0[i] + b1[j];
+        for (int j0 = 0; j0 < TN; j0 += H) {
+            double u[H], v[H], w[H];
 #pragma unroll
-        for (int j = 0; j < TN; ++j) v[j] = a1[i] + b0[j];
+            for (int j = 0; j < H; ++j) u[j] = a0[i] + b1[j0 + j];
 #pragma unroll
-        for (int j = 0; j < TN; ++j) w[j] = u[j] * v[j];
+            for (int j = 0; j < H; ++j) v[j] = a1[i] + b0[j0 + j];
 #pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = acc[i][j] + w[j];
-    }
+            for (int j = 0; j < H; ++j) w[j] = u[j] * v[j];
+#pragma unroll
+            for (int j = 0; j < H; ++j) acc[i][j0 + j] = acc[i][j0 + j] + w[j];
+        }
 }
 
 // a group of Q consecutive k: (p_1 + p_2 (+ p_3 (+ p_4))) left to right,
@@ -419,23 +424,37 @@ struct ValuTile {
         // (host-checked); otherwise kmax is a whole number of steps
         const i64 nt = PART ? (kmax + BK - 1) / BK : kmax / BK;
         // lane l of a wave instruction writes LDS bytes 16 l .. 16 l + 15 of
-        // its KiB block; it fetches the global chunk that belongs there
+        // its KiB block; it fetches the global chunk that belongs there.
+        // Per-lane element offsets from the tile's corner are 32-bit (host-
+        // checked), the corner itself wave-uniform, so no 64-bit per-lane
+        // addresses stay live across the loop.
+        unsigned offa[NA / 4], offb[NB / 4];
+#pragma unroll
+        for (int q = 0; q < NA / 4; ++q) {
+            const int p = (q * 4 + wave) * 64 + lane;
+            const int r = p / CH, c = (p % CH) ^ swz(r);
+            offa[q] = (unsigned)(r * g.lda + 2 * c);
+        }
+#pragma unroll
+        for (int q = 0; q < NB / 4; ++q) {
+            const int p = (q * 4 + wave) * 64 + lane;
+            const int r = p / (BN / 2), c = bslot(p % (BN / 2));
+            offb[q] = (unsigned)(r * g.ldb + 2 * c);
+        }
+        const double* a_corner = g.A + m0 * g.lda;
+        const double* b_corner = g.B + n0;
         auto issue = [&](i64 t, int buf) __attribute__((always_inline)) {
             const i64 k0 = t * BK;
+            const double* a0 = a_corner + k0;
+            const double* b0 = b_corner + k0 * g.ldb;
 #pragma unroll
-            for (int q = 0; q < NA / 4; ++q) {
-                const int blk = q * 4 + wave, p = blk * 64 + lane;
-                const int r = p / CH, c = (p % CH) ^ swz(r);
-                const double* src = g.A + (m0 + r) * g.lda + k0 + 2 * c;
-                __builtin_amdgcn_global_load_lds((gbl_ptr_t)src, (lds_ptr_t)&sm.A[buf][blk * 128], 16, 0, 0);
-            }
+            for (int q = 0; q < NA / 4; ++q)
+                __builtin_amdgcn_global_load_lds((gbl_ptr_t)(a0 + offa[q]), (lds_ptr_t)&sm.A[buf][(q * 4 + wave) * 128],
+                                                 16, 0, 0);
 #pragma unroll
-            for (int q = 0; q < NB / 4; ++q) {
-                const int blk = q * 4 + wave, p = blk * 64 + lane;
-                const int r = p / (BN / 2), c = bslot(p % (BN / 2));
-                const double* src = g.B + (k0 + r) * g.ldb + n0 + 2 * c;
-                __builtin_amdgcn_global_load_lds((gbl_ptr_t)src, (lds_ptr_t)&sm.B[buf][blk * 128], 16, 0, 0);
-            }
+            for (int q = 0; q < NB / 4; ++q)
+                __builtin_amdgcn_global_load_lds((gbl_ptr_t)(b0 + offb[q]), (lds_ptr_t)&sm.B[buf][(q * 4 + wave) * 128],
+                                                 16, 0, 0);
         };
         // operands of k = 2 kp and 2 kp + 1
         auto frag_pair = [&](int buf, int kp, double(&a0)[TM], double(&a1)[TM], double(&b0)[TN],
@@ -636,6 +655,8 @@ int direct_mode(const SingleSrc& src, i64 bm, i64 bn)
     if (!(MMM_VALU_DMA && T::DMA_OK && g.N % bm == 0 && g.M % bn == 0 && kmax > 0 && g.lda % 2 == 0 &&
           g.ldb % 2 == 0 && aligned16(g.A) && aligned16(g.B)))
         return 0;
+    // the loads' per-lane element offsets are 32-bit
+    if ((double)bm * g.lda + T::BK * (double)g.ldb + bn >= 4294967296.0) return 0;
     if (kmax % T::BK == 0) return 1;
     return kcap >= (kmax + T::BK - 1) / T::BK * T::BK ? 2 : 0;
 }
