@@ -359,6 +359,20 @@ def precision_section(args, mmm, torch, synth, dev, stream, errors_needed):
             ent["rel_err_inf_sampled"] = oracle.norm_inf(oracle.minus(got, ref)) / nrm
         out[name] = ent
         del ws
+    # ceilings measured with the vendor library on the same box (context for
+    # the peaks, never part of the path): FP64 and BF16 GEMMs of this size
+    ceil = {}
+    for name, X, Y, peak in (("vendor_fp64_gemm", Ad, Bd, PEAK_FP64_MFMA_TFLOPS),
+                             ("vendor_bf16_gemm", Ad.to(torch.bfloat16).contiguous(),
+                              Bd.to(torch.bfloat16).contiguous(), PEAK_BF16_MFMA_TFLOPS)):
+        Z = torch.empty((n, n), dtype=X.dtype, device=dev)
+        with torch.cuda.stream(stream):
+            torch.matmul(X, Y, out=Z)
+            ms = _time(torch, stream, lambda: torch.matmul(X, Y, out=Z), args.precision_reps)
+        tf = 2.0 * n ** 3 / (ms / 1e3) / 1e12
+        ceil[name] = {"ms_p50": ms, "tflops": tf, "frac_peak": tf / peak}
+        del Z
+    out["library_ceilings"] = ceil
     return out
 
 
@@ -403,6 +417,12 @@ def aux_section(mmm, torch, dev, stream):
         ms = _time(torch, stream, fn, 10)
         gbs = bpe * n * n / (ms / 1e3) / 1e9
         res[name] = {"ms_p50": ms, "GB_s": gbs, "frac_hbm_peak": gbs / PEAK_HBM_GBS}
+    # ceiling: the runtime's own device-to-device copy of one operand (16 bytes per entry)
+    with torch.cuda.stream(stream):
+        Z.copy_(X)
+        ms = _time(torch, stream, lambda: Z.copy_(X), 10)
+    gbs = 16 * n * n / (ms / 1e3) / 1e9
+    res["ceiling_device_copy"] = {"ms_p50": ms, "GB_s": gbs, "frac_hbm_peak": gbs / PEAK_HBM_GBS}
     return res
 
 

@@ -16,6 +16,51 @@ __device__ inline double max_s13(double x, double y) { return x >= y ? x : y; } 
 // neighbouring columns); 16 lanes then fold their vector's chunk in order.
 constexpr int RV = 16, RL = 256, RPER = RV * RL / 256;
 
+// Folds one full chunk of RL entries of a vector (in LDS) into acc in
+// order.  The LDS reads run one group of 16 entries ahead of the adds, so
+// the dependent chain of adds does not wait on LDS latency per group; the
+// empty asm statements keep the compiler from hoisting later groups' reads
+// (which would hold the whole chunk in registers).
+template <int OP>
+__device__ __forceinline__ double fold_group(const double (&v)[16], double acc)
+{
+    if (OP == RED_ABS_SUM) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc = acc + fabs(v[e]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 16; e += 2) {
+            const double p = v[e] * v[e + 1];
+            acc = acc + p;
+        }
+    }
+    return acc;
+}
+
+template <int OP>
+__device__ __forceinline__ double fold_chunk(const double* row, double acc)
+{
+    constexpr int G = 16;
+    static_assert(RL % (2 * G) == 0, "chunk must hold an even number of groups");
+    double va[G], vb[G];
+#pragma unroll
+    for (int e = 0; e < G; ++e) va[e] = row[e];
+#pragma unroll 1
+    for (int g = 0; g < RL; g += 2 * G) {
+#pragma unroll
+        for (int e = 0; e < G; ++e) vb[e] = row[g + G + e];
+        asm volatile("" ::: "memory");
+        acc = fold_group<OP>(va, acc);
+        if (g + 2 * G < RL) {
+#pragma unroll
+            for (int e = 0; e < G; ++e) va[e] = row[g + 2 * G + e];
+        }
+        asm volatile("" ::: "memory");
+        acc = fold_group<OP>(vb, acc);
+    }
+    return acc;
+}
+
 template <int OP, bool COLS, bool FOLD_MAX>
 __device__ __forceinline__ void vecred_body(const double* __restrict__ X, i64 ld, i64 nvec, i64 len,
                                             double* __restrict__ out, i64 block, double (*T)[RV][RL + 1])
@@ -59,7 +104,9 @@ __device__ __forceinline__ void vecred_body(const double* __restrict__ X, i64 ld
             const i64 rem = lim - c * RL;
             const int cnt = rem < RL ? (int)rem : RL;
             const double* row = T[cur][tid];
-            if (OP == RED_ABS_SUM) {
+            if (cnt == RL) {
+                acc = fold_chunk<OP>(row, acc);
+            } else if (OP == RED_ABS_SUM) {
                 for (int x = 0; x < cnt; ++x) acc = acc + fabs(row[x]);
             } else if (OP == RED_PAIR_SUM) {
                 for (int x = 0; x < cnt; x += 2) {

@@ -576,7 +576,9 @@ __global__ __launch_bounds__(256) void stats_kernel(const double* __restrict__ X
             const i64 rem = len - c * RL;
             const int cnt = rem < RL ? (int)rem : RL;
             const double* row = T[cur][tid];
-            for (int x = 0; x < cnt; ++x) acc = acc + row[x];
+            if (cnt == RL) acc = fold_chunk<RED_ABS_SUM>(row, acc);  // entries already |x|
+            else
+                for (int x = 0; x < cnt; ++x) acc = acc + row[x];
         }
         if (ROWMAX) {
             // entries past the end were stored as 0.0, below every |x|
