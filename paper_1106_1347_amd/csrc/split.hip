@@ -205,14 +205,6 @@ __device__ __forceinline__ void split_a_body(const double* __restrict__ A, i64 N
     }
 }
 
-template <int DT>
-__global__ __launch_bounds__(256) void split_a_kernel(const double* __restrict__ A, i64 N, i64 P, i64 Np, i64 Kp,
-                                                      const double* __restrict__ rmax, const int* lam, int s,
-                                                      char* __restrict__ SA, int* __restrict__ ea, bool rmax_raw)
-{
-    split_a_body<DT>(A, N, P, Np, Kp, rmax, lam, s, SA, ea, blockIdx.x, gridDim.x, rmax_raw);
-}
-
 // B (P x M, row-major) to SB[kb][u][j][64 bytes]: a 64 (k) x 64 (j) tile
 // goes through LDS so both the loads (along j) and the stores (64-byte
 // blocks of neighbouring columns) are contiguous.
@@ -254,13 +246,20 @@ __device__ __forceinline__ void split_b_body(const double* __restrict__ B, i64 P
     }
 }
 
+// One launch for both operands' digits: workgroups below nblk_a stride over
+// A's (row, 8-entry chunk) pairs, the rest take one 64 x 64 tile of B each.
 template <int DT>
-__global__ __launch_bounds__(256) void split_b_kernel(const double* __restrict__ B, i64 P, i64 M, i64 Mp, i64 Kp,
-                                                      const double* __restrict__ cmax, const int* lam, int s,
-                                                      char* __restrict__ SB, int* __restrict__ fb, bool cmax_raw)
+__global__ __launch_bounds__(256) void split_ab_kernel(const double* __restrict__ A, i64 N, i64 P, i64 Np, i64 Kp,
+                                                       const double* __restrict__ rmax, const int* lam, int s,
+                                                       char* __restrict__ SA, int* __restrict__ ea, i64 nblk_a,
+                                                       const double* __restrict__ B, i64 M, i64 Mp,
+                                                       const double* __restrict__ cmax, char* __restrict__ SB,
+                                                       int* __restrict__ fb)
 {
     __shared__ double T[64][65];
-    split_b_body<DT>(B, P, M, Mp, Kp, cmax, lam, s, SB, fb, blockIdx.x, T, cmax_raw);
+    const i64 b = blockIdx.x;
+    if (b < nblk_a) split_a_body<DT>(A, N, P, Np, Kp, rmax, lam, s, SA, ea, b, nblk_a, true);
+    else split_b_body<DT>(B, P, M, Mp, Kp, cmax, lam, s, SB, fb, b - nblk_a, T, true);
 }
 
 // ---- the digit-product GEMM -------------------------------------------------
@@ -536,14 +535,13 @@ __global__ __launch_bounds__(grouped_tile_cfg(DT, S, FLUSH).threads(), grouped_t
 // Only the sums are bound to an order; the maxima use every thread.
 // *norm is cleared beforehand.
 template <bool NORMS, bool ROWMAX, bool COLMAX>
-__global__ __launch_bounds__(256) void stats_kernel(const double* __restrict__ X, i64 rows, i64 len,
-                                                    double* __restrict__ norm, double* __restrict__ rmax,
-                                                    double* __restrict__ cpart)
+__device__ __forceinline__ void stats_body(const double* __restrict__ X, i64 rows, i64 len,
+                                           double* __restrict__ norm, double* __restrict__ rmax,
+                                           double* __restrict__ cpart, i64 block, double (*T)[RV][RL + 1])
 {
     static_assert(RL == 256, "one column of the chunk per thread");
-    __shared__ double T[2][RV][RL + 1];
     const int tid = threadIdx.x;
-    const i64 v0 = (i64)blockIdx.x * RV;
+    const i64 v0 = block * RV;
     const i64 nchunks = (len + RL - 1) / RL;
     double r[RPER];
     auto load = [&](i64 c) {
@@ -593,7 +591,7 @@ __global__ __launch_bounds__(256) void stats_kernel(const double* __restrict__ X
 #pragma unroll
             for (int v = 0; v < RV; ++v) m = max_s13(m, T[cur][v][tid]);
             const i64 gx = c * RL + tid;
-            if (gx < len) cpart[(i64)blockIdx.x * len + gx] = m;
+            if (gx < len) cpart[block * len + gx] = m;
         }
         if (c + 1 < nchunks) store(cur ^ 1);
         __syncthreads();
@@ -609,6 +607,21 @@ __global__ __launch_bounds__(256) void stats_kernel(const double* __restrict__ X
         }
         if (tid % 16 == 0 && v0 + tid / 16 < rows) rmax[v0 + tid / 16] = __longlong_as_double((long long)u);
     }
+}
+
+// One launch for both operands: workgroups below nblk_a take 16 rows of A
+// (its norm and row maxima), the rest 16 rows of B (its norm and per-
+// workgroup column maxima), so the two passes share the machine.
+template <bool NORMS>
+__global__ __launch_bounds__(256) void stats_pair_kernel(const double* __restrict__ A, i64 N, i64 P,
+                                                         double* __restrict__ nA, double* __restrict__ rmax,
+                                                         i64 nblk_a, const double* __restrict__ B, i64 M,
+                                                         double* __restrict__ nB, double* __restrict__ cpart)
+{
+    __shared__ double T[2][RV][RL + 1];
+    const i64 b = blockIdx.x;
+    if (b < nblk_a) stats_body<NORMS, true, false>(A, N, P, nA, rmax, nullptr, b, T);
+    else stats_body<NORMS, false, true>(B, P, M, nB, nullptr, cpart, b - nblk_a, T);
 }
 
 // cmax[j] = max over the nparts rows of cpart (nparts x M) of column j:
@@ -864,41 +877,35 @@ hipError_t run_split_dt(const double* A, const double* B, double* C, i64 N, i64 
     double* nB = (double*)(ws + L.nB);
     double* rmax = (double*)(ws + L.rmax);
     double* cmax = (double*)(ws + L.cmax);
-    // one pass per operand: A's norm and row maxima, B's norm and column
-    // maxima (the maxima before the 2^lambda scaling, which split_a/split_b
-    // apply when they form the exponents).  B's per-workgroup column maxima
-    // (cdiv(P, 16) x M doubles, at most half of B's digit planes) are staged
-    // in the digit-plane region, which split_b overwrites only afterwards.
+    // one pass per operand, both in one launch: A's norm and row maxima, B's
+    // norm and column maxima (the maxima before the 2^lambda scaling, which
+    // the digit pass applies when it forms the exponents).  B's
+    // per-workgroup column maxima (cdiv(P, 16) x M doubles, at most half of
+    // B's digit planes) are staged in the digit-plane region, which the
+    // digit pass overwrites only afterwards.
     const i64 nparts = cdiv(P, RV);
     double* cpart = (double*)(ws + L.SB);
     if (scale && (e = launch_fill_zero(nA, 1, st)) != hipSuccess) return e;
     if (scale && (e = launch_fill_zero(nB, 1, st)) != hipSuccess) return e;
-    if (scale) {
-        hipLaunchKernelGGL((stats_kernel<true, true, false>), dim3((unsigned)cdiv(N, RV)), dim3(256), 0, st, A, N, P, nA,
-                           rmax, nullptr);
-        hipLaunchKernelGGL((stats_kernel<true, false, true>), dim3((unsigned)nparts), dim3(256), 0, st, B, P, M, nB,
-                           nullptr, cpart);
-    } else {
-        hipLaunchKernelGGL((stats_kernel<false, true, false>), dim3((unsigned)cdiv(N, RV)), dim3(256), 0, st, A, N, P,
-                           nullptr, rmax, nullptr);
-        hipLaunchKernelGGL((stats_kernel<false, false, true>), dim3((unsigned)nparts), dim3(256), 0, st, B, P, M,
-                           nullptr, nullptr, cpart);
-    }
+    const i64 nblk_a = cdiv(N, RV);
+    if (nblk_a + nparts > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    if (scale)
+        hipLaunchKernelGGL(stats_pair_kernel<true>, dim3((unsigned)(nblk_a + nparts)), dim3(256), 0, st, A, N, P, nA,
+                           rmax, nblk_a, B, M, nB, cpart);
+    else
+        hipLaunchKernelGGL(stats_pair_kernel<false>, dim3((unsigned)(nblk_a + nparts)), dim3(256), 0, st, A, N, P,
+                           nullptr, rmax, nblk_a, B, M, nullptr, cpart);
     hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)cdiv(M, 32)), dim3(256), 0, st, cpart, nparts, M, cmax);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (scale && (e = launch_lambda(nA, nB, lam, st)) != hipSuccess) return e;
     {
-        const i64 total = L.Np * (L.Kp / 8);
-        i64 blocks = cdiv(total, 256);
-        if (blocks > 256 * 64) blocks = 256 * 64;
-        hipLaunchKernelGGL((split_a_kernel<DT>), dim3((unsigned)blocks), dim3(256), 0, st, A, N, P, L.Np, L.Kp, rmax,
-                           lam, L.s, ws + L.SA, (int*)(ws + L.ea), true);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    {
-        const i64 blocks = (L.Kp / 64) * (L.Mp / 64);
-        hipLaunchKernelGGL((split_b_kernel<DT>), dim3((unsigned)blocks), dim3(256), 0, st, B, P, M, L.Mp, L.Kp, cmax,
-                           lam, L.s, ws + L.SB, (int*)(ws + L.fb), true);
+        i64 blk_a = cdiv(L.Np * (L.Kp / 8), 256);
+        if (blk_a > 256 * 64) blk_a = 256 * 64;
+        const i64 blk_b = (L.Kp / 64) * (L.Mp / 64);
+        if (blk_a + blk_b > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+        hipLaunchKernelGGL((split_ab_kernel<DT>), dim3((unsigned)(blk_a + blk_b)), dim3(256), 0, st, A, N, P, L.Np,
+                           L.Kp, rmax, lam, L.s, ws + L.SA, (int*)(ws + L.ea), blk_a, B, M, L.Mp, cmax, ws + L.SB,
+                           (int*)(ws + L.fb));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return dispatch_s<DT>(L, ws, C, N, M, st);
