@@ -268,8 +268,7 @@ mmm_status run_winograd(const double* A, const double* B, const Gemm& g, bool sc
         double* nA = (double*)(ws + w.nA);
         double* nB = (double*)(ws + w.nB);
         int* lam = (int*)(ws + w.lam);
-        if ((e = launch_norm_inf(A, N, P, nA, s)) != hipSuccess) return from_hip(e, "norm A");
-        if ((e = launch_norm_inf(B, P, M, nB, s)) != hipSuccess) return from_hip(e, "norm B");
+        if ((e = launch_norm_inf_pair(A, N, P, nA, B, M, nB, s)) != hipSuccess) return from_hip(e, "norms");
         if ((e = launch_lambda(nA, nB, lam, s)) != hipSuccess) return from_hip(e, "lambda");
         double* As = g.A != A ? (double*)g.A : (double*)sws;
         if (g.A == A) {
@@ -286,10 +285,7 @@ mmm_status run_winograd(const double* A, const double* B, const Gemm& g, bool sc
         if ((e = launch_scale_pow2(g.B, g.ldb, P, M, Bs, gs.ldb, lam, -1, s)) != hipSuccess) return from_hip(e, "scale B");
     }
     // y_i over the rows of (scaled) A, z_k over the columns of (scaled) B
-    if ((e = launch_vector_reduce(RED_PAIR_SUM, false, gs.A, gs.lda, N, P, y, s)) != hipSuccess)
-        return from_hip(e, "y");
-    if ((e = launch_vector_reduce(RED_PAIR_SUM, true, gs.B, gs.ldb, M, P, z, s)) != hipSuccess)
-        return from_hip(e, "z");
+    if ((e = launch_winograd_yz(gs.A, gs.lda, N, P, y, gs.B, gs.ldb, M, z, s)) != hipSuccess) return from_hip(e, "y, z");
     return from_hip(launch_winograd_main(gs, y, z, s), "winograd");
 }
 

@@ -95,21 +95,6 @@ __global__ __launch_bounds__(256) void vecred_kernel(const double* __restrict__ 
     vecred_body<OP, COLS, FOLD_MAX>(X, ld, nvec, len, out, blockIdx.x, T);
 }
 
-template <int OP, bool COLS>
-hipError_t launch_vr2(const double* X, i64 ld, i64 nvec, i64 len, double* out, hipStream_t s)
-{
-    const i64 blocks = cdiv(nvec, RV);
-    if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((vecred_kernel<OP, COLS, false>), dim3((unsigned)blocks), dim3(256), 0, s, X, ld, nvec, len, out);
-    return hipGetLastError();
-}
-
-template <int OP>
-hipError_t launch_vr1(bool cols, const double* X, i64 ld, i64 nvec, i64 len, double* out, hipStream_t s)
-{
-    return cols ? launch_vr2<OP, true>(X, ld, nvec, len, out, s) : launch_vr2<OP, false>(X, ld, nvec, len, out, s);
-}
-
 __device__ inline long long floor_half(long long x) { return x >= 0 ? x / 2 : -((-x + 1) / 2); }
 
 // Section 2.3.2: largest integer lambda with 1/2 <= 2^(2 lambda) nA/nB <= 2.
@@ -181,6 +166,32 @@ __global__ __launch_bounds__(256) void zero_kernel(double* dst, i64 n)
     for (i64 e = (i64)blockIdx.x * 256 + threadIdx.x; e < n; e += (i64)gridDim.x * 256) dst[e] = 0.0;
 }
 
+// Two independent reductions in one launch (workgroups below nblk1 take the
+// first, the rest the second), so each fills the CUs the other leaves idle.
+template <int OP, bool COLS1, bool COLS2, bool FOLD_MAX>
+__global__ __launch_bounds__(256) void vecred_pair_kernel(const double* __restrict__ X1, i64 ld1, i64 nvec1,
+                                                          i64 len1, double* __restrict__ out1, i64 nblk1,
+                                                          const double* __restrict__ X2, i64 ld2, i64 nvec2,
+                                                          i64 len2, double* __restrict__ out2)
+{
+    __shared__ double T[2][RV][RL + 1];
+    const i64 b = blockIdx.x;
+    if (b < nblk1) vecred_body<OP, COLS1, FOLD_MAX>(X1, ld1, nvec1, len1, out1, b, T);
+    else vecred_body<OP, COLS2, FOLD_MAX>(X2, ld2, nvec2, len2, out2, b - nblk1, T);
+}
+
+template <int OP, bool COLS1, bool COLS2, bool FOLD_MAX>
+hipError_t launch_pair(const double* X1, i64 ld1, i64 nvec1, i64 len1, double* out1, const double* X2, i64 ld2,
+                       i64 nvec2, i64 len2, double* out2, hipStream_t s)
+{
+    const i64 nb1 = cdiv(nvec1, RV), nb2 = cdiv(nvec2, RV);
+    if (nb1 + nb2 == 0) return hipSuccess;
+    if (nb1 + nb2 > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((vecred_pair_kernel<OP, COLS1, COLS2, FOLD_MAX>), dim3((unsigned)(nb1 + nb2)), dim3(256), 0, s,
+                       X1, ld1, nvec1, len1, out1, nb1, X2, ld2, nvec2, len2, out2);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_elementwise(EwOp op, const double* A, const double* B, double alpha, double* C, i64 n,
@@ -191,13 +202,6 @@ hipError_t launch_elementwise(EwOp op, const double* A, const double* B, double 
     return launch_ew<EW_SCALE>(A, B, alpha, C, n, s);
 }
 
-hipError_t launch_vector_reduce(RedOp op, bool cols, const double* X, i64 ld, i64 nvec, i64 len, double* out,
-                                hipStream_t s)
-{
-    if (op == RED_ABS_SUM) return launch_vr1<RED_ABS_SUM>(cols, X, ld, nvec, len, out, s);
-    return launch_vr1<RED_PAIR_SUM>(cols, X, ld, nvec, len, out, s);
-}
-
 hipError_t launch_norm_inf(const double* X, i64 rows, i64 cols, double* out, hipStream_t s)
 {
     hipError_t e = launch_fill_zero(out, 1, s);
@@ -205,6 +209,21 @@ hipError_t launch_norm_inf(const double* X, i64 rows, i64 cols, double* out, hip
     hipLaunchKernelGGL((vecred_kernel<RED_ABS_SUM, false, true>), dim3((unsigned)cdiv(rows, RV)), dim3(256), 0, s, X,
                        cols, rows, cols, out);
     return hipGetLastError();
+}
+
+hipError_t launch_norm_inf_pair(const double* A, i64 N, i64 P, double* nA, const double* B, i64 M, double* nB,
+                                hipStream_t s)
+{
+    hipError_t e = launch_fill_zero(nA, 1, s);
+    if (e == hipSuccess) e = launch_fill_zero(nB, 1, s);
+    if (e != hipSuccess) return e;
+    return launch_pair<RED_ABS_SUM, false, false, true>(A, P, N, P, nA, B, M, P, M, nB, s);
+}
+
+hipError_t launch_winograd_yz(const double* A, i64 lda, i64 N, i64 P, double* y, const double* B, i64 ldb, i64 M,
+                              double* z, hipStream_t s)
+{
+    return launch_pair<RED_PAIR_SUM, false, true, false>(A, lda, N, P, y, B, ldb, M, P, z, s);
 }
 
 hipError_t launch_lambda(const double* nA, const double* nB, int* lam, hipStream_t s)

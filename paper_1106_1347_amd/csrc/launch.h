@@ -55,15 +55,19 @@ enum EwOp { EW_PLUS = 0, EW_MINUS = 1, EW_SCALE = 2 };
 hipError_t launch_elementwise(EwOp op, const double* A, const double* B, double alpha, double* C, i64 n,
                               hipStream_t s);
 
-// Sequential reductions of the rows (cols = false) or columns (cols = true)
-// of a row-major rows x cols matrix with leading dimension ld:
+// Sequential reductions of the rows or columns of a row-major matrix:
 //   RED_ABS_SUM   out[v] = sum_q |x_q|            (q ascending, from 0.0)
 //   RED_PAIR_SUM  out[v] = sum_p x_{2p} x_{2p+1}  (p ascending, from 0.0)
 enum RedOp { RED_ABS_SUM = 0, RED_PAIR_SUM = 1 };
-hipError_t launch_vector_reduce(RedOp op, bool cols, const double* X, i64 ld, i64 nvec, i64 len, double* out,
-                                hipStream_t s);
 // Section 1.4: *out = max_i sum_j |X_ij| (row sums sequential in j).
 hipError_t launch_norm_inf(const double* X, i64 rows, i64 cols, double* out, hipStream_t s);
+// Both NormInfs of an A (N x P) and B (P x M) in one launch.
+hipError_t launch_norm_inf_pair(const double* A, i64 N, i64 P, double* nA, const double* B, i64 M, double* nB,
+                                hipStream_t s);
+// Winograd's y (pair sums along the rows of A, N x P, leading dim lda) and z
+// (pair sums down the columns of B, P x M, leading dim ldb) in one launch.
+hipError_t launch_winograd_yz(const double* A, i64 lda, i64 N, i64 P, double* y, const double* B, i64 ldb, i64 M,
+                              double* z, hipStream_t s);
 hipError_t launch_lambda(const double* nA, const double* nB, int* lam, hipStream_t s);
 // Copy an r x c block (leading dims lds/ldd) into the top-left of an
 // R x C destination whose remaining entries are set to zero.
