@@ -746,24 +746,27 @@ __global__ void jobs_lambda_kernel(const SplitJob* jobs, int n)
     }
 }
 
+// Digits of every job of a group in one launch: workgroups below na take
+// an entry of the A table (a range of one job's (row, 8-entry chunk)
+// pairs), the rest an entry of the B table (one 64 x 64 tile of a job's B).
 template <int DT>
-__global__ __launch_bounds__(256) void jobs_split_a_kernel(const SplitJob* __restrict__ jobs,
-                                                           const JobBlock* __restrict__ blocks, int s, bool scaled)
-{
-    const JobBlock b = blocks[blockIdx.x];
-    const SplitJob& j = jobs[b.job];
-    split_a_body<DT>(j.A, j.N, j.P, j.Np, j.Kp, j.rmax, scaled ? j.lam : nullptr, s, j.SA, j.ea, b.index,
-                     split_a_blocks(j), true);
-}
-
-template <int DT>
-__global__ __launch_bounds__(256) void jobs_split_b_kernel(const SplitJob* __restrict__ jobs,
-                                                           const JobBlock* __restrict__ blocks, int s, bool scaled)
+__global__ __launch_bounds__(256) void jobs_split_ab_kernel(const SplitJob* __restrict__ jobs,
+                                                            const JobBlock* __restrict__ ablocks, i64 na,
+                                                            const JobBlock* __restrict__ bblocks, int s, bool scaled)
 {
     __shared__ double T[64][65];
-    const JobBlock b = blocks[blockIdx.x];
-    const SplitJob& j = jobs[b.job];
-    split_b_body<DT>(j.B, j.P, j.M, j.Mp, j.Kp, j.cmax, scaled ? j.lam : nullptr, s, j.SB, j.fb, b.index, T, true);
+    const i64 w = blockIdx.x;
+    if (w < na) {
+        const JobBlock b = ablocks[w];
+        const SplitJob& j = jobs[b.job];
+        split_a_body<DT>(j.A, j.N, j.P, j.Np, j.Kp, j.rmax, scaled ? j.lam : nullptr, s, j.SA, j.ea, b.index,
+                         split_a_blocks(j), true);
+    } else {
+        const JobBlock b = bblocks[w - na];
+        const SplitJob& j = jobs[b.job];
+        split_b_body<DT>(j.B, j.P, j.M, j.Mp, j.Kp, j.cmax, scaled ? j.lam : nullptr, s, j.SB, j.fb, b.index, T,
+                         true);
+    }
 }
 
 struct SplitLayout {
@@ -964,12 +967,11 @@ hipError_t launch_split_grouped_dt(const SplitGroup& g, const SplitJob* jobs, in
     }
     if (scale) hipLaunchKernelGGL(jobs_lambda_kernel, dim3((unsigned)cdiv(n, 256)), blk, 0, st, jobs, n);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (tab.nablocks > 0)
-        hipLaunchKernelGGL(jobs_split_a_kernel<DT>, dim3((unsigned)tab.nablocks), blk, 0, st, jobs, tab.ablocks, g.s,
-                           scale);
-    if (tab.nbblocks > 0)
-        hipLaunchKernelGGL(jobs_split_b_kernel<DT>, dim3((unsigned)tab.nbblocks), blk, 0, st, jobs, tab.bblocks, g.s,
-                           scale);
+    const i64 nab = (i64)tab.nablocks + tab.nbblocks;
+    if (nab > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    if (nab > 0)
+        hipLaunchKernelGGL(jobs_split_ab_kernel<DT>, dim3((unsigned)nab), blk, 0, st, jobs,
+                           tab.ablocks, (i64)tab.nablocks, tab.bblocks, g.s, scale);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return total > 0 ? grouped_s<DT>(g, jobs, prefix, n, grid, tab.sched, st) : hipSuccess;
 }
