@@ -11,7 +11,8 @@
 //   4. For g = 2..s+1: G_g = sum_{t+u=g} D_A^(t) D_B^(u), an exact integer
 //      matrix formed on the matrix cores (digits are exact in bf16/fp16/int8;
 //      products and partial sums stay below the accumulator's exact range
-//      and are flushed to FP64 before they could exceed it).
+//      and are flushed to FP64 before they could exceed it, each group at
+//      the interval its own number of pairs allows).
 //   5. c = sum_{g = s+1 .. 2} 2^(-beta g) G_g in FP64, in that order; then
 //      C_ij = 2^(e_i + f_j) c.
 //
@@ -403,7 +404,13 @@ __device__ __forceinline__ void split_tile(const char* __restrict__ SA, const ch
     // is never too lax
     constexpr int PER_BLOCK = NBLK / NW + S;
 
-    int since_flush = 0;
+    // Group g (pairs with t + u = g, index from 0) holds g + 1 digit pairs;
+    // flush_steps is the exact-range interval of the fullest group (S
+    // pairs), so group g may run flush_steps * S / (g + 1) steps between
+    // flushes: its partial sums then stay within the same bound.
+    int left[FLUSH ? G : 1];
+#pragma unroll
+    for (int g = 0; g < (FLUSH ? G : 1); ++g) left[g] = flush_steps * S / (g + 1);
 #pragma unroll
     for (int q = 0; q < NST - 1; ++q)
         if (q < steps) {
@@ -438,17 +445,17 @@ __device__ __forceinline__ void split_tile(const char* __restrict__ SA, const ch
             }
         if (MMM_SPLIT_SCHED > 0 && S >= MMM_SPLIT_SCHED) sched_digit_pairs<S, WBM>();
         if (FLUSH) {
-            if (++since_flush == flush_steps) {
-                since_flush = 0;
 #pragma unroll
-                for (int g = 0; g < G; ++g)
+            for (int g = 0; g < G; ++g)
+                if (--left[g] == 0) {
+                    left[g] = flush_steps * S / (g + 1);
 #pragma unroll
                     for (int i = 0; i < WBM; ++i) {
 #pragma unroll
                         for (int r = 0; r < 4; ++r) acc64[g][i][r] += (double)acc[g][i][r];
                         acc[g][i] = (acc_t){0, 0, 0, 0};
                     }
-            }
+                }
         }
     };
     for (i64 kb = 0; kb < steps; kb += NST) {
