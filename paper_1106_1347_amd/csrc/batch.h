@@ -10,6 +10,7 @@ enum DgemmTile { DGEMM_TILE_AUTO = 0, DGEMM_TILE_128x128 = 1, DGEMM_TILE_64x64 =
 
 int dgemm_tile_bm(int tile);
 int dgemm_tile_bn(int tile);
+int dgemm_grouped_per_cu(int tile);
 // Tiles of a persistent grouped kernel per workgroup: workgroup w runs the
 // global tile indices list[off[w]] .. list[off[w + 1] - 1] (device arrays
 // of grid + 1 and total ints), a schedule balanced on the host.

@@ -411,6 +411,27 @@ hipError_t launch_dgemm_strassen_leaves(const StrassenLeafSrc& src, hipStream_t 
 int dgemm_tile_bm(int tile) { return tile == DGEMM_TILE_64x64 ? 64 : 128; }
 int dgemm_tile_bn(int tile) { return tile == DGEMM_TILE_128x128 ? 128 : 64; }
 
+// Workgroups of the persistent grouped kernel that fit on one CU at once (its
+// register and LDS footprint for that tile shape), so the grid can fill the
+// chip: smaller tiles leave room for more resident workgroups, whose loads
+// then overlap.
+int dgemm_grouped_per_cu(int tile)
+{
+    int n = 0;
+    hipError_t e;
+    if (tile == DGEMM_TILE_128x128)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, dgemm_grouped_kernel<4, 4>, NT, 0);
+    else if (tile == DGEMM_TILE_64x64)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, dgemm_grouped_kernel<2, 2>, NT, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, dgemm_grouped_kernel<4, 2>, NT, 0);
+    if (e != hipSuccess || n < 1) {
+        (void)hipGetLastError();
+        return 2;
+    }
+    return n;
+}
+
 hipError_t launch_dgemm_grouped(int tile, const Gemm* probs, const i64* prefix, int nprob, i64 total, int grid,
                                 TileSchedule sch, hipStream_t s)
 {
