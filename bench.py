@@ -58,6 +58,7 @@ PRECISION = [
     ("dgemm", "dgemm", {}),
     ("split_int8_s7", "split", {"split_type": "int8", "split_slices": 7}),
     ("split_bf16_s6", "split", {"split_type": "bf16", "split_slices": 6}),
+    ("split_fp16_s6", "split", {"split_type": "fp16", "split_slices": 6}),
     ("strassen_winograd_L1", "strassen_winograd", {"strassen_levels": 1}),
     ("strassen_winograd_L2", "strassen_winograd", {"strassen_levels": 2}),
 ]
@@ -69,8 +70,8 @@ PRECISION = [
 COUNTED_TRAFFIC = {
     "kahan": {"bytes": 3.3576e+09, "file": "paper_1106_1347_amd/csrc/valu_gemm.hip",
               "sha256": "c222f1ed93ef6f95a59b2dd1ad0c3a9a77fe8ea689a6f0462e24b53b7677e36c"},
-    "dgemm": {"bytes": 1.8760e+09, "file": "paper_1106_1347_amd/csrc/dgemm.hip",
-              "sha256": "24497d9b97af0b017fd2fe4cd65849e426d88907de939fd8aa63f446cb48c267"},
+    "dgemm": {"bytes": 1.8663e+09, "file": "paper_1106_1347_amd/csrc/dgemm.hip",
+              "sha256": "6cde41f24dff417abc4b34646945670d8025cd7dcfaed948b7a1f600fb7a36e7"},
 }
 
 
