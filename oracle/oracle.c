@@ -579,8 +579,10 @@ int oracle_strassen(const double* A, const double* B, double* C, i64 N, i64 P, i
 /* Split-precision model (not a method of the paper)                      */
 /* ---------------------------------------------------------------------- */
 
-/* Model of the split product.  Parity unpinned beyond integer exactness,
- * invariance under the lambda scaling and its truncation bound.
+/* Model of the split product.  Pinned by integer exactness, invariance
+ * under the lambda scaling, the digits' exact reconstruction and the
+ * truncation bound; the order of the final FP64 recombination (step 5) is
+ * this model's own choice, which no external value fixes.
  *
  * 1. If scale_lambda is set, lambda is computed from the infinity norms as
  *    in WinogradScaled and A is taken as 2^lambda A, B as 2^-lambda B.
