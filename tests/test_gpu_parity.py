@@ -380,3 +380,34 @@ def test_dot2_recovers_cancellation(mmm, orc):
     C = run(mmm, A, B, "dot2")
     assert bits_equal(C, orc.dot2(A, B))
     assert (C[1::2] == 1.0).all() and (C[::2] == -1.0).all()
+
+
+@pytest.mark.parametrize("n", [384, 2048])
+def test_nonfinite_inputs_stay_in_their_rows(mmm, orc, n):
+    """Reading of non-finite inputs: nothing beyond IEEE propagation is
+    promised, which for the plain sums (NaivStandard, DGEMM) means a NaN in
+    row i of A makes row i of C NaN, an infinity makes it infinite (B has no
+    zeros here), and every other row is the finite product.  n = 384 takes
+    the register kernels, n = 2048 the direct-load ones."""
+    A = synth.uniform((n, n), 41)
+    B = synth.uniform((n, n), 42)
+    B[B == 0.0] = 0.5
+    i_nan, i_inf = 5, n - 3
+    A[i_nan, n // 2] = np.nan
+    A[i_inf, 7] = np.inf
+    rows = np.array([0, i_nan, i_inf, n - 1], dtype=np.int64)
+    ref = orc.naive_rows(A, B, rows)
+    for method in ("naive", "dgemm"):
+        print("case", method, n, flush=True)
+        C = mmm.multiply(dev(A), dev(B), method)
+        torch.cuda.synchronize()
+        got = C.cpu().numpy()[rows]
+        assert np.isnan(got[1]).all() and np.isnan(ref[1]).all(), method
+        assert np.isinf(got[2]).all() and np.array_equal(np.sign(got[2]), np.sign(ref[2])), method
+        fin = [0, 3]
+        assert np.isfinite(got[fin]).all(), method
+        if method == "naive":
+            assert bits_equal(got[fin], ref[fin])
+        else:
+            err = orc.norm_inf(orc.minus(got[fin], ref[fin])) / (orc.norm_inf(A[[0, n - 1]]) * orc.norm_inf(B))
+            assert err <= TOL_PLAIN
