@@ -277,8 +277,10 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
     for (auto& kv : sg)
         if (e == hipSuccess) e = split_grouped_prepare(kv.second.g);
 
-    // record the launch sequence: FP64 groups on the capture stream, split
-    // groups on a forked branch
+    // record the launch sequence: split groups on a forked branch, recorded
+    // first so their short memory-bound preprocessing kernels are dispatched
+    // before the persistent FP64 kernels take every workgroup slot; FP64
+    // groups on the capture stream
     hipStream_t cap = nullptr, side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
@@ -289,13 +291,6 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
     if (e == hipSuccess) {
         hipError_t le = hipEventRecord(fork, cap);
         if (le == hipSuccess) le = hipStreamWaitEvent(side, fork, 0);
-        for (auto& kv : dg) {
-            if (le != hipSuccess) break;
-            DGroup& g = kv.second;
-            const TileSchedule sch{(const int*)(base + g.off_soff), (const int*)(base + g.off_slist)};
-            le = launch_dgemm_grouped(g.tile, (const Gemm*)(base + g.off_probs), (const i64*)(base + g.off_prefix),
-                                      (int)g.probs.size(), g.prefix.back(), g.grid, sch, cap);
-        }
         for (auto& kv : sg) {
             if (le != hipSuccess) break;
             SGroup& g = kv.second;
@@ -309,6 +304,13 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
             le = launch_split_grouped(g.g, (const SplitJob*)(base + g.off_jobs), (int)g.jobs.size(),
                                       (const i64*)(base + g.off_prefix), g.prefix.back(), tab,
                                       c.split_scale_lambda != 0, g.grid, side);
+        }
+        for (auto& kv : dg) {
+            if (le != hipSuccess) break;
+            DGroup& g = kv.second;
+            const TileSchedule sch{(const int*)(base + g.off_soff), (const int*)(base + g.off_slist)};
+            le = launch_dgemm_grouped(g.tile, (const Gemm*)(base + g.off_probs), (const i64*)(base + g.off_prefix),
+                                      (int)g.probs.size(), g.prefix.back(), g.grid, sch, cap);
         }
         if (le == hipSuccess) le = hipEventRecord(join, side);
         if (le == hipSuccess) le = hipStreamWaitEvent(cap, join, 0);
