@@ -75,13 +75,18 @@ double oracle_max_double(double x, double y) { return x >= y ? x : y; }
 
 /* Section 1.4 (NormInf): max over rows of the row sum of |A_ij|.  Each row
  * sum runs over j in ascending order from 0.0; the maximum is taken with the
- * max of Section 1.3 starting from 0.0 (an empty matrix has norm 0). */
+ * max of Section 1.3 starting from 0.0 (an empty matrix has norm 0).
+ * The max of Section 1.3 is defined by a comparison, and comparisons do not
+ * order NaN; the paper is silent on it.  Reading: a NaN row sum makes the
+ * norm NaN (the first such row sum is returned and kept), so a NaN entry
+ * anywhere in A gives a NaN norm whichever row it sits in. */
 double oracle_norm_inf(const double* A, i64 rows, i64 cols)
 {
     double best = 0.0;
     for (i64 i = 0; i < rows; ++i) {
         double s = 0.0;
         for (i64 j = 0; j < cols; ++j) s = s + fabs(A[i * cols + j]);
+        if (isnan(s)) return s;
         best = oracle_max_double(best, s);
     }
     return best;
@@ -177,23 +182,25 @@ void oracle_naive_unroll(const double* A, const double* B, double* C, i64 N, i64
     }
 }
 
-/* Section 2.1.3 (NaivKahan): the naive sum with Kahan's compensation in the
- * form the paper prints: with x = A_ik * B_kj rounded on its own,
- *   err = err + x;  t = sum + err;  err = (sum - t) + err;  sum = t;
- * starting from sum = err = 0.0.  The entry is the final sum; the residual
- * err is dropped.  (err carries the negated classic compensation term, so
- * this is Kahan's algorithm operation for operation.) */
+/* Section 2.1.3 (NaivKahan): the naive sum of the products x_k = A_ik B_kj
+ * (each rounded on its own) with Kahan's compensated summation, written
+ * from the classic published algorithm (Kahan 1965; Higham, "Accuracy and
+ * Stability of Numerical Algorithms", Algorithm 4.2): with sum = c = 0.0,
+ * for each k the corrected term y = x_k - c is added, t = sum + y, the
+ * rounding error of that addition is recovered as c = (t - sum) - y, and
+ * sum = t.  The entry is the final sum; the last c is dropped.  The paper's
+ * error variable holds -c, so its rounded sums are the same. */
 void oracle_kahan(const double* A, const double* B, double* C, i64 N, i64 P, i64 M)
 {
 #pragma omp parallel for schedule(static) num_threads(g_threads) if (N * P * M > 32768)
     for (i64 i = 0; i < N; ++i) {
         for (i64 j = 0; j < M; ++j) {
-            double sum = 0.0, err = 0.0, t;
+            double sum = 0.0, c = 0.0;
             for (i64 k = 0; k < P; ++k) {
                 const double x = A[i * P + k] * B[k * M + j];
-                err = err + x;
-                t = sum + err;
-                err = (sum - t) + err;
+                const double y = x - c;
+                const double t = sum + y;
+                c = (t - sum) - y;
                 sum = t;
             }
             C[i * M + j] = sum;
@@ -210,12 +217,12 @@ void oracle_kahan_rows(const double* A, const double* B, double* out, i64 N, i64
     for (i64 r = 0; r < nrows; ++r) {
         const i64 i = rows[r];
         for (i64 j = 0; j < M; ++j) {
-            double sum = 0.0, err = 0.0, t;
+            double sum = 0.0, c = 0.0;
             for (i64 k = 0; k < P; ++k) {
                 const double x = A[i * P + k] * B[k * M + j];
-                err = err + x;
-                t = sum + err;
-                err = (sum - t) + err;
+                const double y = x - c;
+                const double t = sum + y;
+                c = (t - sum) - y;
                 sum = t;
             }
             out[r * M + j] = sum;

@@ -126,8 +126,11 @@ __device__ __forceinline__ void arith_k(const double (&a)[TM], const double (&b)
                                         double (&cmp)[TM][TN])
 {
     if constexpr (OP == OP_KAHAN) {
-        // as printed: err = err + x; t = sum + err; err = (sum - t) + err; sum = t
-        double x[TM][TN], e[TM][TN], t[TM][TN];
+        // Kahan's compensated summation in its classic published form
+        // (Higham, Algorithm 4.2): the product x is rounded on its own, the
+        // corrected term y = x - c is added, c = (t - sum) - y recovers the
+        // rounding error of that addition.  cmp holds c.
+        double x[TM][TN], y[TM][TN], t[TM][TN];
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -135,16 +138,16 @@ __device__ __forceinline__ void arith_k(const double (&a)[TM], const double (&b)
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
-            for (int j = 0; j < TN; ++j) e[i][j] = cmp[i][j] + x[i][j];
+            for (int j = 0; j < TN; ++j) y[i][j] = x[i][j] - cmp[i][j];
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
-            for (int j = 0; j < TN; ++j) t[i][j] = acc[i][j] + e[i][j];
+            for (int j = 0; j < TN; ++j) t[i][j] = acc[i][j] + y[i][j];
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
             for (int j = 0; j < TN; ++j) {
-                cmp[i][j] = (acc[i][j] - t[i][j]) + e[i][j];
+                cmp[i][j] = (t[i][j] - acc[i][j]) - y[i][j];
                 acc[i][j] = t[i][j];
             }
     } else if constexpr (OP == OP_DOT2) {

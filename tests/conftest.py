@@ -1,3 +1,4 @@
+import json
 import os
 import sys
 
@@ -18,3 +19,19 @@ def orc():
 
     oracle.set_threads(min(8, max(1, len(os.sched_getaffinity(0)))))
     return oracle
+
+
+def _hexf(v):
+    return float(v) if v in ("inf", "-inf") else float.fromhex(v)
+
+
+@pytest.fixture(scope="session")
+def aux_cases():
+    """Plus / Minus / MultiplyWithScalar cases whose results were worked by
+    hand from the binary64 rounding rule (tests/golden/aux_worked_values.json):
+    (plus, minus, scale) lists of (x, y, result) / (alpha, x, result)."""
+    with open(os.path.join(os.path.dirname(__file__), "golden", "aux_worked_values.json")) as f:
+        doc = json.load(f)
+    pm = [[(_hexf(c["x"]), _hexf(c["y"]), _hexf(c["result"])) for c in doc[k]] for k in ("plus", "minus")]
+    sc = [(_hexf(c["alpha"]), _hexf(c["x"]), _hexf(c["result"])) for c in doc["multiply_with_scalar"]]
+    return pm[0], pm[1], sc

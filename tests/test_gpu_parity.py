@@ -8,6 +8,8 @@ normwise tolerance ||C - C_oracle||inf / (||A||inf ||B||inf) <= 1e-13
 (DGEMM) and <= 1e-11 (Strassen, up to 3 levels); integer-valued inputs
 must give the exact product bit for bit for every method.
 """
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -179,6 +181,43 @@ def test_auxiliaries_bitwise(mmm, orc):
     t = 2.0 ** -53
     assert mmm.norm_inf(dev(np.array([[1.0, t, t]]))).item() == 1.0
     assert mmm.norm_inf(dev(np.array([[t, t, 1.0]]))).item() == 1.0 + 2.0 ** -52
+
+
+def test_auxiliaries_worked_values(mmm, orc, aux_cases):
+    # Sections 1.1, 1.2, 1.5: the hand-worked roundings (ties, signed zeros,
+    # overflow, subnormals), bitwise, through the C ABI; the oracle gives the
+    # same bits (pinned on the CPU against the same cases).
+    plus_c, minus_c, scale_c = aux_cases
+    for cases, f, g in ((plus_c, mmm.plus, orc.plus), (minus_c, mmm.minus, orc.minus)):
+        X = np.array([[c[0] for c in cases]] * 3)
+        Y = np.array([[c[1] for c in cases]] * 3)
+        want = np.array([[c[2] for c in cases]] * 3)
+        got = f(dev(X), dev(Y)).cpu().numpy()
+        assert bits_equal(got, want), (got, want)
+        assert bits_equal(got, g(X, Y))
+    for alpha, x, w in scale_c:
+        got = mmm.multiply_with_scalar(alpha, dev(np.array([[x, -x, x]]))).cpu().numpy()
+        assert bits_equal(got, np.array([[w, -w, w]])), (alpha, x, got, w)
+
+
+def test_norm_inf_nan_and_inf(mmm, orc):
+    # Section 1.4 with the NaN reading: a NaN anywhere gives a NaN norm (the
+    # same bits as the oracle's), an infinity gives +inf, in a middle row and
+    # in the last row, across row blocks; WinogradScaled's lambda from such a
+    # norm is 0 on the device as in the oracle.
+    nan = float("nan")
+    for rows, cols in ((5, 3), (300, 257), (1024, 1030)):
+        for r in (rows // 2, rows - 1):
+            for bad in (nan, -math.inf):
+                print("case", rows, cols, r, bad, flush=True)
+                X = synth.uniform((rows, cols), 7)
+                X[r, cols // 3] = bad
+                got = mmm.norm_inf(dev(X))
+                want = orc.norm_inf(X)
+                assert bits_equal(got.cpu().numpy().reshape(1), np.array([want])), (got.item(), want)
+                Y = synth.uniform((cols, 4), 8)
+                lam = mmm.winograd_lambda(got, mmm.norm_inf(dev(Y)))
+                assert lam.item() == orc.winograd_lambda(want, orc.norm_inf(Y)) == 0
 
 
 def test_lambda_on_device(mmm, orc):

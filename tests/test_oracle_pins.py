@@ -328,13 +328,67 @@ def test_norm_inf_and_aux(orc):
     t = 2.0 ** -53
     assert orc.norm_inf(np.array([[1.0, t, t]])) == 1.0
     assert orc.norm_inf(np.array([[t, t, 1.0]])) == 1.0 + 2.0 ** -52
-    X = synth.uniform((7, 9), 1)
-    Y = synth.uniform((7, 9), 2)
-    assert np.array_equal(orc.plus(X, Y), X + Y)
-    assert np.array_equal(orc.minus(X, Y), X - Y)
-    assert np.array_equal(orc.scale(0.375, X), 0.375 * X)
     assert orc.max_int(3, -2) == 3 and orc.max_int(-5, -5) == -5
     assert orc.max_double(-0.5, 0.25) == 0.25
+
+
+def _bits(x):
+    return np.asarray(x, dtype=np.float64).view(np.int64)
+
+
+def _row(*v):
+    return np.array([v], dtype=np.float64)
+
+
+def test_plus_minus_scale_worked_by_hand(orc, aux_cases):
+    # Sections 1.1, 1.2, 1.5: one rounding per entry.  Every expected value
+    # is worked from the binary64 rounding rule; laying the cases out as a
+    # matrix also checks that entries do not mix.
+    PLUS_CASES, MINUS_CASES, SCALE_CASES = aux_cases
+    for cases, f in ((PLUS_CASES, orc.plus), (MINUS_CASES, orc.minus)):
+        X = np.array([c[0] for c in cases]).reshape(1, -1)
+        Y = np.array([c[1] for c in cases]).reshape(1, -1)
+        want = np.array([c[2] for c in cases]).reshape(1, -1)
+        got = f(X, Y)
+        assert np.array_equal(_bits(got), _bits(want)), (got, want)
+        n = X.size
+        got2 = f(np.tile(X, (3, 1)).reshape(3, n), np.tile(Y, (3, 1)).reshape(3, n))
+        assert np.array_equal(_bits(got2), _bits(np.tile(want, (3, 1))))
+    X = np.array([[c[1] for c in SCALE_CASES]])
+    for idx, (alpha, x, w) in enumerate(SCALE_CASES):
+        got = orc.scale(alpha, _row(x, x, -x))
+        assert _bits(got[0, 0]) == _bits(w) and _bits(got[0, 1]) == _bits(w), (alpha, x, got, w)
+        # (-x) alpha = -(x alpha) under round-to-nearest
+        assert _bits(got[0, 2]) == _bits(-w), (alpha, x, got)
+    got = orc.scale(0.5, np.tile(X, (2, 1)))
+    assert np.array_equal(_bits(got), _bits(np.tile(X * 0.5, (2, 1))))  # entries stay in place
+    # NaN operands give NaN
+    assert np.isnan(orc.plus(_row(math.inf), _row(-math.inf))[0, 0])
+    assert np.isnan(orc.minus(_row(math.inf), _row(math.inf))[0, 0])
+    assert np.isnan(orc.scale(0.0, _row(math.inf))[0, 0])
+    # empty matrices are accepted
+    assert orc.plus(np.zeros((0, 4)), np.zeros((0, 4))).shape == (0, 4)
+
+
+def test_norm_inf_nan_and_inf_reading(orc):
+    # Section 1.4 with the Section 1.3 max, whose comparison does not order
+    # NaN: a NaN anywhere makes the norm NaN (the reading), an infinity
+    # makes it +inf; the position of the row does not matter.
+    nan = float("nan")
+    for r in range(4):
+        A = np.ones((4, 3))
+        A[r, 1] = nan
+        got = orc.norm_inf(A)
+        assert math.isnan(got), r
+        assert _bits(got) == _bits(abs(nan)), r          # the NaN of the row sum, sign cleared by |.|
+        A[r, 1] = -math.inf
+        assert orc.norm_inf(A) == math.inf, r
+    A = np.ones((5, 2))
+    A[1, 0] = -math.inf
+    A[3, 1] = nan
+    assert math.isnan(orc.norm_inf(A))
+    # lambda of WinogradScaled from a NaN or infinite norm is 0 (Section 2.3.2 reading)
+    assert orc.winograd_lambda(nan, 2.0) == 0 and orc.winograd_lambda(2.0, math.inf) == 0
 
 
 def test_rel_err_closed_form(orc):
