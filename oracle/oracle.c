@@ -104,18 +104,64 @@ void oracle_scale(double alpha, const double* A, double* C, i64 rows, i64 cols)
 
 /* Section 2.1.1 (NaivStandard): (AB)_ij = sum_k A_ik B_kj, accumulated in an
  * auxiliary variable that starts at 0.0, k ascending.  Leading dimensions
- * allow the routine to serve as the leaf of the Strassen recursion. */
+ * allow the routine to serve as the leaf of the Strassen recursion.
+ *
+ * The auxiliary variables of a few rows of C are kept side by side (one
+ * per entry) and the k loop runs outside the j loop, so B is read along its
+ * rows: every entry still starts at 0.0 and takes its products in ascending
+ * k, each product and each sum rounded on its own, which is the same chain
+ * of roundings as one entry at a time. */
+enum { NAIVE_ROWS = 8 };
+
+static void naive_row_block(const double* A, i64 lda, const double* B, i64 ldb, i64 P, i64 M,
+                            const i64* rows, i64 nr, double* aux)
+{
+    for (i64 r = 0; r < nr * M; ++r) aux[r] = 0.0;
+    for (i64 k = 0; k < P; ++k) {
+        const double* b = B + k * ldb;
+        for (i64 r = 0; r < nr; ++r) {
+            const double a = A[rows[r] * lda + k];
+            double* x = aux + r * M;
+            for (i64 j = 0; j < M; ++j) x[j] = x[j] + a * b[j];
+        }
+    }
+}
+
+static void naive_rows_ld(const double* A, i64 lda, const double* B, i64 ldb, double* C, i64 ldc, i64 N, i64 P,
+                          i64 M, const i64* rows)
+{
+    const i64 nblk = (N + NAIVE_ROWS - 1) / NAIVE_ROWS;
+#pragma omp parallel num_threads(g_threads) if (N * P * M > 32768)
+    {
+        double* aux = (double*)malloc(sizeof(double) * NAIVE_ROWS * (size_t)(M > 0 ? M : 1));
+#pragma omp for schedule(dynamic, 1)
+        for (i64 bk = 0; bk < nblk; ++bk) {
+            const i64 r0 = bk * NAIVE_ROWS;
+            const i64 nr = N - r0 < NAIVE_ROWS ? N - r0 : NAIVE_ROWS;
+            i64 idx[NAIVE_ROWS];
+            for (i64 r = 0; r < nr; ++r) idx[r] = rows ? rows[r0 + r] : r0 + r;
+            if (aux) {
+                naive_row_block(A, lda, B, ldb, P, M, idx, nr, aux);
+                for (i64 r = 0; r < nr; ++r)
+                    for (i64 j = 0; j < M; ++j) C[(r0 + r) * ldc + j] = aux[r * M + j];
+            } else {
+                /* no memory for the row block: one entry at a time */
+                for (i64 r = 0; r < nr; ++r)
+                    for (i64 j = 0; j < M; ++j) {
+                        double v = 0.0;
+                        for (i64 k = 0; k < P; ++k) v = v + A[idx[r] * lda + k] * B[k * ldb + j];
+                        C[(r0 + r) * ldc + j] = v;
+                    }
+            }
+        }
+        free(aux);
+    }
+}
+
 static void naive_ld(const double* A, i64 lda, const double* B, i64 ldb, double* C, i64 ldc,
                      i64 N, i64 P, i64 M)
 {
-#pragma omp parallel for schedule(static) num_threads(g_threads) if (N * P * M > 32768)
-    for (i64 i = 0; i < N; ++i) {
-        for (i64 j = 0; j < M; ++j) {
-            double aux = 0.0;
-            for (i64 k = 0; k < P; ++k) aux = aux + A[i * lda + k] * B[k * ldb + j];
-            C[i * ldc + j] = aux;
-        }
-    }
+    naive_rows_ld(A, lda, B, ldb, C, ldc, N, P, M, NULL);
 }
 
 void oracle_naive(const double* A, const double* B, double* C, i64 N, i64 P, i64 M)
@@ -130,15 +176,7 @@ void oracle_naive_rows(const double* A, const double* B, double* out, i64 N, i64
                        const i64* rows, i64 nrows)
 {
     (void)N;
-#pragma omp parallel for schedule(static) num_threads(g_threads)
-    for (i64 r = 0; r < nrows; ++r) {
-        const i64 i = rows[r];
-        for (i64 j = 0; j < M; ++j) {
-            double aux = 0.0;
-            for (i64 k = 0; k < P; ++k) aux = aux + A[i * P + k] * B[k * M + j];
-            out[r * M + j] = aux;
-        }
-    }
+    naive_rows_ld(A, P, B, M, out, M, nrows, P, M, rows);
 }
 
 /* Section 2.1.2 (NaivOnArray): the same sum accumulated directly in the
