@@ -18,9 +18,9 @@ def serve():
     return s
 
 
-def make_requests(n, seed):
+def make_requests(n, seed, hi=1536):
     reqs = []
-    for r in synth.serving_requests(n, seed, rate_per_s=1000.0, lo=32, hi=1536):
+    for r in synth.serving_requests(n, seed, rate_per_s=1000.0, lo=32, hi=hi):
         N, P, M = r["shape"]
         g = torch.Generator(device="cuda").manual_seed(seed * 1000 + r["id"])
         A = torch.rand((N, P), generator=g, dtype=torch.float64, device="cuda") * 2 - 1
@@ -58,3 +58,39 @@ def test_alone_equals_mix(serve, orc):
         An, Bn = reqs[k][0].cpu().numpy(), reqs[k][1].cpu().numpy()
         e = orc.rel_err_inf(mix[k].numpy(), orc.naive(An, Bn), orc.norm_inf(An), orc.norm_inf(Bn))
         assert e <= reqs[k][2], (k, e)
+
+
+def test_alone_equals_mix_up_to_4096_routed_by_measured_cost(serve, orc):
+    # the serving shape range (dims log-uniform on 32..4096), the method of
+    # each request picked by a router calibrated on this GPU; every result
+    # bitwise equal alone and in the mix, and within its tolerance against
+    # the oracle on sampled rows (the row of A with the largest row sum among
+    # them)
+    reqs = make_requests(24, 11, hi=4096)
+    router = serve.Router()
+    router.calibrate(reps=2)
+    methods = set()
+    alone = []
+    srv = serve.Server(budget_bytes=32 << 30, streams=1, router=router)
+    for (A, B, tol) in reqs:
+        alone.append(srv.submit(A, B, tol).result(timeout=120))
+    methods |= set(srv.stats()["methods"])
+    srv.close()
+    srv = serve.Server(budget_bytes=6 << 30, streams=4, router=router)
+    futs = [srv.submit(A, B, tol) for (A, B, tol) in reqs]
+    mix = [f.result(timeout=300) for f in futs]
+    st = srv.stats()
+    srv.close()
+    assert st["requests"] == len(reqs) and st["failed"] == 0
+    assert st["peak_budget_used"] <= 6 << 30
+    rng = np.random.default_rng(12)
+    for k, ((A, B, tol), a, m) in enumerate(zip(reqs, alone, mix)):
+        print("request", k, tuple(A.shape), B.shape[1], tol, flush=True)
+        assert torch.equal(a.view(torch.int64), m.view(torch.int64)), k
+        An, Bn = A.cpu().numpy(), B.cpu().numpy()
+        rows = np.unique(np.concatenate([rng.choice(An.shape[0], size=min(3, An.shape[0]), replace=False),
+                                         [int(np.argmax(np.abs(An).sum(axis=1)))]])).astype(np.int64)
+        got = m.cpu().numpy()[rows]
+        e = orc.rel_err_inf(got, orc.naive_rows(An, Bn, rows), orc.norm_inf(An), orc.norm_inf(Bn))
+        assert e <= tol, (k, e)
+    print("methods used", sorted(methods), flush=True)
