@@ -1,20 +1,29 @@
-"""Benchmark of the hot path: C = AB by every method of the library on the
-N = M = 4096, P in {4096, 4097} FP64 workload (entries uniform on [-1, 1]).
+"""Benchmark of the hot path: FP64-grade C = AB on one MI355X.
 
-One step = one pass of every method over both shapes (P = 4096 and the odd
-P = 4097).  Prints ONE JSON line with the whole-step FP64-grade throughput
-(sum of 2NPM over the step's products divided by the step's time), the
-per-method median and p99 latency, TFLOP/s and relative infinity-norm error
-on sampled rows, the roofline of the dominant kernel measured live with HIP
-events on the stream the kernels run on, and the CPU oracle timed on a
-bounded sample of the same workload.
+Headline (one JSON line): the split-precision product against the plain
+FP64 matrix-core GEMM at N = P = M = 8192 on the wide-range workload
+(entries +-2^u, u ~ U[-20, 20], rows scaled by 2^v, v ~ U{-10..10}).  One
+step = one full product (digit extraction, digit GEMM, recombination) with
+the operands resident in HBM.  ``value`` is the FP64-grade TFLOP/s (2NPM per
+step time) of the fastest split configuration whose relative infinity-norm
+error on the sampled rows is <= 1e-13; DGEMM's TFLOP/s, the ratio and the
+p99 latency of a step stand beside it, with the serving p99.  ``roofline``
+is the digit GEMM kernel of that configuration (the dominant kernel), its
+mean launch time measured with HIP events on the stream it runs on, against
+the published matrix-core peak of its digit type.  ``cpu_baseline`` is the
+CPU oracle (the naive definition, all usable host cores) on a bounded sample
+of the rows of the same product.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Extra keys: the 256^3 latency of every method (and the single-core oracle
+time), the all-methods step at N = M = 4096, P in {4096, 4097}, the
+auxiliaries' HBM bandwidth, the 2048-problem batch graph, the serving loop
+at 50% and 80% of its capacity, and the paper's test table at n = 800.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--only SECTIONS]
 """
 import argparse
 import json
 import os
-import platform
 import sys
 import time
 
@@ -28,20 +37,28 @@ FP64_GRADE = 1e-13
 
 # MI355X published peaks and chip constants.
 PEAK_FP64_MFMA_TFLOPS = 78.6
+PEAK_BF16_MFMA_TFLOPS = 2516.6   # dense; FP16 the same
+PEAK_INT8_MFMA_TOPS = 5033.2     # dense
 PEAK_HBM_GBS = 8000.0
 CUS, SIMDS_PER_CU, LANES_PER_SIMD, CLOCK_GHZ = 256, 4, 16, 2.4
 # non-fused FP64 vector operations per second (each op one flop): one wave64
 # instruction per SIMD every 4 clocks
 PEAK_FP64_VALU_OPS_T = CUS * SIMDS_PER_CU * LANES_PER_SIMD * CLOCK_GHZ * 1e9 / 1e12  # 39.3
 
-# (name, method, config kwargs, algorithmic cost per multiply-add, bound, unit of the cost)
-#   naive:   1 mul + 1 add (rounded separately)           -> 2 VALU ops / MAC
-#   kahan:   1 mul + 4 add/sub                             -> 5 VALU ops / MAC
-#   winograd: 2 add + 1 mul + 1 add per pair of MACs       -> 2 VALU ops / MAC
-#   dgemm:   2 flop / MAC on FP64 matrix cores
-#   split:   s(s+1)/2 digit-pair products x 2 ops / MAC on the bf16 / int8 matrix cores
-PEAK_BF16_MFMA_TFLOPS = 2516.6
-PEAK_INT8_MFMA_TOPS = 5033.2
+SECTIONS = ("headline", "latency", "allmethods", "aux", "batch", "serve", "paper")
+
+# the comparison at 8192^3: (name, method, config kwargs)
+HEADLINE = [
+    ("dgemm", "dgemm", {}),
+    ("split_int8_s7", "split", {"split_type": "int8", "split_slices": 7}),
+    ("split_bf16_s6", "split", {"split_type": "bf16", "split_slices": 6}),
+    ("split_fp16_s6", "split", {"split_type": "fp16", "split_slices": 6}),
+    ("strassen_winograd_L2", "strassen_winograd", {"strassen_levels": 2}),
+]
+
+# the all-methods step at 4096: (name, method, config kwargs, algorithmic ops per multiply-add, bound)
+#   naive: 1 mul + 1 add (rounded separately) -> 2 VALU ops / MAC; kahan: 1 mul + 4 add/sub -> 5;
+#   winograd: 2 add + 1 mul + 1 add per pair of MACs -> 2; dgemm: 2 flop / MAC on the FP64 matrix cores
 METHODS = [
     ("dgemm", "dgemm", {}, 2.0, "mfma"),
     ("naive", "naive", {}, 2.0, "alu"),
@@ -53,14 +70,14 @@ METHODS = [
     ("split_int8_s7", "split", {"split_type": "int8", "split_slices": 7}, None, None),
     ("split_bf16_s6", "split", {"split_type": "bf16", "split_slices": 6}, None, None),
 ]
-# the precision comparison at 8192^3 on the wide-range distribution
-PRECISION = [
-    ("dgemm", "dgemm", {}),
+
+LATENCY_METHODS = [
+    ("naive", "naive", {}), ("kahan", "kahan", {}), ("winograd", "winograd", {}),
+    ("winograd_scaled", "winograd_scaled", {}), ("dgemm", "dgemm", {}),
+    ("strassen_naive_L2", "strassen_naive", {"strassen_levels": 2}),
+    ("strassen_winograd_L2", "strassen_winograd", {"strassen_levels": 2}),
     ("split_int8_s7", "split", {"split_type": "int8", "split_slices": 7}),
     ("split_bf16_s6", "split", {"split_type": "bf16", "split_slices": 6}),
-    ("split_fp16_s6", "split", {"split_type": "fp16", "split_slices": 6}),
-    ("strassen_winograd_L1", "strassen_winograd", {"strassen_levels": 1}),
-    ("strassen_winograd_L2", "strassen_winograd", {"strassen_levels": 2}),
 ]
 
 
@@ -89,316 +106,324 @@ def counted_traffic(name):
     return rec["bytes"] if ok else None
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--size", type=int, default=4096)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", default="", help="comma-separated subset of methods (for profiling)")
-    ap.add_argument("--no-precision", action="store_true", help="skip the 8192^3 split-vs-DGEMM comparison")
-    ap.add_argument("--precision-reps", type=int, default=5)
-    ap.add_argument("--precision-only", action="store_true", help="run only the 8192^3 comparison (profiling)")
-    ap.add_argument("--no-aux", action="store_true", help="skip the auxiliary-kernel bandwidth section")
-    ap.add_argument("--no-batch", action="store_true", help="skip the 2048-problem batch section")
-    ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
-    ap.add_argument("--no-paper-test", action="store_true", help="skip the paper's test table (n = 800)")
-    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--size", type=int, default=4096, help="N = M of the all-methods step")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip timing the CPU oracle (errors are still taken on a few sampled rows)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--only", default="", help="comma-separated sections of %s" % (SECTIONS,))
+    ap.add_argument("--headline", default="", help="comma-separated subset of the 8192^3 configurations")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-budget-gib", type=float, default=96.0)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
-    return ap.parse_args()
+    return ap.parse_args(argv)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: there is no multi-GPU path (the products of the workload "
-              "are independent per GPU; see the design notes on sharding). Use --gpus 1.", file=sys.stderr)
-        sys.exit(2)
-    import torch
-
-    import paper_1106_1347_amd as mmm
-    import synth
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
-    if args.precision_only:
-        stream = torch.cuda.current_stream()
-        print(json.dumps({"precision_8192": precision_section(args, mmm, torch, synth, dev, stream,
-                                                              errors_needed=not args.no_cpu_baseline)}), flush=True)
-        return
-    n = args.size
-    shapes = [(n, n, n), (n, n + 1, n)]
-    methods = [m for m in METHODS if not args.only or m[0] in args.only.split(",")]
-
-    data = {}
-    for (N, P, M) in shapes:
-        A = synth.uniform((N, P), synth.seed_a(1))
-        B = synth.uniform((P, M), synth.seed_b(1))
-        Ad = torch.from_numpy(A).to(dev)
-        Bd = torch.from_numpy(B).to(dev)
-        C = torch.empty((N, M), dtype=torch.float64, device=dev)
-        data[P] = (A, B, Ad, Bd, C)
-    ws = {}
-    for name, method, kw, _, _ in methods:
-        cfg = mmm.Config(**kw)
-        for (N, P, M) in shapes:
-            need = mmm.workspace_bytes(method, N, P, M, cfg)
-            ws[(name, P)] = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
-    stream = torch.cuda.current_stream()
-
-    def one_step(timings):
-        for name, method, kw, _, _ in methods:
-            cfg = mmm.Config(**kw)
-            for (N, P, M) in shapes:
-                _, _, Ad, Bd, C = data[P]
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                mmm.multiply(Ad, Bd, method, cfg, out=C, workspace=ws[(name, P)], stream=stream)
-                e1.record(stream)
-                if timings is not None:
-                    timings.append((name, P, e0, e1))
-
-    for _ in range(args.warmup):
-        one_step(None)
-    torch.cuda.synchronize()
-    if args.copy_mib:
-        src = torch.ones(args.copy_mib * (1 << 20) // 8, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-
-    timings = []
-    step_events = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s0 = torch.cuda.Event(enable_timing=True)
-        s1 = torch.cuda.Event(enable_timing=True)
-        s0.record(stream)
-        one_step(timings)
-        s1.record(stream)
-        step_events.append((s0, s1))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-
-    step_ms = [a.elapsed_time(b) for a, b in step_events]
-    per = {}
-    for name, P, e0, e1 in timings:
-        per.setdefault((name, P), []).append(e0.elapsed_time(e1))
-    flop_step = sum(2.0 * N * P * M for (N, P, M) in shapes) * len(methods)
-    total_s = sum(step_ms) / 1e3
-    value = flop_step * args.steps / total_s / 1e12
-
-    # errors on sampled rows, against the oracle (also the CPU baseline sample)
-    errors = {}
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-
-        # the host cores this process may use (the GPU machine grants 16 per GPU)
-        threads = min(len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS", "16")))
-        oracle.set_threads(threads)
-        rows = np.linspace(0, n - 1, 8 * threads).round().astype(np.int64)
-        ref = {}
-        cpu_t = 0.0
-        cpu_flop = 0.0
-        for (N, P, M) in shapes:
-            A, B, _, _, _ = data[P]
-            t = time.perf_counter()
-            ref[P] = oracle.naive_rows(A, B, rows)
-            cpu_t += time.perf_counter() - t
-            cpu_flop += 2.0 * len(rows) * P * M
-        cpu = {"value": cpu_flop / cpu_t / 1e12, "unit": "TFLOP/s", "cores": oracle.get_threads(), "kind": "oracle",
-               "sample": "%d of %d rows of C at P=4096 and P=4097 by the naive definition (FP64, k ascending, "
-                         "threads split rows), %.1f s wall" % (len(rows), n, cpu_t),
-               "cpu_model": platform.processor() or _cpu_model()}
-        nrm = {P: (oracle.norm_inf(data[P][0]), oracle.norm_inf(data[P][1])) for (_, P, _) in shapes}
-        ridx = torch.from_numpy(rows).to(dev)
-        for name, method, kw, _, _ in methods:
-            cfg = mmm.Config(**kw)
-            worst = 0.0
-            for (N, P, M) in shapes:
-                _, _, Ad, Bd, C = data[P]
-                mmm.multiply(Ad, Bd, method, cfg, out=C, workspace=ws[(name, P)], stream=stream)
-                got = C[ridx].cpu().numpy()
-                e = oracle.norm_inf(oracle.minus(got, ref[P])) / (nrm[P][0] * nrm[P][1])
-                worst = max(worst, e)
-            errors[name] = worst
-
-    precision = None
-    if not args.no_precision:
-        precision = precision_section(args, mmm, torch, synth, dev, stream, errors_needed=not args.no_cpu_baseline)
-    aux = None if args.no_aux else aux_section(mmm, torch, dev, stream)
-    batch = None if args.no_batch else batch_section(mmm, torch, synth, dev, stream)
-    serving = None if args.no_serve else serve_section(args, mmm, torch, synth, dev)
-    paper_test = None if args.no_paper_test else paper_test_section()
-
-    results = {}
-    for name, method, kw, cost, bound in methods:
-        ms = []
-        for (N, P, M) in shapes:
-            ms += per[(name, P)]
-        ms = np.array(ms)
-        fl = np.mean([2.0 * N * P * M for (N, P, M) in shapes])
-        med = float(np.median(ms))
-        results[name] = {"ms_p50": med, "ms_p99": float(np.percentile(ms, 99)), "ms_mean": float(ms.mean()),
-                         "tflops_p50": fl / (med / 1e3) / 1e12,
-                         "rel_err_inf_sampled": errors.get(name)}
-
-    # dominant single-kernel method: the largest share of the step
-    single = [m for m in methods if m[3] is not None]
-    dom = max(single, key=lambda m: results[m[0]]["ms_mean"])
-    dname, _, _, dcost, dbound = dom
-    dms = results[dname]["ms_mean"]
-    macs = np.mean([N * P * M for (N, P, M) in shapes])
-    if dbound == "mfma":
-        achieved = dcost * macs / (dms / 1e3) / 1e12
-        peak = PEAK_FP64_MFMA_TFLOPS
-    else:
-        achieved = dcost * macs / (dms / 1e3) / 1e12
-        peak = PEAK_FP64_VALU_OPS_T
-    roofline = {"bound": dbound, "kernel": dname, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": counted_traffic(dname),
-                "note": "achieved = %g algorithmic FP64 ops per multiply-add x N*P*M / mean launch time; "
-                        "alu peak = 256 CU x 4 SIMD x 16 lanes x 2.4 GHz non-fused FP64 ops" % dcost}
-
-    fp64_grade = all((e is None or e <= FP64_GRADE) for e in errors.values()) if errors else None
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "TFLOP/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": total_s * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "C = AB, N = M = %d, P in {%d, %d}, entries U[-1,1] (seeds 1001/1002), one product "
-                               "per method per shape per step" % (n, n, n + 1),
-                   "methods": [m[0] for m in methods], "global_batch": len(shapes) * len(methods),
-                   "parallelism": "single GPU"},
-        "fp64_grade_all": fp64_grade,
-        "step_ms_p50": float(np.median(step_ms)),
-        "step_ms_p99": float(np.percentile(step_ms, 99)),
-        "wall_s": wall,
-        "methods": results,
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "precision_8192": precision,
-        "aux_8192": aux,
-        "batch_2048": batch,
-        "serving": serving,
-        "paper_test_800": paper_test,
-        "device": torch.cuda.get_device_name(0),
-    }
-    print(json.dumps(out), flush=True)
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
-def precision_section(args, mmm, torch, synth, dev, stream, errors_needed):
-    """DGEMM against the split products and Strassen-Winograd (DGEMM leaf, 1
-    and 2 levels) at N = P = M = 8192 on the wide-range distribution: median
-    time, FP64-grade TFLOP/s (2NPM/t) and relative infinity-norm error on
-    sampled rows against the oracle."""
+def _time(torch, stream, fn, reps):
+    ms = []
+    for _ in range(reps):
+        e0, e1 = _events(torch)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    return float(np.median(ms))
+
+
+def _pct(xs, p):
+    return float(np.percentile(np.asarray(xs), p))
+
+
+def _rel_err(oracle, got, ref, nrm):
+    return float(oracle.norm_inf(oracle.minus(got, ref)) / nrm) if nrm > 0 else 0.0
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _host_threads():
+    # the host cores this process may use (the GPU machine grants 16 per GPU)
+    return max(1, min(len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS", "16"))))
+
+
+# ---------------------------------------------------------------------------------------------------
+# the headline: split against DGEMM at 8192^3
+
+def headline_section(args, mmm, torch, synth, dev, stream):
+    import oracle
+
     n = 8192
     A = synth.wide_range((n, n), synth.seed_a(2))
     B = synth.wide_range((n, n), synth.seed_b(2))
     Ad = torch.from_numpy(A).to(dev)
     Bd = torch.from_numpy(B).to(dev)
     C = torch.empty((n, n), dtype=torch.float64, device=dev)
-    out = {"workload": "N = P = M = 8192, entries +-2^u (u ~ U[-20,20]), rows scaled by 2^v (v ~ U{-10..10}), "
-                       "seeds 2001/2002", "reps": args.precision_reps}
-    # fixed rows plus the two rows of A with the largest absolute row sums:
-    # every row of this workload has its own 2^v scale, and the normwise
-    # error is set by the largest rows
-    big = np.argsort(np.abs(A).sum(axis=1))[-2:]
-    rows = np.unique(np.concatenate([np.array([0, 1, 2048, 4095, 6000, 8191]), big]))
-    ref = None
-    if errors_needed:
-        import oracle
+    torch.cuda.synchronize()
+    flop = 2.0 * n ** 3
+    todo = [h for h in HEADLINE if not args.headline or h[0] in args.headline.split(",")]
 
-        ref = oracle.naive_rows(A, B, rows)
-        nrm = oracle.norm_inf(A) * oracle.norm_inf(B)
+    # the CPU oracle on sampled rows first: the two rows of A with the
+    # largest absolute row sums (each row carries its own 2^v scale, so they
+    # set the normwise error) plus evenly spaced rows, extended to about
+    # cpu_seconds of oracle work; these rows time the CPU baseline and give
+    # every configuration's error
+    threads = _host_threads()
+    oracle.set_threads(threads)
+    big = np.argsort(np.abs(A).sum(axis=1))[-2:]
+    rows = np.unique(np.concatenate([np.linspace(0, n - 1, 8 * threads - 2).round().astype(np.int64), big]))
+    nrm = oracle.norm_inf(A) * oracle.norm_inf(B)
+    t = time.perf_counter()
+    ref = oracle.naive_rows(A, B, rows)
+    cpu_t = time.perf_counter() - t
+    if not args.no_cpu_baseline and cpu_t < args.cpu_seconds:
+        more = int(len(rows) * (args.cpu_seconds / max(cpu_t, 1e-3) - 1.0))
+        more = max(0, min(more, n - len(rows)))
+        if more > 0:
+            rest = np.setdiff1d(np.arange(n), rows)
+            extra = np.sort(np.random.default_rng(2003).choice(rest, size=more, replace=False))
+            t = time.perf_counter()
+            ref2 = oracle.naive_rows(A, B, extra)
+            cpu_t += time.perf_counter() - t
+            rows = np.concatenate([rows, extra])
+            ref = np.concatenate([ref, ref2])
     ridx = torch.from_numpy(rows).to(dev)
-    for name, method, kw in PRECISION:
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = {"value": 2.0 * len(rows) * n * n / cpu_t / 1e12, "unit": "TFLOP/s", "cores": oracle.get_threads(),
+               "kind": "oracle",
+               "sample": "%d of the %d rows of C = AB at N = P = M = 8192 (wide-range workload) by the naive "
+                         "definition in FP64 (k ascending, threads split rows), %.1f s wall"
+                         % (len(rows), n, cpu_t),
+               "cpu_model": _cpu_model(), "seconds": cpu_t}
+
+    runs = {}
+    for name, method, kw in todo:
         cfg = mmm.Config(**kw)
         ws = torch.empty(max(mmm.workspace_bytes(method, n, n, n, cfg), 1), dtype=torch.uint8, device=dev)
-        mmm.multiply(Ad, Bd, method, cfg, out=C, workspace=ws, stream=stream)
+        for _ in range(args.warmup):
+            mmm.multiply(Ad, Bd, method, cfg, out=C, workspace=ws, stream=stream)
         torch.cuda.synchronize()
-        ms = []
-        for _ in range(args.precision_reps):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
+        evs = []
+        mmm.timer_start()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            e0, e1 = _events(torch)
             e0.record(stream)
             mmm.multiply(Ad, Bd, method, cfg, out=C, workspace=ws, stream=stream)
             e1.record(stream)
-            torch.cuda.synchronize()
-            ms.append(e0.elapsed_time(e1))
-        med = float(np.median(ms))
-        ent = {"ms_p50": med, "ms_min": float(np.min(ms)), "tflops_fp64_grade": 2.0 * n ** 3 / (med / 1e3) / 1e12}
-        if name == "dgemm":
+            evs.append((e0, e1))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kern_ms, launches = mmm.timer_stop()
+        ms = [a.elapsed_time(b) for a, b in evs]
+        mean = float(np.mean(ms))
+        err = _rel_err(oracle, C[ridx].cpu().numpy(), ref, nrm)
+        ent = {"ms_mean": mean, "ms_p50": _pct(ms, 50), "ms_p99": _pct(ms, 99), "ms_min": float(np.min(ms)),
+               "wall_s": wall, "tflops_fp64_grade": flop / (mean / 1e3) / 1e12,
+               "dominant_kernel_ms_mean": kern_ms / max(launches, 1), "dominant_kernel_launches": launches,
+               "rel_err_inf_sampled_rows": err, "fp64_grade": err <= FP64_GRADE}
+        if method == "dgemm":
             ent["frac_fp64_mfma_peak"] = ent["tflops_fp64_grade"] / PEAK_FP64_MFMA_TFLOPS
-        elif method == "strassen_winograd":
-            L = kw["strassen_levels"]
-            ent["leaf_flop_share"] = (7.0 / 8.0) ** L  # of 2NPM, on the FP64 matrix cores
-        else:
+        elif method == "split":
             s = kw["split_slices"]
             pairs = s * (s + 1) // 2
             peak = PEAK_INT8_MFMA_TOPS if kw["split_type"] == "int8" else PEAK_BF16_MFMA_TFLOPS
-            ent["lowprec_ops_per_s_T"] = pairs * 2.0 * n ** 3 / (med / 1e3) / 1e12
-            ent["frac_lowprec_mfma_peak"] = ent["lowprec_ops_per_s_T"] / peak
-        if ref is not None:
-            import oracle
-
-            got = C[ridx].cpu().numpy()
-            ent["rel_err_inf_sampled"] = oracle.norm_inf(oracle.minus(got, ref)) / nrm
-        out[name] = ent
+            ent["digit_pairs"] = pairs
+            ent["digit_gemm_T_ops_per_s"] = pairs * flop / (ent["dominant_kernel_ms_mean"] / 1e3) / 1e12
+            ent["digit_gemm_frac_peak"] = ent["digit_gemm_T_ops_per_s"] / peak
+        elif method == "strassen_winograd":
+            ent["leaf_flop_share"] = (7.0 / 8.0) ** kw["strassen_levels"]
+        runs[name] = ent
         del ws
-    # ceilings measured with the vendor library on the same box (context for
-    # the peaks, never part of the path): FP64 and BF16 GEMMs of this size
+
+    out = {"workload": "C = AB, N = P = M = 8192, entries +-2^u (u ~ U[-20,20]) with rows scaled by 2^v "
+                       "(v ~ U{-10..10}), seeds 2001/2002; one product per step, operands resident in HBM",
+           "rows_checked": int(len(rows)),
+           "error_note": "relative infinity-norm error on the sampled rows (including the two rows of A with "
+                         "the largest row sums): a lower bound of the error over all rows",
+           "configs": runs}
+    # vendor-library ceilings measured on the same box (context for the peaks, never part of the path)
     ceil = {}
-    for name, X, Y, peak in (("vendor_fp64_gemm", Ad, Bd, PEAK_FP64_MFMA_TFLOPS),
-                             ("vendor_bf16_gemm", Ad.to(torch.bfloat16).contiguous(),
-                              Bd.to(torch.bfloat16).contiguous(), PEAK_BF16_MFMA_TFLOPS)):
+    for cname, X, Y, peak in (("vendor_fp64_gemm", Ad, Bd, PEAK_FP64_MFMA_TFLOPS),
+                              ("vendor_bf16_gemm", Ad.to(torch.bfloat16).contiguous(),
+                               Bd.to(torch.bfloat16).contiguous(), PEAK_BF16_MFMA_TFLOPS)):
         Z = torch.empty((n, n), dtype=X.dtype, device=dev)
         with torch.cuda.stream(stream):
             torch.matmul(X, Y, out=Z)
-            ms = _time(torch, stream, lambda: torch.matmul(X, Y, out=Z), args.precision_reps)
-        tf = 2.0 * n ** 3 / (ms / 1e3) / 1e12
-        ceil[name] = {"ms_p50": ms, "tflops": tf, "frac_peak": tf / peak}
+            ms = _time(torch, stream, lambda: torch.matmul(X, Y, out=Z), 5)
+        tf = flop / (ms / 1e3) / 1e12
+        ceil[cname] = {"ms_p50": ms, "tflops": tf, "frac_peak": tf / peak}
         del Z
     out["library_ceilings"] = ceil
+    return out, cpu
+
+
+# ---------------------------------------------------------------------------------------------------
+# 256^3 latency (the small configuration) and the single-core oracle time
+
+def latency_section(mmm, torch, synth, dev, stream):
+    import oracle
+
+    n = 256
+    out = {"workload": "N = P = M = 256, U[-1,1] (seeds 1/2) and integers in {-8..8} (bitwise check)"}
+    A = synth.uniform((n, n), synth.seed_a(0))
+    B = synth.uniform((n, n), synth.seed_b(0))
+    Ai = synth.integers((n, n), synth.seed_a(0))
+    Bi = synth.integers((n, n), synth.seed_b(0))
+    exact = (Ai.astype(np.int64) @ Bi.astype(np.int64)).astype(np.float64)
+    Ad, Bd = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+    Aid, Bid = torch.from_numpy(Ai).to(dev), torch.from_numpy(Bi).to(dev)
+    C = torch.empty((n, n), dtype=torch.float64, device=dev)
+    oracle.set_threads(1)
+    t = time.perf_counter()
+    ref = oracle.naive(A, B)
+    out["oracle_single_core_ms"] = 1e3 * (time.perf_counter() - t)
+    oracle.set_threads(_host_threads())
+    nrm = oracle.norm_inf(A) * oracle.norm_inf(B)
+    res = {}
+    for name, method, kw in LATENCY_METHODS:
+        cfg = mmm.Config(**kw)
+        ws = torch.empty(max(mmm.workspace_bytes(method, n, n, n, cfg), 1), dtype=torch.uint8, device=dev)
+        run = lambda: mmm.multiply(Ad, Bd, method, cfg, out=C, workspace=ws, stream=stream)  # noqa: E731
+        run()
+        ms = []
+        for _ in range(20):
+            e0, e1 = _events(torch)
+            e0.record(stream)
+            run()
+            e1.record(stream)
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        err = _rel_err(oracle, C.cpu().numpy(), ref, nrm)
+        mmm.multiply(Aid, Bid, method, cfg, out=C, workspace=ws, stream=stream)
+        ok = bool(np.array_equal(C.cpu().numpy().view(np.int64), exact.view(np.int64)))
+        res[name] = {"us_p50": 1e3 * _pct(ms, 50), "us_p99": 1e3 * _pct(ms, 99), "rel_err_inf": err,
+                     "integer_inputs_exact": ok}
+    out["methods"] = res
     return out
 
 
-def _time(torch, stream, fn, reps):
-    ms = []
-    for _ in range(reps):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        fn()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms.append(e0.elapsed_time(e1))
-    return float(np.median(ms))
+# ---------------------------------------------------------------------------------------------------
+# every method at N = M = 4096, P in {4096, 4097}
+
+def allmethods_section(args, mmm, torch, synth, dev, stream):
+    import oracle
+
+    n = args.size
+    shapes = [(n, n, n), (n, n + 1, n)]
+    data = {}
+    for (N, P, M) in shapes:
+        A = synth.uniform((N, P), synth.seed_a(1))
+        B = synth.uniform((P, M), synth.seed_b(1))
+        data[P] = (A, B, torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev),
+                   torch.empty((N, M), dtype=torch.float64, device=dev))
+    ws = {}
+    for name, method, kw, _, _ in METHODS:
+        cfg = mmm.Config(**kw)
+        for (N, P, M) in shapes:
+            ws[(name, P)] = torch.empty(max(mmm.workspace_bytes(method, N, P, M, cfg), 1), dtype=torch.uint8,
+                                        device=dev)
+
+    def one_step(timings):
+        for name, method, kw, _, _ in METHODS:
+            cfg = mmm.Config(**kw)
+            for (N, P, M) in shapes:
+                _, _, Ad, Bd, C = data[P]
+                e0, e1 = _events(torch)
+                e0.record(stream)
+                mmm.multiply(Ad, Bd, method, cfg, out=C, workspace=ws[(name, P)], stream=stream)
+                e1.record(stream)
+                if timings is not None:
+                    timings.append((name, P, e0, e1))
+
+    one_step(None)
+    torch.cuda.synchronize()
+    timings, steps = [], []
+    steps_n = max(1, min(args.steps, 3))
+    for _ in range(steps_n):
+        s0, s1 = _events(torch)
+        s0.record(stream)
+        one_step(timings)
+        s1.record(stream)
+        steps.append((s0, s1))
+    torch.cuda.synchronize()
+    step_ms = [a.elapsed_time(b) for a, b in steps]
+    per = {}
+    for name, P, e0, e1 in timings:
+        per.setdefault(name, []).append(e0.elapsed_time(e1))
+    # the dominant kernel of each single-kernel method, timed with the library's event brackets
+    kern = {}
+    for name, method, kw, cost, _ in METHODS:
+        if cost is None:
+            continue
+        cfg = mmm.Config(**kw)
+        mmm.timer_start()
+        for _ in range(steps_n):
+            for (N, P, M) in shapes:
+                _, _, Ad, Bd, C = data[P]
+                mmm.multiply(Ad, Bd, method, cfg, out=C, workspace=ws[(name, P)], stream=stream)
+        tot, cnt = mmm.timer_stop()
+        kern[name] = tot / max(cnt, 1)
+    # errors on sampled rows against the oracle
+    oracle.set_threads(_host_threads())
+    rows = np.linspace(0, n - 1, 64).round().astype(np.int64)
+    ridx = torch.from_numpy(rows).to(dev)
+    ref = {P: oracle.naive_rows(data[P][0], data[P][1], rows) for (_, P, _) in shapes}
+    nrm = {P: oracle.norm_inf(data[P][0]) * oracle.norm_inf(data[P][1]) for (_, P, _) in shapes}
+    res = {}
+    macs = np.mean([N * P * M for (N, P, M) in shapes])
+    for name, method, kw, cost, bound in METHODS:
+        cfg = mmm.Config(**kw)
+        worst = 0.0
+        for (N, P, M) in shapes:
+            _, _, Ad, Bd, C = data[P]
+            mmm.multiply(Ad, Bd, method, cfg, out=C, workspace=ws[(name, P)], stream=stream)
+            worst = max(worst, _rel_err(oracle, C[ridx].cpu().numpy(), ref[P], nrm[P]))
+        ms = np.array(per[name])
+        ent = {"ms_mean": float(ms.mean()), "ms_p50": _pct(ms, 50), "ms_p99": _pct(ms, 99),
+               "tflops_fp64_grade": 2.0 * macs / (ms.mean() / 1e3) / 1e12, "rel_err_inf_sampled_rows": worst}
+        if cost is not None:
+            km = kern[name]
+            peak = PEAK_FP64_MFMA_TFLOPS if bound == "mfma" else PEAK_FP64_VALU_OPS_T
+            ent["kernel_ms_mean"] = km
+            ent["kernel_T_ops_per_s"] = cost * macs / (km / 1e3) / 1e12
+            ent["kernel_frac_peak"] = ent["kernel_T_ops_per_s"] / peak
+            ent["bound"] = bound
+        res[name] = ent
+    flop_step = sum(2.0 * N * P * M for (N, P, M) in shapes) * len(METHODS)
+    dom = max((m for m in METHODS if m[3] is not None), key=lambda m: res[m[0]]["kernel_ms_mean"])
+    return {"workload": "C = AB, N = M = %d, P in {%d, %d}, U[-1,1] (seeds 1001/1002); one step = every method "
+                        "once on each shape" % (n, n, n + 1),
+            "step_ms_mean": float(np.mean(step_ms)), "steps": steps_n,
+            "tflops_fp64_grade_step": flop_step / (np.mean(step_ms) / 1e3) / 1e12,
+            "fp64_grade_all": all(r["rel_err_inf_sampled_rows"] <= FP64_GRADE for r in res.values()),
+            "dominant_kernel": {"kernel": dom[0], "bound": "alu" if dom[4] == "alu" else "mfma",
+                                "achieved": res[dom[0]]["kernel_T_ops_per_s"],
+                                "peak": PEAK_FP64_VALU_OPS_T if dom[4] == "alu" else PEAK_FP64_MFMA_TFLOPS,
+                                "unit": "TFLOP/s", "frac": res[dom[0]]["kernel_frac_peak"],
+                                "traffic": counted_traffic(dom[0])},
+            "methods": res}
 
 
-def paper_test_section():
-    """The paper's test program at n = 800, R = 10 (C = A (8A), N := NaivKahan):
-    per method the median time of one product and NormInf(N - C)."""
-    from paper_1106_1347_amd import papertest
-
-    res = papertest.run(n=800, repeats=10, seed=500)
-    return {"workload": "C = A (8A), A 800 x 800 ~ U[0,1) (seed 500), N := NaivKahan, R = 10",
-            "rows": {r["label"]: {"ms": 1e3 * r["seconds"], "norm_inf_n_minus_c": r["err"]} for r in res["rows"]}}
-
+# ---------------------------------------------------------------------------------------------------
 
 def aux_section(mmm, torch, dev, stream):
     """Plus, Minus, MultiplyWithScalar and NormInf on 8192 x 8192 operands
@@ -427,24 +452,57 @@ def aux_section(mmm, torch, dev, stream):
     return res
 
 
-def batch_section(mmm, torch, synth, dev, stream):
+def batch_section(mmm, torch, synth, dev, stream, split_type="bf16", split_slices=6, tuner_path=None):
     """2048 independent products, N, P, M uniform on 16..512, entries
-    U[-1,1]; even index FP64 DGEMM, odd index split (int8 digits, 7): one
-    graph launch against 2048 separate calls."""
+    U[-1,1]; even index FP64 DGEMM, odd index split: one graph launch
+    (DGEMM tile shapes from the autotuner) against 2048 separate calls, then
+    every result against the CPU oracle."""
+    import oracle
+    from paper_1106_1347_amd.tune import TileTuner
+
     shapes = synth.batch_shapes(2048, synth.seed_a(3), 16, 512)
-    probs = []
+    probs, host = [], []
     for g, (N, P, M) in enumerate(shapes):
-        gen = torch.Generator(device=dev).manual_seed(3010 + g)
-        A = torch.rand((N, P), generator=gen, dtype=torch.float64, device=dev) * 2 - 1
-        B = torch.rand((P, M), generator=gen, dtype=torch.float64, device=dev) * 2 - 1
-        probs.append((A, B, torch.empty((N, M), dtype=torch.float64, device=dev), "dgemm" if g % 2 == 0 else "split"))
-    cfg = mmm.Config(split_type="int8", split_slices=7)
+        A = synth.uniform((N, P), synth.seed_item(3, g, "A"))
+        B = synth.uniform((P, M), synth.seed_item(3, g, "B"))
+        host.append((A, B))
+        probs.append((torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev),
+                      torch.empty((N, M), dtype=torch.float64, device=dev), "dgemm" if g % 2 == 0 else "split"))
+    cfg = mmm.Config(split_type=split_type, split_slices=split_slices)
     t0 = time.perf_counter()
-    plan = mmm.Batch(probs, cfg, stream=stream)
+    if tuner_path is None:
+        import tempfile
+
+        # a fresh table for this run (tuned, persisted, then read back by the plan)
+        tuner_path = os.path.join(tempfile.mkdtemp(prefix="mmm_tiles_"), "tiles.json")
+    tuner = TileTuner(path=tuner_path)
+    tuner.tune([s for g, s in enumerate(shapes) if g % 2 == 0], split=[s for g, s in enumerate(shapes) if g % 2 == 1],
+               split_config=cfg)
+    tune_s = time.perf_counter() - t0
+    plan_probs = [(A, B, C, m, 0, tuner.tile_for(A.shape[0], A.shape[1], B.shape[1], m, cfg))
+                  for (A, B, C, m) in probs]
+    t0 = time.perf_counter()
+    plan = mmm.Batch(plan_probs, cfg, stream=stream)
     create_s = time.perf_counter() - t0
     plan.launch(stream)
     torch.cuda.synchronize()
-    ms_graph = _time(torch, stream, lambda: plan.launch(stream), 5)
+    ms_graph = []
+    for _ in range(10):
+        e0, e1 = _events(torch)
+        e0.record(stream)
+        plan.launch(stream)
+        e1.record(stream)
+        e1.synchronize()
+        ms_graph.append(e0.elapsed_time(e1))
+    plan_auto = mmm.Batch(probs, cfg, stream=stream)
+    plan_auto.launch(stream)
+    ms_auto = _time(torch, stream, lambda: plan_auto.launch(stream), 5)
+    plan_auto.close()
+    plan.launch(stream)  # the results checked below come from the tuned graph
+
+    torch.cuda.synchronize()
+    outs = [C.cpu().numpy() for (_, _, C, _) in probs]
+
     def separate():
         for (A, B, C, m) in probs:
             mmm.multiply(A, B, m, cfg, out=C, stream=stream)
@@ -452,18 +510,35 @@ def batch_section(mmm, torch, synth, dev, stream):
     separate()
     ms_sep = _time(torch, stream, separate, 3)
     plan.close()
+    # every result against the oracle (the naive definition, full products)
+    oracle.set_threads(_host_threads())
+    t0 = time.perf_counter()
+    worst = {"dgemm": 0.0, "split": 0.0}
+    for g, ((A, B), C) in enumerate(zip(host, outs)):
+        e = _rel_err(oracle, C, oracle.naive(A, B), oracle.norm_inf(A) * oracle.norm_inf(B))
+        k = "dgemm" if g % 2 == 0 else "split"
+        worst[k] = max(worst[k], e)
+    check_s = time.perf_counter() - t0
     flop = sum(2.0 * N * P * M for (N, P, M) in shapes)
-    return {"workload": "2048 products, N,P,M ~ U{16..512}, half DGEMM, half split int8 x7, one HIP graph",
-            "plan_create_s": create_s, "ms_graph_p50": ms_graph, "ms_separate_calls_p50": ms_sep,
-            "tflops_fp64_grade_graph": flop / (ms_graph / 1e3) / 1e12, "speedup_vs_separate": ms_sep / ms_graph,
-            "flop": flop}
+    med = float(np.median(ms_graph))
+    return {"workload": "2048 products, N,P,M ~ U{16..512}, U[-1,1] (item seeds 3010+2g / 3011+2g), even index "
+                        "DGEMM, odd index split %s x%d, one HIP graph" % (split_type, split_slices),
+            "tune_s": tune_s, "plan_create_s": create_s, "ms_graph_p50": med, "ms_graph_p99": _pct(ms_graph, 99),
+            "ms_graph_untuned_p50": ms_auto, "ms_separate_calls_p50": ms_sep,
+            "tflops_fp64_grade_graph": flop / (med / 1e3) / 1e12, "speedup_vs_separate": ms_sep / med,
+            "flop": flop, "rel_err_inf_worst": worst, "all_within_1e-13": max(worst.values()) <= FP64_GRADE,
+            "oracle_check": "every product in full against the naive definition, %.1f s" % check_s,
+            "tiles": tuner.summary()}
 
 
 def serve_section(args, mmm, torch, synth, dev):
     """Poisson request stream, dims log-uniform on 32..4096 (half square),
-    tolerance 1e-13 or 1e-10: capacity measured closed-loop, then p50/p99
-    latency (arrival to completion event) at 50% and 80% of it."""
-    from paper_1106_1347_amd.serve import Server
+    tolerance 1e-13 or 1e-10, methods routed by measured cost: capacity
+    measured closed-loop, then p50/p99 latency (arrival to completion event)
+    at 50% and 80% of it; afterwards every result of the 80% run against the
+    CPU oracle on sampled rows."""
+    import oracle
+    from paper_1106_1347_amd.serve import Router, Server
 
     n = args.serve_requests
     reqs = synth.serving_requests(n, synth.seed_a(4), rate_per_s=1.0)
@@ -475,23 +550,30 @@ def serve_section(args, mmm, torch, synth, dev):
         B = torch.rand((P, M), generator=gen, dtype=torch.float64, device=dev) * 2 - 1
         data.append((A, B, r["tol"]))
     torch.cuda.synchronize()
-    budget = 64 << 30
+    budget = int(args.serve_budget_gib * (1 << 30))
+    t0 = time.perf_counter()
+    router = Router()
+    router.calibrate()
+    cal_s = time.perf_counter() - t0
     # warm-up and closed-loop capacity
-    srv = Server(budget, streams=4)
+    srv = Server(budget, streams=4, router=router)
     for f in [srv.submit(A, B, tol) for (A, B, tol) in data[: min(40, n)]]:
         f.result()
     srv.close()
-    srv = Server(budget, streams=4)
+    srv = Server(budget, streams=4, router=router)
     for f in [srv.submit(A, B, tol) for (A, B, tol) in data]:
         f.result()
     cap = srv.stats()
     srv.close()
-    out = {"workload": "%d requests, dims log-uniform 32..4096 (half square), tol 1e-13 | 1e-10, HBM budget 64 GiB, "
-                       "4 streams" % n, "capacity_req_per_s": cap["req_per_s"], "closed_loop": cap}
+    out = {"workload": "%d requests, dims log-uniform 32..4096 (half square), U[-1,1], tol 1e-13 | 1e-10, HBM "
+                       "budget %.0f GiB, 4 streams, methods routed by measured cost" % (n, args.serve_budget_gib),
+           "router_calibration_s": cal_s, "router_ms": router.table, "router_sizes": router.sizes,
+           "capacity_req_per_s": cap["req_per_s"], "closed_loop": cap}
+    results = None
     for frac in (0.5, 0.8):
         rate = frac * cap["req_per_s"]
         arrivals = np.cumsum(np.random.default_rng(4004).exponential(1.0 / rate, size=n))
-        srv = Server(budget, streams=4)
+        srv = Server(budget, streams=4, router=router)
         t0 = time.perf_counter()
         futs = []
         for (A, B, tol), ta in zip(data, arrivals):
@@ -499,24 +581,136 @@ def serve_section(args, mmm, torch, synth, dev):
             if dt > 0:
                 time.sleep(dt)
             futs.append(srv.submit(A, B, tol))
-        for f in futs:
-            f.result()
+        results = [f.result() for f in futs]
         st = srv.stats()
         srv.close()
         st["offered_req_per_s"] = rate
         out["load_%d" % int(frac * 100)] = st
+    # every result of the last run against the oracle: 4 rows each (the row of
+    # A with the largest absolute row sum among them)
+    oracle.set_threads(_host_threads())
+    t0 = time.perf_counter()
+    worst = {1e-13: 0.0, 1e-10: 0.0}
+    fails = 0
+    rng = np.random.default_rng(4005)
+    for (A, B, tol), C in zip(data, results):
+        An, Bn = A.cpu().numpy(), B.cpu().numpy()
+        N = An.shape[0]
+        rows = np.unique(np.concatenate([rng.choice(N, size=min(3, N), replace=False),
+                                         [int(np.argmax(np.abs(An).sum(axis=1)))]])).astype(np.int64)
+        ridx = torch.from_numpy(rows).to(dev)
+        e = _rel_err(oracle, C[ridx].cpu().numpy(), oracle.naive_rows(An, Bn, rows),
+                     oracle.norm_inf(An) * oracle.norm_inf(Bn))
+        worst[tol] = max(worst[tol], e)
+        fails += e > tol
+    out["oracle_check"] = {"requests": n, "rows_per_request": "up to 4 (incl. the largest row sum of A)",
+                           "worst_rel_err_tol_1e-13": worst[1e-13], "worst_rel_err_tol_1e-10": worst[1e-10],
+                           "over_tolerance": int(fails), "seconds": time.perf_counter() - t0}
     return out
 
 
-def _cpu_model():
-    try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
-    except OSError:
-        pass
-    return "unknown"
+def paper_test_section():
+    """The paper's test program at n = 800, R = 10 (C = A (8A), N := NaivKahan):
+    per method the median time of one product and NormInf(N - C)."""
+    from paper_1106_1347_amd import papertest
+
+    res = papertest.run(n=800, repeats=10, seed=500)
+    return {"workload": "C = A (8A), A 800 x 800 ~ U[0,1) (seed 500), N := NaivKahan, R = 10",
+            "rows": {r["label"]: {"ms": 1e3 * r["seconds"], "norm_inf_n_minus_c": r["err"]} for r in res["rows"]}}
+
+
+# ---------------------------------------------------------------------------------------------------
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: there is no multi-GPU path (the products of the workload "
+              "are independent per GPU; see the design notes on sharding). Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1106_1347_amd as mmm
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    only = set(args.only.split(",")) if args.only else set(SECTIONS)
+    bad = only - set(SECTIONS)
+    if bad:
+        print("unknown sections %s; choose from %s" % (sorted(bad), SECTIONS), file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    if args.copy_mib:
+        src = torch.ones(args.copy_mib * (1 << 20) // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    def log(msg):
+        print("[bench] %s" % msg, file=sys.stderr, flush=True)
+
+    head, cpu = (None, None)
+    if "headline" in only:
+        log("headline 8192^3")
+        head, cpu = headline_section(args, mmm, torch, synth, dev, stream)
+    extra = {}
+    for key, sec, fn in (("latency_256", "latency", lambda: latency_section(mmm, torch, synth, dev, stream)),
+                         ("allmethods_4096", "allmethods",
+                          lambda: allmethods_section(args, mmm, torch, synth, dev, stream)),
+                         ("aux_8192", "aux", lambda: aux_section(mmm, torch, dev, stream)),
+                         ("batch_2048", "batch", lambda: batch_section(mmm, torch, synth, dev, stream)),
+                         ("serving", "serve", lambda: serve_section(args, mmm, torch, synth, dev)),
+                         ("paper_test_800", "paper", paper_test_section)):
+        if sec in only:
+            log(sec)
+            extra[key] = fn()
+            torch.cuda.empty_cache()
+
+    out = {"metric": METRIC, "value": None, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": None, "data": "synthetic",
+           "config": {"workload": "C = AB, N = P = M = 8192, FP64 wide-range entries (+-2^u, u ~ U[-20,20], rows "
+                                  "x 2^v, v ~ U{-10..10}); split-precision product vs the plain FP64 matrix-core "
+                                  "GEMM; one product per step", "parallelism": "single GPU"}}
+    if head is not None:
+        cf = head["configs"]
+        splits = [k for k in cf if k.startswith("split") and cf[k]["fp64_grade"]]
+        best = max(splits, key=lambda k: cf[k]["tflops_fp64_grade"]) if splits else None
+        dg = cf.get("dgemm")
+        if best is not None:
+            b = cf[best]
+            kw = [h for h in HEADLINE if h[0] == best][0][2]
+            peak = PEAK_INT8_MFMA_TOPS if kw["split_type"] == "int8" else PEAK_BF16_MFMA_TFLOPS
+            out.update({"value": b["tflops_fp64_grade"], "ms_per_step": b["ms_mean"],
+                        "dtype": {"int8": "i8 digits, i32 accumulation, f64 recombination",
+                                  "bf16": "bf16 digits, f32 accumulation, f64 recombination",
+                                  "fp16": "f16 digits, f32 accumulation, f64 recombination"}[kw["split_type"]],
+                        "p50_ms": b["ms_p50"], "p99_ms": b["ms_p99"],
+                        "rel_err_inf": b["rel_err_inf_sampled_rows"],
+                        "best_split": best})
+            out["config"].update({"split": best, "digits": kw["split_slices"], "digit_type": kw["split_type"]})
+            out["roofline"] = {"bound": "mfma", "kernel": "digit GEMM of %s" % best,
+                               "achieved": b["digit_gemm_T_ops_per_s"], "peak": peak, "unit": "TFLOP/s",
+                               "frac": b["digit_gemm_frac_peak"], "traffic": counted_traffic(best),
+                               "note": "achieved = %d digit pairs x 2NPM / mean launch time of the digit GEMM "
+                                       "kernel (HIP events on its stream, %d launches); peak = the published "
+                                       "dense %s matrix-core rate (int8: operations)"
+                                       % (b["digit_pairs"], b["dominant_kernel_launches"], kw["split_type"])}
+        if dg is not None:
+            out["dgemm_tflops"] = dg["tflops_fp64_grade"]
+            out["dgemm_ms"] = dg["ms_mean"]
+            out["dgemm_rel_err_inf"] = dg["rel_err_inf_sampled_rows"]
+            if out["value"] is not None:
+                out["vs_dgemm"] = out["value"] / dg["tflops_fp64_grade"]
+        out["precision_8192"] = head
+    out["cpu_baseline"] = cpu
+    if "serving" in extra:
+        out["serving_p50_ms"] = extra["serving"]["load_80"]["p50_ms"]
+        out["serving_p99_ms"] = extra["serving"]["load_80"]["p99_ms"]
+    out.update(extra)
+    out["device"] = torch.cuda.get_device_name(0)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -152,7 +152,8 @@ typedef struct {
     int64_t N, P, M;
     int32_t method;  /* MMM_DGEMM or MMM_SPLIT */
     int32_t slices;  /* split digits (MMM_SPLIT), 0 = the config's default */
-    int32_t tile;    /* DGEMM tile shape: 0 = library's choice, 1 = 128x128, 2 = 64x64, 3 = 128x64 */
+    int32_t tile;    /* tile shape: 0 = library's choice; DGEMM 1 = 128x128, 2 = 64x64, 3 = 128x64;
+                        SPLIT 1 = the wide tile, 2 = the narrow tile (half its rows) */
     int32_t reserved;/* must be zero */
 } mmm_problem;
 
@@ -177,6 +178,17 @@ mmm_status mmm_batch_launch(mmm_batch* plan, void* stream);
 mmm_status mmm_batch_destroy(mmm_batch* plan);
 
 /* ---- Diagnostics ------------------------------------------------------ */
+
+/* Kernel timer, per calling thread.  After mmm_timer_start, every
+ * mmm_multiply on this thread records a pair of HIP events on its stream
+ * immediately before and after the launch of its dominant kernel (the
+ * product kernel of NAIVE ... DOT2 and DGEMM, WinogradOriginal's main loop,
+ * the Strassen leaf launch, the split product's digit GEMM); no other work
+ * is added to the stream.  mmm_timer_stop ends the recording, waits for the
+ * recorded events and returns the summed elapsed time in milliseconds and
+ * the number of bracketed launches.  Not for use under graph capture. */
+mmm_status mmm_timer_start(void);
+mmm_status mmm_timer_stop(double* total_ms, int64_t* launches);
 
 const char* mmm_status_string(mmm_status s);
 const char* mmm_last_error(void);

@@ -22,6 +22,8 @@ from ._lib import (  # noqa: F401
     multiply_with_scalar,
     norm_inf,
     plus,
+    timer_start,
+    timer_stop,
     version,
     winograd_lambda,
     workspace_bytes,

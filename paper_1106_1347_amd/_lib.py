@@ -66,6 +66,8 @@ _sigs = {
                                         ctypes.POINTER(_vp)]),
     "mmm_batch_launch": (ctypes.c_int, [_vp, _vp]),
     "mmm_batch_destroy": (ctypes.c_int, [_vp]),
+    "mmm_timer_start": (ctypes.c_int, []),
+    "mmm_timer_stop": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]),
     "mmm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "mmm_last_error": (ctypes.c_char_p, []),
     "mmm_version": (_i32, []),
@@ -212,6 +214,19 @@ def winograd_lambda(normA: torch.Tensor, normB: torch.Tensor, stream=None):
     _check(_lib.mmm_winograd_lambda(normA.data_ptr(), normB.data_ptr(), out.data_ptr(), _stream(stream)),
            "mmm_winograd_lambda")
     return out
+
+
+def timer_start() -> None:
+    """Start bracketing each call's dominant kernel with HIP events (this thread)."""
+    _check(_lib.mmm_timer_start(), "mmm_timer_start")
+
+
+def timer_stop():
+    """Stop the kernel timer: (summed milliseconds, number of bracketed launches)."""
+    ms = ctypes.c_double()
+    n = _i64()
+    _check(_lib.mmm_timer_stop(ctypes.byref(ms), ctypes.byref(n)), "mmm_timer_stop")
+    return float(ms.value), int(n.value)
 
 
 TILES = {"auto": 0, "128x128": 1, "64x64": 2, "128x64": 3}

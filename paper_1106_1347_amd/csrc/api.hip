@@ -12,9 +12,49 @@
 
 using namespace mmm;
 
+#include <vector>
+
 namespace {
 thread_local char g_err[512] = "";
+
+// Event pairs of the kernel timer: `used` in recording order, `spare` kept
+// for reuse after a stop.
+struct KernelTimer {
+    bool on = false;
+    bool failed = false;
+    std::vector<hipEvent_t> used, spare;
+    ~KernelTimer()
+    {
+        for (hipEvent_t e : used) (void)hipEventDestroy(e);
+        for (hipEvent_t e : spare) (void)hipEventDestroy(e);
+    }
+    void record(hipStream_t s)
+    {
+        hipEvent_t e = nullptr;
+        if (!spare.empty()) {
+            e = spare.back();
+            spare.pop_back();
+        } else if (hipEventCreate(&e) != hipSuccess) {
+            failed = true;
+            return;
+        }
+        if (hipEventRecord(e, s) != hipSuccess) failed = true;
+        used.push_back(e);
+    }
+};
+thread_local KernelTimer g_timer;
+}  // namespace
+
+namespace mmm {
+void timer_begin(hipStream_t s)
+{
+    if (g_timer.on) g_timer.record(s);
 }
+void timer_end(hipStream_t s)
+{
+    if (g_timer.on) g_timer.record(s);
+}
+}  // namespace mmm
 
 namespace mmm {
 
@@ -150,7 +190,14 @@ bool plan_strassen(i64 N, i64 P, i64 M, const mmm_config& c, StrassenPlan& pl)
         pl.off_B = take((double)pl.Pp * pl.Mp);
         pl.off_C = take((double)pl.Np * pl.Mp);
     }
+    // the deepest two levels run fused (run_strassen): level depth - 1's
+    // sums and products live only in registers and get no buffers
+    const int fused = pl.depth >= 2 ? pl.depth - 1 : 0;
     for (int d = 1; d <= pl.depth; ++d) {
+        if (d == fused) {
+            pl.off_WA[d] = pl.off_WB[d] = pl.off_H[d] = 0;
+            continue;
+        }
         const double nodes = (double)pow7(d);
         pl.off_WA[d] = take(nodes * pl.n[d] * pl.p[d]);
         pl.off_WB[d] = take(nodes * pl.p[d] * pl.m[d]);
@@ -195,7 +242,7 @@ mmm_status run_strassen(int variant, const double* A, const double* B, double* C
         T.n[d] = pl.n[d];
         T.p[d] = pl.p[d];
         T.m[d] = pl.m[d];
-        if (d > 0) {
+        if (d > 0 && d != T.fused) {
             T.WA[d] = (double*)(ws + pl.off_WA[d]);
             T.WB[d] = (double*)(ws + pl.off_WB[d]);
             T.H[d] = (double*)(ws + pl.off_H[d]);
@@ -211,7 +258,9 @@ mmm_status run_strassen(int variant, const double* A, const double* B, double* C
         }
     }
     StrassenLeafSrc leaves{T, pow7(pl.depth)};
+    timer_begin(s);
     e = pl.naive_leaf ? launch_naive_strassen_leaves(leaves, s) : launch_dgemm_strassen_leaves(leaves, s);
+    timer_end(s);
     if (e != hipSuccess) return from_hip(e, "strassen leaves");
     for (int d = pl.depth; d >= 1; --d) {
         if (T.fused && d == T.fused + 1) {
@@ -286,7 +335,26 @@ mmm_status run_winograd(const double* A, const double* B, const Gemm& g, bool sc
     }
     // y_i over the rows of (scaled) A, z_k over the columns of (scaled) B
     if ((e = launch_winograd_yz(gs.A, gs.lda, N, P, y, gs.B, gs.ldb, M, z, s)) != hipSuccess) return from_hip(e, "y, z");
-    return from_hip(launch_winograd_main(gs, y, z, s), "winograd");
+    timer_begin(s);
+    e = launch_winograd_main(gs, y, z, s);
+    timer_end(s);
+    return from_hip(e, "winograd");
+}
+
+// The single-kernel methods bracket their one product kernel.
+void timer_begin_if(mmm_method m, hipStream_t s)
+{
+    switch (m) {
+    case MMM_NAIVE:
+    case MMM_KAHAN:
+    case MMM_NAIVE_ON_ARRAY:
+    case MMM_NAIVE_UNROLL2:
+    case MMM_NAIVE_UNROLL3:
+    case MMM_NAIVE_UNROLL4:
+    case MMM_DOT2:
+    case MMM_DGEMM: timer_begin(s); break;
+    default: break;
+    }
 }
 
 // Bytes of WinogradScaled's scaled operands beyond the padded copies.
@@ -439,21 +507,28 @@ mmm_status mmm_multiply(const double* A, const double* B, double* C, int64_t N, 
     hipError_t pe = apply_pad(plan, g, ws + pad_at, s);
     if (pe != hipSuccess) return from_hip(pe, "pad operands");
     char* sws = ws ? ws + pad_at + pad_bytes(plan, N, M) : nullptr;
+    // the single-kernel methods: the product kernel is the dominant one
+    hipError_t ke = hipSuccess;
+    const char* kname = nullptr;
+    timer_begin_if(method, s);
     switch (method) {
-    case MMM_NAIVE:
-        return from_hip(launch_naive(g, c.naive_fma != 0, s), "naive");
-    case MMM_KAHAN:
-        return from_hip(launch_kahan(g, s), "kahan");
-    case MMM_NAIVE_ON_ARRAY:
-        return from_hip(launch_naive_variant(g, 0, s), "naive on array");
+    case MMM_NAIVE: ke = launch_naive(g, c.naive_fma != 0, s), kname = "naive"; break;
+    case MMM_KAHAN: ke = launch_kahan(g, s), kname = "kahan"; break;
+    case MMM_NAIVE_ON_ARRAY: ke = launch_naive_variant(g, 0, s), kname = "naive on array"; break;
     case MMM_NAIVE_UNROLL2:
     case MMM_NAIVE_UNROLL3:
     case MMM_NAIVE_UNROLL4:
-        return from_hip(launch_naive_variant(g, 2 + (int)(method - MMM_NAIVE_UNROLL2), s), "naive unrolled");
-    case MMM_DOT2:
-        return from_hip(launch_naive_variant(g, 5, s), "dot2");
-    case MMM_DGEMM:
-        return from_hip(launch_dgemm(g, s), "dgemm");
+        ke = launch_naive_variant(g, 2 + (int)(method - MMM_NAIVE_UNROLL2), s), kname = "naive unrolled";
+        break;
+    case MMM_DOT2: ke = launch_naive_variant(g, 5, s), kname = "dot2"; break;
+    case MMM_DGEMM: ke = launch_dgemm(g, s), kname = "dgemm"; break;
+    default: break;
+    }
+    if (kname) {
+        timer_end(s);
+        return from_hip(ke, kname);
+    }
+    switch (method) {
     case MMM_WINOGRAD:
         return run_winograd(A, B, g, false, ws, sws, s);
     case MMM_WINOGRAD_SCALED:
@@ -514,6 +589,34 @@ mmm_status mmm_winograd_lambda(const double* normA, const double* normB, int32_t
 {
     if (!normA || !normB || !lambda_out) return fail(MMM_EINVAL, "null pointer");
     return from_hip(launch_lambda(normA, normB, (int*)lambda_out, (hipStream_t)stream), "lambda");
+}
+
+mmm_status mmm_timer_start(void)
+{
+    for (hipEvent_t e : g_timer.used) g_timer.spare.push_back(e);
+    g_timer.used.clear();
+    g_timer.failed = false;
+    g_timer.on = true;
+    return MMM_OK;
+}
+
+mmm_status mmm_timer_stop(double* total_ms, int64_t* launches)
+{
+    if (!total_ms || !launches) return fail(MMM_EINVAL, "null pointer");
+    g_timer.on = false;
+    *total_ms = 0.0;
+    *launches = 0;
+    if (g_timer.failed) return fail(MMM_ELAUNCH, "timer: an event could not be created or recorded");
+    const size_t n = g_timer.used.size() / 2 * 2;
+    for (size_t i = 0; i < n; i += 2) {
+        hipError_t e = hipEventSynchronize(g_timer.used[i + 1]);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, g_timer.used[i], g_timer.used[i + 1]);
+        if (e != hipSuccess) return from_hip(e, "timer");
+        *total_ms += ms;
+        ++*launches;
+    }
+    return MMM_OK;
 }
 
 const char* mmm_status_string(mmm_status s)

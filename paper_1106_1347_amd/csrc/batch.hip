@@ -118,7 +118,8 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
         if (p.method != MMM_DGEMM && p.method != MMM_SPLIT)
             return bfail(MMM_EINVAL, "problem %d: batches take MMM_DGEMM or MMM_SPLIT", i);
         if (p.slices < 0 || p.slices > kMaxSlices) return bfail(MMM_EINVAL, "problem %d: slices outside 0..8", i);
-        if (p.tile < 0 || p.tile > 3 || p.reserved != 0) return bfail(MMM_EINVAL, "problem %d: bad tile", i);
+        if (p.tile < 0 || p.tile > (p.method == MMM_SPLIT ? 2 : 3) || p.reserved != 0)
+            return bfail(MMM_EINVAL, "problem %d: bad tile", i);
         if (p.N > 0 && p.M > 0 && !p.C) return bfail(MMM_EINVAL, "problem %d: C is null", i);
         if (p.N > 0 && p.M > 0 && p.P > 0 && (!p.A || !p.B)) return bfail(MMM_EINVAL, "problem %d: A or B is null", i);
         if (p.N > 0 && p.M > 0) iv.push_back({(uintptr_t)p.C, (uintptr_t)p.C + 8 * (size_t)(p.N * p.M), true, i});
@@ -140,7 +141,7 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
 
     // grouping
     std::map<int, DGroup> dg;
-    std::map<std::tuple<int, int, bool>, SGroup> sg;
+    std::map<std::tuple<int, int, bool, int>, SGroup> sg;
     size_t split_ws = 0;
     for (int i = 0; i < count; ++i) {
         const mmm_problem& p = problems[i];
@@ -154,9 +155,10 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
             const int s = p.slices ? p.slices : c.split_slices;
             SplitGroup grp;
             i64 Np, Mp, Kp;
-            const size_t bytes = split_job_bytes(p.N, p.P, p.M, c.split_type, s, grp, Np, Mp, Kp);
+            const int variant = p.tile == SPLIT_TILE_NARROW ? 1 : 0;
+            const size_t bytes = split_job_bytes(p.N, p.P, p.M, c.split_type, s, variant, grp, Np, Mp, Kp);
             if (bytes == (size_t)-1) return bfail(MMM_EUNSUPPORTED, "problem %d: split configuration", i);
-            SGroup& g = sg[std::make_tuple(grp.dt, grp.s, grp.flush)];
+            SGroup& g = sg[std::make_tuple(grp.dt, grp.s, grp.flush, grp.variant)];
             g.g = grp;
             SplitJob j;
             memset(&j, 0, sizeof(j));
@@ -228,7 +230,9 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
         g.off_bblocks = take(sizeof(JobBlock) * g.bblocks.size());
         std::vector<i64> cost;  // K blocks of 64 plus the fixed cost of a tile
         for (size_t k = 0; k < g.jobs.size(); ++k) {
-            const i64 nt = (g.jobs[k].Np / g.g.bm) * (g.jobs[k].Mp / g.g.bn);
+            // row tiles over N only: the padded rows of the digit layout
+            // beyond them are zeros that no tile needs
+            const i64 nt = cdiv(g.jobs[k].N, g.g.bm) * (g.jobs[k].Mp / g.g.bn);
             g.prefix[k + 1] = g.prefix[k] + nt;
             cost.insert(cost.end(), (size_t)nt, g.jobs[k].Kp / 64 + 2);
         }

@@ -157,4 +157,10 @@ mmm_status set_error(mmm_status st, const char* fmt, ...);
 // MMM_OK when every field of the config is valid (message set otherwise).
 mmm_status check_config(const mmm_config& c);
 
+// Kernel timer (mmm_timer_start / mmm_timer_stop): while it is on for the
+// calling thread, the launch of each call's dominant kernel is bracketed by
+// a pair of HIP events recorded on the stream it runs on.
+void timer_begin(hipStream_t s);
+void timer_end(hipStream_t s);
+
 }  // namespace mmm

@@ -106,10 +106,18 @@ __host__ __device__ constexpr TileCfg tile_cfg(int dt, int s, bool flush)
 // flushing, one wave per SIMD where the flushing tile is at the two-wave
 // limit.  Its tiles divide the single-product ones, so one workspace
 // layout serves both.
-__host__ __device__ constexpr TileCfg grouped_tile_cfg(int dt, int s, bool flush)
+// Variant 1 ("narrow") halves the tile's rows for products whose row count
+// would leave most of a wide tile empty; the halved accumulator set lets a
+// one-wave-per-SIMD tile run two waves per SIMD.
+__host__ __device__ constexpr TileCfg narrow_cfg(TileCfg t)
 {
-    return !flush ? (s <= 7 ? TileCfg{4, 2, 4, 2} : TileCfg{2, 2, 4, 2})
-                  : (s >= 4 ? TileCfg{2, 1, 4, 2} : tile_cfg(dt, s, flush));
+    return t.wbm > 1 ? TileCfg{t.wbm / 2, t.minw < 2 ? 2 : t.minw, t.nw, t.stages} : t;
+}
+__host__ __device__ constexpr TileCfg grouped_tile_cfg(int dt, int s, bool flush, int variant = 0)
+{
+    return variant == 1 ? narrow_cfg(grouped_tile_cfg(dt, s, flush, 0))
+                        : (!flush ? (s <= 7 ? TileCfg{4, 2, 4, 2} : TileCfg{2, 2, 4, 2})
+                                  : (s >= 4 ? TileCfg{2, 1, 4, 2} : tile_cfg(dt, s, flush)));
 }
 
 __host__ __device__ inline int beta_of(int dt) { return dt == DT_BF16 ? 8 : (dt == DT_FP16 ? 9 : 7); }
@@ -501,16 +509,17 @@ __global__ __launch_bounds__(tile_cfg(DT, S, FLUSH).threads(), tile_cfg(DT, S, F
                                                           flush_steps, lds);
 }
 
-// Persistent grid over the tiles of a group of split jobs (same digit type
-// and count): tile t is job p's (t - prefix[p])-th tile, row-major.
-template <int DT, int S, bool FLUSH>
-__global__ __launch_bounds__(grouped_tile_cfg(DT, S, FLUSH).threads(), grouped_tile_cfg(DT, S, FLUSH).minw) void split_gemm_grouped_kernel(const SplitJob* __restrict__ jobs,
+// Persistent grid over the tiles of a group of split jobs (same digit type,
+// count and tile variant): tile t is job p's (t - prefix[p])-th tile,
+// row-major over ceil(N / BM) x (Mp / BN) tiles.
+template <int DT, int S, bool FLUSH, int V>
+__global__ __launch_bounds__(grouped_tile_cfg(DT, S, FLUSH, V).threads(), grouped_tile_cfg(DT, S, FLUSH, V).minw) void split_gemm_grouped_kernel(const SplitJob* __restrict__ jobs,
                                                                  const i64* __restrict__ prefix, int njobs,
                                                                  int flush_steps, const int* __restrict__ soff,
                                                                  const int* __restrict__ slist)
 {
     extern __shared__ __align__(16) char lds[];
-    constexpr TileCfg TC = grouped_tile_cfg(DT, S, FLUSH);
+    constexpr TileCfg TC = grouped_tile_cfg(DT, S, FLUSH, V);
     for (int q = soff[blockIdx.x]; q < soff[blockIdx.x + 1]; ++q) {
         const i64 t = slist[q];
         int lo = 0, hi = njobs - 1;
@@ -918,27 +927,38 @@ hipError_t run_split_dt(const double* A, const double* B, double* C, i64 N, i64 
                            (int*)(ws + L.fb));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    return dispatch_s<DT>(L, ws, C, N, M, st);
+    timer_begin(st);
+    e = dispatch_s<DT>(L, ws, C, N, M, st);
+    timer_end(st);
+    return e;
 }
 
-template <int DT, int S, bool FLUSH>
+template <int DT, int S, bool FLUSH, int V>
 hipError_t launch_grouped_gemm(const SplitJob* jobs, const i64* prefix, int n, int flush_steps, int grid,
                                TileSchedule sch, hipStream_t st)
 {
-    constexpr TileCfg TC = grouped_tile_cfg(DT, S, FLUSH);
+    constexpr TileCfg TC = grouped_tile_cfg(DT, S, FLUSH, V);
     const size_t lds = split_lds_bytes(TC, S);
-    auto kern = split_gemm_grouped_kernel<DT, S, FLUSH>;
+    auto kern = split_gemm_grouped_kernel<DT, S, FLUSH, V>;
     if (!jobs) return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(TC.threads()), lds, st, jobs, prefix, n, flush_steps, sch.off, sch.list);
     return hipGetLastError();
+}
+
+template <int DT, int S, bool FLUSH>
+hipError_t grouped_variant(const SplitGroup& g, const SplitJob* jobs, const i64* prefix, int n, int grid,
+                           TileSchedule sch, hipStream_t st)
+{
+    if (g.variant == 1) return launch_grouped_gemm<DT, S, FLUSH, 1>(jobs, prefix, n, g.flush_steps, grid, sch, st);
+    return launch_grouped_gemm<DT, S, FLUSH, 0>(jobs, prefix, n, g.flush_steps, grid, sch, st);
 }
 
 template <int DT, int S>
 hipError_t grouped_flush(const SplitGroup& g, const SplitJob* jobs, const i64* prefix, int n, int grid,
                          TileSchedule sch, hipStream_t st)
 {
-    if (g.flush) return launch_grouped_gemm<DT, S, true>(jobs, prefix, n, g.flush_steps, grid, sch, st);
-    return launch_grouped_gemm<DT, S, false>(jobs, prefix, n, g.flush_steps, grid, sch, st);
+    if (g.flush) return grouped_variant<DT, S, true>(g, jobs, prefix, n, grid, sch, st);
+    return grouped_variant<DT, S, false>(g, jobs, prefix, n, grid, sch, st);
 }
 
 template <int DT>
@@ -1011,7 +1031,8 @@ hipError_t run_split(const double* A, const double* B, double* C, i64 N, i64 P, 
 
 namespace mmm {
 
-size_t split_job_bytes(i64 N, i64 P, i64 M, int dt, int s, SplitGroup& grp, i64& Np, i64& Mp, i64& Kp)
+size_t split_job_bytes(i64 N, i64 P, i64 M, int dt, int s, int variant, SplitGroup& grp, i64& Np, i64& Mp,
+                       i64& Kp)
 {
     mmm_config c = mmm_config_default();
     c.split_type = dt;
@@ -1020,9 +1041,10 @@ size_t split_job_bytes(i64 N, i64 P, i64 M, int dt, int s, SplitGroup& grp, i64&
     if (!split_layout(N, P, M, c, L)) return (size_t)-1;
     const int fs = flush_steps_for(dt, s);
     if (fs < 1) return (size_t)-1;
-    const TileCfg tc = grouped_tile_cfg(dt, s, L.flush);
+    const TileCfg tc = grouped_tile_cfg(dt, s, L.flush, variant);
     grp.dt = dt;
     grp.s = s;
+    grp.variant = variant;
     grp.flush = L.flush;
     grp.flush_steps = fs;
     grp.bm = tc.bm();

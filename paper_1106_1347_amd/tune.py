@@ -1,26 +1,31 @@
-"""Autotuner for the DGEMM tile shape of batched products.
+"""Autotuner for the tile shapes of batched products.
 
 Problems are grouped into shape classes (powers of two of max(N, M) and of
 P).  For each class the tuner builds a batch of that class's problems once
 per candidate tile shape, times the graph launch with HIP events and keeps
-the fastest.  Choices persist in a JSON cache keyed by device architecture,
-method, shape class and data type, so a later process picks them up
-without re-measuring.
+the fastest.  DGEMM problems choose among three tile shapes, split problems
+(per digit type and count) between the wide tile and the narrow one (half
+its rows).  Choices persist in a JSON cache keyed by device architecture,
+method, shape class and data type, so a later process picks them up without
+re-measuring; a batch plan takes its tiles from ``tile_for``.
 
-    tuner = TileTuner()                      # loads the cache if present
-    tuner.tune(shapes)                       # measures classes not cached
-    tile = tuner.tile_for(N, P, M)           # "128x128", "64x64", ... or "auto"
+    tuner = TileTuner()                          # loads the cache if present
+    tuner.tune(dgemm_shapes, split=split_shapes, split_config=cfg)
+    tile = tuner.tile_for(N, P, M)               # "128x128", "64x64", ... or "auto"
+    tile = tuner.tile_for(N, P, M, "split", cfg) # "wide", "narrow" or "auto"
 """
 import json
 import math
 import os
-from typing import Dict, Iterable, Optional, Tuple
+from typing import Dict, Iterable, Optional, Sequence, Tuple
 
 import torch
 
 from ._lib import Batch, Config
 
 CANDIDATES = ("128x128", "64x64", "128x64")
+SPLIT_CANDIDATES = ("wide", "narrow")
+SPLIT_TILE_CODES = {"auto": 0, "wide": 1, "narrow": 2}
 
 
 def default_cache_path() -> str:
@@ -38,6 +43,7 @@ class TileTuner:
         self.device = device
         self.arch = self._arch()
         self.table: Dict[str, str] = {}
+        self.timings: Dict[str, Dict[str, float]] = {}
         if os.path.exists(self.path):
             with open(self.path) as f:
                 self.table = json.load(f)
@@ -48,48 +54,71 @@ class TileTuner:
             return getattr(props, "gcnArchName", "unknown").split(":")[0]
         return "unknown"
 
-    def key(self, cls: Tuple[int, int]) -> str:
-        return "%s/dgemm/f64/n%d_p%d" % (self.arch, cls[0], cls[1])
+    def key(self, cls: Tuple[int, int], method: str = "dgemm", config: Optional[Config] = None) -> str:
+        if method == "dgemm":
+            return "%s/dgemm/f64/n%d_p%d" % (self.arch, cls[0], cls[1])
+        c = config or Config()
+        return "%s/split/%s_s%d/n%d_p%d" % (self.arch, c.split_type, c.split_slices, cls[0], cls[1])
 
-    def tile_for(self, N: int, P: int, M: int) -> str:
-        return self.table.get(self.key(shape_class(N, P, M)), "auto")
+    def tile_for(self, N: int, P: int, M: int, method: str = "dgemm", config: Optional[Config] = None):
+        """The tile a batch problem should request: a DGEMM tile name, or for
+        split problems the integer code of the chosen variant."""
+        t = self.table.get(self.key(shape_class(N, P, M), method, config), "auto")
+        return t if method == "dgemm" else SPLIT_TILE_CODES[t]
 
-    def tune(self, shapes: Iterable[Tuple[int, int, int]], reps: int = 5, max_per_class: int = 64) -> Dict[str, str]:
+    def _time(self, problems, config, reps):
+        b = Batch(problems, config)
+        b.launch()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            b.launch()
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        b.close()
+        return sorted(times)[len(times) // 2]
+
+    def _tune_classes(self, shapes, method, config, candidates, reps, max_per_class):
         by_cls: Dict[Tuple[int, int], list] = {}
         for s in shapes:
             by_cls.setdefault(shape_class(*s), []).append(s)
         dev = torch.device("cuda", self.device)
         for cls, group in sorted(by_cls.items()):
-            k = self.key(cls)
+            k = self.key(cls, method, config)
             if k in self.table:
                 continue
             group = group[:max_per_class]
             mats = [(torch.rand(N, P, dtype=torch.float64, device=dev), torch.rand(P, M, dtype=torch.float64, device=dev),
                      torch.empty(N, M, dtype=torch.float64, device=dev)) for (N, P, M) in group]
-            best, best_ms = None, float("inf")
-            for tile in CANDIDATES:
-                b = Batch([(A, B, C, "dgemm", 0, tile) for (A, B, C) in mats], Config())
-                b.launch()
-                torch.cuda.synchronize()
-                times = []
-                for _ in range(reps):
-                    e0 = torch.cuda.Event(enable_timing=True)
-                    e1 = torch.cuda.Event(enable_timing=True)
-                    e0.record()
-                    b.launch()
-                    e1.record()
-                    torch.cuda.synchronize()
-                    times.append(e0.elapsed_time(e1))
-                b.close()
-                ms = sorted(times)[len(times) // 2]
-                if ms < best_ms:
-                    best, best_ms = tile, ms
-            self.table[k] = best
+            res = {}
+            for tile in candidates:
+                code = tile if method == "dgemm" else SPLIT_TILE_CODES[tile]
+                res[tile] = self._time([(A, B, C, method, 0, code) for (A, B, C) in mats], config, reps)
+            self.timings[k] = res
+            self.table[k] = min(res, key=res.get)
+
+    def tune(self, shapes: Iterable[Tuple[int, int, int]], reps: int = 5, max_per_class: int = 64,
+             split: Optional[Sequence[Tuple[int, int, int]]] = None,
+             split_config: Optional[Config] = None) -> Dict[str, str]:
+        """Measure every class of ``shapes`` (DGEMM) and of ``split`` (split
+        products with ``split_config``) that the cache does not hold yet."""
+        self._tune_classes(list(shapes), "dgemm", Config(), CANDIDATES, reps, max_per_class)
+        if split:
+            self._tune_classes(list(split), "split", split_config or Config(), SPLIT_CANDIDATES, reps, max_per_class)
         self.save()
         return self.table
 
+    def summary(self) -> Dict[str, object]:
+        """Chosen tile per class (and the measured candidates of the classes
+        tuned by this process)."""
+        return {"choices": dict(sorted(self.table.items())), "measured_ms": dict(sorted(self.timings.items()))}
+
     def save(self) -> None:
-        os.makedirs(os.path.dirname(self.path), exist_ok=True)
+        os.makedirs(os.path.dirname(os.path.abspath(self.path)), exist_ok=True)
         tmp = self.path + ".tmp%d" % os.getpid()
         with open(tmp, "w") as f:
             json.dump(self.table, f, indent=1, sort_keys=True)

@@ -65,12 +65,18 @@ def test_workspace_arithmetic(lib):
     # WinogradScaled also holds 2^l A (5600 B -> 5632) and 2^-l B (16800 B -> 16896)
     assert ws("winograd_scaled", 100, 7, 300) == 1024 + 2560 + 3 * 256 + 5632 + 16896
     cfg = lib.Config(strassen_levels=2)
-    # no padding at 4096^3: two levels of (7^d slots of A, B and products)
+    # no padding at 4096^3: the deepest two levels run fused, so level 1 (the
+    # fused level) holds nothing and level 2 holds 49 slots of A, B and products
     n1, n2 = 2048 * 2048 * 8, 1024 * 1024 * 8
-    assert ws("strassen_winograd", 4096, 4096, 4096, cfg) == 3 * (7 * n1 + 49 * n2)
+    assert ws("strassen_winograd", 4096, 4096, 4096, cfg) == 3 * 49 * n2
+    # three levels: level 2 is fused; levels 1 and 3 hold their slots
+    n3 = 512 * 512 * 8
+    assert ws("strassen_winograd", 4096, 4096, 4096, lib.Config(strassen_levels=3)) == 3 * (7 * n1 + 343 * n3)
+    # one level: nothing fused
+    assert ws("strassen_winograd", 4096, 4096, 4096, lib.Config(strassen_levels=1)) == 3 * 7 * n1
     # P = 4097 pads to 4100; A, B, C padded copies come first
     b = ws("strassen_winograd", 4096, 4097, 4096, cfg)
-    assert b > 3 * (7 * n1 + 49 * n2)
+    assert b > 3 * 49 * n2
     assert ws("strassen_naive", 0, 5, 5) == 0
     # DGEMM leaf: P = 4097 is padded to a multiple of 16 * 2^L = 64 (4160), the
     # naive leaf only to a multiple of 2^L (4100); both pad copies of A, B, C
@@ -78,6 +84,8 @@ def test_workspace_arithmetic(lib):
         al = lambda x: (x + 255) // 256 * 256
         tot = al(8 * Np * Pp) + al(8 * Pp * Mp) + al(8 * Np * Mp)
         for d in range(1, L + 1):
+            if L >= 2 and d == L - 1:
+                continue  # the fused level
             n, p_, m = Np >> d, Pp >> d, Mp >> d
             tot += al(8 * 7 ** d * n * p_) + al(8 * 7 ** d * p_ * m) + al(8 * 7 ** d * n * m)
         return tot

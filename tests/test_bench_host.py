@@ -29,9 +29,31 @@ def test_counted_traffic_is_reported_only_for_the_measured_source(monkeypatch):
     assert bench.counted_traffic("no such kernel") is None
 
 
-def test_defaults_finish_within_minutes(monkeypatch):
-    monkeypatch.setattr(sys, "argv", ["bench.py"])
-    a = bench.parse()
+def test_defaults_finish_within_minutes():
+    a = bench.parse([])
     assert a.gpus == 1 and a.size == 4096
     assert 1 <= a.steps <= 10 and 0 <= a.warmup <= 5
-    assert a.precision_reps <= 10
+    assert a.cpu_seconds <= 30  # the bounded CPU-oracle sample
+    assert a.serve_requests == 2000
+
+
+def test_headline_is_the_metric_configuration():
+    # the headline compares split configurations with the plain FP64 GEMM
+    names = [h[0] for h in bench.HEADLINE]
+    assert "dgemm" in names and any(n.startswith("split_bf16") for n in names)
+    assert any(n.startswith("split_int8") for n in names) and any(n.startswith("split_fp16") for n in names)
+    assert bench.FP64_GRADE == 1e-13
+    assert set(bench.SECTIONS) >= {"headline", "latency", "allmethods", "batch", "serve"}
+
+
+def test_tile_tuner_split_keys(tmp_path):
+    from paper_1106_1347_amd import tune
+    from paper_1106_1347_amd._lib import Config
+
+    t = tune.TileTuner(path=str(tmp_path / "t.json"))
+    cfg = Config(split_type="bf16", split_slices=6)
+    k = t.key((9, 8), "split", cfg)
+    assert k.endswith("/split/bf16_s6/n9_p8") and k != t.key((9, 8))
+    t.table[k] = "narrow"
+    assert t.tile_for(300, 200, 400, "split", cfg) == tune.SPLIT_TILE_CODES["narrow"]
+    assert t.tile_for(300, 200, 400, "split", Config(split_type="int8", split_slices=7)) == 0
