@@ -24,9 +24,12 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_build.LIB) or os.path.getmtime(_build.LIB) < os.path.getmtime(_build.SRC):
-        _build.build()
-    lib = ctypes.CDLL(_build.LIB)
+    path = os.environ.get("MMM_ORACLE_LIB")  # the sanitizer build, for the checking run
+    if not path:
+        path = _build.LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+            _build.build()
+    lib = ctypes.CDLL(path)
     dp, i64 = ctypes.c_void_p, _i64
     sig = {
         "oracle_set_threads": (None, [ctypes.c_int]),
