@@ -53,6 +53,7 @@ HEADLINE = [
     ("split_int8_s7", "split", {"split_type": "int8", "split_slices": 7}),
     ("split_bf16_s6", "split", {"split_type": "bf16", "split_slices": 6}),
     ("split_fp16_s6", "split", {"split_type": "fp16", "split_slices": 6}),
+    ("split_fp16_s5", "split", {"split_type": "fp16", "split_slices": 5}),
     ("strassen_winograd_L2", "strassen_winograd", {"strassen_levels": 2}),
 ]
 

@@ -230,6 +230,7 @@ def timer_stop():
 
 
 TILES = {"auto": 0, "128x128": 1, "64x64": 2, "128x64": 3}
+SPLIT_TILES = {"auto": 0, "wide": 1, "narrow": 2}
 
 
 class Batch:
@@ -237,7 +238,7 @@ class Batch:
 
     problems: sequence of (A, B, C, method[, slices[, tile]]) with CUDA
     float64 tensors; method is "dgemm" or "split"; slices 0 = the config's
-    digit count; tile a key of TILES (DGEMM only) or an int.
+    digit count; tile a key of TILES (DGEMM) or SPLIT_TILES (split), or an int.
     """
 
     def __init__(self, problems: Sequence[tuple], config: Optional[Config] = None, stream=None):
@@ -256,7 +257,8 @@ class Batch:
             arr[i].M = B.shape[1]
             arr[i].method = METHODS[method]
             arr[i].slices = int(slices)
-            arr[i].tile = TILES[tile] if isinstance(tile, str) else int(tile)
+            names = SPLIT_TILES if method == "split" else TILES
+            arr[i].tile = names[tile] if isinstance(tile, str) else int(tile)
             self._keep.append((A, B, C))
         c = (config or Config())._c()
         h = ctypes.c_void_p()

@@ -23,13 +23,24 @@ def mmm():
     return m
 
 
-def make_problems(shapes, seed, methods, slices, tiles):
+DGEMM_TILES = ["auto", "128x128", "64x64", "128x64"]
+SPLIT_TILES = ["auto", "wide", "narrow"]
+
+
+def make_problems(shapes, seed, methods, slices):
+    # tile choices cycle per method: every DGEMM and every split tile shape
+    # is exercised across the list
     out = []
+    seen = {}
     for g, (N, P, M) in enumerate(shapes):
         A = torch.from_numpy(synth.uniform((N, P), seed + 2 * g)).cuda()
         B = torch.from_numpy(synth.uniform((P, M), seed + 2 * g + 1)).cuda()
         C = torch.full((N, M), float("nan"), dtype=torch.float64, device="cuda")
-        out.append((A, B, C, methods[g % len(methods)], slices[g % len(slices)], tiles[g % len(tiles)]))
+        m = methods[g % len(methods)]
+        tiles = SPLIT_TILES if m == "split" else DGEMM_TILES
+        n = seen.get(m, 0)
+        seen[m] = n + 1
+        out.append((A, B, C, m, slices[g % len(slices)], tiles[n % len(tiles)]))
     return out
 
 
@@ -42,7 +53,7 @@ def single(mmm, A, B, method, s, cfg):
 def test_batch_equals_single_calls_and_replays(mmm, typ, slices):
     cfg = mmm.Config(split_type=typ, split_slices=7 if typ == "int8" else 6)
     shapes = synth.batch_shapes(48, 7, 1, 200) + [(16, 0, 9), (0, 5, 5), (300, 257, 3)]
-    probs = make_problems(shapes, 100, ["dgemm", "split"], slices, ["auto", "128x128", "64x64", "128x64"])
+    probs = make_problems(shapes, 100, ["dgemm", "split"], slices)
     want = [single(mmm, A, B, m, s, cfg).cpu() for (A, B, C, m, s, t) in probs]
     plan = mmm.Batch(probs, cfg)
     for rep in range(3):
