@@ -143,6 +143,27 @@ mmm_status mmm_norm_inf(const double* A, int64_t rows, int64_t cols, double* out
  * zero, infinite or NaN). */
 mmm_status mmm_winograd_lambda(const double* normA, const double* normB, int32_t* lambda_out, void* stream);
 
+/* ---- Products without any allocation ---------------------------------- */
+
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, hosts that forbid allocation on the hot
+ * path): mmm_multiply with its workspace taken from a library-owned device
+ * array of MMM_NOALLOC_SCRATCH_BYTES bytes instead of a caller buffer.
+ * Each device the library runs on holds its own array from the first call
+ * there until the process ends; the call itself allocates and frees
+ * nothing.  Arguments, layout, asynchrony and results are those of
+ * mmm_multiply (bitwise the same C).  A product whose mmm_workspace_bytes
+ * exceeds the array is refused with MMM_EWORKSPACE before anything is
+ * enqueued.  The array keeps whatever the last call left in it (every
+ * method clears what it needs cleared); calls on one device that overlap
+ * in time share it and race, so the caller serialises them (one stream, or
+ * events between streams). */
+#define MMM_NOALLOC_SCRATCH_BYTES (64u << 20)
+mmm_status mmm_multiply_noalloc(const double* A, const double* B, double* C, int64_t N, int64_t P, int64_t M,
+                                mmm_method method, const mmm_config* cfg, void* stream);
+/* Size of that array in bytes (MMM_NOALLOC_SCRATCH_BYTES). */
+size_t mmm_noalloc_scratch_bytes(void);
+
 /* ---- Batches: many independent products in one launch sequence ------- */
 
 typedef struct {

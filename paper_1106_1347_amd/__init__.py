@@ -19,6 +19,8 @@ from ._lib import (  # noqa: F401
     lib_path,
     minus,
     multiply,
+    multiply_noalloc,
+    noalloc_scratch_bytes,
     multiply_with_scalar,
     norm_inf,
     plus,

@@ -57,6 +57,9 @@ _sigs = {
     "mmm_workspace_bytes": (_sz, [ctypes.c_int, _i64, _i64, _i64, ctypes.POINTER(_CConfig)]),
     "mmm_multiply": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _i64, ctypes.c_int, ctypes.POINTER(_CConfig), _vp,
                                     _sz, _vp]),
+    "mmm_multiply_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _i64, ctypes.c_int,
+                                            ctypes.POINTER(_CConfig), _vp]),
+    "mmm_noalloc_scratch_bytes": (_sz, []),
     "mmm_plus": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _vp]),
     "mmm_minus": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _vp]),
     "mmm_multiply_with_scalar": (ctypes.c_int, [ctypes.c_double, _vp, _vp, _i64, _i64, _vp]),
@@ -171,6 +174,30 @@ def multiply(A: torch.Tensor, B: torch.Tensor, method: str = "dgemm", config: Op
     st = _lib.mmm_multiply(A.data_ptr(), B.data_ptr(), out.data_ptr(), N, P, M, METHODS[method], ctypes.byref(c),
                            wptr, wbytes, _stream(stream))
     _check(st, "mmm_multiply(%s)" % method)
+    return out
+
+
+def noalloc_scratch_bytes() -> int:
+    """Bytes of the library-owned workspace array used by multiply_noalloc."""
+    return int(_lib.mmm_noalloc_scratch_bytes())
+
+
+def multiply_noalloc(A: torch.Tensor, B: torch.Tensor, out: torch.Tensor, method: str = "dgemm",
+                     config: Optional[Config] = None, stream=None):
+    """out = A B by `method` with the library's static workspace array
+    (mmm_multiply_noalloc): nothing is allocated, by the library or here."""
+    _dev(A, "A")
+    _dev(B, "B")
+    _dev(out, "out")
+    N, P = A.shape
+    P2, M = B.shape
+    if P != P2 or tuple(out.shape) != (N, M):
+        raise ValueError("shapes do not match: A %s, B %s, out %s" % (tuple(A.shape), tuple(B.shape),
+                                                                      tuple(out.shape)))
+    c = (config or Config())._c()
+    st = _lib.mmm_multiply_noalloc(A.data_ptr(), B.data_ptr(), out.data_ptr(), N, P, M, METHODS[method],
+                                   ctypes.byref(c), _stream(stream))
+    _check(st, "mmm_multiply_noalloc(%s)" % method)
     return out
 
 

@@ -140,6 +140,26 @@ def test_argument_errors_before_any_launch(lib):
     assert lib._lib.mmm_status_string(2) == b"output overlaps an input"
 
 
+def test_noalloc_refuses_before_any_launch(lib):
+    """mmm_multiply_noalloc refuses a product whose workspace exceeds the
+    static array, and bad arguments, on the host (no device call)."""
+    f = lib._lib.mmm_multiply_noalloc
+    c = lib._lib.mmm_config_default()
+    r = ctypes.byref
+    cap = lib.noalloc_scratch_bytes()
+    assert cap == 64 << 20
+    # the split digits of an 8192^3 product (1.5 GiB) do not fit
+    assert lib.workspace_bytes("split", 8192, 8192, 8192) > cap
+    assert f(0x1000, 0x90000, 0x200000, 8192, 8192, 8192, 7, r(c), None) == 3
+    assert b"static scratch" in lib._lib.mmm_last_error()
+    # argument errors are mmm_multiply's
+    assert f(8, 8, 8, -1, 2, 2, 6, r(c), None) == 1
+    assert f(8, 8, 8, 2, 2, 2, 99, r(c), None) == 1
+    assert f(8, 8, None, 2, 2, 2, 6, r(c), None) == 1
+    assert f(0x1000, 0x90000, 0x1008, 4, 4, 4, 6, r(c), None) == 2
+    assert f(None, None, None, 0, 5, 5, 7, r(c), None) == 0
+
+
 def test_batch_validation_before_any_allocation(lib):
     P = lib._CProblem
     f = lib._lib.mmm_batch_create
