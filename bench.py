@@ -54,6 +54,7 @@ HEADLINE = [
     ("split_bf16_s6", "split", {"split_type": "bf16", "split_slices": 6}),
     ("split_fp16_s6", "split", {"split_type": "fp16", "split_slices": 6}),
     ("split_fp16_s5", "split", {"split_type": "fp16", "split_slices": 5}),
+    ("split_bf16_b9_s5", "split", {"split_type": "bf16", "split_slices": 5, "split_bits": 9}),
     ("strassen_winograd_L2", "strassen_winograd", {"strassen_levels": 2}),
 ]
 

@@ -92,7 +92,13 @@ typedef struct {
     int32_t split_scale_lambda; /* 1: apply WinogradScaled's 2^(+-lambda) before slicing (default 1) */
     int32_t naive_fma;          /* NAIVE only. 0: product and sum rounded separately as in the
                                    paper (default); 1: fused multiply-add */
-    int32_t reserved[9];        /* must be zero */
+    int32_t split_bits;         /* digit width beta of the split product: 0 = the digit type's default
+                                   (bf16 8, fp16 9, int8 7); bf16 and fp16 2..9, int8 2..7 (a digit of
+                                   beta bits is at most 2^(beta-1) in magnitude, which the type holds
+                                   exactly; with every allowed width and digit count, the fullest
+                                   digit-pair group stays in the accumulator's exact range for at least
+                                   one matrix-core step) */
+    int32_t reserved[8];        /* must be zero */
 } mmm_config;
 
 /* Default configuration (values above). */

@@ -667,6 +667,8 @@ void oracle_split_model_rows(const double* A, const double* B, double* out, i64 
     int* fb = (int*)malloc(sizeof(int) * (size_t)(M > 0 ? M : 1));
     /* digits of B: dB[t][k*M+j] */
     int32_t* dB = (int32_t*)malloc(sizeof(int32_t) * (size_t)(s * P * M > 0 ? s * P * M : 1));
+    /* columns are independent: threads split them, as they split rows below */
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (P * M > 32768)
     for (i64 j = 0; j < M; ++j) {
         double mx = 0.0;
         for (i64 k = 0; k < P; ++k) mx = oracle_max_double(mx, fabs(sb * B[k * M + j]));

@@ -41,7 +41,7 @@ class _CConfig(ctypes.Structure):
     _fields_ = [("strassen_levels", ctypes.c_int32), ("pad_mode", ctypes.c_int32),
                 ("strassen_leaf", ctypes.c_int32), ("split_slices", ctypes.c_int32),
                 ("split_type", ctypes.c_int32), ("split_scale_lambda", ctypes.c_int32),
-                ("naive_fma", ctypes.c_int32), ("reserved", ctypes.c_int32 * 9)]
+                ("naive_fma", ctypes.c_int32), ("split_bits", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8)]
 
 
 class _CProblem(ctypes.Structure):
@@ -111,6 +111,7 @@ class Config:
     split_type: str = "bf16"
     split_scale_lambda: bool = True
     naive_fma: bool = False
+    split_bits: int = 0  # 0: the digit type's default width (bf16 8, fp16 9, int8 7)
 
     def _c(self) -> _CConfig:
         c = _CConfig()
@@ -121,6 +122,7 @@ class Config:
         c.split_type = SLICE_TYPES[self.split_type]
         c.split_scale_lambda = int(bool(self.split_scale_lambda))
         c.naive_fma = int(bool(self.naive_fma))
+        c.split_bits = int(self.split_bits)
         return c
 
 

@@ -93,7 +93,7 @@ bool overlap(const void* a, size_t abytes, const void* b, size_t bbytes)
 
 mmm_status mmm::check_config(const mmm_config& c)
 {
-    for (int i = 0; i < 9; ++i)
+    for (int i = 0; i < 8; ++i)
         if (c.reserved[i] != 0) return fail(MMM_EINVAL, "config: reserved fields must be zero");
     if (c.strassen_levels < 0 || c.strassen_levels > kMaxDepth)
         return fail(MMM_EINVAL, "config: strassen_levels %d outside 0..%d", c.strassen_levels, kMaxDepth);
@@ -105,6 +105,9 @@ mmm_status mmm::check_config(const mmm_config& c)
     if (c.split_type != MMM_SLICE_BF16 && c.split_type != MMM_SLICE_FP16 && c.split_type != MMM_SLICE_INT8)
         return fail(MMM_EINVAL, "config: bad split_type");
     if (c.split_scale_lambda != 0 && c.split_scale_lambda != 1) return fail(MMM_EINVAL, "config: bad split_scale_lambda");
+    if (c.split_bits != 0 && (c.split_bits < 2 || c.split_bits > (c.split_type == MMM_SLICE_INT8 ? 7 : 9)))
+        return fail(MMM_EINVAL, "config: split_bits %d outside 2..%d for this digit type", c.split_bits,
+                    c.split_type == MMM_SLICE_INT8 ? 7 : 9);
     if (c.naive_fma != 0 && c.naive_fma != 1) return fail(MMM_EINVAL, "config: bad naive_fma");
     return MMM_OK;
 }

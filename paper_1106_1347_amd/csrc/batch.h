@@ -48,9 +48,10 @@ enum SplitTile { SPLIT_TILE_AUTO = 0, SPLIT_TILE_WIDE = 1, SPLIT_TILE_NARROW = 2
 // Split jobs of one digit type and count, sharing one tile shape.
 struct SplitGroup {
     int dt, s;
+    int beta;     // digit width
+    int unit;     // MFMA steps one digit pair may accumulate exactly
     int variant;  // 0: the wide tile, 1: the narrow one (half the rows)
     bool flush;
-    int flush_steps;
     int bm, bn;
     int per_cu;  // workgroups of the group's kernel resident per CU
 };
@@ -83,8 +84,8 @@ __host__ __device__ inline i64 split_b_blocks(const SplitJob& j) { return (j.Kp 
 // Workspace bytes for one split job; fills the job's Np/Mp/Kp and returns
 // (size_t)-1 when unsupported.  Offsets of the job's buffers inside its
 // workspace are assigned by split_job_bind.
-size_t split_job_bytes(i64 N, i64 P, i64 M, int dt, int s, int variant, SplitGroup& grp, i64& Np, i64& Mp,
-                       i64& Kp);
+size_t split_job_bytes(i64 N, i64 P, i64 M, int dt, int s, int bits, int variant, SplitGroup& grp, i64& Np,
+                       i64& Mp, i64& Kp);
 void split_job_bind(SplitJob& j, char* base, int dt, int s);
 // Host-side set-up of a group's kernels (dynamic LDS size); call once
 // before recording launches into a graph.

@@ -156,7 +156,7 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
             SplitGroup grp;
             i64 Np, Mp, Kp;
             const int variant = p.tile == SPLIT_TILE_NARROW ? 1 : 0;
-            const size_t bytes = split_job_bytes(p.N, p.P, p.M, c.split_type, s, variant, grp, Np, Mp, Kp);
+            const size_t bytes = split_job_bytes(p.N, p.P, p.M, c.split_type, s, c.split_bits, variant, grp, Np, Mp, Kp);
             if (bytes == (size_t)-1) return bfail(MMM_EUNSUPPORTED, "problem %d: split configuration", i);
             SGroup& g = sg[std::make_tuple(grp.dt, grp.s, grp.flush, grp.variant)];
             g.g = grp;

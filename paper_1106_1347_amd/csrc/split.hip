@@ -16,8 +16,10 @@
 //   5. c = sum_{g = s+1 .. 2} 2^(-beta g) G_g in FP64, in that order; then
 //      C_ij = 2^(e_i + f_j) c.
 //
-// Digit types: BF16 (beta = 8, FP32 accumulation, 16x16x32 MFMA), FP16
-// (beta = 9), INT8 (beta = 7, INT32 accumulation, 16x16x64 MFMA).
+// Digit types: BF16 (default beta = 8, at most 9: |d| <= 256 has 8
+// significant bits), FP16 (default and at most 9), both with FP32
+// accumulation on the 16x16x32 MFMA; INT8 (default and at most 7: |d| <= 64
+// fits a signed byte, INT32 accumulation, 16x16x64 MFMA).
 //
 // Layouts (workspace): K is padded to a multiple of 64 entries and cut into
 // blocks of 64 bytes (64 int8 or 32 bf16/fp16 digits: one MFMA step of
@@ -54,17 +56,17 @@ template <int DT>
 struct Digit;
 template <>
 struct Digit<DT_BF16> {
-    static constexpr int beta = 8, esize = 2, mfma_k = 32;
+    static constexpr int esize = 2, mfma_k = 32;
     static constexpr double budget = 16777216.0;  // 2^24: exact FP32 integers
 };
 template <>
 struct Digit<DT_FP16> {
-    static constexpr int beta = 9, esize = 2, mfma_k = 32;
+    static constexpr int esize = 2, mfma_k = 32;
     static constexpr double budget = 16777216.0;
 };
 template <>
 struct Digit<DT_INT8> {
-    static constexpr int beta = 7, esize = 1, mfma_k = 64;
+    static constexpr int esize = 1, mfma_k = 64;
     static constexpr double budget = 2147483647.0;  // int32
 };
 
@@ -120,7 +122,8 @@ __host__ __device__ constexpr TileCfg grouped_tile_cfg(int dt, int s, bool flush
                                   : (s >= 4 ? TileCfg{2, 1, 4, 2} : tile_cfg(dt, s, flush)));
 }
 
-__host__ __device__ inline int beta_of(int dt) { return dt == DT_BF16 ? 8 : (dt == DT_FP16 ? 9 : 7); }
+// digit width: the configured one, else the type's default
+__host__ inline int beta_of(int dt, int bits) { return bits ? bits : (dt == DT_BF16 ? 8 : (dt == DT_FP16 ? 9 : 7)); }
 
 // e = E(mx) + 1 (0 for an all-zero vector)
 __device__ inline int vec_exponent(double mx)
@@ -147,10 +150,10 @@ __device__ inline void store_digits(char* dst, const double* d)
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             if (DT == DT_BF16) {
-                const float f = (float)d[q];  // |d| <= 2^7: exact; bf16 keeps the top 16 bits exactly
+                const float f = (float)d[q];  // |d| <= 2^8: 8 significant bits, so the top 16 bits are exact
                 h[q] = (unsigned short)(__float_as_uint(f) >> 16);
             } else {
-                const _Float16 x = (_Float16)(float)d[q];  // |d| <= 2^8: exact in fp16
+                const _Float16 x = (_Float16)(float)d[q];  // |d| <= 2^8: exact in fp16 (11 bits)
                 h[q] = *reinterpret_cast<const unsigned short*>(&x);
             }
         }
@@ -166,9 +169,8 @@ __device__ inline void store_digits(char* dst, const double* d)
 // Digits of 8 consecutive entries along k of one row of A (or one column
 // of B).  x[q] are the unscaled entries (0 outside the matrix).
 template <int DT>
-__device__ inline void cut(const double* x, double sc, int e, int s, char* out, i64 slice_stride)
+__device__ inline void cut(const double* x, double sc, int e, int s, int beta, char* out, i64 slice_stride)
 {
-    constexpr int beta = Digit<DT>::beta;
     const double up = (double)(1 << beta);
     double r[8];
 #pragma unroll
@@ -192,7 +194,7 @@ template <int DT>
 // rmax_raw: rmax holds max_k |A_ik| before the 2^lambda scaling (exact to
 // scale afterwards: x -> fl(2^lambda x) is monotone, so it commutes with max).
 __device__ __forceinline__ void split_a_body(const double* __restrict__ A, i64 N, i64 P, i64 Np, i64 Kp,
-                                             const double* __restrict__ rmax, const int* lam, int s,
+                                             const double* __restrict__ rmax, const int* lam, int s, int beta,
                                              char* __restrict__ SA, int* __restrict__ ea, i64 block, i64 nblocks,
                                              bool rmax_raw = false)
 {
@@ -209,7 +211,7 @@ __device__ __forceinline__ void split_a_body(const double* __restrict__ A, i64 N
 #pragma unroll
         for (int r = 0; r < 8; ++r) x[r] = (i < N && k0 + r < P) ? A[i * P + k0 + r] : 0.0;
         char* out = SA + (kb * s * Np + i) * KB + q * 8 * ES;
-        cut<DT>(x, sc, e, s, out, Np * KB);
+        cut<DT>(x, sc, e, s, beta, out, Np * KB);
         if (k0 == 0) ea[i] = e;
     }
 }
@@ -219,7 +221,7 @@ __device__ __forceinline__ void split_a_body(const double* __restrict__ A, i64 N
 // blocks of neighbouring columns) are contiguous.
 template <int DT>
 __device__ __forceinline__ void split_b_body(const double* __restrict__ B, i64 P, i64 M, i64 Mp, i64 Kp,
-                                             const double* __restrict__ cmax, const int* lam, int s,
+                                             const double* __restrict__ cmax, const int* lam, int s, int beta,
                                              char* __restrict__ SB, int* __restrict__ fb, i64 block, double (*T)[65],
                                              bool cmax_raw = false)
 {
@@ -250,7 +252,7 @@ __device__ __forceinline__ void split_b_body(const double* __restrict__ B, i64 P
         for (int r = 0; r < 8; ++r) x[r] = T[kk + r][jc];
         const i64 kb = kt * ES + blk;
         char* out = SB + (kb * s * Mp + j) * KB + q * 8 * ES;
-        cut<DT>(x, sc, e, s, out, Mp * KB);
+        cut<DT>(x, sc, e, s, beta, out, Mp * KB);
         if (kt == 0 && kk == 0) fb[j] = e;
     }
 }
@@ -260,15 +262,15 @@ __device__ __forceinline__ void split_b_body(const double* __restrict__ B, i64 P
 template <int DT>
 __global__ __launch_bounds__(256) void split_ab_kernel(const double* __restrict__ A, i64 N, i64 P, i64 Np, i64 Kp,
                                                        const double* __restrict__ rmax, const int* lam, int s,
-                                                       char* __restrict__ SA, int* __restrict__ ea, i64 nblk_a,
+                                                       int beta, char* __restrict__ SA, int* __restrict__ ea, i64 nblk_a,
                                                        const double* __restrict__ B, i64 M, i64 Mp,
                                                        const double* __restrict__ cmax, char* __restrict__ SB,
                                                        int* __restrict__ fb)
 {
     __shared__ double T[64][65];
     const i64 b = blockIdx.x;
-    if (b < nblk_a) split_a_body<DT>(A, N, P, Np, Kp, rmax, lam, s, SA, ea, b, nblk_a, true);
-    else split_b_body<DT>(B, P, M, Mp, Kp, cmax, lam, s, SB, fb, b - nblk_a, T, true);
+    if (b < nblk_a) split_a_body<DT>(A, N, P, Np, Kp, rmax, lam, s, beta, SA, ea, b, nblk_a, true);
+    else split_b_body<DT>(B, P, M, Mp, Kp, cmax, lam, s, beta, SB, fb, b - nblk_a, T, true);
 }
 
 // ---- the digit-product GEMM -------------------------------------------------
@@ -352,7 +354,7 @@ template <int DT, int S, bool FLUSH, int WBM, int NW, int NST>
 __device__ __forceinline__ void split_tile(const char* __restrict__ SA, const char* __restrict__ SB,
                                            const int* __restrict__ ea, const int* __restrict__ fb,
                                            double* __restrict__ C, i64 N, i64 M, i64 Np, i64 Mp, i64 Kp, i64 tm,
-                                           i64 tn, int flush_steps, char* lds)
+                                           i64 tn, int beta, int unit, char* lds)
 {
     typedef Digit<DT> D;
     typedef typename Mfma<DT>::acc_t acc_t;
@@ -413,12 +415,13 @@ __device__ __forceinline__ void split_tile(const char* __restrict__ SA, const ch
     constexpr int PER_BLOCK = NBLK / NW + S;
 
     // Group g (pairs with t + u = g, index from 0) holds g + 1 digit pairs;
-    // flush_steps is the exact-range interval of the fullest group (S
-    // pairs), so group g may run flush_steps * S / (g + 1) steps between
-    // flushes: its partial sums then stay within the same bound.
+    // `unit` is the number of steps one pair's products can be summed
+    // within the accumulator's exact range, so group g may run
+    // unit / (g + 1) steps between flushes: (g + 1) (unit / (g + 1)) <= unit
+    // pairs' worth of products, each of its partial sums within the range.
     int left[FLUSH ? G : 1];
 #pragma unroll
-    for (int g = 0; g < (FLUSH ? G : 1); ++g) left[g] = flush_steps * S / (g + 1);
+    for (int g = 0; g < (FLUSH ? G : 1); ++g) left[g] = unit / (g + 1);
 #pragma unroll
     for (int q = 0; q < NST - 1; ++q)
         if (q < steps) {
@@ -456,7 +459,7 @@ __device__ __forceinline__ void split_tile(const char* __restrict__ SA, const ch
 #pragma unroll
             for (int g = 0; g < G; ++g)
                 if (--left[g] == 0) {
-                    left[g] = flush_steps * S / (g + 1);
+                    left[g] = unit / (g + 1);
 #pragma unroll
                     for (int i = 0; i < WBM; ++i) {
 #pragma unroll
@@ -484,7 +487,7 @@ __device__ __forceinline__ void split_tile(const char* __restrict__ SA, const ch
 #pragma unroll
             for (int g = G - 1; g >= 0; --g) {
                 const double Gg = FLUSH ? acc64[g][i][r] + (double)acc[g][i][r] : (double)acc[g][i][r];
-                const double term = ldexp(Gg, -D::beta * (g + 2));
+                const double term = ldexp(Gg, -beta * (g + 2));
                 c = c + term;
             }
             if (gm < N && gn < M) C[gm * M + gn] = ldexp(c, ea[gm] + fb[gn]);
@@ -495,7 +498,7 @@ template <int DT, int S, bool FLUSH>
 __global__ __launch_bounds__(tile_cfg(DT, S, FLUSH).threads(), tile_cfg(DT, S, FLUSH).minw) void split_gemm_kernel(const char* __restrict__ SA, const char* __restrict__ SB,
                                                          const int* __restrict__ ea, const int* __restrict__ fb,
                                                          double* __restrict__ C, i64 N, i64 M, i64 Np, i64 Mp,
-                                                         i64 Kp, i64 tiles_m, i64 tiles_n, int flush_steps)
+                                                         i64 Kp, i64 tiles_m, i64 tiles_n, int beta, int unit)
 {
     extern __shared__ __align__(16) char lds[];
     // tile order: XCD-contiguous ranges, 8 tile-rows per group
@@ -506,7 +509,7 @@ __global__ __launch_bounds__(tile_cfg(DT, S, FLUSH).threads(), tile_cfg(DT, S, F
     const i64 gs = (tiles_m - first) < 8 ? (tiles_m - first) : 8;
     const i64 w = b - grp * 8 * tiles_n;
     split_tile<DT, S, FLUSH, tile_cfg(DT, S, FLUSH).wbm, tile_cfg(DT, S, FLUSH).nw, tile_cfg(DT, S, FLUSH).stages>(SA, SB, ea, fb, C, N, M, Np, Mp, Kp, first + w % gs, w / gs,
-                                                          flush_steps, lds);
+                                                          beta, unit, lds);
 }
 
 // Persistent grid over the tiles of a group of split jobs (same digit type,
@@ -515,7 +518,7 @@ __global__ __launch_bounds__(tile_cfg(DT, S, FLUSH).threads(), tile_cfg(DT, S, F
 template <int DT, int S, bool FLUSH, int V>
 __global__ __launch_bounds__(grouped_tile_cfg(DT, S, FLUSH, V).threads(), grouped_tile_cfg(DT, S, FLUSH, V).minw) void split_gemm_grouped_kernel(const SplitJob* __restrict__ jobs,
                                                                  const i64* __restrict__ prefix, int njobs,
-                                                                 int flush_steps, const int* __restrict__ soff,
+                                                                 int beta, int unit, const int* __restrict__ soff,
                                                                  const int* __restrict__ slist)
 {
     extern __shared__ __align__(16) char lds[];
@@ -532,7 +535,7 @@ __global__ __launch_bounds__(grouped_tile_cfg(DT, S, FLUSH, V).threads(), groupe
         const i64 local = t - prefix[lo];
         const i64 tiles_n = j.Mp / TC.bn();
         split_tile<DT, S, FLUSH, TC.wbm, TC.nw, TC.stages>(j.SA, j.SB, j.ea, j.fb, j.C, j.N, j.M, j.Np, j.Mp, j.Kp, local / tiles_n,
-                                 local % tiles_n, flush_steps, lds);
+                                 local % tiles_n, beta, unit, lds);
         __syncthreads();
     }
 }
@@ -768,25 +771,26 @@ __global__ void jobs_lambda_kernel(const SplitJob* jobs, int n)
 template <int DT>
 __global__ __launch_bounds__(256) void jobs_split_ab_kernel(const SplitJob* __restrict__ jobs,
                                                             const JobBlock* __restrict__ ablocks, i64 na,
-                                                            const JobBlock* __restrict__ bblocks, int s, bool scaled)
+                                                            const JobBlock* __restrict__ bblocks, int s, int beta,
+                                                            bool scaled)
 {
     __shared__ double T[64][65];
     const i64 w = blockIdx.x;
     if (w < na) {
         const JobBlock b = ablocks[w];
         const SplitJob& j = jobs[b.job];
-        split_a_body<DT>(j.A, j.N, j.P, j.Np, j.Kp, j.rmax, scaled ? j.lam : nullptr, s, j.SA, j.ea, b.index,
+        split_a_body<DT>(j.A, j.N, j.P, j.Np, j.Kp, j.rmax, scaled ? j.lam : nullptr, s, beta, j.SA, j.ea, b.index,
                          split_a_blocks(j), true);
     } else {
         const JobBlock b = bblocks[w - na];
         const SplitJob& j = jobs[b.job];
-        split_b_body<DT>(j.B, j.P, j.M, j.Mp, j.Kp, j.cmax, scaled ? j.lam : nullptr, s, j.SB, j.fb, b.index, T,
-                         true);
+        split_b_body<DT>(j.B, j.P, j.M, j.Mp, j.Kp, j.cmax, scaled ? j.lam : nullptr, s, beta, j.SB, j.fb, b.index,
+                         T, true);
     }
 }
 
 struct SplitLayout {
-    int dt = 0, s = 0;
+    int dt = 0, s = 0, beta = 0, unit = 0;
     bool flush = false;
     i64 Np = 0, Mp = 0, Kp = 0;
     size_t nA = 0, nB = 0, lam = 0, rmax = 0, cmax = 0, ea = 0, fb = 0, SA = 0, SB = 0, bytes = 0;
@@ -797,28 +801,32 @@ size_t al(size_t x) { return (x + 255) / 256 * 256; }
 // the LDS stages of the A digit planes (S x BM rows x 64 bytes each)
 size_t split_lds_bytes(const TileCfg& tc, int s) { return (size_t)tc.stages * s * tc.bm() * KB; }
 
-// exact-accumulation budget: digit products are at most 2^(2 beta - 2);
-// a group of at most s pairs over kb entries must stay below the budget.
-// Returns the number of MFMA k-steps between flushes to FP64.
-int flush_steps_for(int dt, int s)
+// Exact-accumulation budget: digit products are at most 2^(2 beta - 2) in
+// magnitude, so one digit pair's products may be summed over
+// budget / 2^(2 beta - 2) entries of K, i.e. this many MFMA k-steps, before
+// a partial sum could leave the accumulator's exact range (FP32: 2^24;
+// INT32: 2^31 - 1).  A group of p pairs gets unit / p steps; the fullest
+// group holds s pairs, so a digit count needs unit / s >= 1.
+int flush_unit(int dt, int beta)
 {
-    const int beta = beta_of(dt);
     const double prod = ldexp(1.0, 2 * beta - 2);
     const double budget = dt == DT_INT8 ? Digit<DT_INT8>::budget : Digit<DT_BF16>::budget;
     const int mk = dt == DT_INT8 ? Digit<DT_INT8>::mfma_k : Digit<DT_BF16>::mfma_k;
-    const double kb = budget / (prod * s);
-    return (int)(kb / mk);
+    const double steps = budget / prod / mk;
+    return steps >= 1e9 ? 1000000000 : (int)steps;
 }
 
 bool split_layout(i64 N, i64 P, i64 M, const mmm_config& c, SplitLayout& L)
 {
     L.dt = c.split_type;
     L.s = c.split_slices;
+    L.beta = beta_of(L.dt, c.split_bits);
+    L.unit = flush_unit(L.dt, L.beta);
+    if (L.unit / L.s < 1) return false;
     const int es = L.dt == DT_INT8 ? 1 : 2;
     const int mk = L.dt == DT_INT8 ? Digit<DT_INT8>::mfma_k : Digit<DT_BF16>::mfma_k;
     L.Kp = cdiv(P, KT) * KT;
-    const int fs = flush_steps_for(L.dt, L.s);
-    L.flush = fs < L.Kp / mk;
+    L.flush = L.unit / L.s < L.Kp / mk;
     const TileCfg tc = tile_cfg(L.dt, L.s, L.flush);
     L.Np = cdiv(N, tc.bm()) * tc.bm();
     L.Mp = cdiv(M, tc.bn()) * tc.bn();
@@ -844,7 +852,7 @@ bool split_layout(i64 N, i64 P, i64 M, const mmm_config& c, SplitLayout& L)
 }
 
 template <int DT, int S, bool FLUSH>
-hipError_t launch_split_gemm(const SplitLayout& L, char* ws, double* C, i64 N, i64 M, int flush_steps, hipStream_t st)
+hipError_t launch_split_gemm(const SplitLayout& L, char* ws, double* C, i64 N, i64 M, hipStream_t st)
 {
     constexpr TileCfg TC = tile_cfg(DT, S, FLUSH);
     const i64 tiles_m = L.Np / TC.bm(), tiles_n = L.Mp / TC.bn();
@@ -857,17 +865,16 @@ hipError_t launch_split_gemm(const SplitLayout& L, char* ws, double* C, i64 N, i
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(TC.threads()), lds, st, (const char*)(ws + L.SA),
                        (const char*)(ws + L.SB), (const int*)(ws + L.ea), (const int*)(ws + L.fb), C, N, M, L.Np, L.Mp,
-                       L.Kp, tiles_m, tiles_n, flush_steps);
+                       L.Kp, tiles_m, tiles_n, L.beta, L.unit);
     return hipGetLastError();
 }
 
 template <int DT, int S>
 hipError_t dispatch_flush(const SplitLayout& L, char* ws, double* C, i64 N, i64 M, hipStream_t st)
 {
-    const int fs = flush_steps_for(DT, S);
-    if (fs < 1) return hipErrorNotSupported;
-    if (!L.flush) return launch_split_gemm<DT, S, false>(L, ws, C, N, M, fs, st);
-    return launch_split_gemm<DT, S, true>(L, ws, C, N, M, fs, st);
+    if (L.unit / S < 1) return hipErrorNotSupported;
+    if (!L.flush) return launch_split_gemm<DT, S, false>(L, ws, C, N, M, st);
+    return launch_split_gemm<DT, S, true>(L, ws, C, N, M, st);
 }
 
 template <int DT>
@@ -923,7 +930,8 @@ hipError_t run_split_dt(const double* A, const double* B, double* C, i64 N, i64 
         const i64 blk_b = (L.Kp / 64) * (L.Mp / 64);
         if (blk_a + blk_b > 0x7fffffffLL) return hipErrorInvalidConfiguration;
         hipLaunchKernelGGL((split_ab_kernel<DT>), dim3((unsigned)(blk_a + blk_b)), dim3(256), 0, st, A, N, P, L.Np,
-                           L.Kp, rmax, lam, L.s, ws + L.SA, (int*)(ws + L.ea), blk_a, B, M, L.Mp, cmax, ws + L.SB,
+                           L.Kp, rmax, lam, L.s, L.beta, ws + L.SA, (int*)(ws + L.ea), blk_a, B, M, L.Mp, cmax,
+                           ws + L.SB,
                            (int*)(ws + L.fb));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
@@ -934,14 +942,14 @@ hipError_t run_split_dt(const double* A, const double* B, double* C, i64 N, i64 
 }
 
 template <int DT, int S, bool FLUSH, int V>
-hipError_t launch_grouped_gemm(const SplitJob* jobs, const i64* prefix, int n, int flush_steps, int grid,
+hipError_t launch_grouped_gemm(const SplitJob* jobs, const i64* prefix, int n, int beta, int unit, int grid,
                                TileSchedule sch, hipStream_t st)
 {
     constexpr TileCfg TC = grouped_tile_cfg(DT, S, FLUSH, V);
     const size_t lds = split_lds_bytes(TC, S);
     auto kern = split_gemm_grouped_kernel<DT, S, FLUSH, V>;
     if (!jobs) return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(TC.threads()), lds, st, jobs, prefix, n, flush_steps, sch.off, sch.list);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(TC.threads()), lds, st, jobs, prefix, n, beta, unit, sch.off, sch.list);
     return hipGetLastError();
 }
 
@@ -949,8 +957,8 @@ template <int DT, int S, bool FLUSH>
 hipError_t grouped_variant(const SplitGroup& g, const SplitJob* jobs, const i64* prefix, int n, int grid,
                            TileSchedule sch, hipStream_t st)
 {
-    if (g.variant == 1) return launch_grouped_gemm<DT, S, FLUSH, 1>(jobs, prefix, n, g.flush_steps, grid, sch, st);
-    return launch_grouped_gemm<DT, S, FLUSH, 0>(jobs, prefix, n, g.flush_steps, grid, sch, st);
+    if (g.variant == 1) return launch_grouped_gemm<DT, S, FLUSH, 1>(jobs, prefix, n, g.beta, g.unit, grid, sch, st);
+    return launch_grouped_gemm<DT, S, FLUSH, 0>(jobs, prefix, n, g.beta, g.unit, grid, sch, st);
 }
 
 template <int DT, int S>
@@ -998,7 +1006,7 @@ hipError_t launch_split_grouped_dt(const SplitGroup& g, const SplitJob* jobs, in
     if (nab > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     if (nab > 0)
         hipLaunchKernelGGL(jobs_split_ab_kernel<DT>, dim3((unsigned)nab), blk, 0, st, jobs,
-                           tab.ablocks, (i64)tab.nablocks, tab.bblocks, g.s, scale);
+                           tab.ablocks, (i64)tab.nablocks, tab.bblocks, g.s, g.beta, scale);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return total > 0 ? grouped_s<DT>(g, jobs, prefix, n, grid, tab.sched, st) : hipSuccess;
 }
@@ -1009,7 +1017,6 @@ size_t split_workspace_bytes(i64 N, i64 P, i64 M, const mmm_config& c)
 {
     SplitLayout L;
     if (!split_layout(N, P, M, c, L)) return (size_t)-1;
-    if (flush_steps_for(c.split_type, c.split_slices) < 1) return (size_t)-1;
     return L.bytes;
 }
 
@@ -1031,22 +1038,22 @@ hipError_t run_split(const double* A, const double* B, double* C, i64 N, i64 P, 
 
 namespace mmm {
 
-size_t split_job_bytes(i64 N, i64 P, i64 M, int dt, int s, int variant, SplitGroup& grp, i64& Np, i64& Mp,
-                       i64& Kp)
+size_t split_job_bytes(i64 N, i64 P, i64 M, int dt, int s, int bits, int variant, SplitGroup& grp, i64& Np,
+                       i64& Mp, i64& Kp)
 {
     mmm_config c = mmm_config_default();
     c.split_type = dt;
     c.split_slices = s;
+    c.split_bits = bits;
     SplitLayout L;
     if (!split_layout(N, P, M, c, L)) return (size_t)-1;
-    const int fs = flush_steps_for(dt, s);
-    if (fs < 1) return (size_t)-1;
     const TileCfg tc = grouped_tile_cfg(dt, s, L.flush, variant);
     grp.dt = dt;
     grp.s = s;
+    grp.beta = L.beta;
+    grp.unit = L.unit;
     grp.variant = variant;
     grp.flush = L.flush;
-    grp.flush_steps = fs;
     grp.bm = tc.bm();
     grp.bn = tc.bn();
     grp.per_cu = tc.minw * 4 / tc.nw > 0 ? tc.minw * 4 / tc.nw : 1;

@@ -30,8 +30,8 @@ def dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).cuda()
 
 
-def split(mmm, A, B, typ, s, scale=True):
-    cfg = mmm.Config(split_type=typ, split_slices=s, split_scale_lambda=scale)
+def split(mmm, A, B, typ, s, scale=True, bits=0):
+    cfg = mmm.Config(split_type=typ, split_slices=s, split_scale_lambda=scale, split_bits=bits)
     C = mmm.multiply(dev(A), dev(B), "split", cfg)
     torch.cuda.synchronize()
     return C.cpu().numpy()
@@ -42,19 +42,32 @@ def bits_equal(X, Y):
 
 
 SHAPES = [(1, 1, 1), (5, 3, 7), (64, 64, 64), (65, 130, 63), (129, 257, 131), (200, 64, 300), (256, 300, 256)]
-CASES = [("bf16", 6), ("bf16", 3), ("bf16", 8), ("fp16", 4), ("fp16", 6), ("int8", 7), ("int8", 4), ("int8", 8),
-         ("int8", 1)]
+# (digit type, digit count, digit width; 0 = the type's default)
+CASES = [("bf16", 6, 0), ("bf16", 3, 0), ("bf16", 8, 0), ("fp16", 4, 0), ("fp16", 6, 0), ("fp16", 5, 0),
+         ("int8", 7, 0), ("int8", 4, 0), ("int8", 8, 0), ("int8", 1, 0),
+         ("bf16", 5, 9), ("bf16", 8, 9), ("bf16", 4, 5), ("fp16", 3, 7), ("int8", 5, 6), ("int8", 8, 3)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
-@pytest.mark.parametrize("typ,s", CASES)
-def test_split_bitwise_vs_model(mmm, orc, shape, typ, s):
+@pytest.mark.parametrize("typ,s,bits", CASES)
+def test_split_bitwise_vs_model(mmm, orc, shape, typ, s, bits):
     N, P, M = shape
-    print("case", shape, typ, s, flush=True)
+    print("case", shape, typ, s, bits, flush=True)
     A = synth.wide_range((N, P), 11 + N)
     B = synth.wide_range((P, M), 12 + M) * 2.0 ** 17
-    got = split(mmm, A, B, typ, s)
-    assert bits_equal(got, orc.split_model(A, B, s, BETA[typ], True))
+    got = split(mmm, A, B, typ, s, bits=bits)
+    assert bits_equal(got, orc.split_model(A, B, s, bits or BETA[typ], True))
+
+
+@pytest.mark.parametrize("typ,s,bits", [("bf16", 5, 9), ("fp16", 5, 9), ("bf16", 6, 8), ("fp16", 8, 9)])
+def test_split_flush_every_interval(mmm, orc, typ, s, bits):
+    """K = 3000 runs every digit-pair group through several flushes at its
+    own interval (with 9-bit digits the fullest groups flush every step):
+    the result still equals the model bit for bit."""
+    print("case flush", typ, s, bits, flush=True)
+    A = synth.wide_range((70, 3000), 21)
+    B = synth.wide_range((3000, 50), 22)
+    assert bits_equal(split(mmm, A, B, typ, s, bits=bits), orc.split_model(A, B, s, bits, True))
 
 
 @pytest.mark.parametrize("typ,s", [("bf16", 6), ("int8", 7), ("fp16", 5)])
@@ -80,10 +93,10 @@ def test_split_fp64_grade(mmm, orc):
     B = synth.wide_range((1024, 192), 6)
     ref = orc.naive(A, B)
     nA, nB = orc.norm_inf(A), orc.norm_inf(B)
-    for typ, s in (("bf16", 6), ("int8", 7), ("fp16", 6)):
-        e = orc.rel_err_inf(split(mmm, A, B, typ, s), ref, nA, nB)
-        print(typ, s, e, flush=True)
-        assert e <= 1e-13, (typ, s, e)
+    for typ, s, bits in (("bf16", 6, 0), ("int8", 7, 0), ("fp16", 6, 0), ("fp16", 5, 0), ("bf16", 5, 9)):
+        e = orc.rel_err_inf(split(mmm, A, B, typ, s, bits=bits), ref, nA, nB)
+        print(typ, s, bits, e, flush=True)
+        assert e <= 1e-13, (typ, s, bits, e)
 
 
 def test_split_int8_flush_path(mmm, orc):
@@ -107,11 +120,11 @@ def test_split_full_size_sampled_rows(mmm, orc):
     Ad, Bd = dev(A), dev(B)
     ref = orc.naive_rows(A, B, rows)
     nA, nB = orc.norm_inf(A), orc.norm_inf(B)
-    for typ, s in (("int8", 7), ("bf16", 6)):
-        print("case full size", typ, s, flush=True)
-        C = mmm.multiply(Ad, Bd, "split", mmm.Config(split_type=typ, split_slices=s))
+    for typ, s, bits in (("int8", 7, 0), ("bf16", 6, 0), ("bf16", 5, 9)):
+        print("case full size", typ, s, bits, flush=True)
+        C = mmm.multiply(Ad, Bd, "split", mmm.Config(split_type=typ, split_slices=s, split_bits=bits))
         torch.cuda.synchronize()
         got = C[torch.from_numpy(rows).cuda()].cpu().numpy()
         del C
-        assert bits_equal(got, orc.split_model_rows(A, B, rows, s, BETA[typ], True)), typ
+        assert bits_equal(got, orc.split_model_rows(A, B, rows, s, bits or BETA[typ], True)), typ
         assert orc.norm_inf(orc.minus(got, ref)) / (nA * nB) <= 1e-13
