@@ -59,6 +59,7 @@ def _load():
                                       ctypes.c_int]),
         "oracle_split_model_rows": (None, [dp, dp, dp, i64, i64, i64, dp, i64, ctypes.c_int,
                                            ctypes.c_int, ctypes.c_int]),
+        "oracle_split_run_length": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, i64]),
         "oracle_split_digits": (None, [dp, i64, i64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_int, dp, dp]),
         "oracle_rel_err_inf": (ctypes.c_double, [dp, dp, i64, i64, ctypes.c_double,
@@ -273,6 +274,11 @@ def split_model_rows(A, B, rows, slices, beta, scale_lambda=True):
     _load().oracle_split_model_rows(_p(A), _p(B), _p(out), N, P, M, _p(r), r.size, int(slices),
                                     int(beta), int(bool(scale_lambda)))
     return out
+
+
+def split_run_length(slices, beta, P):
+    """Run length L of the split model's recombination (step 5)."""
+    return int(_load().oracle_split_run_length(int(slices), int(beta), int(P)))
 
 
 def split_digits(X, slices, beta, lam, is_b):

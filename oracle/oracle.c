@@ -642,8 +642,17 @@ int oracle_strassen(const double* A, const double* B, double* C, i64 N, i64 P, i
  * 4. For g = 2 .. s+1 the exact integer
  *      G_g[i][j] = sum_{t+u=g} sum_k dA_t[i][k] dB_u[k][j]
  *    is formed (int64; no rounding).  Pairs with t+u > s+1 are dropped.
- * 5. c = 0.0; for g = s+1 down to 2: c = c + ldexp(G_g, -beta g) (one
- *    rounding each); C_ij = ldexp(c, e_i + f_j).
+ * 5. The groups are merged exactly into runs of L consecutive groups,
+ *    starting from the finest scale: g = s+1, s, ..., s+2-L form the first
+ *    run, the next L groups the second, and so on (the last run may be
+ *    shorter).  A run whose finest group is f holds the exact integer
+ *      T = sum_{g in run} G_g 2^(beta (f - g)),
+ *    so that its value is T 2^(-beta f).  L is the largest of 3, 2, 1 for
+ *    which every run's worst case  sum_{g in run} (g - 1) P 2^(2 beta - 2)
+ *    2^(beta (f - g))  is at most 2^53 (then T is an integer binary64 holds
+ *    exactly; L = 1 is the group-by-group sum).  Then c = 0.0 and, run by
+ *    run from the finest, c = c + ldexp(T, -beta f) (one rounding per run);
+ *    C_ij = ldexp(c, e_i + f_j).
  * All digit products are exact in any accumulator of >= 2*(beta-1) +
  * log2(P) + log2(s) bits, so steps 3-5 fix the result bit for bit. */
 static int row_exponent(double mx)
@@ -652,6 +661,22 @@ static int row_exponent(double mx)
     int e;
     frexp(mx, &e);
     return e + 1;
+}
+
+/* Run length L of step 5 for s digits of beta bits over P products. */
+int oracle_split_run_length(int s, int beta, i64 P)
+{
+    for (int L = 3; L >= 2; --L) {
+        int ok = 1;
+        for (int f = s + 1; f >= 2 && ok; f -= L) {
+            unsigned __int128 bound = 0;
+            for (int g = f; g > f - L && g >= 2; --g)
+                bound += ((unsigned __int128)(g - 1) * (unsigned __int128)P) << (2 * beta - 2 + beta * (f - g));
+            if (bound > ((unsigned __int128)1 << 53)) ok = 0;
+        }
+        if (ok) return L;
+    }
+    return 1;
 }
 
 /* The model evaluated for the listed rows of C only:
@@ -664,6 +689,7 @@ void oracle_split_model_rows(const double* A, const double* B, double* out, i64 
     if (scale_lambda) lambda = oracle_winograd_lambda(oracle_norm_inf(A, N, P), oracle_norm_inf(B, P, M));
     const double sa = ldexp(1.0, lambda), sb = ldexp(1.0, -lambda);
     const double up = ldexp(1.0, beta);
+    const int L = oracle_split_run_length(s, beta, P);
     int* fb = (int*)malloc(sizeof(int) * (size_t)(M > 0 ? M : 1));
     /* digits of B: dB[t][k*M+j] */
     int32_t* dB = (int32_t*)malloc(sizeof(int32_t) * (size_t)(s * P * M > 0 ? s * P * M : 1));
@@ -711,7 +737,11 @@ void oracle_split_model_rows(const double* A, const double* B, double* out, i64 
                     G[t + u] += acc;
                 }
             double c = 0.0;
-            for (int g = s + 1; g >= 2; --g) c = c + ldexp((double)G[g], -beta * g);
+            for (int f = s + 1; f >= 2; f -= L) {
+                int64_t T = 0;
+                for (int g = f; g > f - L && g >= 2; --g) T += G[g] * ((int64_t)1 << (beta * (f - g)));
+                c = c + ldexp((double)T, -beta * f);
+            }
             out[r * M + j] = ldexp(c, ea + fb[j]);
         }
         free(dA);

@@ -40,6 +40,7 @@ struct SplitJob {
     int* fb;      // Mp
     char* SA;
     char* SB;
+    int runlen;   // recombination run length (depends on P)
 };
 
 // Split tile variants a batch problem may request (mmm_problem.tile).
@@ -86,7 +87,7 @@ __host__ __device__ inline i64 split_b_blocks(const SplitJob& j) { return (j.Kp 
 // workspace are assigned by split_job_bind.
 size_t split_job_bytes(i64 N, i64 P, i64 M, int dt, int s, int bits, int variant, SplitGroup& grp, i64& Np,
                        i64& Mp, i64& Kp);
-void split_job_bind(SplitJob& j, char* base, int dt, int s);
+void split_job_bind(SplitJob& j, char* base, int dt, int s, int bits);
 // Host-side set-up of a group's kernels (dynamic LDS size); call once
 // before recording launches into a graph.
 hipError_t split_grouped_prepare(const SplitGroup& grp);

@@ -255,7 +255,7 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
     char* base = (char*)plan->dmem;
     for (auto& kv : sg) {
         SGroup& g = kv.second;
-        for (size_t k = 0; k < g.jobs.size(); ++k) split_job_bind(g.jobs[k], base + off_ws + g.ws_off[k], g.g.dt, g.g.s);
+        for (size_t k = 0; k < g.jobs.size(); ++k) split_job_bind(g.jobs[k], base + off_ws + g.ws_off[k], g.g.dt, g.g.s, c.split_bits);
     }
     // upload tables
     std::vector<char> host(off_ws > 0 ? off_ws : 1, 0);

@@ -13,8 +13,12 @@
 //      products and partial sums stay below the accumulator's exact range
 //      and are flushed to FP64 before they could exceed it, each group at
 //      the interval its own number of pairs allows).
-//   5. c = sum_{g = s+1 .. 2} 2^(-beta g) G_g in FP64, in that order; then
-//      C_ij = 2^(e_i + f_j) c.
+//   5. The groups, from the finest scale (g = s+1) down, are merged into
+//      runs of L consecutive groups; a run with finest group f holds the
+//      exact integer T = sum_{g in run} G_g 2^(beta (f - g)) (L is the
+//      largest of 3, 2, 1 whose worst-case run sums stay within 2^53, so T
+//      is exact in FP64).  c = 0; run by run from the finest,
+//      c = c + 2^(-beta f) T (one rounding per run); C_ij = 2^(e_i + f_j) c.
 //
 // Digit types: BF16 (default beta = 8, at most 9: |d| <= 256 has 8
 // significant bits), FP16 (default and at most 9), both with FP32
@@ -91,6 +95,16 @@ struct Digit<DT_INT8> {
 #ifndef MMM_SPLIT_SCHED
 #define MMM_SPLIT_SCHED 6  // scheduling hints for digit counts from this value up (0: never)
 #endif
+// the flushing tile for 4..6 digits
+#ifndef MMM_SPLIT_FWBM
+#define MMM_SPLIT_FWBM 2
+#endif
+#ifndef MMM_SPLIT_FMINW
+#define MMM_SPLIT_FMINW 2
+#endif
+#ifndef MMM_SPLIT_FSTAGES
+#define MMM_SPLIT_FSTAGES 2
+#endif
 struct TileCfg {
     int wbm, minw, nw, stages;
     constexpr int bm() const { return 16 * wbm; }
@@ -101,7 +115,9 @@ __host__ __device__ constexpr TileCfg tile_cfg(int dt, int s, bool flush)
 {
     return (void)dt, !flush ? (s <= 7 ? TileCfg{MMM_SPLIT_WBM, MMM_SPLIT_MINW, MMM_SPLIT_NW, MMM_SPLIT_STAGES}
                                       : TileCfg{2, 2, 4, 2})
-                            : (s <= 3 ? TileCfg{4, 2, 4, 2} : (s <= 6 ? TileCfg{2, 2, 4, 2} : TileCfg{2, 1, 4, 2}));
+                            : (s <= 3 ? TileCfg{4, 2, 4, 2}
+                                      : (s <= 6 ? TileCfg{MMM_SPLIT_FWBM, MMM_SPLIT_FMINW, 4, MMM_SPLIT_FSTAGES}
+                                                : TileCfg{2, 1, 4, 2}));
 }
 // The persistent batch kernel keeps the job-table walk live as well, so it
 // takes smaller register footprints: 4 waves and two stages without
@@ -354,7 +370,7 @@ template <int DT, int S, bool FLUSH, int WBM, int NW, int NST>
 __device__ __forceinline__ void split_tile(const char* __restrict__ SA, const char* __restrict__ SB,
                                            const int* __restrict__ ea, const int* __restrict__ fb,
                                            double* __restrict__ C, i64 N, i64 M, i64 Np, i64 Mp, i64 Kp, i64 tm,
-                                           i64 tn, int beta, int unit, char* lds)
+                                           i64 tn, int beta, int unit, int runlen, char* lds)
 {
     typedef Digit<DT> D;
     typedef typename Mfma<DT>::acc_t acc_t;
@@ -476,19 +492,28 @@ __device__ __forceinline__ void split_tile(const char* __restrict__ SA, const ch
         if (NST >= 4 && kb + 3 < steps) step(std::integral_constant<int, (NST >= 4 ? 3 : 0)>(), kb + 3);
     }
 
-    // c = sum over g = S+1 .. 2 of 2^(-beta g) G_g, then scale by 2^(e_i + f_j)
+    // runs of `runlen` groups from the finest (index G - 1, scale 2^(-beta (G + 1)))
+    // down: T = sum G_g 2^(beta pos), pos = the group's distance from its
+    // run's finest group, exact; each run added to c with one rounding; then
+    // the scale 2^(e_i + f_j)
     const i64 gn = n0 + wave * 16 + li;
 #pragma unroll
     for (int i = 0; i < WBM; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const i64 gm = m0 + i * 16 + 4 * lq + r;
-            double c = 0.0;
+            double c = 0.0, T = 0.0;
+            int pos = 0;
 #pragma unroll
             for (int g = G - 1; g >= 0; --g) {
                 const double Gg = FLUSH ? acc64[g][i][r] + (double)acc[g][i][r] : (double)acc[g][i][r];
-                const double term = ldexp(Gg, -beta * (g + 2));
-                c = c + term;
+                T = pos == 0 ? Gg : T + Gg * ldexp(1.0, beta * pos);
+                if (pos == runlen - 1 || g == 0) {
+                    c = c + ldexp(T, -beta * (g + pos + 2));
+                    pos = 0;
+                } else {
+                    ++pos;
+                }
             }
             if (gm < N && gn < M) C[gm * M + gn] = ldexp(c, ea[gm] + fb[gn]);
         }
@@ -498,7 +523,8 @@ template <int DT, int S, bool FLUSH>
 __global__ __launch_bounds__(tile_cfg(DT, S, FLUSH).threads(), tile_cfg(DT, S, FLUSH).minw) void split_gemm_kernel(const char* __restrict__ SA, const char* __restrict__ SB,
                                                          const int* __restrict__ ea, const int* __restrict__ fb,
                                                          double* __restrict__ C, i64 N, i64 M, i64 Np, i64 Mp,
-                                                         i64 Kp, i64 tiles_m, i64 tiles_n, int beta, int unit)
+                                                         i64 Kp, i64 tiles_m, i64 tiles_n, int beta, int unit,
+                                                         int runlen)
 {
     extern __shared__ __align__(16) char lds[];
     // tile order: XCD-contiguous ranges, 8 tile-rows per group
@@ -509,7 +535,7 @@ __global__ __launch_bounds__(tile_cfg(DT, S, FLUSH).threads(), tile_cfg(DT, S, F
     const i64 gs = (tiles_m - first) < 8 ? (tiles_m - first) : 8;
     const i64 w = b - grp * 8 * tiles_n;
     split_tile<DT, S, FLUSH, tile_cfg(DT, S, FLUSH).wbm, tile_cfg(DT, S, FLUSH).nw, tile_cfg(DT, S, FLUSH).stages>(SA, SB, ea, fb, C, N, M, Np, Mp, Kp, first + w % gs, w / gs,
-                                                          beta, unit, lds);
+                                                          beta, unit, runlen, lds);
 }
 
 // Persistent grid over the tiles of a group of split jobs (same digit type,
@@ -535,7 +561,7 @@ __global__ __launch_bounds__(grouped_tile_cfg(DT, S, FLUSH, V).threads(), groupe
         const i64 local = t - prefix[lo];
         const i64 tiles_n = j.Mp / TC.bn();
         split_tile<DT, S, FLUSH, TC.wbm, TC.nw, TC.stages>(j.SA, j.SB, j.ea, j.fb, j.C, j.N, j.M, j.Np, j.Mp, j.Kp, local / tiles_n,
-                                 local % tiles_n, beta, unit, lds);
+                                 local % tiles_n, beta, unit, j.runlen, lds);
         __syncthreads();
     }
 }
@@ -790,7 +816,7 @@ __global__ __launch_bounds__(256) void jobs_split_ab_kernel(const SplitJob* __re
 }
 
 struct SplitLayout {
-    int dt = 0, s = 0, beta = 0, unit = 0;
+    int dt = 0, s = 0, beta = 0, unit = 0, runlen = 1;
     bool flush = false;
     i64 Np = 0, Mp = 0, Kp = 0;
     size_t nA = 0, nB = 0, lam = 0, rmax = 0, cmax = 0, ea = 0, fb = 0, SA = 0, SB = 0, bytes = 0;
@@ -807,6 +833,26 @@ size_t split_lds_bytes(const TileCfg& tc, int s) { return (size_t)tc.stages * s 
 // a partial sum could leave the accumulator's exact range (FP32: 2^24;
 // INT32: 2^31 - 1).  A group of p pairs gets unit / p steps; the fullest
 // group holds s pairs, so a digit count needs unit / s >= 1.
+// Run length of the recombination (step 5): the largest of 3, 2, 1 for
+// which every run of consecutive groups, from the finest, keeps its
+// worst-case exact sum within 2^53.  Group g (0-based) holds g + 1 digit
+// pairs, each product at most 2^(2 beta - 2), summed over P entries; inside
+// a run group g is weighted by 2^(beta (f - g)), f the run's finest group.
+int split_run_length(int s, int beta, i64 P)
+{
+    for (int L = 3; L >= 2; --L) {
+        bool ok = true;
+        for (int f = s - 1; f >= 0 && ok; f -= L) {
+            unsigned __int128 worst = 0;
+            for (int g = f; g > f - L && g >= 0; --g)
+                worst += ((unsigned __int128)(g + 1) * (unsigned __int128)P) << (2 * beta - 2 + beta * (f - g));
+            ok = worst <= ((unsigned __int128)1 << 53);
+        }
+        if (ok) return L;
+    }
+    return 1;
+}
+
 int flush_unit(int dt, int beta)
 {
     const double prod = ldexp(1.0, 2 * beta - 2);
@@ -827,6 +873,7 @@ bool split_layout(i64 N, i64 P, i64 M, const mmm_config& c, SplitLayout& L)
     const int mk = L.dt == DT_INT8 ? Digit<DT_INT8>::mfma_k : Digit<DT_BF16>::mfma_k;
     L.Kp = cdiv(P, KT) * KT;
     L.flush = L.unit / L.s < L.Kp / mk;
+    L.runlen = split_run_length(L.s, L.beta, P);
     const TileCfg tc = tile_cfg(L.dt, L.s, L.flush);
     L.Np = cdiv(N, tc.bm()) * tc.bm();
     L.Mp = cdiv(M, tc.bn()) * tc.bn();
@@ -865,7 +912,7 @@ hipError_t launch_split_gemm(const SplitLayout& L, char* ws, double* C, i64 N, i
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(TC.threads()), lds, st, (const char*)(ws + L.SA),
                        (const char*)(ws + L.SB), (const int*)(ws + L.ea), (const int*)(ws + L.fb), C, N, M, L.Np, L.Mp,
-                       L.Kp, tiles_m, tiles_n, L.beta, L.unit);
+                       L.Kp, tiles_m, tiles_n, L.beta, L.unit, L.runlen);
     return hipGetLastError();
 }
 
@@ -1063,13 +1110,15 @@ size_t split_job_bytes(i64 N, i64 P, i64 M, int dt, int s, int bits, int variant
     return L.bytes;
 }
 
-void split_job_bind(SplitJob& j, char* base, int dt, int s)
+void split_job_bind(SplitJob& j, char* base, int dt, int s, int bits)
 {
     mmm_config c = mmm_config_default();
     c.split_type = dt;
     c.split_slices = s;
+    c.split_bits = bits;
     SplitLayout L;
     split_layout(j.N, j.P, j.M, c, L);
+    j.runlen = L.runlen;
     j.Np = L.Np;
     j.Mp = L.Mp;
     j.Kp = L.Kp;

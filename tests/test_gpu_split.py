@@ -88,6 +88,23 @@ def test_split_integer_inputs_exact(mmm):
         assert np.array_equal(split(mmm, A, B, typ, s), ref), (typ, s)
 
 
+@pytest.mark.parametrize("typ,s,bits", [("bf16", 8, 9), ("fp16", 5, 9)])
+def test_split_run_length_edges(mmm, orc, typ, s, bits):
+    """The recombination merges runs of three groups only while their exact
+    sums fit binary64; K just below and just above the first K where that
+    fails (two-group runs from there) still gives the model's bits."""
+    lo, hi = 1, 1 << 20
+    assert orc.split_run_length(s, bits, lo) == 3 and orc.split_run_length(s, bits, hi) < 3
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        lo, hi = (mid, hi) if orc.split_run_length(s, bits, mid) == 3 else (lo, mid)
+    for P in (lo, hi):
+        print("case run edge", typ, s, bits, P, orc.split_run_length(s, bits, P), flush=True)
+        A = synth.wide_range((5, P), 41)
+        B = synth.wide_range((P, 3), 42)
+        assert bits_equal(split(mmm, A, B, typ, s, bits=bits), orc.split_model(A, B, s, bits, True)), P
+
+
 def test_split_fp64_grade(mmm, orc):
     A = synth.wide_range((256, 1024), 5)
     B = synth.wide_range((1024, 192), 6)

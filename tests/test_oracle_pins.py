@@ -452,6 +452,94 @@ def test_split_truncation_bound(orc):
         assert np.abs(C1 - C).max() > 0
 
 
+def test_split_single_run_is_correctly_rounded(orc):
+    """With s <= 2 digits the s groups form one run (L >= 2 for these sizes),
+    so the model rounds once: every entry is the correctly rounded value of
+    the exact truncated digit product (rational arithmetic from the
+    digits), times 2^(e_i + f_j).  A wrong shift inside the run or a
+    misplaced pair would change the exact value and fail."""
+    N, P, M = 5, 37, 4
+    A = synth.wide_range((N, P), 31)
+    B = synth.wide_range((P, M), 32)
+    for s, beta in ((1, 8), (2, 8), (2, 9), (2, 7)):
+        assert orc.split_run_length(s, beta, P) >= s
+        C = orc.split_model(A, B, s, beta, False)
+        dA, ea = orc.split_digits(A, s, beta, 0, False)
+        dB, fb = orc.split_digits(B, s, beta, 0, True)
+        for i in range(N):
+            for j in range(M):
+                v = Fraction(0)
+                for t in range(s):
+                    for u in range(s):
+                        if t + u + 2 <= s + 1:
+                            g = sum(int(dA[t, i, k]) * int(dB[u, k, j]) for k in range(P))
+                            v += Fraction(g, 2 ** (beta * (t + u + 2)))
+                want = np.ldexp(float(v), int(ea[i] + fb[j]))  # float(Fraction) rounds to nearest
+                assert C[i, j] == want, (s, beta, i, j)
+
+
+def _split_runs_reference(orc, A, B, s, beta, runs):
+    """The model's result with the given runs, from the oracle's digits by
+    rational arithmetic: exact group sums, each run rounded once when it is
+    added, finest run first."""
+    N, P = A.shape
+    M = B.shape[1]
+    dA, ea = orc.split_digits(A, s, beta, 0, False)
+    dB, fb = orc.split_digits(B, s, beta, 0, True)
+    out = np.empty((N, M))
+    for i in range(N):
+        for j in range(M):
+            G = {g: 0 for g in range(2, s + 2)}
+            for t in range(s):
+                for u in range(s):
+                    if t + u + 2 <= s + 1:
+                        G[t + u + 2] += int(np.dot(dA[t, i, :].astype(object), dB[u, :, j].astype(object)))
+            c = 0.0
+            for run in runs:
+                c = float(Fraction(c) + sum(Fraction(G[g], 2 ** (beta * g)) for g in run))
+            out[i, j] = np.ldexp(c, int(ea[i] + fb[j]))
+    return out
+
+
+def test_split_runs_of_three(orc):
+    """Runs of three groups from the finest scale: with five 9-bit digits
+    {6, 5, 4}, {3, 2}; with eight, {9, 8, 7}, {6, 5, 4}, {3, 2}; with seven
+    7-bit digits {8, 7, 6}, {5, 4, 3}, {2}.  Every entry of the model equals
+    the rational-arithmetic reference; on these 3600 entries a boundary in
+    the wrong place (eight digits as two runs of four) changes about 1% of
+    them, so the check sees where the roundings fall."""
+    A = synth.wide_range((60, 6), 51)
+    B = synth.wide_range((6, 60), 52)
+    cases = ((5, 9, [(6, 5, 4), (3, 2)]), (8, 9, [(9, 8, 7), (6, 5, 4), (3, 2)]), (7, 7, [(8, 7, 6), (5, 4, 3), (2,)]))
+    for s, beta, runs in cases:
+        assert orc.split_run_length(s, beta, A.shape[1]) == 3
+        C = orc.split_model(A, B, s, beta, False)
+        assert np.array_equal(C, _split_runs_reference(orc, A, B, s, beta, runs)), (s, beta)
+    wrong = _split_runs_reference(orc, A, B, 8, 9, [(9, 8, 7, 6), (5, 4, 3, 2)])
+    assert (wrong != orc.split_model(A, B, 8, 9, False)).sum() >= 10
+
+
+def test_split_run_length_rule(orc):
+    """L is the largest of 3, 2, 1 for which every run's worst-case exact
+    sum stays within 2^53, evaluated here with Python integers."""
+    def rule(s, beta, P):
+        for L in (3, 2):
+            ok = True
+            f = s + 1
+            while f >= 2:
+                bound = sum((g - 1) * P * 2 ** (2 * beta - 2 + beta * (f - g)) for g in range(f, max(f - L, 1), -1))
+                ok = ok and bound <= 2 ** 53
+                f -= L
+            if ok:
+                return L
+        return 1
+    rng = np.random.default_rng(5)
+    cases = [(s, b, int(P)) for s in range(1, 9) for b in (7, 8, 9) for P in (1, 64, 8192, 70000, 2 ** 17, 2 ** 21 + 1, 2 ** 26, 2 ** 30)]
+    cases += [(int(rng.integers(1, 9)), int(rng.integers(2, 10)), int(rng.integers(1, 2 ** 34))) for _ in range(300)]
+    for s, b, P in cases:
+        assert orc.split_run_length(s, b, P) == rule(s, b, P), (s, b, P)
+
+
 def test_split_accuracy_fp64_grade(orc):
     """On the wide-range distribution (rows scaled by 2^v, entries 2^u),
     6 bf16-sized digits reach a relative infinity-norm error well below
