@@ -95,6 +95,19 @@ struct Digit<DT_INT8> {
 #ifndef MMM_SPLIT_SCHED
 #define MMM_SPLIT_SCHED 6  // scheduling hints for digit counts from this value up (0: never)
 #endif
+// the 64 x 64 LDS kernel for 16-bit digits with flushing (4 or 5 digits)
+#ifndef MMM_SPLIT_LDS2
+#define MMM_SPLIT_LDS2 1
+#endif
+#ifndef MMM_SPLIT_LDS2_STAGES
+#define MMM_SPLIT_LDS2_STAGES 2
+#endif
+#ifndef MMM_SPLIT_LDS2_WM
+#define MMM_SPLIT_LDS2_WM 2  // waves along the rows (32 rows each)
+#endif
+#ifndef MMM_SPLIT_LDS2_WN
+#define MMM_SPLIT_LDS2_WN 2  // waves along the columns (32 columns each)
+#endif
 // the flushing tile for 4..6 digits
 #ifndef MMM_SPLIT_FWBM
 #define MMM_SPLIT_FWBM 2
@@ -519,6 +532,268 @@ __device__ __forceinline__ void split_tile(const char* __restrict__ SA, const ch
         }
 }
 
+// ---- 16-bit digits with flushing: both operands in LDS, 2 x 2 blocks per wave --
+//
+// With the recombination in runs of three groups, an output needs one FP32
+// accumulator per group but only two FP64 run accumulators (instead of one
+// per group), which leaves room for each wave to own 2 x 2 blocks of
+// 16 x 16 outputs.  A workgroup of 4 waves (2 x 2) then owns a 64 x 64 tile
+// and reads 20 KiB of digits per K block (S = 5) for 60 products per wave,
+// against 30 KiB for 30 products of the 32 x 64 tile: a third fewer bytes
+// per product.  Both operands' digit planes go global -> LDS by
+// global_load_lds (1 KiB blocks of 16 rows or columns x 64 bytes, the
+// chunks swizzled as in split_tile), two stages; each wave then reads all
+// its 4 S fragments of the K block and runs the products group by group,
+// finest group last.
+//
+// Flushes follow a static schedule instead of per-group counters: the K loop
+// is unrolled over periods of 8 steps and group g (g + 1 pairs) restarts
+// every iv_g steps, iv_g the largest power of two not above
+// min(8, unit / (g + 1)) (unit: steps one pair may accumulate exactly), so
+// its partial sums stay in FP32's exact range.  Restarting means its old
+// FP32 value goes into its run's FP64 accumulator (weighted by
+// 2^(beta pos), exact) and its first product of the step takes a zero
+// accumulator; with the groups run in ascending order, the flush of a
+// finer group can issue while the matrix cores work on the coarser ones.
+// Where a flush happens cannot change the exact sums, so every schedule
+// within the range gives the same bits.
+template <int BETA>
+struct FlushSched {
+    static constexpr int unit = 1 << (21 - 2 * BETA);  // 2^24 / 2^(2 beta - 2) / 32
+    static constexpr int period = 8;
+    static constexpr int iv(int g)
+    {
+        const int q = unit / (g + 1);
+        int p = 1;
+        while (p * 2 <= q && p * 2 <= period) p *= 2;
+        return p;
+    }
+    // groups starting a window at step j of a period (bit g)
+    static constexpr unsigned starts(int j, int S)
+    {
+        unsigned m = 0;
+        for (int g = 0; g < S; ++g)
+            if (j % iv(g) == 0) m |= 1u << g;
+        return m;
+    }
+};
+
+constexpr int popcount_c(unsigned m) { return m ? (int)(m & 1u) + popcount_c(m >> 1) : 0; }
+
+// Round 0 of a step in the LDS kernel: 4 S products, and 32 flush operations
+// (16 conversions, 16 fused adds) per group starting a window; interleave
+// them so that the flushes issue in the shadow of the products.
+template <int NM, int NV, int K = 0>
+__device__ __forceinline__ void sched_round0_k()
+{
+    if constexpr (K < NM) {
+        constexpr int nv = NV / NM + (K < NV % NM ? 1 : 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        if constexpr (nv > 0) __builtin_amdgcn_sched_group_barrier(0x002, nv, 0);
+        sched_round0_k<NM, NV, K + 1>();
+    }
+}
+template <int S, int NFLUSH>
+__device__ __forceinline__ void sched_round0()
+{
+    sched_round0_k<4 * S, 32 * NFLUSH>();
+}
+
+template <int DT, int S, int BETA, int NST, int WM, int WN>
+__device__ __forceinline__ void split_tile_lds2(const char* __restrict__ SA, const char* __restrict__ SB,
+                                                const int* __restrict__ ea, const int* __restrict__ fb,
+                                                double* __restrict__ C, i64 N, i64 M, i64 Np, i64 Mp, i64 Kp, i64 tm,
+                                                i64 tn, char* lds)
+{
+    typedef typename Mfma<DT>::acc_t acc_t;
+    typedef FlushSched<BETA> F;
+    constexpr int BM = 32 * WM, BN = 32 * WN, NW = WM * WN;
+    constexpr int RBA = BM / 16, RBB = BN / 16;  // 16-row / 16-column blocks per digit
+    constexpr int ABLK = S * RBA, NBLK = ABLK + S * RBB;  // KiB blocks per stage: A's, then B's
+    constexpr int STAGE = NBLK * 1024;
+    constexpr int R = (S + 2) / 3;  // runs of three groups, from the finest
+    static_assert(RBA <= NW && RBB <= NW, "one block of each digit per wave at most");
+    const i64 m0 = tm * BM, n0 = tn * BN;
+    // the wave index is uniform across the wave: said so, the compiler keeps
+    // the per-wave bases in scalar registers (loads: scalar base + 32-bit lane offset)
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave % WM, wn = wave / WM;  // this wave: rows 32 wm .., columns 32 wn ..
+    const int li = lane & 15, lq = lane >> 4;
+    const i64 steps = Kp * 2 / KB;
+    const i64 plane_a = Np * KB, plane_b = Mp * KB;
+
+    acc_t acc[S][2][2];
+    double run64[R][2][2][4];
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) run64[q][i][j][r] = 0.0;
+
+    // the loads of a stage: for every digit, wave w brings A's 16-row block w
+    // (w < BM / 16) and B's 16-column block w (w < BN / 16); lane l lands at
+    // byte 16 l of the block, taking the source chunk the swizzle puts there
+    const int dr = lane >> 2;
+    const unsigned offs = (unsigned)(dr * KB + swz(dr, lane & 3) * 16);
+    const char* sa0 = SA + (m0 + wave * 16) * KB;
+    const char* sb0 = SB + (n0 + wave * 16) * KB;
+    const int rd = li * KB + swz(li, lq) * 16;  // this lane's fragment within a KiB block
+    auto issue = [&](i64 kb, int buf) __attribute__((always_inline)) {
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            if (RBA == NW || wave < RBA)
+                __builtin_amdgcn_global_load_lds((gbl_ptr_t)(sa0 + (kb * S + q) * plane_a + offs),
+                                                 (lds_ptr_t)(lds + buf * STAGE + (q * RBA + wave) * 1024), 16, 0, 0);
+            if (RBB == NW || wave < RBB)
+                __builtin_amdgcn_global_load_lds((gbl_ptr_t)(sb0 + (kb * S + q) * plane_b + offs),
+                                                 (lds_ptr_t)(lds + buf * STAGE + (ABLK + q * RBB + wave) * 1024), 16, 0, 0);
+        }
+    };
+
+    // one K block: J = stage; the groups in START begin a new exact-range
+    // window at this step: the FP32 value of their previous window goes into
+    // their run's FP64 accumulator (weighted by 2^(beta pos), exact) and
+    // their first product here takes a zero accumulator.  Products run digit
+    // t of A by digit t of A (round t); round 0 gives group u its first
+    // product at position u, so the flush of group u can issue while the
+    // matrix cores work on groups 0 .. u - 1.
+    // K block kb lives in stage kb % NST; the loads of the next NST - 2
+    // blocks may still be in flight while it is used
+    auto step = [&](auto Sc, i64 kb) __attribute__((always_inline)) {
+        constexpr unsigned START = decltype(Sc)::value;
+        // this block's loads (own) have landed; after the barrier everyone's
+        // have, and everyone is done with the stage the next loads overwrite
+        // (block kb - 1's).  The next NST - 2 blocks' loads may stay in flight.
+        const i64 ahead = steps - 1 - kb;
+        if (NST >= 4 && ahead >= 2) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(4 * S) : "memory");
+        else if (NST >= 3 && ahead >= 1) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * S) : "memory");
+        else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        const int J = (int)(kb % NST);
+        if (kb + NST - 1 < steps) issue(kb + NST - 1, J == 0 ? NST - 1 : J - 1);
+        const char* la = lds + J * STAGE + rd;
+        u32x4 bf[S][2];
+#pragma unroll
+        for (int u = 0; u < S; ++u)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                bf[u][j] = *reinterpret_cast<const u32x4*>(la + (ABLK + u * RBB + wn * 2 + j) * 1024);
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            u32x4 af[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) af[i] = *reinterpret_cast<const u32x4*>(la + (t * RBA + wm * 2 + i) * 1024);
+#pragma unroll
+            for (int u = 0; u + t < S; ++u) {
+                const int g = t + u;
+                const bool restart = t == 0 && ((START >> g) & 1u);
+                if (restart) {
+                    const int q = (S - 1 - g) / 3;
+                    const double w = (double)(1ull << (BETA * ((S - 1 - g) % 3)));
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+#pragma unroll
+                        for (int j = 0; j < 2; ++j)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                run64[q][i][j][r] = fma((double)acc[g][i][j][r], w, run64[q][i][j][r]);
+                                // computed here, not sunk to the end of the tile with
+                                // the FP32 values kept alive (spilled) until then
+                                asm volatile("" : "+v"(run64[q][i][j][r]));
+                            }
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[g][i][j] = Mfma<DT>::run(af[i], bf[u][j], restart ? (acc_t){0, 0, 0, 0} : acc[g][i][j]);
+            }
+            // round 0: each product of group u issues between the flush
+            // operations of the groups after it (cvt + fma per value)
+            if (t == 0) sched_round0<S, popcount_c(START)>();
+            // keep the rounds in order (LDS reads may move up a round): the
+            // scheduler would otherwise gather the zero-accumulator products
+            // at the end and lengthen the fragments' lifetimes past the
+            // register budget
+            __builtin_amdgcn_sched_barrier(0x100);
+        }
+    };
+
+    // a window of group g starts at step j of a period when j is a multiple
+    // of iv_g: every group starts one at the first step of each period (the
+    // first of the tile adds the zero accumulators to the runs)
+    constexpr unsigned ALL = (1u << S) - 1;
+#pragma unroll
+    for (int g = 0; g < S; ++g)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[g][i][j] = (acc_t){0, 0, 0, 0};
+#define MMM_LDS2_STEP(j) step(std::integral_constant<unsigned, F::starts(j, S)>(), kb + (j))
+    i64 kb = 0;
+#pragma unroll
+    for (int q = 0; q < NST - 1; ++q)
+        if (q < steps) issue(q, q);
+    for (; kb + F::period <= steps; kb += F::period) {
+        MMM_LDS2_STEP(0);
+        MMM_LDS2_STEP(1);
+        MMM_LDS2_STEP(2);
+        MMM_LDS2_STEP(3);
+        MMM_LDS2_STEP(4);
+        MMM_LDS2_STEP(5);
+        MMM_LDS2_STEP(6);
+        MMM_LDS2_STEP(7);
+    }
+#undef MMM_LDS2_STEP
+    // the last steps are windows of one step each
+    for (; kb < steps; ++kb) step(std::integral_constant<unsigned, ALL>(), kb);
+
+    // close the last windows, then runs from the finest: c = c + 2^(-beta (f + 2)) T
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const i64 gn = n0 + wn * 32 + j * 16 + li;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+#pragma unroll
+                for (int g = 0; g < S; ++g)
+                    run64[(S - 1 - g) / 3][i][j][r] = fma((double)acc[g][i][j][r],
+                                                          (double)(1ull << (BETA * ((S - 1 - g) % 3))),
+                                                          run64[(S - 1 - g) / 3][i][j][r]);
+                double c = 0.0;
+#pragma unroll
+                for (int q = 0; q < R; ++q) c = c + ldexp(run64[q][i][j][r], -BETA * (S - 1 - 3 * q + 2));
+                const i64 gm = m0 + wm * 32 + i * 16 + 4 * lq + r;
+                if (gm < N && gn < M) C[gm * M + gn] = ldexp(c, ea[gm] + fb[gn]);
+            }
+        }
+}
+
+constexpr int kLds2BM = 32 * MMM_SPLIT_LDS2_WM, kLds2BN = 32 * MMM_SPLIT_LDS2_WN;
+constexpr int kLds2Threads = 64 * MMM_SPLIT_LDS2_WM * MMM_SPLIT_LDS2_WN;
+
+template <int DT, int S, int BETA>
+__global__ __launch_bounds__(kLds2Threads, 2) void split_gemm_lds2_kernel(const char* __restrict__ SA, const char* __restrict__ SB,
+                                                              const int* __restrict__ ea, const int* __restrict__ fb,
+                                                              double* __restrict__ C, i64 N, i64 M, i64 Np, i64 Mp,
+                                                              i64 Kp, i64 tiles_m, i64 tiles_n)
+{
+    extern __shared__ __align__(16) char lds[];
+    // tile order: XCD-contiguous ranges, 8 tile-rows per group
+    const i64 total = tiles_m * tiles_n;
+    i64 b = blockIdx.x;
+    if (total % 8 == 0) b = (b % 8) * (total / 8) + b / 8;
+    const i64 grp = b / (8 * tiles_n), first = grp * 8;
+    const i64 gs = (tiles_m - first) < 8 ? (tiles_m - first) : 8;
+    const i64 w = b - grp * 8 * tiles_n;
+    split_tile_lds2<DT, S, BETA, MMM_SPLIT_LDS2_STAGES, MMM_SPLIT_LDS2_WM, MMM_SPLIT_LDS2_WN>(
+        SA, SB, ea, fb, C, N, M, Np, Mp, Kp, first + w % gs, w / gs, lds);
+}
+
 template <int DT, int S, bool FLUSH>
 __global__ __launch_bounds__(tile_cfg(DT, S, FLUSH).threads(), tile_cfg(DT, S, FLUSH).minw) void split_gemm_kernel(const char* __restrict__ SA, const char* __restrict__ SB,
                                                          const int* __restrict__ ea, const int* __restrict__ fb,
@@ -875,8 +1150,12 @@ bool split_layout(i64 N, i64 P, i64 M, const mmm_config& c, SplitLayout& L)
     L.flush = L.unit / L.s < L.Kp / mk;
     L.runlen = split_run_length(L.s, L.beta, P);
     const TileCfg tc = tile_cfg(L.dt, L.s, L.flush);
-    L.Np = cdiv(N, tc.bm()) * tc.bm();
-    L.Mp = cdiv(M, tc.bn()) * tc.bn();
+    // 16-bit digits with flushing may run the LDS kernel: pad for both tiles
+    // (all tile sides are powers of two)
+    const int pm = L.dt != DT_INT8 && L.flush && tc.bm() < kLds2BM ? kLds2BM : tc.bm();
+    const int pn = L.dt != DT_INT8 && L.flush && tc.bn() < kLds2BN ? kLds2BN : tc.bn();
+    L.Np = cdiv(N, pm) * pm;
+    L.Mp = cdiv(M, pn) * pn;
     const double sa = (double)L.Np * L.Kp * L.s * es, sb = (double)L.Mp * L.Kp * L.s * es;
     if (sa + sb > 4.0e18) return false;
     size_t off = 0;
@@ -896,6 +1175,23 @@ bool split_layout(i64 N, i64 P, i64 M, const mmm_config& c, SplitLayout& L)
     L.SB = take((size_t)sb);
     L.bytes = off;
     return true;
+}
+
+template <int DT, int S, int BETA>
+hipError_t launch_split_lds2(const SplitLayout& L, char* ws, double* C, i64 N, i64 M, hipStream_t st)
+{
+    const i64 tiles_m = L.Np / kLds2BM, tiles_n = L.Mp / kLds2BN;
+    const i64 blocks = tiles_m * tiles_n;
+    if (blocks == 0) return hipSuccess;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    const size_t lds = (size_t)MMM_SPLIT_LDS2_STAGES * S * (kLds2BM + kLds2BN) * KB;
+    auto kern = split_gemm_lds2_kernel<DT, S, BETA>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kLds2Threads), lds, st, (const char*)(ws + L.SA),
+                       (const char*)(ws + L.SB), (const int*)(ws + L.ea), (const int*)(ws + L.fb), C, N, M, L.Np, L.Mp,
+                       L.Kp, tiles_m, tiles_n);
+    return hipGetLastError();
 }
 
 template <int DT, int S, bool FLUSH>
@@ -921,6 +1217,13 @@ hipError_t dispatch_flush(const SplitLayout& L, char* ws, double* C, i64 N, i64 
 {
     if (L.unit / S < 1) return hipErrorNotSupported;
     if (!L.flush) return launch_split_gemm<DT, S, false>(L, ws, C, N, M, st);
+#if MMM_SPLIT_LDS2
+    // 16-bit digits, 4 or 5 of them, recombined in runs of three: the 64 x 64 LDS kernel
+    if constexpr (DT != DT_INT8 && (S == 4 || S == 5)) {
+        if (L.runlen == 3 && L.beta == 9) return launch_split_lds2<DT, S, 9>(L, ws, C, N, M, st);
+        if (L.runlen == 3 && L.beta == 8) return launch_split_lds2<DT, S, 8>(L, ws, C, N, M, st);
+    }
+#endif
     return launch_split_gemm<DT, S, true>(L, ws, C, N, M, st);
 }
 
