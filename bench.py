@@ -56,6 +56,7 @@ HEADLINE = [
     ("split_fp16_s5", "split", {"split_type": "fp16", "split_slices": 5}),
     ("split_bf16_b9_s5", "split", {"split_type": "bf16", "split_slices": 5, "split_bits": 9}),
     ("strassen_winograd_L2", "strassen_winograd", {"strassen_levels": 2}),
+    ("strassen_winograd_L3", "strassen_winograd", {"strassen_levels": 3}),
 ]
 
 # the all-methods step at 4096: (name, method, config kwargs, algorithmic ops per multiply-add, bound)

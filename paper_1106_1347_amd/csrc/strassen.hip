@@ -201,60 +201,93 @@ __device__ __forceinline__ void fold_products(const double (&h)[7], double& c11,
     }
 }
 
+// W adjacent entries of a row (W = 1, or 2 when rows, strides and bases are
+// even and 16-byte aligned): one load or store per W entries
+template <int W>
+struct Vec;
+template <>
+struct Vec<1> {
+    typedef double T;
+    __device__ static T ld(const double* p) { return *p; }
+    __device__ static void st(double* p, T v) { *p = v; }
+    __device__ static double get(const T& v, int) { return v; }
+    __device__ static void set(T& v, int, double x) { v = x; }
+};
+template <>
+struct Vec<2> {
+    typedef double2 T;
+    __device__ static T ld(const double* p) { return *reinterpret_cast<const double2*>(p); }
+    __device__ static void st(double* p, T v) { *reinterpret_cast<double2*>(p) = v; }
+    __device__ static double get(const T& v, int k) { return k ? v.y : v.x; }
+    __device__ static void set(T& v, int k, double x) { (k ? v.y : v.x) = x; }
+};
+
 // Levels f and f + 1 in one pass: for every node of level f - 1, each
 // thread reads the 16 entries of the node's operand that one position of a
-// level-(f+1) block touches, forms the 7 x 4 level-f operand entries in
-// registers (level f is never written) and writes the level-(f+1)
-// operands that are not views of the node's own operand.
-template <int VARIANT, bool IS_B>
+// level-(f+1) block touches (W adjacent positions at a time), forms the
+// 7 x 4 level-f operand entries in registers (level f is never written)
+// and writes the level-(f+1) operands that are not views of the node's own
+// operand.
+template <int VARIANT, bool IS_B, int W>
 __global__ __launch_bounds__(256) void strassen_pre2_kernel(StrassenTree T, int f, i64 bpp)
 {
+    typedef Vec<W> V;
     const i64 parent = blockIdx.x / bpp;
     const i64 chunk = blockIdx.x - parent * bpp;
     const View par = strassen_operand(T, f - 1, parent, IS_B);
     const i64 rows = IS_B ? T.p[f + 1] : T.n[f + 1];
     const i64 cols = IS_B ? T.m[f + 1] : T.p[f + 1];
     const i64 sz = rows * cols;
-    double* W = (IS_B ? T.WB[f + 1] : T.WA[f + 1]) + parent * 49 * sz;
+    double* W_ = (IS_B ? T.WB[f + 1] : T.WA[f + 1]) + parent * 49 * sz;
     const i64 base = chunk * 256 * EPT + threadIdx.x;
 #pragma unroll 1
     for (int u = 0; u < EPT; ++u) {
-        const i64 e = base + u * 256;
+        const i64 e = (base + u * 256) * W;
         if (e >= sz) break;
         const i64 r = e / cols, c = e - r * cols;
         const double* q = par.p + r * par.ld + c;
-        double x[4][4];  // x[i][j]: block (i, j) of the 4 x 4 grid of level-(f+1) blocks
+        typename V::T x[4][4];  // x[i][j]: block (i, j) of the 4 x 4 grid of level-(f+1) blocks
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) x[i][j] = q[i * rows * par.ld + j * cols];
+            for (int j = 0; j < 4; ++j) x[i][j] = V::ld(q + i * rows * par.ld + j * cols);
 #pragma unroll
         for (int c1 = 0; c1 < 7; ++c1) {
-            double y[2][2];  // level-f operand of child c1, its quadrant (qi, qj)
+            typename V::T y[2][2];  // level-f operand of child c1, its quadrant (qi, qj)
 #pragma unroll
             for (int qi = 0; qi < 2; ++qi)
 #pragma unroll
                 for (int qj = 0; qj < 2; ++qj)
-                    y[qi][qj] = child_value<VARIANT, IS_B>(c1, x[qi][qj], x[qi][2 + qj], x[2 + qi][qj],
-                                                           x[2 + qi][2 + qj]);
+#pragma unroll
+                    for (int k = 0; k < W; ++k)
+                        V::set(y[qi][qj], k,
+                               child_value<VARIANT, IS_B>(c1, V::get(x[qi][qj], k), V::get(x[qi][2 + qj], k),
+                                                          V::get(x[2 + qi][qj], k), V::get(x[2 + qi][2 + qj], k)));
             const bool v1 = (IS_B ? view_quadrant_b(VARIANT, c1) : view_quadrant_a(VARIANT, c1)) >= 0;
 #pragma unroll
             for (int c2 = 0; c2 < 7; ++c2) {
                 const bool v2 = (IS_B ? view_quadrant_b(VARIANT, c2) : view_quadrant_a(VARIANT, c2)) >= 0;
                 if (v1 && v2) continue;  // a view of the node's own operand
-                W[(c1 * 7 + c2) * sz + e] = child_value<VARIANT, IS_B>(c2, y[0][0], y[0][1], y[1][0], y[1][1]);
+                typename V::T o;
+#pragma unroll
+                for (int k = 0; k < W; ++k)
+                    V::set(o, k, child_value<VARIANT, IS_B>(c2, V::get(y[0][0], k), V::get(y[0][1], k),
+                                                            V::get(y[1][0], k), V::get(y[1][1], k)));
+                V::st(W_ + (c1 * 7 + c2) * sz + e, o);
             }
         }
     }
 }
 
 // Levels f + 1 and f folded in one pass: for every node of level f - 1,
-// each thread reads its 49 grandchild products at one position, forms the
-// 7 x 4 level-f product entries in registers (level f is never written)
-// and writes the 16 entries of the node's product that position feeds.
-template <int VARIANT>
+// each thread reads its 49 grandchild products at one position (W adjacent
+// positions at a time), forms the 7 x 4 level-f product entries in
+// registers (level f is never written) and writes the 16 entries of the
+// node's product that position feeds.
+template <int VARIANT, int W>
 __global__ __launch_bounds__(256) void strassen_post2_kernel(StrassenTree T, int f, i64 bpp, double* C, i64 ldc)
 {
+    typedef Vec<W> V;
     const i64 parent = blockIdx.x / bpp;
     const i64 chunk = blockIdx.x - parent * bpp;
     const i64 rows = T.n[f + 1], cols = T.m[f + 1];
@@ -272,31 +305,45 @@ __global__ __launch_bounds__(256) void strassen_post2_kernel(StrassenTree T, int
     const i64 base = chunk * 256 * EPT + threadIdx.x;
 #pragma unroll 1
     for (int u = 0; u < EPT; ++u) {
-        const i64 e = base + u * 256;
+        const i64 e = (base + u * 256) * W;
         if (e >= sz) break;
         const i64 r = e / cols, c = e - r * cols;
-        double z[7][2][2];  // level-f product of child c1, its quadrant (qi, qj)
+        double z[7][2][2][W];  // level-f product of child c1, its quadrant (qi, qj), position k
 #pragma unroll
         for (int c1 = 0; c1 < 7; ++c1) {
-            double h[7];
+            typename V::T hv[7];
 #pragma unroll
-            for (int c2 = 0; c2 < 7; ++c2) h[c2] = H[(c1 * 7 + c2) * sz + e];
-            fold_products<VARIANT>(h, z[c1][0][0], z[c1][0][1], z[c1][1][0], z[c1][1][1]);
+            for (int c2 = 0; c2 < 7; ++c2) hv[c2] = V::ld(H + (c1 * 7 + c2) * sz + e);
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                double h[7];
+#pragma unroll
+                for (int c2 = 0; c2 < 7; ++c2) h[c2] = V::get(hv[c2], k);
+                fold_products<VARIANT>(h, z[c1][0][0][k], z[c1][0][1][k], z[c1][1][0][k], z[c1][1][1][k]);
+            }
         }
         double* o = out + r * ld + c;
 #pragma unroll
         for (int qi = 0; qi < 2; ++qi)
 #pragma unroll
             for (int qj = 0; qj < 2; ++qj) {
-                double h[7];
+                typename V::T c11, c12, c21, c22;
 #pragma unroll
-                for (int c1 = 0; c1 < 7; ++c1) h[c1] = z[c1][qi][qj];
-                double c11, c12, c21, c22;
-                fold_products<VARIANT>(h, c11, c12, c21, c22);
-                o[qi * rows * ld + qj * cols] = c11;
-                o[qi * rows * ld + (2 + qj) * cols] = c12;
-                o[(2 + qi) * rows * ld + qj * cols] = c21;
-                o[(2 + qi) * rows * ld + (2 + qj) * cols] = c22;
+                for (int k = 0; k < W; ++k) {
+                    double h[7];
+#pragma unroll
+                    for (int c1 = 0; c1 < 7; ++c1) h[c1] = z[c1][qi][qj][k];
+                    double v11, v12, v21, v22;
+                    fold_products<VARIANT>(h, v11, v12, v21, v22);
+                    V::set(c11, k, v11);
+                    V::set(c12, k, v12);
+                    V::set(c21, k, v21);
+                    V::set(c22, k, v22);
+                }
+                V::st(o + qi * rows * ld + qj * cols, c11);
+                V::st(o + qi * rows * ld + (2 + qj) * cols, c12);
+                V::st(o + (2 + qi) * rows * ld + qj * cols, c21);
+                V::st(o + (2 + qi) * rows * ld + (2 + qj) * cols, c22);
             }
     }
 }
@@ -355,23 +402,38 @@ hipError_t launch_strassen_post(const StrassenTree& T, int level, double* C, i64
 
 namespace mmm {
 
+// Two entries per position when every row length, stride and base the
+// fused passes touch at levels up to f + 1 is even and 16-byte aligned.
+bool strassen_pairs_ok(const StrassenTree& T, int f, const double* C, i64 ldc)
+{
+    auto al = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+    if (!al(T.A) || !al(T.B) || (T.lda & 1) || (T.ldb & 1)) return false;
+    if (C && (!al(C) || (ldc & 1))) return false;
+    for (int e = 1; e <= f + 1 && e <= T.depth; ++e)
+        if ((T.n[e] | T.p[e] | T.m[e]) & 1) return false;
+    return true;
+}
+
 hipError_t launch_strassen_pre2(const StrassenTree& T, int f, hipStream_t s)
 {
     const i64 parents = pow7(f - 1);
+    const bool pairs = strassen_pairs_ok(T, f, nullptr, 0);
     for (int side = 0; side < 2; ++side) {
         const i64 sz = side ? T.p[f + 1] * T.m[f + 1] : T.n[f + 1] * T.p[f + 1];
-        const i64 bpp = cdiv(sz, 256 * EPT);
+        const i64 bpp = cdiv(pairs ? sz / 2 : sz, 256 * EPT);
         const i64 blocks = parents * bpp;
         if (blocks == 0) continue;
         if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
         const dim3 g((unsigned)blocks), b(256);
-        if (T.variant == 0) {
-            if (side) hipLaunchKernelGGL((strassen_pre2_kernel<0, true>), g, b, 0, s, T, f, bpp);
-            else hipLaunchKernelGGL((strassen_pre2_kernel<0, false>), g, b, 0, s, T, f, bpp);
+#define MMM_PRE2(V, IB, W) hipLaunchKernelGGL((strassen_pre2_kernel<V, IB, W>), g, b, 0, s, T, f, bpp)
+        if (pairs) {
+            if (T.variant == 0) { if (side) MMM_PRE2(0, true, 2); else MMM_PRE2(0, false, 2); }
+            else { if (side) MMM_PRE2(1, true, 2); else MMM_PRE2(1, false, 2); }
         } else {
-            if (side) hipLaunchKernelGGL((strassen_pre2_kernel<1, true>), g, b, 0, s, T, f, bpp);
-            else hipLaunchKernelGGL((strassen_pre2_kernel<1, false>), g, b, 0, s, T, f, bpp);
+            if (T.variant == 0) { if (side) MMM_PRE2(0, true, 1); else MMM_PRE2(0, false, 1); }
+            else { if (side) MMM_PRE2(1, true, 1); else MMM_PRE2(1, false, 1); }
         }
+#undef MMM_PRE2
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -382,14 +444,19 @@ hipError_t launch_strassen_post2(const StrassenTree& T, int f, double* C, i64 ld
 {
     const i64 parents = pow7(f - 1);
     const i64 sz = T.n[f + 1] * T.m[f + 1];
-    const i64 bpp = cdiv(sz, 256 * EPT);
+    const bool pairs = strassen_pairs_ok(T, f, f - 1 >= 1 ? nullptr : C, ldc);
+    const i64 bpp = cdiv(pairs ? sz / 2 : sz, 256 * EPT);
     const i64 blocks = parents * bpp;
     if (blocks == 0) return hipSuccess;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    if (T.variant == 0)
-        hipLaunchKernelGGL((strassen_post2_kernel<0>), dim3((unsigned)blocks), dim3(256), 0, s, T, f, bpp, C, ldc);
-    else
-        hipLaunchKernelGGL((strassen_post2_kernel<1>), dim3((unsigned)blocks), dim3(256), 0, s, T, f, bpp, C, ldc);
+    const dim3 g((unsigned)blocks), b(256);
+    if (pairs) {
+        if (T.variant == 0) hipLaunchKernelGGL((strassen_post2_kernel<0, 2>), g, b, 0, s, T, f, bpp, C, ldc);
+        else hipLaunchKernelGGL((strassen_post2_kernel<1, 2>), g, b, 0, s, T, f, bpp, C, ldc);
+    } else {
+        if (T.variant == 0) hipLaunchKernelGGL((strassen_post2_kernel<0, 1>), g, b, 0, s, T, f, bpp, C, ldc);
+        else hipLaunchKernelGGL((strassen_post2_kernel<1, 1>), g, b, 0, s, T, f, bpp, C, ldc);
+    }
     return hipGetLastError();
 }
 
