@@ -121,7 +121,14 @@ mmm_status check_cfg(const mmm_config& c) { return mmm::check_config(c); }
 struct StrassenPlan {
     int depth = 0;
     bool direct_naive = false;  // paper rule gave k = 0: one naive product
+    bool direct_dgemm = false;  // peeling left no core: one DGEMM product
     bool pad = false;
+    // peeling (LEVELS mode, DGEMM leaf): the recursion runs on the leading
+    // Np x Pp x Mp core of the caller's operands, whose sizes are the largest
+    // multiples of its granularity; the leftover columns of A (rows of B),
+    // rows of A and columns of B are DGEMM products added or written
+    // afterwards
+    bool peel = false;
     bool naive_leaf = false;
     i64 Np = 0, Pp = 0, Mp = 0;
     i64 n[kMaxDepth + 1], p[kMaxDepth + 1], m[kMaxDepth + 1];
@@ -166,11 +173,24 @@ bool plan_strassen(i64 N, i64 P, i64 M, const mmm_config& c, StrassenPlan& pl)
         // of A and rows of B); the naive leaf keeps the 2^L rule, whose block
         // split defines its rounding
         const i64 qp = (!pl.naive_leaf && P >= 64 * q) ? 16 * q : q;
-        pl.Np = cdiv(N, q) * q;
-        pl.Pp = cdiv(P, qp) * qp;
-        pl.Mp = cdiv(M, q) * q;
+        if (!pl.naive_leaf) {
+            // peel instead of padding: the core is what the block split divides
+            pl.Np = N / q * q;
+            pl.Pp = P / qp * qp;
+            pl.Mp = M / q * q;
+            if (pl.Np == 0 || pl.Pp == 0 || pl.Mp == 0) {
+                pl.direct_dgemm = true;
+                return true;
+            }
+            pl.peel = pl.Np != N || pl.Pp != P || pl.Mp != M;
+        } else {
+            pl.Np = cdiv(N, q) * q;
+            pl.Pp = cdiv(P, qp) * qp;
+            pl.Mp = cdiv(M, q) * q;
+        }
     }
     pl.pad = pl.Np != N || pl.Pp != P || pl.Mp != M;
+    if (pl.peel) pl.pad = false;
     size_t off = 0;
     auto take = [&](double elems) -> size_t {
         const size_t at = off;
@@ -215,6 +235,7 @@ mmm_status run_strassen(int variant, const double* A, const double* B, double* C
 {
     hipError_t e;
     if (pl.direct_naive) return from_hip(launch_naive(Gemm{A, P, B, M, C, M, N, P, M}, false, s), "naive");
+    if (pl.direct_dgemm) return from_hip(launch_dgemm(Gemm{A, P, B, M, C, M, N, P, M}, s), "dgemm");
     StrassenTree T;
     memset(&T, 0, sizeof(T));
     T.variant = variant;
@@ -236,10 +257,15 @@ mmm_status run_strassen(int variant, const double* A, const double* B, double* C
         Croot = (double*)(ws + pl.off_C);
         ldc = pl.Mp;
     } else {
+        // the caller's operands (or, when peeling, their leading core): leaf
+        // operands that stay views of them need 16-byte aligned rows for the
+        // direct-load leaf product, else the sum passes copy them
         T.A = A;
         T.lda = P;
         T.B = B;
         T.ldb = M;
+        T.copy_leaf_views_a = !pl.naive_leaf && (((uintptr_t)A & 15) || (P & 1));
+        T.copy_leaf_views_b = !pl.naive_leaf && (((uintptr_t)B & 15) || (M & 1));
     }
     for (int d = 0; d <= pl.depth; ++d) {
         T.n[d] = pl.n[d];
@@ -274,6 +300,22 @@ mmm_status run_strassen(int variant, const double* A, const double* B, double* C
         }
     }
     if (pl.pad && (e = launch_pad_copy(Croot, ldc, N, M, C, M, N, M, s)) != hipSuccess) return from_hip(e, "extract C");
+    if (pl.peel) {
+        // C = A B over the peeled parts, with Nc, Pc, Mc the core sizes:
+        //   C[:Nc, :Mc] += A[:Nc, Pc:] B[Pc:, :Mc]   (the leftover inner terms)
+        //   C[:Nc, Mc:]  = A[:Nc, :] B[:, Mc:]       (the leftover columns)
+        //   C[Nc:, :]    = A[Nc:, :] B               (the leftover rows)
+        const i64 Nc = pl.Np, Pc = pl.Pp, Mc = pl.Mp;
+        if (Pc < P) {
+            Gemm g{A + Pc, P, B + Pc * M, M, C, M, Nc, P - Pc, Mc};
+            g.accumulate = 1;
+            if ((e = launch_dgemm(g, s)) != hipSuccess) return from_hip(e, "peeled inner terms");
+        }
+        if (Mc < M && (e = launch_dgemm(Gemm{A, P, B + Mc, M, C + Mc, M, Nc, P, M - Mc}, s)) != hipSuccess)
+            return from_hip(e, "peeled columns");
+        if (Nc < N && (e = launch_dgemm(Gemm{A + Nc * P, P, B, M, C + Nc * M, M, N - Nc, P, M}, s)) != hipSuccess)
+            return from_hip(e, "peeled rows");
+    }
     return MMM_OK;
 }
 

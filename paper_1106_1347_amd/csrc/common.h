@@ -28,6 +28,9 @@ struct Gemm {
     // operands are zero-padded copies, which lets the direct-load kernels
     // load a whole last K step (0 means P)
     i64 kcap;
+    // DGEMM kernels only: 1 = C <- C + A B (the product added to C with one
+    // rounding per entry) instead of C <- A B
+    int accumulate;
 };
 
 // A single product: every workgroup works on the same problem.
@@ -56,6 +59,10 @@ struct StrassenTree {
     i64 lda;
     const double* B;
     i64 ldb;
+    // leaf operands that are quadrant views of the root are instead written
+    // to their level slots (A side, B side): set when the root's rows are
+    // not 16-byte aligned, so the leaf product can still load them directly
+    bool copy_leaf_views_a, copy_leaf_views_b;
     i64 n[kMaxDepth + 1], p[kMaxDepth + 1], m[kMaxDepth + 1];
     double* WA[kMaxDepth + 1];
     double* WB[kMaxDepth + 1];
@@ -100,7 +107,8 @@ __device__ inline View strassen_operand(const StrassenTree& T, int d, i64 q, boo
         const int quad = is_b ? view_quadrant_b(T.variant, c) : view_quadrant_a(T.variant, c);
         const i64 rows = is_b ? T.p[e] : T.n[e];
         const i64 cols = is_b ? T.m[e] : T.p[e];
-        if (quad >= 0 && !virt) {
+        const bool copied = e == T.depth && (is_b ? T.copy_leaf_views_b : T.copy_leaf_views_a);
+        if (quad >= 0 && !virt && !copied) {
             v.p += (quad >> 1) * rows * v.ld + (quad & 1) * cols;
         } else if (e == T.fused) {
             virt = true;
@@ -124,7 +132,7 @@ struct StrassenLeafSrc {
         const int d = T.depth;
         View a = strassen_operand(T, d, q, false);
         View b = strassen_operand(T, d, q, true);
-        Gemm g;
+        Gemm g{};  // every field set: no kcap, no accumulation
         g.A = a.p;
         g.lda = a.ld;
         g.B = b.p;

@@ -169,7 +169,10 @@ struct DTile {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const i64 gm = m0 + wm * WMB * 16 + i * 16 + lk + 4 * r;
-                    if (gm < g.N) g.C[gm * g.ldc + gn] = acc[i][j][r];
+                    if (gm < g.N) {
+                        double* c = g.C + gm * g.ldc + gn;
+                        *c = g.accumulate ? *c + acc[i][j][r] : acc[i][j][r];
+                    }
                 }
             }
     }
@@ -399,9 +402,11 @@ hipError_t launch_dgemm_strassen_leaves(const StrassenLeafSrc& src, hipStream_t 
     const StrassenTree& T = src.T;
     const int d = T.depth;
     // every leaf operand is the root, a quadrant view or a dense slot: all
-    // leading dimensions and offsets stay even when these are
-    bool ok = MMM_DGEMM_DMA && T.n[d] % 128 == 0 && T.m[d] % 128 == 0 && T.p[d] % 16 == 0 && T.lda % 2 == 0 &&
-              T.ldb % 2 == 0 && aligned16(T.A) && aligned16(T.B);
+    // leading dimensions and offsets stay even when these are (views of a
+    // misaligned root are copied to their slots by the sum passes)
+    bool ok = MMM_DGEMM_DMA && T.n[d] % 128 == 0 && T.m[d] % 128 == 0 && T.p[d] % 16 == 0 &&
+              (T.copy_leaf_views_a || (T.lda % 2 == 0 && aligned16(T.A))) &&
+              (T.copy_leaf_views_b || (T.ldb % 2 == 0 && aligned16(T.B)));
     for (int e = 1; e <= d && ok; ++e)
         ok = T.p[e] % 2 == 0 && T.m[e] % 2 == 0 && aligned16(T.WA[e]) && aligned16(T.WB[e]);
     if (ok) return launch_dgemm_dma(src, T.n[d], T.m[d], s);

@@ -76,6 +76,15 @@ __global__ __launch_bounds__(256) void strassen_pre_kernel(StrassenTree T, int l
                 W[6 * sz + e] = x21 - b2;     // H7 = A22 (B21 - B2)
             }
         }
+        // leaves whose operand would be a misaligned view of the root get a copy
+        if (level == T.depth && (IS_B ? T.copy_leaf_views_b : T.copy_leaf_views_a)) {
+            const double xq[4] = {x11, x12, x21, x22};
+#pragma unroll
+            for (int c = 0; c < 7; ++c) {
+                const int quad = IS_B ? view_quadrant_b(VARIANT, c) : view_quadrant_a(VARIANT, c);
+                if (quad >= 0) W[c * sz + e] = xq[quad];
+            }
+        }
     }
 }
 
@@ -240,6 +249,8 @@ __global__ __launch_bounds__(256) void strassen_pre2_kernel(StrassenTree T, int 
     const i64 sz = rows * cols;
     double* W_ = (IS_B ? T.WB[f + 1] : T.WA[f + 1]) + parent * 49 * sz;
     const i64 base = chunk * 256 * EPT + threadIdx.x;
+    // leaves whose operand would be a misaligned view of the root get a copy
+    const bool copy_views = f + 1 == T.depth && (IS_B ? T.copy_leaf_views_b : T.copy_leaf_views_a);
 #pragma unroll 1
     for (int u = 0; u < EPT; ++u) {
         const i64 e = (base + u * 256) * W;
@@ -267,7 +278,7 @@ __global__ __launch_bounds__(256) void strassen_pre2_kernel(StrassenTree T, int 
 #pragma unroll
             for (int c2 = 0; c2 < 7; ++c2) {
                 const bool v2 = (IS_B ? view_quadrant_b(VARIANT, c2) : view_quadrant_a(VARIANT, c2)) >= 0;
-                if (v1 && v2) continue;  // a view of the node's own operand
+                if (v1 && v2 && !copy_views) continue;  // a view of the node's own operand
                 typename V::T o;
 #pragma unroll
                 for (int k = 0; k < W; ++k)

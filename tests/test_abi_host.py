@@ -75,26 +75,29 @@ def test_workspace_arithmetic(lib):
     assert ws("strassen_winograd", 4096, 4096, 4096, lib.Config(strassen_levels=3)) == 3 * (7 * n1 + 343 * n3)
     # one level: nothing fused
     assert ws("strassen_winograd", 4096, 4096, 4096, lib.Config(strassen_levels=1)) == 3 * 7 * n1
-    # P = 4097 pads to 4100; A, B, C padded copies come first
-    b = ws("strassen_winograd", 4096, 4097, 4096, cfg)
-    assert b > 3 * 49 * n2
     assert ws("strassen_naive", 0, 5, 5) == 0
-    # DGEMM leaf: P = 4097 is padded to a multiple of 16 * 2^L = 64 (4160), the
-    # naive leaf only to a multiple of 2^L (4100); both pad copies of A, B, C
-    def plan_bytes(Np, Pp, Mp, L):
+    # the naive leaf pads P = 4097 to a multiple of 2^L (4100), with padded
+    # copies of A, B, C first; the DGEMM leaf peels instead: the recursion
+    # runs on the leading 4096 (a multiple of 16 * 2^L) and the last column
+    # of A / row of B is a DGEMM product added afterwards, so no copies
+    def plan_bytes(Np, Pp, Mp, L, pad):
         al = lambda x: (x + 255) // 256 * 256
-        tot = al(8 * Np * Pp) + al(8 * Pp * Mp) + al(8 * Np * Mp)
+        tot = al(8 * Np * Pp) + al(8 * Pp * Mp) + al(8 * Np * Mp) if pad else 0
         for d in range(1, L + 1):
             if L >= 2 and d == L - 1:
                 continue  # the fused level
             n, p_, m = Np >> d, Pp >> d, Mp >> d
             tot += al(8 * 7 ** d * n * p_) + al(8 * 7 ** d * p_ * m) + al(8 * 7 ** d * n * m)
         return tot
-    assert b == plan_bytes(4096, 4160, 4096, 2)
+    assert ws("strassen_winograd", 4096, 4097, 4096, cfg) == plan_bytes(4096, 4096, 4096, 2, False) == 3 * 49 * n2
     assert ws("strassen_winograd", 4096, 4097, 4096, lib.Config(strassen_levels=2, strassen_leaf="naive")) == \
-        plan_bytes(4096, 4100, 4096, 2)
-    # small P keeps the 2^L rule for both leaves
-    assert ws("strassen_winograd", 64, 33, 64, lib.Config(strassen_levels=2)) == plan_bytes(64, 36, 64, 2)
+        plan_bytes(4096, 4100, 4096, 2, True)
+    # small P: the 2^L granularity for both leaves (pad 33 -> 36, peel to 32)
+    assert ws("strassen_winograd", 64, 33, 64, lib.Config(strassen_levels=2, strassen_leaf="naive")) == \
+        plan_bytes(64, 36, 64, 2, True)
+    assert ws("strassen_winograd", 64, 33, 64, lib.Config(strassen_levels=2)) == plan_bytes(64, 32, 64, 2, False)
+    # a core with no rows left (N < 2^L): one DGEMM product, no workspace
+    assert ws("strassen_winograd", 3, 5, 7, lib.Config(strassen_levels=2)) == 0
     with pytest.raises(ValueError):
         ws("dgemm", -1, 2, 2)
     # paper mode at X < 32 is a single naive product (no workspace)

@@ -450,3 +450,34 @@ def test_nonfinite_inputs_stay_in_their_rows(mmm, orc, n):
         else:
             err = orc.norm_inf(orc.minus(got[fin], ref[fin])) / (orc.norm_inf(A[[0, n - 1]]) * orc.norm_inf(B))
             assert err <= TOL_PLAIN
+
+
+@pytest.mark.parametrize("shape,L", [((517, 1031, 263), 2), ((2048, 4097, 2048), 2), ((1030, 777, 1025), 3),
+                                     ((300, 2049, 7), 1), ((3, 100, 9), 2)])
+def test_strassen_dgemm_leaf_peeling(mmm, orc, shape, L):
+    """The DGEMM leaf peels instead of padding (Section 2.4.1's embedding is
+    the alternative): the recursion runs on the leading block whose sizes
+    the block split divides, leftover rows, columns and inner terms are
+    DGEMM products added afterwards.  Odd sizes on every side (and a core
+    with no rows at all) stay within the Strassen tolerance and give the
+    exact product on integer data, also with operands 8 bytes off
+    alignment (leaf operands that would be views of the root are copied)."""
+    N, P, M = shape
+    print("case peel", shape, L, flush=True)
+    cfg = mmm.Config(strassen_levels=L)
+    A = synth.uniform((N, P), 61)
+    B = synth.uniform((P, M), 62)
+    ref = orc.naive(A, B)
+
+    def shifted(X):
+        flat = dev(np.concatenate([[0.0], X.ravel()]))
+        return flat[1:].view(*X.shape)
+
+    for name in ("strassen_winograd", "strassen_naive"):
+        assert relerr(orc, run(mmm, A, B, name, cfg), ref, A, B) <= TOL_STRASSEN, name
+        C = mmm.multiply(shifted(A), shifted(B), name, cfg)
+        torch.cuda.synchronize()
+        assert relerr(orc, C.cpu().numpy(), ref, A, B) <= TOL_STRASSEN, (name, "shifted")
+    Ai = synth.integers((N, P), 63)
+    Bi = synth.integers((P, M), 64)
+    assert np.array_equal(run(mmm, Ai, Bi, "strassen_winograd", cfg), Ai @ Bi)
