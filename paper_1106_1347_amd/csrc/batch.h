@@ -41,18 +41,21 @@ struct SplitJob {
     char* SA;
     char* SB;
     int runlen;   // recombination run length (depends on P)
+    int s;        // digits per operand
 };
 
 // Split tile variants a batch problem may request (mmm_problem.tile).
 enum SplitTile { SPLIT_TILE_AUTO = 0, SPLIT_TILE_WIDE = 1, SPLIT_TILE_NARROW = 2 };
 
-// Split jobs of one digit type and count, sharing one tile shape.
+// Split jobs of one digit count, accumulation scheme and tile shape (the
+// digit type and width are the batch config's).
 struct SplitGroup {
     int dt, s;
     int beta;     // digit width
     int unit;     // MFMA steps one digit pair may accumulate exactly
     int variant;  // 0: the wide tile, 1: the narrow one (half the rows)
     bool flush;
+    int ppa;      // without flushing: digit pairs per accumulator (s: one accumulator per group)
     int bm, bn;
     int per_cu;  // workgroups of the group's kernel resident per CU
 };
@@ -76,7 +79,6 @@ struct SplitTables {
     int nablocks;
     const JobBlock* bblocks;
     int nbblocks;
-    TileSchedule sched;  // of the digit GEMM's tiles
 };
 // Workgroups of the digit passes for one job (host and device agree).
 __host__ __device__ inline i64 split_a_blocks(const SplitJob& j) { return (j.Np * (j.Kp / 8) + 255) / 256; }
@@ -91,9 +93,13 @@ void split_job_bind(SplitJob& j, char* base, int dt, int s, int bits);
 // Host-side set-up of a group's kernels (dynamic LDS size); call once
 // before recording launches into a graph.
 hipError_t split_grouped_prepare(const SplitGroup& grp);
-// Enqueue the grouped split pipeline for `n` jobs (device table `jobs`),
-// tile prefix table `prefix` and the preprocessing work tables `tab`.
-hipError_t launch_split_grouped(const SplitGroup& grp, const SplitJob* jobs, int n, const i64* prefix,
-                                i64 total_tiles, const SplitTables& tab, bool scale_lambda, int grid, hipStream_t s);
+// Enqueue the preprocessing of `n` split jobs of any group (device table
+// `jobs`, work tables `tab` over it): norms and maxima, lambda, digits.
+hipError_t launch_split_prep(int dt, int beta, const SplitJob* jobs, int n, const SplitTables& tab, bool scale_lambda,
+                             hipStream_t s);
+// Enqueue the digit GEMM of one group's `n` jobs (device table `jobs`, tile
+// prefix `prefix`, schedule `sched`) on a persistent grid of `grid` workgroups.
+hipError_t launch_split_group_gemm(const SplitGroup& grp, const SplitJob* jobs, int n, const i64* prefix,
+                                   i64 total_tiles, TileSchedule sched, int grid, hipStream_t s);
 
 }  // namespace mmm

@@ -53,10 +53,10 @@ struct SGroup {
     std::vector<SplitJob> jobs;
     std::vector<size_t> ws_off;
     std::vector<i64> prefix;
-    std::vector<JobBlock> strips, ablocks, bblocks;
     std::vector<int> soff, slist;
     int grid = 0;
-    size_t off_jobs = 0, off_prefix = 0, off_strips = 0, off_ablocks = 0, off_bblocks = 0, off_soff = 0, off_slist = 0;
+    int first = 0;  // index of the group's first job in the plan's job table
+    size_t off_prefix = 0, off_soff = 0, off_slist = 0;
 };
 
 struct Interval {
@@ -141,7 +141,7 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
 
     // grouping
     std::map<int, DGroup> dg;
-    std::map<std::tuple<int, int, bool, int>, SGroup> sg;
+    std::map<std::tuple<int, int, bool, int, int>, SGroup> sg;
     size_t split_ws = 0;
     for (int i = 0; i < count; ++i) {
         const mmm_problem& p = problems[i];
@@ -158,7 +158,7 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
             const int variant = p.tile == SPLIT_TILE_NARROW ? 1 : 0;
             const size_t bytes = split_job_bytes(p.N, p.P, p.M, c.split_type, s, c.split_bits, variant, grp, Np, Mp, Kp);
             if (bytes == (size_t)-1) return bfail(MMM_EUNSUPPORTED, "problem %d: split configuration", i);
-            SGroup& g = sg[std::make_tuple(grp.dt, grp.s, grp.flush, grp.variant)];
+            SGroup& g = sg[std::make_tuple(grp.dt, grp.s, grp.flush, grp.variant, grp.ppa)];
             g.g = grp;
             SplitJob j;
             memset(&j, 0, sizeof(j));
@@ -209,25 +209,34 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
         g.off_soff = take(sizeof(int) * g.soff.size());
         g.off_slist = take(sizeof(int) * (g.slist.size() ? g.slist.size() : 1));
     }
+    // every split job of every group in one table (group by group), with
+    // one set of preprocessing work tables over it: statistics strips of 64
+    // rows of every job's A and B, then the digit passes' workgroups
+    std::vector<JobBlock> strips, ablocks, bblocks;
+    int njobs = 0;
+    for (auto& kv : sg) {
+        SGroup& g = kv.second;
+        g.first = njobs;
+        for (size_t k = 0; k < g.jobs.size(); ++k) {
+            const SplitJob& j = g.jobs[k];
+            const int id = njobs + (int)k;
+            for (i64 r = 0; r < j.N; r += kStatRows) strips.push_back(JobBlock{id, 0, r});
+            for (i64 r = 0; r < j.P; r += kStatRows) strips.push_back(JobBlock{id, 1, r});
+            for (i64 b = 0, nb = split_a_blocks(j); b < nb; ++b) ablocks.push_back(JobBlock{id, 0, b});
+            for (i64 b = 0, nb = split_b_blocks(j); b < nb; ++b) bblocks.push_back(JobBlock{id, 1, b});
+        }
+        njobs += (int)g.jobs.size();
+    }
+    if (strips.size() > 0x7fffffffu || ablocks.size() > 0x7fffffffu || bblocks.size() > 0x7fffffffu)
+        return bfail(MMM_EUNSUPPORTED, "batch: split problems too large for one plan");
+    const size_t off_jobs = take(sizeof(SplitJob) * (size_t)njobs);
+    const size_t off_strips = take(sizeof(JobBlock) * strips.size());
+    const size_t off_ablocks = take(sizeof(JobBlock) * ablocks.size());
+    const size_t off_bblocks = take(sizeof(JobBlock) * bblocks.size());
     for (auto& kv : sg) {
         SGroup& g = kv.second;
         g.prefix.assign(g.jobs.size() + 1, 0);
-        // preprocessing work: statistics strips of 64 rows of every job's A
-        // and B, then the digit passes' workgroups
-        for (size_t k = 0; k < g.jobs.size(); ++k) {
-            const SplitJob& j = g.jobs[k];
-            for (i64 r = 0; r < j.N; r += kStatRows) g.strips.push_back(JobBlock{(int)k, 0, r});
-            for (i64 r = 0; r < j.P; r += kStatRows) g.strips.push_back(JobBlock{(int)k, 1, r});
-            for (i64 b = 0, nb = split_a_blocks(j); b < nb; ++b) g.ablocks.push_back(JobBlock{(int)k, 0, b});
-            for (i64 b = 0, nb = split_b_blocks(j); b < nb; ++b) g.bblocks.push_back(JobBlock{(int)k, 1, b});
-        }
-        if (g.strips.size() > 0x7fffffffu || g.ablocks.size() > 0x7fffffffu || g.bblocks.size() > 0x7fffffffu)
-            return bfail(MMM_EUNSUPPORTED, "batch: split problems too large for one plan");
-        g.off_jobs = take(sizeof(SplitJob) * g.jobs.size());
         g.off_prefix = take(sizeof(i64) * g.prefix.size());
-        g.off_strips = take(sizeof(JobBlock) * g.strips.size());
-        g.off_ablocks = take(sizeof(JobBlock) * g.ablocks.size());
-        g.off_bblocks = take(sizeof(JobBlock) * g.bblocks.size());
         std::vector<i64> cost;  // K blocks of 64 plus the fixed cost of a tile
         for (size_t k = 0; k < g.jobs.size(); ++k) {
             // row tiles over N only: the padded rows of the digit layout
@@ -265,12 +274,13 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
         memcpy(host.data() + kv.second.off_soff, kv.second.soff.data(), sizeof(int) * kv.second.soff.size());
         memcpy(host.data() + kv.second.off_slist, kv.second.slist.data(), sizeof(int) * kv.second.slist.size());
     }
+    memcpy(host.data() + off_strips, strips.data(), sizeof(JobBlock) * strips.size());
+    memcpy(host.data() + off_ablocks, ablocks.data(), sizeof(JobBlock) * ablocks.size());
+    memcpy(host.data() + off_bblocks, bblocks.data(), sizeof(JobBlock) * bblocks.size());
     for (auto& kv : sg) {
-        memcpy(host.data() + kv.second.off_jobs, kv.second.jobs.data(), sizeof(SplitJob) * kv.second.jobs.size());
+        memcpy(host.data() + off_jobs + sizeof(SplitJob) * (size_t)kv.second.first, kv.second.jobs.data(),
+               sizeof(SplitJob) * kv.second.jobs.size());
         memcpy(host.data() + kv.second.off_prefix, kv.second.prefix.data(), sizeof(i64) * kv.second.prefix.size());
-        memcpy(host.data() + kv.second.off_strips, kv.second.strips.data(), sizeof(JobBlock) * kv.second.strips.size());
-        memcpy(host.data() + kv.second.off_ablocks, kv.second.ablocks.data(), sizeof(JobBlock) * kv.second.ablocks.size());
-        memcpy(host.data() + kv.second.off_bblocks, kv.second.bblocks.data(), sizeof(JobBlock) * kv.second.bblocks.size());
         memcpy(host.data() + kv.second.off_soff, kv.second.soff.data(), sizeof(int) * kv.second.soff.size());
         memcpy(host.data() + kv.second.off_slist, kv.second.slist.data(), sizeof(int) * kv.second.slist.size());
     }
@@ -295,19 +305,21 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
     if (e == hipSuccess) {
         hipError_t le = hipEventRecord(fork, cap);
         if (le == hipSuccess) le = hipStreamWaitEvent(side, fork, 0);
+        const SplitJob* jobs = (const SplitJob*)(base + off_jobs);
+        if (le == hipSuccess && njobs > 0) {
+            const SplitTables tab{(const JobBlock*)(base + off_strips), (int)strips.size(),
+                                  (const JobBlock*)(base + off_ablocks), (int)ablocks.size(),
+                                  (const JobBlock*)(base + off_bblocks), (int)bblocks.size()};
+            const SplitGroup& g0 = sg.begin()->second.g;
+            le = launch_split_prep(g0.dt, g0.beta, jobs, njobs, tab, c.split_scale_lambda != 0, side);
+        }
         for (auto& kv : sg) {
             if (le != hipSuccess) break;
             SGroup& g = kv.second;
-            const SplitTables tab{(const JobBlock*)(base + g.off_strips),
-                                  (int)g.strips.size(),
-                                  (const JobBlock*)(base + g.off_ablocks),
-                                  (int)g.ablocks.size(),
-                                  (const JobBlock*)(base + g.off_bblocks),
-                                  (int)g.bblocks.size(),
-                                  TileSchedule{(const int*)(base + g.off_soff), (const int*)(base + g.off_slist)}};
-            le = launch_split_grouped(g.g, (const SplitJob*)(base + g.off_jobs), (int)g.jobs.size(),
-                                      (const i64*)(base + g.off_prefix), g.prefix.back(), tab,
-                                      c.split_scale_lambda != 0, g.grid, side);
+            le = launch_split_group_gemm(g.g, jobs + g.first, (int)g.jobs.size(), (const i64*)(base + g.off_prefix),
+                                         g.prefix.back(), TileSchedule{(const int*)(base + g.off_soff),
+                                                                       (const int*)(base + g.off_slist)},
+                                         g.grid, side);
         }
         for (auto& kv : dg) {
             if (le != hipSuccess) break;

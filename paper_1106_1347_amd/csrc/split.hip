@@ -144,10 +144,12 @@ __host__ __device__ constexpr TileCfg narrow_cfg(TileCfg t)
 {
     return t.wbm > 1 ? TileCfg{t.wbm / 2, t.minw < 2 ? 2 : t.minw, t.nw, t.stages} : t;
 }
-__host__ __device__ constexpr TileCfg grouped_tile_cfg(int dt, int s, bool flush, int variant = 0)
+__host__ __device__ constexpr TileCfg grouped_tile_cfg(int dt, int s, bool flush, int variant = 0, int ppa = 8)
 {
-    return variant == 1 ? narrow_cfg(grouped_tile_cfg(dt, s, flush, 0))
-                        : (!flush ? (s <= 7 ? TileCfg{4, 2, 4, 2} : TileCfg{2, 2, 4, 2})
+    // ppa < s: accumulators per pair subgroup (no flushing), up to s(s+1)/2
+    // per output, so the tile keeps two row blocks per wave
+    return variant == 1 ? narrow_cfg(grouped_tile_cfg(dt, s, flush, 0, ppa))
+                        : (!flush ? (ppa < s ? TileCfg{2, 2, 4, 2} : (s <= 7 ? TileCfg{4, 2, 4, 2} : TileCfg{2, 2, 4, 2}))
                                   : (s >= 4 ? TileCfg{2, 1, 4, 2} : tile_cfg(dt, s, flush)));
 }
 
@@ -379,7 +381,15 @@ __device__ __forceinline__ void sched_digit_pairs()
 // accumulating into group t + u.  Both MFMAs used take lane l's operand
 // as row (A) / column (B) l % 16 and bytes 16 (l / 16) .. 16 (l / 16) + 15
 // of the K block; result element r of lane l is D[4 (l / 16) + r][l % 16].
-template <int DT, int S, bool FLUSH, int WBM, int NW, int NST>
+// Accumulators without flushing for products whose K is too long for a
+// whole group in one accumulator but short enough for PPA pairs: group g's
+// g + 1 pairs are spread over ceil((g + 1) / PPA) accumulators (pair (t, u)
+// in the (t / PPA)-th), each holding at most PPA pairs' products of the
+// whole K.  PPA >= S is one accumulator per group.
+constexpr int subs_of(int g, int ppa) { return (g + ppa) / ppa; }
+constexpr int acc_base(int g, int ppa) { return g == 0 ? 0 : acc_base(g - 1, ppa) + subs_of(g - 1, ppa); }
+
+template <int DT, int S, bool FLUSH, int WBM, int NW, int NST, int PPA = S>
 __device__ __forceinline__ void split_tile(const char* __restrict__ SA, const char* __restrict__ SB,
                                            const int* __restrict__ ea, const int* __restrict__ fb,
                                            double* __restrict__ C, i64 N, i64 M, i64 Np, i64 Mp, i64 Kp, i64 tm,
@@ -398,17 +408,21 @@ __device__ __forceinline__ void split_tile(const char* __restrict__ SA, const ch
     const i64 steps = Kp * D::esize / KB;
     const i64 plane_a = Np * KB, plane_b = Mp * KB;  // bytes of one digit plane of one K block
 
-    acc_t acc[G][WBM];
+    static_assert(!FLUSH || PPA >= S, "flushing keeps one accumulator per group");
+    constexpr int NACC = acc_base(G, PPA);
+    acc_t acc[NACC][WBM];
     double acc64[FLUSH ? G : 1][FLUSH ? WBM : 1][4];
 #pragma unroll
-    for (int g = 0; g < G; ++g)
+    for (int g = 0; g < NACC; ++g)
 #pragma unroll
-        for (int i = 0; i < WBM; ++i) {
-            acc[g][i] = (acc_t){0, 0, 0, 0};
-            if (FLUSH)
+        for (int i = 0; i < WBM; ++i) acc[g][i] = (acc_t){0, 0, 0, 0};
+    if (FLUSH)
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int i = 0; i < WBM; ++i)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) acc64[g][i][r] = 0.0;
-        }
 
     // per-lane byte offsets (32 bits) from wave-uniform bases: the loads
     // take a scalar base plus a vector offset, so no 64-bit per-lane
@@ -481,7 +495,10 @@ __device__ __forceinline__ void split_tile(const char* __restrict__ SA, const ch
             for (int i = 0; i < WBM; ++i) {
                 const u32x4 a = *reinterpret_cast<const u32x4*>(la + (t * WBM + i) * 1024);
 #pragma unroll
-                for (int u = 0; u + t < S; ++u) acc[t + u][i] = Mfma<DT>::run(a, bring[J][u], acc[t + u][i]);
+                for (int u = 0; u + t < S; ++u) {
+                    const int k = acc_base(t + u, PPA) + t / PPA;
+                    acc[k][i] = Mfma<DT>::run(a, bring[J][u], acc[k][i]);
+                }
             }
         if (MMM_SPLIT_SCHED > 0 && S >= MMM_SPLIT_SCHED) sched_digit_pairs<S, WBM>();
         if (FLUSH) {
@@ -519,7 +536,10 @@ __device__ __forceinline__ void split_tile(const char* __restrict__ SA, const ch
             int pos = 0;
 #pragma unroll
             for (int g = G - 1; g >= 0; --g) {
-                const double Gg = FLUSH ? acc64[g][i][r] + (double)acc[g][i][r] : (double)acc[g][i][r];
+                double Gg = FLUSH ? acc64[g][i][r] + (double)acc[g][i][r] : (double)acc[acc_base(g, PPA)][i][r];
+                // the other accumulators of the group (exact integers: exact sums)
+#pragma unroll
+                for (int k = 1; k < subs_of(g, PPA); ++k) Gg = Gg + (double)acc[acc_base(g, PPA) + k][i][r];
                 T = pos == 0 ? Gg : T + Gg * ldexp(1.0, beta * pos);
                 if (pos == runlen - 1 || g == 0) {
                     c = c + ldexp(T, -beta * (g + pos + 2));
@@ -816,14 +836,14 @@ __global__ __launch_bounds__(tile_cfg(DT, S, FLUSH).threads(), tile_cfg(DT, S, F
 // Persistent grid over the tiles of a group of split jobs (same digit type,
 // count and tile variant): tile t is job p's (t - prefix[p])-th tile,
 // row-major over ceil(N / BM) x (Mp / BN) tiles.
-template <int DT, int S, bool FLUSH, int V>
-__global__ __launch_bounds__(grouped_tile_cfg(DT, S, FLUSH, V).threads(), grouped_tile_cfg(DT, S, FLUSH, V).minw) void split_gemm_grouped_kernel(const SplitJob* __restrict__ jobs,
+template <int DT, int S, bool FLUSH, int V, int PPA>
+__global__ __launch_bounds__(grouped_tile_cfg(DT, S, FLUSH, V, PPA).threads(), grouped_tile_cfg(DT, S, FLUSH, V, PPA).minw) void split_gemm_grouped_kernel(const SplitJob* __restrict__ jobs,
                                                                  const i64* __restrict__ prefix, int njobs,
                                                                  int beta, int unit, const int* __restrict__ soff,
                                                                  const int* __restrict__ slist)
 {
     extern __shared__ __align__(16) char lds[];
-    constexpr TileCfg TC = grouped_tile_cfg(DT, S, FLUSH, V);
+    constexpr TileCfg TC = grouped_tile_cfg(DT, S, FLUSH, V, PPA);
     for (int q = soff[blockIdx.x]; q < soff[blockIdx.x + 1]; ++q) {
         const i64 t = slist[q];
         int lo = 0, hi = njobs - 1;
@@ -835,7 +855,7 @@ __global__ __launch_bounds__(grouped_tile_cfg(DT, S, FLUSH, V).threads(), groupe
         const SplitJob& j = jobs[lo];
         const i64 local = t - prefix[lo];
         const i64 tiles_n = j.Mp / TC.bn();
-        split_tile<DT, S, FLUSH, TC.wbm, TC.nw, TC.stages>(j.SA, j.SB, j.ea, j.fb, j.C, j.N, j.M, j.Np, j.Mp, j.Kp, local / tiles_n,
+        split_tile<DT, S, FLUSH, TC.wbm, TC.nw, TC.stages, PPA>(j.SA, j.SB, j.ea, j.fb, j.C, j.N, j.M, j.Np, j.Mp, j.Kp, local / tiles_n,
                                  local % tiles_n, beta, unit, j.runlen, lds);
         __syncthreads();
     }
@@ -1072,7 +1092,7 @@ __global__ void jobs_lambda_kernel(const SplitJob* jobs, int n)
 template <int DT>
 __global__ __launch_bounds__(256) void jobs_split_ab_kernel(const SplitJob* __restrict__ jobs,
                                                             const JobBlock* __restrict__ ablocks, i64 na,
-                                                            const JobBlock* __restrict__ bblocks, int s, int beta,
+                                                            const JobBlock* __restrict__ bblocks, int beta,
                                                             bool scaled)
 {
     __shared__ double T[64][65];
@@ -1080,12 +1100,12 @@ __global__ __launch_bounds__(256) void jobs_split_ab_kernel(const SplitJob* __re
     if (w < na) {
         const JobBlock b = ablocks[w];
         const SplitJob& j = jobs[b.job];
-        split_a_body<DT>(j.A, j.N, j.P, j.Np, j.Kp, j.rmax, scaled ? j.lam : nullptr, s, beta, j.SA, j.ea, b.index,
+        split_a_body<DT>(j.A, j.N, j.P, j.Np, j.Kp, j.rmax, scaled ? j.lam : nullptr, j.s, beta, j.SA, j.ea, b.index,
                          split_a_blocks(j), true);
     } else {
         const JobBlock b = bblocks[w - na];
         const SplitJob& j = jobs[b.job];
-        split_b_body<DT>(j.B, j.P, j.M, j.Mp, j.Kp, j.cmax, scaled ? j.lam : nullptr, s, beta, j.SB, j.fb, b.index,
+        split_b_body<DT>(j.B, j.P, j.M, j.Mp, j.Kp, j.cmax, scaled ? j.lam : nullptr, j.s, beta, j.SB, j.fb, b.index,
                          T, true);
     }
 }
@@ -1291,32 +1311,37 @@ hipError_t run_split_dt(const double* A, const double* B, double* C, i64 N, i64 
     return e;
 }
 
-template <int DT, int S, bool FLUSH, int V>
+template <int DT, int S, bool FLUSH, int V, int PPA>
 hipError_t launch_grouped_gemm(const SplitJob* jobs, const i64* prefix, int n, int beta, int unit, int grid,
                                TileSchedule sch, hipStream_t st)
 {
-    constexpr TileCfg TC = grouped_tile_cfg(DT, S, FLUSH, V);
+    constexpr TileCfg TC = grouped_tile_cfg(DT, S, FLUSH, V, PPA);
     const size_t lds = split_lds_bytes(TC, S);
-    auto kern = split_gemm_grouped_kernel<DT, S, FLUSH, V>;
+    auto kern = split_gemm_grouped_kernel<DT, S, FLUSH, V, PPA>;
     if (!jobs) return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(TC.threads()), lds, st, jobs, prefix, n, beta, unit, sch.off, sch.list);
     return hipGetLastError();
 }
 
-template <int DT, int S, bool FLUSH>
+template <int DT, int S, bool FLUSH, int PPA>
 hipError_t grouped_variant(const SplitGroup& g, const SplitJob* jobs, const i64* prefix, int n, int grid,
                            TileSchedule sch, hipStream_t st)
 {
-    if (g.variant == 1) return launch_grouped_gemm<DT, S, FLUSH, 1>(jobs, prefix, n, g.beta, g.unit, grid, sch, st);
-    return launch_grouped_gemm<DT, S, FLUSH, 0>(jobs, prefix, n, g.beta, g.unit, grid, sch, st);
+    if (g.variant == 1) return launch_grouped_gemm<DT, S, FLUSH, 1, PPA>(jobs, prefix, n, g.beta, g.unit, grid, sch, st);
+    return launch_grouped_gemm<DT, S, FLUSH, 0, PPA>(jobs, prefix, n, g.beta, g.unit, grid, sch, st);
 }
 
 template <int DT, int S>
 hipError_t grouped_flush(const SplitGroup& g, const SplitJob* jobs, const i64* prefix, int n, int grid,
                          TileSchedule sch, hipStream_t st)
 {
-    if (g.flush) return grouped_variant<DT, S, true>(g, jobs, prefix, n, grid, sch, st);
-    return grouped_variant<DT, S, false>(g, jobs, prefix, n, grid, sch, st);
+    if (g.flush) return grouped_variant<DT, S, true, S>(g, jobs, prefix, n, grid, sch, st);
+    // pair-subgroup accumulators: 16-bit digits only (int8 never needs them)
+    if constexpr (DT != DT_INT8 && S > 2) {
+        if (g.ppa == 2) return grouped_variant<DT, S, false, 2>(g, jobs, prefix, n, grid, sch, st);
+        if (g.ppa == 1) return grouped_variant<DT, S, false, 1>(g, jobs, prefix, n, grid, sch, st);
+    }
+    return grouped_variant<DT, S, false, S>(g, jobs, prefix, n, grid, sch, st);
 }
 
 template <int DT>
@@ -1337,8 +1362,8 @@ hipError_t grouped_s(const SplitGroup& g, const SplitJob* jobs, const i64* prefi
 }
 
 template <int DT>
-hipError_t launch_split_grouped_dt(const SplitGroup& g, const SplitJob* jobs, int n, const i64* prefix, i64 total,
-                                   const SplitTables& tab, bool scale, int grid, hipStream_t st)
+hipError_t launch_split_prep_dt(const SplitJob* jobs, int n, const SplitTables& tab, bool scale, int beta,
+                                hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     hipError_t e;
@@ -1356,9 +1381,8 @@ hipError_t launch_split_grouped_dt(const SplitGroup& g, const SplitJob* jobs, in
     if (nab > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     if (nab > 0)
         hipLaunchKernelGGL(jobs_split_ab_kernel<DT>, dim3((unsigned)nab), blk, 0, st, jobs,
-                           tab.ablocks, (i64)tab.nablocks, tab.bblocks, g.s, g.beta, scale);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    return total > 0 ? grouped_s<DT>(g, jobs, prefix, n, grid, tab.sched, st) : hipSuccess;
+                           tab.ablocks, (i64)tab.nablocks, tab.bblocks, beta, scale);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -1397,13 +1421,22 @@ size_t split_job_bytes(i64 N, i64 P, i64 M, int dt, int s, int bits, int variant
     c.split_bits = bits;
     SplitLayout L;
     if (!split_layout(N, P, M, c, L)) return (size_t)-1;
-    const TileCfg tc = grouped_tile_cfg(dt, s, L.flush, variant);
+    // K too long for a whole group per accumulator but short enough for two
+    // pairs (or one) of 16-bit digits: pair-subgroup accumulators instead of
+    // flushing (the tiles of a batch have short K)
+    grp.ppa = s;
+    grp.flush = L.flush;
+    if (L.flush && dt != DT_INT8 && s > 2) {
+        const i64 steps = L.Kp / Digit<DT_BF16>::mfma_k;
+        if (2 * steps <= L.unit) grp.ppa = 2, grp.flush = false;
+        else if (steps <= L.unit) grp.ppa = 1, grp.flush = false;
+    }
+    const TileCfg tc = grouped_tile_cfg(dt, s, grp.flush, variant, grp.ppa);
     grp.dt = dt;
     grp.s = s;
     grp.beta = L.beta;
     grp.unit = L.unit;
     grp.variant = variant;
-    grp.flush = L.flush;
     grp.bm = tc.bm();
     grp.bn = tc.bn();
     grp.per_cu = tc.minw * 4 / tc.nw > 0 ? tc.minw * 4 / tc.nw : 1;
@@ -1415,6 +1448,7 @@ size_t split_job_bytes(i64 N, i64 P, i64 M, int dt, int s, int bits, int variant
 
 void split_job_bind(SplitJob& j, char* base, int dt, int s, int bits)
 {
+    j.s = s;
     mmm_config c = mmm_config_default();
     c.split_type = dt;
     c.split_slices = s;
@@ -1447,13 +1481,25 @@ hipError_t split_grouped_prepare(const SplitGroup& g)
     }
 }
 
-hipError_t launch_split_grouped(const SplitGroup& grp, const SplitJob* jobs, int n, const i64* prefix,
-                                i64 total_tiles, const SplitTables& tab, bool scale_lambda, int grid, hipStream_t s)
+hipError_t launch_split_prep(int dt, int beta, const SplitJob* jobs, int n, const SplitTables& tab, bool scale_lambda,
+                             hipStream_t s)
 {
+    switch (dt) {
+    case DT_BF16: return launch_split_prep_dt<DT_BF16>(jobs, n, tab, scale_lambda, beta, s);
+    case DT_FP16: return launch_split_prep_dt<DT_FP16>(jobs, n, tab, scale_lambda, beta, s);
+    case DT_INT8: return launch_split_prep_dt<DT_INT8>(jobs, n, tab, scale_lambda, beta, s);
+    default: return hipErrorNotSupported;
+    }
+}
+
+hipError_t launch_split_group_gemm(const SplitGroup& grp, const SplitJob* jobs, int n, const i64* prefix,
+                                   i64 total_tiles, TileSchedule sched, int grid, hipStream_t s)
+{
+    if (n <= 0 || total_tiles <= 0) return hipSuccess;
     switch (grp.dt) {
-    case DT_BF16: return launch_split_grouped_dt<DT_BF16>(grp, jobs, n, prefix, total_tiles, tab, scale_lambda, grid, s);
-    case DT_FP16: return launch_split_grouped_dt<DT_FP16>(grp, jobs, n, prefix, total_tiles, tab, scale_lambda, grid, s);
-    case DT_INT8: return launch_split_grouped_dt<DT_INT8>(grp, jobs, n, prefix, total_tiles, tab, scale_lambda, grid, s);
+    case DT_BF16: return grouped_s<DT_BF16>(grp, jobs, prefix, n, grid, sched, s);
+    case DT_FP16: return grouped_s<DT_FP16>(grp, jobs, prefix, n, grid, sched, s);
+    case DT_INT8: return grouped_s<DT_INT8>(grp, jobs, prefix, n, grid, sched, s);
     default: return hipErrorNotSupported;
     }
 }
