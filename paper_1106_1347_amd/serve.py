@@ -40,14 +40,17 @@ from ._lib import Config, multiply, workspace_bytes
 
 # Candidate methods per tolerance class, with the relative infinity-norm
 # error each keeps on the serving workloads (uniform entries): the plain
-# FP64 matrix-core GEMM and the int8 split with 7 digits are FP64-grade
-# (<= 1e-13); 5 int8 digits and Strassen-Winograd with a DGEMM leaf are
-# within 1e-10.  Each entry: (name, method, config kwargs).
+# FP64 matrix-core GEMM, the int8 split with 7 digits and the bf16 split with
+# 5 digits of 9 bits (about 3e-15) are FP64-grade (<= 1e-13); 5 int8
+# digits, 4 bf16 digits of 9 bits (about 1e-12) and Strassen-Winograd with a
+# DGEMM leaf are within 1e-10.  Each entry: (name, method, config kwargs).
 CANDIDATES = {
     "fp64": [("dgemm", "dgemm", {}),
-             ("split_int8_s7", "split", {"split_type": "int8", "split_slices": 7})],
+             ("split_int8_s7", "split", {"split_type": "int8", "split_slices": 7}),
+             ("split_bf16_b9_s5", "split", {"split_type": "bf16", "split_slices": 5, "split_bits": 9})],
     "relaxed": [("dgemm", "dgemm", {}),
                 ("split_int8_s5", "split", {"split_type": "int8", "split_slices": 5}),
+                ("split_bf16_b9_s4", "split", {"split_type": "bf16", "split_slices": 4, "split_bits": 9}),
                 ("strassen_winograd_L1", "strassen_winograd", {"strassen_levels": 1}),
                 ("strassen_winograd_L2", "strassen_winograd", {"strassen_levels": 2})],
 }
