@@ -169,9 +169,9 @@ bool plan_strassen(i64 N, i64 P, i64 M, const mmm_config& c, StrassenPlan& pl)
         const i64 q = (i64)1 << pl.depth;
         pl.naive_leaf = c.strassen_leaf == MMM_LEAF_NAIVE;
         // the DGEMM leaf takes its direct-load path when the leaf depth is a
-        // multiple of 16: pad P to a multiple of 16 2^L for it (zero columns
-        // of A and rows of B); the naive leaf keeps the 2^L rule, whose block
-        // split defines its rounding
+        // multiple of 16, so its core P is a multiple of 16 2^L (for P of at
+        // least 64 2^L); the naive leaf pads every side to a multiple of 2^L
+        // (zero rows and columns), the block split that defines its rounding
         const i64 qp = (!pl.naive_leaf && P >= 64 * q) ? 16 * q : q;
         if (!pl.naive_leaf) {
             // peel instead of padding: the core is what the block split divides
