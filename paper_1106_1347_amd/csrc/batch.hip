@@ -1,16 +1,18 @@
 // Batches of independent products (mmm_batch_*): one plan, one HIP graph.
 //
 // The plan groups the FP64 problems by DGEMM tile shape and the split
-// problems by (digit type, digit count, flush scheme); every group runs as
-// one persistent kernel over a grid sized to the chip, each workgroup
-// walking a tile list balanced here (longest tiles first, each to the
-// least-loaded workgroup), preceded for split groups by batched preprocessing kernels:
-// one pass over every 64-row strip of every problem's A and B for the
-// norms and row/column maxima (a strip table built here), lambda, and digit
-// extraction (blockIdx.y selects the problem).  The FP64 groups and the split groups are recorded
-// on two branches of one HIP graph, so they overlap on the device.  A
-// tile's arithmetic does not depend on the tile shape or on which workgroup
-// runs it, so every result equals the single-call result bit for bit.
+// problems by (digit type, digit count, flush scheme, tile variant,
+// accumulator scheme); every group runs as one persistent kernel over a
+// grid sized to the chip, each workgroup walking a tile list balanced here
+// (longest tiles first, each to the least-loaded workgroup).  All split
+// jobs share one preprocessing chain: one pass over every 64-row strip of
+// every problem's A and B for the norms and row/column maxima (a strip
+// table built here), lambda, and one digit pass over tables of row chunks
+// and column tiles.  The FP64 groups run on one branch of one HIP graph,
+// the split preprocessing on another, which then forks into one branch per
+// split group, so all of them overlap on the device.  A tile's arithmetic
+// does not depend on the tile shape or on which workgroup runs it, so every
+// result equals the single-call result bit for bit.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -291,16 +293,30 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
     for (auto& kv : sg)
         if (e == hipSuccess) e = split_grouped_prepare(kv.second.g);
 
-    // record the launch sequence: split groups on a forked branch, recorded
-    // first so their short memory-bound preprocessing kernels are dispatched
-    // before the persistent FP64 kernels take every workgroup slot; FP64
-    // groups on the capture stream
+    // record the launch sequence: the split branch forked first, so its
+    // short memory-bound preprocessing kernels are dispatched before the
+    // persistent FP64 kernels take every workgroup slot; after the shared
+    // preprocessing each split group's GEMM on a branch of its own (largest
+    // first), so the small groups run beside the large one instead of after
+    // it; FP64 groups on the capture stream
+    std::vector<SGroup*> order;
+    for (auto& kv : sg) order.push_back(&kv.second);
+    std::stable_sort(order.begin(), order.end(),
+                     [](const SGroup* a, const SGroup* b) { return a->prefix.back() > b->prefix.back(); });
+    const size_t nbr = order.empty() ? 0 : order.size() - 1;  // extra split branches
     hipStream_t cap = nullptr, side = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr, prepped = nullptr;
+    std::vector<hipStream_t> br(nbr, nullptr);
+    std::vector<hipEvent_t> brj(nbr, nullptr);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&prepped, hipEventDisableTiming);
+    for (size_t i = 0; i < nbr && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&brj[i], hipEventDisableTiming);
+    }
     if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         hipError_t le = hipEventRecord(fork, cap);
@@ -313,13 +329,19 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
             const SplitGroup& g0 = sg.begin()->second.g;
             le = launch_split_prep(g0.dt, g0.beta, jobs, njobs, tab, c.split_scale_lambda != 0, side);
         }
-        for (auto& kv : sg) {
+        if (le == hipSuccess && nbr > 0) le = hipEventRecord(prepped, side);
+        for (size_t i = 0; i < order.size(); ++i) {
             if (le != hipSuccess) break;
-            SGroup& g = kv.second;
-            le = launch_split_group_gemm(g.g, jobs + g.first, (int)g.jobs.size(), (const i64*)(base + g.off_prefix),
-                                         g.prefix.back(), TileSchedule{(const int*)(base + g.off_soff),
-                                                                       (const int*)(base + g.off_slist)},
-                                         g.grid, side);
+            SGroup& g = *order[i];
+            hipStream_t gs = i == 0 ? side : br[i - 1];
+            if (i > 0) le = hipStreamWaitEvent(gs, prepped, 0);
+            if (le == hipSuccess)
+                le = launch_split_group_gemm(g.g, jobs + g.first, (int)g.jobs.size(),
+                                             (const i64*)(base + g.off_prefix), g.prefix.back(),
+                                             TileSchedule{(const int*)(base + g.off_soff),
+                                                          (const int*)(base + g.off_slist)},
+                                             g.grid, gs);
+            if (le == hipSuccess && i > 0) le = hipEventRecord(brj[i - 1], gs);
         }
         for (auto& kv : dg) {
             if (le != hipSuccess) break;
@@ -330,12 +352,19 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
         }
         if (le == hipSuccess) le = hipEventRecord(join, side);
         if (le == hipSuccess) le = hipStreamWaitEvent(cap, join, 0);
+        for (size_t i = 0; i < nbr && le == hipSuccess; ++i)
+            if (i + 1 < order.size()) le = hipStreamWaitEvent(cap, brj[i], 0);
         e = hipStreamEndCapture(cap, &plan->graph);
         if (le != hipSuccess) e = le;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
     if (fork) (void)hipEventDestroy(fork);
     if (join) (void)hipEventDestroy(join);
+    if (prepped) (void)hipEventDestroy(prepped);
+    for (size_t i = 0; i < nbr; ++i) {
+        if (brj[i]) (void)hipEventDestroy(brj[i]);
+        if (br[i]) (void)hipStreamDestroy(br[i]);
+    }
     if (side) (void)hipStreamDestroy(side);
     if (cap) (void)hipStreamDestroy(cap);
     if (e != hipSuccess) {
