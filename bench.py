@@ -84,14 +84,19 @@ LATENCY_METHODS = [
 ]
 
 
-# HBM bytes per launch of a kernel, from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by
-# what the counters read for a plain 512 MiB device copy (FETCH x 2.0, WRITE x 1.0); valid only while the
-# kernel's source is the one measured (sha256 below), otherwise reported as null.
+# HBM bytes per launch of a kernel at the workload it is reported for (Kahan and DGEMM: the 4096 step;
+# the split digit GEMMs: the 8192^3 comparison), from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE)
+# scaled by what the counters read for a plain 512 MiB device copy (FETCH x 2.0, WRITE x 1.0); valid only
+# while the kernel's source is the one measured (sha256 below), otherwise reported as null.
 COUNTED_TRAFFIC = {
-    "kahan": {"bytes": 3.3577e+09, "file": "paper_1106_1347_amd/csrc/valu_gemm.hip",
-              "sha256": "c222f1ed93ef6f95a59b2dd1ad0c3a9a77fe8ea689a6f0462e24b53b7677e36c"},
-    "dgemm": {"bytes": 1.8797e+09, "file": "paper_1106_1347_amd/csrc/dgemm.hip",
-              "sha256": "6cde41f24dff417abc4b34646945670d8025cd7dcfaed948b7a1f600fb7a36e7"},
+    "kahan": {"bytes": 3.3574e+09, "file": "paper_1106_1347_amd/csrc/valu_gemm.hip",
+              "sha256": "3999925ed4c1c3b6c10677ab9428b5bb88f03d0fe1879683c810a2951565c401"},
+    "dgemm": {"bytes": 1.8556e+09, "file": "paper_1106_1347_amd/csrc/dgemm.hip",
+              "sha256": "562e5b4f47f6fd879ea77e84ddd5acf5ae8e5f99d6c49a67b88ae2023150210e"},
+    "split_int8_s7": {"bytes": 2.4026e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
+                      "sha256": "7000d794acc088aa6c4366042bec3dd9a55effbe2b87d8d05874d55844df18ac"},
+    "split_bf16_b9_s5": {"bytes": 6.6611e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
+                         "sha256": "7000d794acc088aa6c4366042bec3dd9a55effbe2b87d8d05874d55844df18ac"},
 }
 
 
