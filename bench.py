@@ -55,6 +55,7 @@ HEADLINE = [
     ("split_fp16_s6", "split", {"split_type": "fp16", "split_slices": 6}),
     ("split_fp16_s5", "split", {"split_type": "fp16", "split_slices": 5}),
     ("split_bf16_b9_s5", "split", {"split_type": "bf16", "split_slices": 5, "split_bits": 9}),
+    ("split_int8_b8_s6", "split", {"split_type": "int8", "split_slices": 6, "split_bits": 8}),
     ("strassen_winograd_L2", "strassen_winograd", {"strassen_levels": 2}),
     ("strassen_winograd_L3", "strassen_winograd", {"strassen_levels": 3}),
 ]
@@ -80,6 +81,7 @@ LATENCY_METHODS = [
     ("strassen_naive_L2", "strassen_naive", {"strassen_levels": 2}),
     ("strassen_winograd_L2", "strassen_winograd", {"strassen_levels": 2}),
     ("split_int8_s7", "split", {"split_type": "int8", "split_slices": 7}),
+    ("split_int8_b8_s6", "split", {"split_type": "int8", "split_slices": 6, "split_bits": 8}),
     ("split_bf16_s6", "split", {"split_type": "bf16", "split_slices": 6}),
 ]
 

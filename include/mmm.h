@@ -93,11 +93,13 @@ typedef struct {
     int32_t naive_fma;          /* NAIVE only. 0: product and sum rounded separately as in the
                                    paper (default); 1: fused multiply-add */
     int32_t split_bits;         /* digit width beta of the split product: 0 = the digit type's default
-                                   (bf16 8, fp16 9, int8 7); bf16 and fp16 2..9, int8 2..7 (a digit of
+                                   (bf16 8, fp16 9, int8 7); bf16 and fp16 2..9, int8 2..8 (a digit of
                                    beta bits is at most 2^(beta-1) in magnitude, which the type holds
-                                   exactly; with every allowed width and digit count, the fullest
-                                   digit-pair group stays in the accumulator's exact range for at least
-                                   one matrix-core step) */
+                                   exactly; int8 with 8 bits takes byte digits in [-128, 127]: each
+                                   scaled entry, one exponent step smaller, rounded once to 8 s bits
+                                   and written in base 256; with every allowed width and digit count,
+                                   the fullest digit-pair group stays in the accumulator's exact range
+                                   for at least one matrix-core step) */
     int32_t reserved[8];        /* must be zero */
 } mmm_config;
 

@@ -56,12 +56,12 @@ def _load():
         "oracle_strassen": (ctypes.c_int, [dp, dp, dp, i64, i64, i64, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_int]),
         "oracle_split_model": (None, [dp, dp, dp, i64, i64, i64, ctypes.c_int, ctypes.c_int,
-                                      ctypes.c_int]),
+                                      ctypes.c_int, ctypes.c_int]),
         "oracle_split_model_rows": (None, [dp, dp, dp, i64, i64, i64, dp, i64, ctypes.c_int,
-                                           ctypes.c_int, ctypes.c_int]),
+                                           ctypes.c_int, ctypes.c_int, ctypes.c_int]),
         "oracle_split_run_length": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, i64]),
         "oracle_split_digits": (None, [dp, i64, i64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                       ctypes.c_int, dp, dp]),
+                                       ctypes.c_int, dp, dp, ctypes.c_int]),
         "oracle_rel_err_inf": (ctypes.c_double, [dp, dp, i64, i64, ctypes.c_double,
                                                  ctypes.c_double]),
     }
@@ -256,23 +256,29 @@ def strassen(A, B, variant, mode=MODE_LEVELS, levels=1, return_depth=False):
     return (C, d) if return_depth else C
 
 
-def split_model(A, B, slices, beta, scale_lambda=True):
+def split_rule(split_type, beta):
+    """Digit rule of the split model for a digit type and width: 1 (byte
+    digits) for int8 with 8 bits, else 0 (repeated nearest digits)."""
+    return 1 if split_type == "int8" and int(beta) == 8 else 0
+
+
+def split_model(A, B, slices, beta, scale_lambda=True, rule=0):
     A, B = _f64(A), _f64(B)
     N, P, M = _shape(A, B)
     C = np.empty((N, M))
     _load().oracle_split_model(_p(A), _p(B), _p(C), N, P, M, int(slices), int(beta),
-                               int(bool(scale_lambda)))
+                               int(bool(scale_lambda)), int(rule))
     return C
 
 
-def split_model_rows(A, B, rows, slices, beta, scale_lambda=True):
+def split_model_rows(A, B, rows, slices, beta, scale_lambda=True, rule=0):
     A, B = _f64(A), _f64(B)
     N, P, M = _shape(A, B)
     r = np.ascontiguousarray(rows, dtype=np.int64)
     assert r.size == 0 or (r.min() >= 0 and r.max() < N)
     out = np.empty((r.size, M))
     _load().oracle_split_model_rows(_p(A), _p(B), _p(out), N, P, M, _p(r), r.size, int(slices),
-                                    int(beta), int(bool(scale_lambda)))
+                                    int(beta), int(bool(scale_lambda)), int(rule))
     return out
 
 
@@ -281,14 +287,14 @@ def split_run_length(slices, beta, P):
     return int(_load().oracle_split_run_length(int(slices), int(beta), int(P)))
 
 
-def split_digits(X, slices, beta, lam, is_b):
+def split_digits(X, slices, beta, lam, is_b, rule=0):
     """Digits (int32, shape (slices, rows, cols)) and exponents of one operand."""
     X = _f64(X)
     rows, cols = X.shape
     d = np.empty((slices, rows, cols), dtype=np.int32)
     e = np.empty(cols if is_b else rows, dtype=np.int32)
     _load().oracle_split_digits(_p(X), rows, cols, int(slices), int(beta), int(lam), int(bool(is_b)),
-                                _p(d), _p(e))
+                                _p(d), _p(e), int(rule))
     return d, e
 
 

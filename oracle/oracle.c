@@ -639,6 +639,13 @@ int oracle_strassen(const double* A, const double* B, double* C, i64 N, i64 P, i
  *    round-to-nearest-even:  r_0 = x,  d_t = rint(2^beta r_{t-1}),
  *    r_t = 2^beta r_{t-1} - d_t  (all exact), so |d_t| <= 2^(beta-1) and
  *    x = sum_t d_t 2^(-beta t) + r_s 2^(-beta s).
+ *    Byte digits (rule 1, beta = 8, for signed 8-bit digit storage, which
+ *    holds -128..127 but not the 257 values of the rule above): the
+ *    exponents of step 2 are one larger (e_i = E + 2, so |x| < 1/4), the
+ *    scaled entry is rounded once, X = rint(x 2^(8 s)), and X is written in
+ *    base 256 with digits in [-128, 127] from the least significant:
+ *    d_s = ((X + 128) mod 256) - 128, X <- (X - d_s) / 256, then d_{s-1},
+ *    and so on; |X| < 2^(8 s - 2) leaves d_1 in range and X = 0 at the end.
  * 4. For g = 2 .. s+1 the exact integer
  *      G_g[i][j] = sum_{t+u=g} sum_k dA_t[i][k] dB_u[k][j]
  *    is formed (int64; no rounding).  Pairs with t+u > s+1 are dropped.
@@ -663,6 +670,28 @@ static int row_exponent(double mx)
     return e + 1;
 }
 
+/* Digits d_1..d_s of one scaled entry x (step 3) into d[0], d[stride], ... */
+static void split_cut(double x, int s, int beta, int rule, int32_t* d, i64 stride)
+{
+    if (rule == 1) {
+        int64_t X = (int64_t)rint(ldexp(x, 8 * s));
+        for (int t = s; t >= 1; --t) {
+            const int64_t v = ((X + 128) & 255) - 128;
+            X = (X - v) / 256;
+            d[(i64)(t - 1) * stride] = (int32_t)v;
+        }
+        return;
+    }
+    const double up = ldexp(1.0, beta);
+    double r = x;
+    for (int t = 1; t <= s; ++t) {
+        const double y = r * up;
+        const double v = rint(y);
+        r = y - v;
+        d[(i64)(t - 1) * stride] = (int32_t)v;
+    }
+}
+
 /* Run length L of step 5 for s digits of beta bits over P products. */
 int oracle_split_run_length(int s, int beta, i64 P)
 {
@@ -683,12 +712,12 @@ int oracle_split_run_length(int s, int beta, i64 P)
  * out[r*M + j] = C_{rows[r], j}.  lambda is still taken from the norms of
  * the whole of A and B. */
 void oracle_split_model_rows(const double* A, const double* B, double* out, i64 N, i64 P, i64 M,
-                             const i64* rows, i64 nrows, int s, int beta, int scale_lambda)
+                             const i64* rows, i64 nrows, int s, int beta, int scale_lambda, int rule)
 {
     int lambda = 0;
     if (scale_lambda) lambda = oracle_winograd_lambda(oracle_norm_inf(A, N, P), oracle_norm_inf(B, P, M));
     const double sa = ldexp(1.0, lambda), sb = ldexp(1.0, -lambda);
-    const double up = ldexp(1.0, beta);
+    const int extra = rule == 1 ? 1 : 0; /* byte digits: one more exponent step */
     const int L = oracle_split_run_length(s, beta, P);
     int* fb = (int*)malloc(sizeof(int) * (size_t)(M > 0 ? M : 1));
     /* digits of B: dB[t][k*M+j] */
@@ -698,16 +727,9 @@ void oracle_split_model_rows(const double* A, const double* B, double* out, i64 
     for (i64 j = 0; j < M; ++j) {
         double mx = 0.0;
         for (i64 k = 0; k < P; ++k) mx = oracle_max_double(mx, fabs(sb * B[k * M + j]));
-        fb[j] = row_exponent(mx);
-        for (i64 k = 0; k < P; ++k) {
-            double r = ldexp(sb * B[k * M + j], -fb[j]);
-            for (int t = 0; t < s; ++t) {
-                const double y = r * up;
-                const double d = rint(y);
-                r = y - d;
-                dB[(i64)t * P * M + k * M + j] = (int32_t)d;
-            }
-        }
+        fb[j] = row_exponent(mx) + extra;
+        for (i64 k = 0; k < P; ++k)
+            split_cut(ldexp(sb * B[k * M + j], -fb[j]), s, beta, rule, dB + k * M + j, P * M);
     }
 #pragma omp parallel for schedule(static) num_threads(g_threads) if (nrows * P * M > 32768)
     for (i64 r = 0; r < nrows; ++r) {
@@ -715,16 +737,8 @@ void oracle_split_model_rows(const double* A, const double* B, double* out, i64 
         int32_t* dA = (int32_t*)malloc(sizeof(int32_t) * (size_t)(s * P > 0 ? s * P : 1));
         double mx = 0.0;
         for (i64 k = 0; k < P; ++k) mx = oracle_max_double(mx, fabs(sa * A[i * P + k]));
-        const int ea = row_exponent(mx);
-        for (i64 k = 0; k < P; ++k) {
-            double rr = ldexp(sa * A[i * P + k], -ea);
-            for (int t = 0; t < s; ++t) {
-                const double y = rr * up;
-                const double d = rint(y);
-                rr = y - d;
-                dA[(i64)t * P + k] = (int32_t)d;
-            }
-        }
+        const int ea = row_exponent(mx) + extra;
+        for (i64 k = 0; k < P; ++k) split_cut(ldexp(sa * A[i * P + k], -ea), s, beta, rule, dA + k, P);
         int64_t G[130];
         for (i64 j = 0; j < M; ++j) {
             for (int g = 0; g < 130; ++g) G[g] = 0;
@@ -751,11 +765,11 @@ void oracle_split_model_rows(const double* A, const double* B, double* out, i64 
 }
 
 void oracle_split_model(const double* A, const double* B, double* C, i64 N, i64 P, i64 M, int s, int beta,
-                        int scale_lambda)
+                        int scale_lambda, int rule)
 {
     i64* rows = (i64*)malloc(sizeof(i64) * (size_t)(N > 0 ? N : 1));
     for (i64 i = 0; i < N; ++i) rows[i] = i;
-    oracle_split_model_rows(A, B, C, N, P, M, rows, N, s, beta, scale_lambda);
+    oracle_split_model_rows(A, B, C, N, P, M, rows, N, s, beta, scale_lambda, rule);
     free(rows);
 }
 
@@ -763,10 +777,9 @@ void oracle_split_model(const double* A, const double* B, double* C, i64 N, i64 
  * (transpose_b = 0) digits[t][i][k] and exps[i]; for B (transpose_b = 1)
  * digits[t][k][j] and exps[j].  rows x cols is the operand's shape. */
 void oracle_split_digits(const double* X, i64 rows, i64 cols, int s, int beta, int lambda, int is_b,
-                         int32_t* digits, int32_t* exps)
+                         int32_t* digits, int32_t* exps, int rule)
 {
     const double sc = ldexp(1.0, is_b ? -lambda : lambda);
-    const double up = ldexp(1.0, beta);
     const i64 nvec = is_b ? cols : rows, len = is_b ? rows : cols;
     for (i64 v = 0; v < nvec; ++v) {
         double mx = 0.0;
@@ -774,17 +787,11 @@ void oracle_split_digits(const double* X, i64 rows, i64 cols, int s, int beta, i
             const i64 idx = is_b ? q * cols + v : v * cols + q;
             mx = oracle_max_double(mx, fabs(sc * X[idx]));
         }
-        const int e = row_exponent(mx);
+        const int e = row_exponent(mx) + (rule == 1 ? 1 : 0);
         exps[v] = e;
         for (i64 q = 0; q < len; ++q) {
             const i64 idx = is_b ? q * cols + v : v * cols + q;
-            double r = ldexp(sc * X[idx], -e);
-            for (int t = 0; t < s; ++t) {
-                const double y = r * up;
-                const double d = rint(y);
-                r = y - d;
-                digits[(i64)t * rows * cols + idx] = (int32_t)d;
-            }
+            split_cut(ldexp(sc * X[idx], -e), s, beta, rule, digits + idx, rows * cols);
         }
     }
 }

@@ -111,7 +111,7 @@ class Config:
     split_type: str = "bf16"
     split_scale_lambda: bool = True
     naive_fma: bool = False
-    split_bits: int = 0  # 0: the digit type's default width (bf16 8, fp16 9, int8 7)
+    split_bits: int = 0  # 0: the digit type's default width (bf16 8, fp16 9, int8 7); int8 8: byte digits
 
     def _c(self) -> _CConfig:
         c = _CConfig()

@@ -105,7 +105,7 @@ mmm_status mmm::check_config(const mmm_config& c)
     if (c.split_type != MMM_SLICE_BF16 && c.split_type != MMM_SLICE_FP16 && c.split_type != MMM_SLICE_INT8)
         return fail(MMM_EINVAL, "config: bad split_type");
     if (c.split_scale_lambda != 0 && c.split_scale_lambda != 1) return fail(MMM_EINVAL, "config: bad split_scale_lambda");
-    if (c.split_bits != 0 && (c.split_bits < 2 || c.split_bits > (c.split_type == MMM_SLICE_INT8 ? 7 : 9)))
+    if (c.split_bits != 0 && (c.split_bits < 2 || c.split_bits > (c.split_type == MMM_SLICE_INT8 ? 8 : 9)))
         return fail(MMM_EINVAL, "config: split_bits %d outside 2..%d for this digit type", c.split_bits,
                     c.split_type == MMM_SLICE_INT8 ? 7 : 9);
     if (c.naive_fma != 0 && c.naive_fma != 1) return fail(MMM_EINVAL, "config: bad naive_fma");

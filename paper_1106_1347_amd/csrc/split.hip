@@ -22,8 +22,11 @@
 //
 // Digit types: BF16 (default beta = 8, at most 9: |d| <= 256 has 8
 // significant bits), FP16 (default and at most 9), both with FP32
-// accumulation on the 16x16x32 MFMA; INT8 (default and at most 7: |d| <= 64
-// fits a signed byte, INT32 accumulation, 16x16x64 MFMA).
+// accumulation on the 16x16x32 MFMA; INT8 (default 7: |d| <= 64 fits a
+// signed byte; INT32 accumulation, 16x16x64 MFMA).  INT8 with beta = 8
+// takes byte digits instead of step 3 (see cut): e_i one larger, the
+// scaled entry rounded once to 8 s bits and written in base 256 with
+// digits in [-128, 127]; steps 4 and 5 are unchanged.
 //
 // Layouts (workspace): K is padded to a multiple of 64 entries and cut into
 // blocks of 64 bytes (64 int8 or 32 bf16/fp16 digits: one MFMA step of
@@ -197,6 +200,14 @@ __device__ inline void store_digits(char* dst, const double* d)
     }
 }
 
+// Byte digits of 8 bits (int8, beta = 8) do not fit the nearest-digit rule
+// (|d| <= 128 needs 257 values): the scaled entry r (|r| < 1/4, from one
+// more exponent step) is rounded once to 8 s fractional bits, X =
+// rint(r 2^(8 s)), and X is written in base 256 with digits in
+// [-128, 127], least significant first: d = ((X + 128) mod 256) - 128,
+// X = (X - d) / 256.
+__host__ __device__ constexpr bool byte_digits(int dt, int beta) { return dt == DT_INT8 && beta == 8; }
+
 // Digits of 8 consecutive entries along k of one row of A (or one column
 // of B).  x[q] are the unscaled entries (0 outside the matrix).
 template <int DT>
@@ -206,6 +217,22 @@ __device__ inline void cut(const double* x, double sc, int e, int s, int beta, c
     double r[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) r[q] = ldexp(x[q] * sc, -e);
+    if (DT == DT_INT8 && beta == 8) {
+        long long X[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) X[q] = (long long)rint(ldexp(r[q], 8 * s));
+        for (int t = s - 1; t >= 0; --t) {
+            double d[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const long long v = ((X[q] + 128) & 255) - 128;
+                X[q] = (X[q] - v) >> 8;
+                d[q] = (double)v;
+            }
+            store_digits<DT>(out + t * slice_stride, d);
+        }
+        return;
+    }
     for (int t = 0; t < s; ++t) {
         double d[8];
 #pragma unroll
@@ -237,7 +264,7 @@ __device__ __forceinline__ void split_a_body(const double* __restrict__ A, i64 N
         const int q = (int)(c % TB);
         const i64 rest = c / TB, i = rest % Np, kb = rest / Np;
         const i64 k0 = kb * (KB / ES) + q * 8;
-        const int e = i < N ? vec_exponent(rmax_raw ? rmax[i] * sc : rmax[i]) : 0;
+        const int e = i < N ? vec_exponent(rmax_raw ? rmax[i] * sc : rmax[i]) + byte_digits(DT, beta) : 0;
         double x[8];
 #pragma unroll
         for (int r = 0; r < 8; ++r) x[r] = (i < N && k0 + r < P) ? A[i * P + k0 + r] : 0.0;
@@ -277,7 +304,7 @@ __device__ __forceinline__ void split_b_body(const double* __restrict__ B, i64 P
         const int q = c % TB, jc = (c / TB) % 64, blk = c / (TB * 64);
         const int kk = blk * (KB / ES) + q * 8;
         const i64 j = j0 + jc;
-        const int e = j < M ? vec_exponent(cmax_raw ? cmax[j] * sc : cmax[j]) : 0;
+        const int e = j < M ? vec_exponent(cmax_raw ? cmax[j] * sc : cmax[j]) + byte_digits(DT, beta) : 0;
         double x[8];
 #pragma unroll
         for (int r = 0; r < 8; ++r) x[r] = T[kk + r][jc];

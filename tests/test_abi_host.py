@@ -135,11 +135,11 @@ def test_argument_errors_before_any_launch(lib):
     bad.reserved[3] = 1
     assert f(8, 8, 8, 2, 2, 2, 6, r(bad), None, 0, None) == 1
     # digit widths beyond what the digit type holds exactly
-    for typ, bits in ((0, 10), (1, 10), (2, 8), (0, 1), (2, -1)):
+    for typ, bits in ((0, 10), (1, 10), (2, 9), (0, 1), (2, -1)):
         bad = lib._lib.mmm_config_default()
         bad.split_type, bad.split_bits = typ, bits
         assert f(8, 8, 8, 2, 2, 2, 7, r(bad), None, 0, None) == 1, (typ, bits)
-    for typ, bits, s in (("bf16", 9, 8), ("fp16", 9, 8), ("int8", 7, 8), ("bf16", 2, 1)):
+    for typ, bits, s in (("bf16", 9, 8), ("fp16", 9, 8), ("int8", 7, 8), ("int8", 8, 8), ("bf16", 2, 1)):
         assert lib.workspace_bytes("split", 64, 3000, 64, lib.Config(split_type=typ, split_bits=bits, split_slices=s)) > 0
     # empty result: nothing to do, no device call
     assert f(None, None, None, 0, 5, 5, 6, r(c), None, 0, None) == 0

@@ -41,11 +41,18 @@ def bits_equal(X, Y):
     return X.shape == Y.shape and np.array_equal(X.view(np.int64), Y.view(np.int64))
 
 
+def model(orc, A, B, typ, s, bits, scale=True):
+    """The oracle's model for a digit type and width (byte digits for int8 with 8 bits)."""
+    beta = bits or BETA[typ]
+    return orc.split_model(A, B, s, beta, scale, rule=orc.split_rule(typ, beta))
+
+
 SHAPES = [(1, 1, 1), (5, 3, 7), (64, 64, 64), (65, 130, 63), (129, 257, 131), (200, 64, 300), (256, 300, 256)]
 # (digit type, digit count, digit width; 0 = the type's default)
 CASES = [("bf16", 6, 0), ("bf16", 3, 0), ("bf16", 8, 0), ("fp16", 4, 0), ("fp16", 6, 0), ("fp16", 5, 0),
          ("int8", 7, 0), ("int8", 4, 0), ("int8", 8, 0), ("int8", 1, 0),
-         ("bf16", 5, 9), ("bf16", 8, 9), ("bf16", 4, 5), ("fp16", 3, 7), ("int8", 5, 6), ("int8", 8, 3)]
+         ("bf16", 5, 9), ("bf16", 8, 9), ("bf16", 4, 5), ("fp16", 3, 7), ("int8", 5, 6), ("int8", 8, 3),
+         ("int8", 6, 8), ("int8", 1, 8), ("int8", 3, 8), ("int8", 8, 8)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -56,7 +63,7 @@ def test_split_bitwise_vs_model(mmm, orc, shape, typ, s, bits):
     A = synth.wide_range((N, P), 11 + N)
     B = synth.wide_range((P, M), 12 + M) * 2.0 ** 17
     got = split(mmm, A, B, typ, s, bits=bits)
-    assert bits_equal(got, orc.split_model(A, B, s, bits or BETA[typ], True))
+    assert bits_equal(got, model(orc, A, B, typ, s, bits))
 
 
 @pytest.mark.parametrize("typ,s,bits", [("bf16", 5, 9), ("fp16", 5, 9), ("bf16", 6, 8), ("fp16", 8, 9)])
@@ -84,8 +91,9 @@ def test_split_integer_inputs_exact(mmm):
     A = synth.integers((100, 257), 3)
     B = synth.integers((257, 90), 4)
     ref = (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float64)
-    for typ, s in (("bf16", 1), ("bf16", 6), ("fp16", 2), ("int8", 1), ("int8", 7)):
-        assert np.array_equal(split(mmm, A, B, typ, s), ref), (typ, s)
+    for typ, s, bits in (("bf16", 1, 0), ("bf16", 6, 0), ("fp16", 2, 0), ("int8", 1, 0), ("int8", 7, 0),
+                         ("int8", 1, 8), ("int8", 6, 8)):
+        assert np.array_equal(split(mmm, A, B, typ, s, bits=bits), ref), (typ, s, bits)
 
 
 @pytest.mark.parametrize("typ,s,bits", [("bf16", 8, 9), ("fp16", 5, 9)])
@@ -110,7 +118,7 @@ def test_split_fp64_grade(mmm, orc):
     B = synth.wide_range((1024, 192), 6)
     ref = orc.naive(A, B)
     nA, nB = orc.norm_inf(A), orc.norm_inf(B)
-    for typ, s, bits in (("bf16", 6, 0), ("int8", 7, 0), ("fp16", 6, 0), ("fp16", 5, 0), ("bf16", 5, 9)):
+    for typ, s, bits in (("bf16", 6, 0), ("int8", 7, 0), ("fp16", 6, 0), ("fp16", 5, 0), ("bf16", 5, 9), ("int8", 6, 8)):
         e = orc.rel_err_inf(split(mmm, A, B, typ, s, bits=bits), ref, nA, nB)
         print(typ, s, bits, e, flush=True)
         assert e <= 1e-13, (typ, s, bits, e)
@@ -122,6 +130,8 @@ def test_split_int8_flush_path(mmm, orc):
     A = synth.wide_range((32, 70000), 7)
     B = synth.wide_range((70000, 40), 8)
     assert bits_equal(split(mmm, A, B, "int8", 8), orc.split_model(A, B, 8, 7, True))
+    # byte digits: 8 pairs of |d| <= 128 fill int32 after 16384 entries
+    assert bits_equal(split(mmm, A, B, "int8", 8, bits=8), model(orc, A, B, "int8", 8, 8))
 
 
 def test_split_full_size_sampled_rows(mmm, orc):
@@ -137,11 +147,12 @@ def test_split_full_size_sampled_rows(mmm, orc):
     Ad, Bd = dev(A), dev(B)
     ref = orc.naive_rows(A, B, rows)
     nA, nB = orc.norm_inf(A), orc.norm_inf(B)
-    for typ, s, bits in (("int8", 7, 0), ("bf16", 6, 0), ("bf16", 5, 9)):
+    for typ, s, bits in (("int8", 7, 0), ("bf16", 6, 0), ("bf16", 5, 9), ("int8", 6, 8)):
         print("case full size", typ, s, bits, flush=True)
         C = mmm.multiply(Ad, Bd, "split", mmm.Config(split_type=typ, split_slices=s, split_bits=bits))
         torch.cuda.synchronize()
         got = C[torch.from_numpy(rows).cuda()].cpu().numpy()
         del C
-        assert bits_equal(got, orc.split_model_rows(A, B, rows, s, bits or BETA[typ], True)), typ
+        beta = bits or BETA[typ]
+        assert bits_equal(got, orc.split_model_rows(A, B, rows, s, beta, True, rule=orc.split_rule(typ, beta))), typ
         assert orc.norm_inf(orc.minus(got, ref)) / (nA * nB) <= 1e-13

@@ -48,6 +48,8 @@ def _methods(orc):
         "split_bf16_s6": lambda A, B: orc.split_model(A, B, 6, 8),
         "split_fp16_s4": lambda A, B: orc.split_model(A, B, 4, 10),
         "split_int8_s7": lambda A, B: orc.split_model(A, B, 7, 7),
+        "split_int8_bytes_s6": lambda A, B: orc.split_model(A, B, 6, 8, rule=1),
+        "split_int8_bytes_s1": lambda A, B: orc.split_model(A, B, 1, 8, rule=1),
     }
     for v, name in ((0, "sn"), (1, "sw")):
         out[name + "_paper"] = (lambda v: lambda A, B: orc.strassen(A, B, v, orc.MODE_PAPER))(v)
@@ -461,11 +463,11 @@ def test_split_single_run_is_correctly_rounded(orc):
     N, P, M = 5, 37, 4
     A = synth.wide_range((N, P), 31)
     B = synth.wide_range((P, M), 32)
-    for s, beta in ((1, 8), (2, 8), (2, 9), (2, 7)):
+    for s, beta, rule in ((1, 8, 0), (2, 8, 0), (2, 9, 0), (2, 7, 0), (1, 8, 1), (2, 8, 1)):
         assert orc.split_run_length(s, beta, P) >= s
-        C = orc.split_model(A, B, s, beta, False)
-        dA, ea = orc.split_digits(A, s, beta, 0, False)
-        dB, fb = orc.split_digits(B, s, beta, 0, True)
+        C = orc.split_model(A, B, s, beta, False, rule=rule)
+        dA, ea = orc.split_digits(A, s, beta, 0, False, rule=rule)
+        dB, fb = orc.split_digits(B, s, beta, 0, True, rule=rule)
         for i in range(N):
             for j in range(M):
                 v = Fraction(0)
@@ -478,14 +480,14 @@ def test_split_single_run_is_correctly_rounded(orc):
                 assert C[i, j] == want, (s, beta, i, j)
 
 
-def _split_runs_reference(orc, A, B, s, beta, runs):
+def _split_runs_reference(orc, A, B, s, beta, runs, rule=0):
     """The model's result with the given runs, from the oracle's digits by
     rational arithmetic: exact group sums, each run rounded once when it is
     added, finest run first."""
     N, P = A.shape
     M = B.shape[1]
-    dA, ea = orc.split_digits(A, s, beta, 0, False)
-    dB, fb = orc.split_digits(B, s, beta, 0, True)
+    dA, ea = orc.split_digits(A, s, beta, 0, False, rule=rule)
+    dB, fb = orc.split_digits(B, s, beta, 0, True, rule=rule)
     out = np.empty((N, M))
     for i in range(N):
         for j in range(M):
@@ -517,6 +519,49 @@ def test_split_runs_of_three(orc):
         assert np.array_equal(C, _split_runs_reference(orc, A, B, s, beta, runs)), (s, beta)
     wrong = _split_runs_reference(orc, A, B, 8, 9, [(9, 8, 7, 6), (5, 4, 3, 2)])
     assert (wrong != orc.split_model(A, B, 8, 9, False)).sum() >= 10
+    # byte digits: the same runs over their own digits
+    assert orc.split_run_length(7, 8, A.shape[1]) == 3
+    assert np.array_equal(orc.split_model(A, B, 7, 8, False, rule=1),
+                          _split_runs_reference(orc, A, B, 7, 8, [(8, 7, 6), (5, 4, 3), (2,)], rule=1))
+
+
+def test_split_byte_digits(orc):
+    """Byte digits (int8 with 8 bits): the exponent is one step larger than
+    the nearest-digit rule's, so every scaled entry lies in [-1/4, 1/4); the
+    digits lie in [-128, 127] and, read in base 256, equal the scaled entry
+    rounded to nearest (ties to even) at 8 s fractional bits, exactly
+    (rational arithmetic; Python's round on a Fraction rounds half to
+    even).  Entries next to a tie and at the top of the range included."""
+    X = synth.wide_range((7, 13), 61)
+    X[0, :4] = [0.49999999999999994, -0.5, 0.25, -0.2490234375]
+    X[1, :3] = [1.0 + 2.0 ** -40, -(1.0 + 2.0 ** -41), 2.0 ** -60]
+    for s in (1, 2, 5, 6, 8):
+        for is_b in (False, True):
+            d, e = orc.split_digits(X, s, 8, 0, is_b, rule=1)
+            _, e0 = orc.split_digits(X, s, 8, 0, is_b, rule=0)
+            assert np.array_equal(e, e0 + 1)
+            assert d.min() >= -128 and d.max() <= 127
+            rows, cols = X.shape
+            for i in range(rows):
+                for j in range(cols):
+                    ex = int(e[j] if is_b else e[i])
+                    x = Fraction(X[i, j]) / Fraction(2) ** ex
+                    assert abs(x) < Fraction(1, 4)
+                    want = round(x * 2 ** (8 * s))
+                    got = sum(int(d[t, i, j]) * 256 ** (s - 1 - t) for t in range(s))
+                    assert got == want, (s, is_b, i, j)
+
+
+def test_split_byte_digits_fp64_grade(orc):
+    """Six byte digits (46 bits of each scaled entry) are FP64-grade on the
+    wide-range distribution; four are not."""
+    A = synth.wide_range((48, 256), 5)
+    B = synth.wide_range((256, 40), 6)
+    ref = orc.naive(A, B)
+    e6 = orc.rel_err_inf(orc.split_model(A, B, 6, 8, rule=1), ref, orc.norm_inf(A), orc.norm_inf(B))
+    assert e6 < 5e-14
+    e4 = orc.rel_err_inf(orc.split_model(A, B, 4, 8, rule=1), ref, orc.norm_inf(A), orc.norm_inf(B))
+    assert e4 > 1e-12
 
 
 def test_split_run_length_rule(orc):
