@@ -520,14 +520,34 @@ def batch_section(mmm, torch, synth, dev, stream, split_type="bf16", split_slice
     separate()
     ms_sep = _time(torch, stream, separate, 3)
     plan.close()
+    # extra: the same graph with the split half as int8 byte digits (6 digits of 8 bits), tiles tuned for it
+    cfg8 = mmm.Config(split_type="int8", split_slices=6, split_bits=8)
+    tuner.tune([s for g, s in enumerate(shapes) if g % 2 == 0], split=[s for g, s in enumerate(shapes) if g % 2 == 1],
+               split_config=cfg8)
+    plan8 = mmm.Batch([(A, B, C, m, 0, tuner.tile_for(A.shape[0], A.shape[1], B.shape[1], m, cfg8))
+                       for (A, B, C, m) in probs], cfg8, stream=stream)
+    plan8.launch(stream)
+    ms8 = _time(torch, stream, lambda: plan8.launch(stream), 10)
+    plan8.launch(stream)
+    torch.cuda.synchronize()
+    outs8 = [C.cpu().numpy() for (_, _, C, m) in probs if m == "split"]
+    plan8.close()
     # every result against the oracle (the naive definition, full products)
     oracle.set_threads(_host_threads())
     t0 = time.perf_counter()
     worst = {"dgemm": 0.0, "split": 0.0}
+    worst8 = 0.0
+    refs = {}
     for g, ((A, B), C) in enumerate(zip(host, outs)):
-        e = _rel_err(oracle, C, oracle.naive(A, B), oracle.norm_inf(A) * oracle.norm_inf(B))
+        ref = oracle.naive(A, B)
+        e = _rel_err(oracle, C, ref, oracle.norm_inf(A) * oracle.norm_inf(B))
         k = "dgemm" if g % 2 == 0 else "split"
         worst[k] = max(worst[k], e)
+        if k == "split":
+            refs[g] = ref
+    for g8, C in zip(sorted(refs), outs8):
+        A, B = host[g8]
+        worst8 = max(worst8, _rel_err(oracle, C, refs[g8], oracle.norm_inf(A) * oracle.norm_inf(B)))
     check_s = time.perf_counter() - t0
     flop = sum(2.0 * N * P * M for (N, P, M) in shapes)
     med = float(np.median(ms_graph))
@@ -538,6 +558,9 @@ def batch_section(mmm, torch, synth, dev, stream, split_type="bf16", split_slice
             "tflops_fp64_grade_graph": flop / (med / 1e3) / 1e12, "speedup_vs_separate": ms_sep / med,
             "flop": flop, "rel_err_inf_worst": worst, "all_within_1e-13": max(worst.values()) <= FP64_GRADE,
             "oracle_check": "every product in full against the naive definition, %.1f s" % check_s,
+            "extra_int8_byte_digits": {"split": "int8 x6, 8-bit byte digits", "ms_graph_p50": ms8,
+                                       "tflops_fp64_grade_graph": flop / (ms8 / 1e3) / 1e12,
+                                       "rel_err_inf_worst_split": worst8},
             "tiles": tuner.summary()}
 
 

@@ -40,16 +40,19 @@ from ._lib import Config, multiply, workspace_bytes
 
 # Candidate methods per tolerance class, with the relative infinity-norm
 # error each keeps on the serving workloads (uniform entries): the plain
-# FP64 matrix-core GEMM, the int8 split with 7 digits and the bf16 split with
-# 5 digits of 9 bits (about 3e-15) are FP64-grade (<= 1e-13); 5 int8
-# digits, 4 bf16 digits of 9 bits (about 1e-12) and Strassen-Winograd with a
-# DGEMM leaf are within 1e-10.  Each entry: (name, method, config kwargs).
+# FP64 matrix-core GEMM, the int8 split with 7 digits, 6 byte digits (int8,
+# 8 bits) and the bf16 split with 5 digits of 9 bits (about 3e-15) are
+# FP64-grade (<= 1e-13); 5 int8 digits, 5 byte digits, 4 bf16 digits of 9
+# bits (about 1e-12) and Strassen-Winograd with a DGEMM leaf are within
+# 1e-10.  Each entry: (name, method, config kwargs).
 CANDIDATES = {
     "fp64": [("dgemm", "dgemm", {}),
              ("split_int8_s7", "split", {"split_type": "int8", "split_slices": 7}),
+             ("split_int8_b8_s6", "split", {"split_type": "int8", "split_slices": 6, "split_bits": 8}),
              ("split_bf16_b9_s5", "split", {"split_type": "bf16", "split_slices": 5, "split_bits": 9})],
     "relaxed": [("dgemm", "dgemm", {}),
                 ("split_int8_s5", "split", {"split_type": "int8", "split_slices": 5}),
+                ("split_int8_b8_s5", "split", {"split_type": "int8", "split_slices": 5, "split_bits": 8}),
                 ("split_bf16_b9_s4", "split", {"split_type": "bf16", "split_slices": 4, "split_bits": 9}),
                 ("strassen_winograd_L1", "strassen_winograd", {"strassen_levels": 1}),
                 ("strassen_winograd_L2", "strassen_winograd", {"strassen_levels": 2})],
@@ -85,7 +88,7 @@ class Router:
     by interpolating the time per multiply-add (log-linear in d) and scaling
     by N P M.  The fastest candidate of the request's tolerance class wins.
     The choice depends on the request alone.  Without a table the rule of
-    thumb is DGEMM below d = 1024 and the int8 split above."""
+    thumb is DGEMM below d = 1024 and the byte-digit int8 split above."""
 
     def __init__(self, table: Optional[Dict[str, List[float]]] = None, sizes: Sequence[int] = CAL_SIZES):
         self.sizes = list(sizes)
@@ -117,7 +120,7 @@ class Router:
         else:
             name = cands[0][0]
             if min(N, P, M) >= 1024:
-                name = "split_int8_s7" if tol_class(tol) == "fp64" else "split_int8_s5"
+                name = "split_int8_b8_s6" if tol_class(tol) == "fp64" else "split_int8_b8_s5"
         return _method(name), Config(**_kw(name))
 
     # -- measurement -----------------------------------------------------------

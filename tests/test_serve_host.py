@@ -106,8 +106,8 @@ def test_oversized_request_rejected():
 
 def test_method_choice_by_tolerance_uncalibrated():
     assert choose(4096, 4096, 4096, 1e-13)[0] == "split"
-    assert choose(4096, 4096, 4096, 1e-13)[1].split_slices == 7
-    assert choose(4096, 4096, 4096, 1e-10)[1].split_slices == 5
+    assert (choose(4096, 4096, 4096, 1e-13)[1].split_slices, choose(4096, 4096, 4096, 1e-13)[1].split_bits) == (6, 8)
+    assert (choose(4096, 4096, 4096, 1e-10)[1].split_slices, choose(4096, 4096, 4096, 1e-10)[1].split_bits) == (5, 8)
     assert choose(100, 4096, 4096, 1e-13)[0] == "dgemm"
 
 

@@ -28,6 +28,7 @@ CASES = [
     ("strassen_naive", {"strassen_levels": 1}),
     ("split", {"split_type": "bf16", "split_slices": 6}),
     ("split", {"split_type": "int8", "split_slices": 7}),
+    ("split", {"split_type": "int8", "split_slices": 6, "split_bits": 8}),
     ("split", {"split_type": "fp16", "split_slices": 5}),
 ]
 SHAPES = [(700, 613, 530), (257, 130, 91)]  # second call smaller
