@@ -49,9 +49,11 @@ def single(mmm, A, B, method, s, cfg):
     return mmm.multiply(A, B, method, c)
 
 
-@pytest.mark.parametrize("typ,slices", [("int8", [0, 4, 7]), ("bf16", [0, 3, 6]), ("fp16", [6])])
-def test_batch_equals_single_calls_and_replays(mmm, typ, slices):
-    cfg = mmm.Config(split_type=typ, split_slices=7 if typ == "int8" else 6)
+@pytest.mark.parametrize("typ,slices,bits", [("int8", [0, 4, 7], 0), ("bf16", [0, 3, 6], 0), ("fp16", [6], 0),
+                                             ("int8", [0, 5, 6], 8), ("bf16", [5], 9)])
+def test_batch_equals_single_calls_and_replays(mmm, typ, slices, bits):
+    print("case batch", typ, slices, bits, flush=True)
+    cfg = mmm.Config(split_type=typ, split_slices=7 if typ == "int8" else 6, split_bits=bits)
     shapes = synth.batch_shapes(48, 7, 1, 200) + [(16, 0, 9), (0, 5, 5), (300, 257, 3)]
     probs = make_problems(shapes, 100, ["dgemm", "split"], slices)
     want = [single(mmm, A, B, m, s, cfg).cpu() for (A, B, C, m, s, t) in probs]
