@@ -94,7 +94,7 @@ COUNTED_TRAFFIC = {
     "kahan": {"bytes": 3.3574e+09, "file": "paper_1106_1347_amd/csrc/valu_gemm.hip",
               "sha256": "3999925ed4c1c3b6c10677ab9428b5bb88f03d0fe1879683c810a2951565c401"},
     "dgemm": {"bytes": 1.8959e+09, "file": "paper_1106_1347_amd/csrc/dgemm.hip",
-              "sha256": "562e5b4f47f6fd879ea77e84ddd5acf5ae8e5f99d6c49a67b88ae2023150210e"},
+              "sha256": "3d5b9cd6f817b5518e0aafbca82be4c003b8373516fa8beb8b3ddf410c48946b"},
     "split_int8_s7": {"bytes": 2.3624e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
                       "sha256": "72537a6f91a796b553668a5f88e7cd8bf4a0923b54af6d00bb6b45d8436c7296"},
     "split_int8_b8_s6": {"bytes": 2.0052e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
