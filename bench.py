@@ -96,11 +96,11 @@ COUNTED_TRAFFIC = {
     "dgemm": {"bytes": 1.8959e+09, "file": "paper_1106_1347_amd/csrc/dgemm.hip",
               "sha256": "3d5b9cd6f817b5518e0aafbca82be4c003b8373516fa8beb8b3ddf410c48946b"},
     "split_int8_s7": {"bytes": 2.3624e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
-                      "sha256": "72537a6f91a796b553668a5f88e7cd8bf4a0923b54af6d00bb6b45d8436c7296"},
+                      "sha256": "1845cce1ddbcee26e5883e89e7f488deb807c39443e1e1d8ff28bb23dba82dcc"},
     "split_int8_b8_s6": {"bytes": 2.0052e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
-                         "sha256": "72537a6f91a796b553668a5f88e7cd8bf4a0923b54af6d00bb6b45d8436c7296"},
+                         "sha256": "1845cce1ddbcee26e5883e89e7f488deb807c39443e1e1d8ff28bb23dba82dcc"},
     "split_bf16_b9_s5": {"bytes": 6.5769e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
-                         "sha256": "72537a6f91a796b553668a5f88e7cd8bf4a0923b54af6d00bb6b45d8436c7296"},
+                         "sha256": "1845cce1ddbcee26e5883e89e7f488deb807c39443e1e1d8ff28bb23dba82dcc"},
 }
 
 

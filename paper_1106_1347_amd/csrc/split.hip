@@ -218,18 +218,35 @@ __device__ inline void cut(const double* x, double sc, int e, int s, int beta, c
 #pragma unroll
     for (int q = 0; q < 8; ++q) r[q] = ldexp(x[q] * sc, -e);
     if (DT == DT_INT8 && beta == 8) {
-        long long X[8];
+        // X (an exact integer in binary64) is cut 24 bits at a time: X =
+        // 2^24 hi + lo with 0 <= lo < 2^24 (exact floor and difference), the
+        // next three digits come from lo in 32-bit integers, and what is left
+        // of lo after them (the carry, 0 or 1) joins hi.  Same digits as the
+        // whole-integer rule, in 32-bit arithmetic.
+        double X[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) X[q] = (long long)rint(ldexp(r[q], 8 * s));
-        for (int t = s - 1; t >= 0; --t) {
-            double d[8];
+        for (int q = 0; q < 8; ++q) X[q] = rint(ldexp(r[q], 8 * s));
+        for (int t = s - 1; t >= 0;) {
+            double hi[8];
+            int lo[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const long long v = ((X[q] + 128) & 255) - 128;
-                X[q] = (X[q] - v) >> 8;
-                d[q] = (double)v;
+                hi[q] = floor(X[q] * 0x1p-24);
+                lo[q] = (int)(X[q] - hi[q] * 0x1p24);
             }
-            store_digits<DT>(out + t * slice_stride, d);
+            for (int n = 0; n < 3 && t >= 0; ++n, --t) {
+                unsigned int w0 = 0, w1 = 0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int v = ((lo[q] + 128) & 255) - 128;
+                    lo[q] = (lo[q] - v) >> 8;
+                    if (q < 4) w0 |= (unsigned int)(v & 255) << (8 * q);
+                    else w1 |= (unsigned int)(v & 255) << (8 * (q - 4));
+                }
+                *reinterpret_cast<uint2*>(out + t * slice_stride) = make_uint2(w0, w1);
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) X[q] = hi[q] + (double)lo[q];
         }
         return;
     }
