@@ -87,6 +87,22 @@ def test_split_lambda_invariance_and_uniform(mmm, orc, typ, s):
     assert bits_equal(on, orc.split_model(A, B, s, BETA[typ], False))
 
 
+@pytest.mark.parametrize("typ,s,bits", [("int8", 6, 8), ("int8", 7, 0), ("bf16", 6, 0), ("fp16", 5, 0)])
+def test_split_zero_rows_and_columns(mmm, orc, typ, s, bits):
+    """All-zero rows of A and columns of B (exponent of an empty maximum),
+    and a zero operand, still give the model's bits (zeros where the row or
+    column is zero)."""
+    A = synth.wide_range((70, 130), 31)
+    B = synth.wide_range((130, 50), 32)
+    A[[0, 33, 69], :] = 0.0
+    B[:, [0, 17, 49]] = 0.0
+    got = split(mmm, A, B, typ, s, bits=bits)
+    assert bits_equal(got, model(orc, A, B, typ, s, bits))
+    assert not got[[0, 33, 69], :].any() and not got[:, [0, 17, 49]].any()
+    Z = np.zeros_like(A)
+    assert bits_equal(split(mmm, Z, B, typ, s, bits=bits), model(orc, Z, B, typ, s, bits))
+
+
 def test_split_integer_inputs_exact(mmm):
     A = synth.integers((100, 257), 3)
     B = synth.integers((257, 90), 4)
