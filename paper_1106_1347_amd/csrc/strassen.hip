@@ -238,11 +238,11 @@ struct Vec<2> {
 // and writes the level-(f+1) operands that are not views of the node's own
 // operand.
 template <int VARIANT, bool IS_B, int W>
-__global__ __launch_bounds__(256) void strassen_pre2_kernel(StrassenTree T, int f, i64 bpp)
+__device__ __forceinline__ void strassen_pre2_body(const StrassenTree& T, int f, i64 bpp, i64 block)
 {
     typedef Vec<W> V;
-    const i64 parent = blockIdx.x / bpp;
-    const i64 chunk = blockIdx.x - parent * bpp;
+    const i64 parent = block / bpp;
+    const i64 chunk = block - parent * bpp;
     const View par = strassen_operand(T, f - 1, parent, IS_B);
     const i64 rows = IS_B ? T.p[f + 1] : T.n[f + 1];
     const i64 cols = IS_B ? T.m[f + 1] : T.p[f + 1];
@@ -288,6 +288,17 @@ __global__ __launch_bounds__(256) void strassen_pre2_kernel(StrassenTree T, int 
             }
         }
     }
+}
+
+// Both operands' fused pre-passes in one launch: workgroups below blocks_a
+// take A's nodes, the rest B's, so the second operand's workgroups fill the
+// CUs the first leaves idle at its tail.
+template <int VARIANT, int W>
+__global__ __launch_bounds__(256) void strassen_pre2_kernel(StrassenTree T, int f, i64 bpp_a, i64 blocks_a, i64 bpp_b)
+{
+    const i64 b = blockIdx.x;
+    if (b < blocks_a) strassen_pre2_body<VARIANT, false, W>(T, f, bpp_a, b);
+    else strassen_pre2_body<VARIANT, true, W>(T, f, bpp_b, b - blocks_a);
 }
 
 // Levels f + 1 and f folded in one pass: for every node of level f - 1,
@@ -429,26 +440,22 @@ hipError_t launch_strassen_pre2(const StrassenTree& T, int f, hipStream_t s)
 {
     const i64 parents = pow7(f - 1);
     const bool pairs = strassen_pairs_ok(T, f, nullptr, 0);
-    for (int side = 0; side < 2; ++side) {
-        const i64 sz = side ? T.p[f + 1] * T.m[f + 1] : T.n[f + 1] * T.p[f + 1];
-        const i64 bpp = cdiv(pairs ? sz / 2 : sz, 256 * EPT);
-        const i64 blocks = parents * bpp;
-        if (blocks == 0) continue;
-        if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-        const dim3 g((unsigned)blocks), b(256);
-#define MMM_PRE2(V, IB, W) hipLaunchKernelGGL((strassen_pre2_kernel<V, IB, W>), g, b, 0, s, T, f, bpp)
-        if (pairs) {
-            if (T.variant == 0) { if (side) MMM_PRE2(0, true, 2); else MMM_PRE2(0, false, 2); }
-            else { if (side) MMM_PRE2(1, true, 2); else MMM_PRE2(1, false, 2); }
-        } else {
-            if (T.variant == 0) { if (side) MMM_PRE2(0, true, 1); else MMM_PRE2(0, false, 1); }
-            else { if (side) MMM_PRE2(1, true, 1); else MMM_PRE2(1, false, 1); }
-        }
-#undef MMM_PRE2
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+    const i64 sz_a = T.n[f + 1] * T.p[f + 1], sz_b = T.p[f + 1] * T.m[f + 1];
+    const i64 bpp_a = cdiv(pairs ? sz_a / 2 : sz_a, 256 * EPT), bpp_b = cdiv(pairs ? sz_b / 2 : sz_b, 256 * EPT);
+    const i64 blocks_a = parents * bpp_a, blocks = blocks_a + parents * bpp_b;
+    if (blocks == 0) return hipSuccess;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    const dim3 g((unsigned)blocks), b(256);
+#define MMM_PRE2(V, W) hipLaunchKernelGGL((strassen_pre2_kernel<V, W>), g, b, 0, s, T, f, bpp_a, blocks_a, bpp_b)
+    if (pairs) {
+        if (T.variant == 0) MMM_PRE2(0, 2);
+        else MMM_PRE2(1, 2);
+    } else {
+        if (T.variant == 0) MMM_PRE2(0, 1);
+        else MMM_PRE2(1, 1);
     }
-    return hipSuccess;
+#undef MMM_PRE2
+    return hipGetLastError();
 }
 
 hipError_t launch_strassen_post2(const StrassenTree& T, int f, double* C, i64 ldc, hipStream_t s)
