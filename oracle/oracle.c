@@ -639,13 +639,14 @@ int oracle_strassen(const double* A, const double* B, double* C, i64 N, i64 P, i
  *    round-to-nearest-even:  r_0 = x,  d_t = rint(2^beta r_{t-1}),
  *    r_t = 2^beta r_{t-1} - d_t  (all exact), so |d_t| <= 2^(beta-1) and
  *    x = sum_t d_t 2^(-beta t) + r_s 2^(-beta s).
- *    Byte digits (rule 1, beta = 8, for signed 8-bit digit storage, which
- *    holds -128..127 but not the 257 values of the rule above): the
+ *    Rule 1 (byte digits when beta = 8, for signed 8-bit digit storage,
+ *    which holds -128..127 but not the 257 values of the rule above): the
  *    exponents of step 2 are one larger (e_i = E + 2, so |x| < 1/4), the
- *    scaled entry is rounded once, X = rint(x 2^(8 s)), and X is written in
- *    base 256 with digits in [-128, 127] from the least significant:
- *    d_s = ((X + 128) mod 256) - 128, X <- (X - d_s) / 256, then d_{s-1},
- *    and so on; |X| < 2^(8 s - 2) leaves d_1 in range and X = 0 at the end.
+ *    scaled entry is rounded once, X = rint(x 2^(beta s)), and X is written
+ *    in base 2^beta with digits in [-2^(beta-1), 2^(beta-1)) from the least
+ *    significant: d_s = ((X + 2^(beta-1)) mod 2^beta) - 2^(beta-1),
+ *    X <- (X - d_s) / 2^beta, then d_{s-1}, and so on; |X| < 2^(beta s - 2)
+ *    leaves d_1 in range and X = 0 at the end.
  * 4. For g = 2 .. s+1 the exact integer
  *      G_g[i][j] = sum_{t+u=g} sum_k dA_t[i][k] dB_u[k][j]
  *    is formed (int64; no rounding).  Pairs with t+u > s+1 are dropped.
@@ -674,10 +675,12 @@ static int row_exponent(double mx)
 static void split_cut(double x, int s, int beta, int rule, int32_t* d, i64 stride)
 {
     if (rule == 1) {
-        int64_t X = (int64_t)rint(ldexp(x, 8 * s));
+        /* base 2^beta, digits in [-2^(beta-1), 2^(beta-1)); byte digits are beta = 8 */
+        const int64_t base = (int64_t)1 << beta, half = base / 2;
+        int64_t X = (int64_t)rint(ldexp(x, beta * s));
         for (int t = s; t >= 1; --t) {
-            const int64_t v = ((X + 128) & 255) - 128;
-            X = (X - v) / 256;
+            const int64_t v = ((X + half) & (base - 1)) - half;
+            X = (X - v) / base;
             d[(i64)(t - 1) * stride] = (int32_t)v;
         }
         return;
