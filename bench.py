@@ -91,16 +91,18 @@ LATENCY_METHODS = [
 # scaled by what the counters read for a plain 512 MiB device copy (FETCH x 2.0, WRITE x 1.0); valid only
 # while the kernel's source is the one measured (sha256 below), otherwise reported as null.
 COUNTED_TRAFFIC = {
-    "kahan": {"bytes": 3.3575e+09, "file": "paper_1106_1347_amd/csrc/valu_gemm.hip",
+    "kahan": {"bytes": 3.3574e+09, "file": "paper_1106_1347_amd/csrc/valu_gemm.hip",
               "sha256": "3999925ed4c1c3b6c10677ab9428b5bb88f03d0fe1879683c810a2951565c401"},
-    "dgemm": {"bytes": 1.8627e+09, "file": "paper_1106_1347_amd/csrc/dgemm.hip",
+    "dgemm": {"bytes": 1.8792e+09, "file": "paper_1106_1347_amd/csrc/dgemm.hip",
               "sha256": "3d5b9cd6f817b5518e0aafbca82be4c003b8373516fa8beb8b3ddf410c48946b"},
-    "split_int8_s7": {"bytes": 2.4837e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
+    "split_int8_s7": {"bytes": 2.3680e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
                       "sha256": "1845cce1ddbcee26e5883e89e7f488deb807c39443e1e1d8ff28bb23dba82dcc"},
-    "split_int8_b8_s6": {"bytes": 2.0035e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
+    "split_int8_b8_s6": {"bytes": 2.0120e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
                          "sha256": "1845cce1ddbcee26e5883e89e7f488deb807c39443e1e1d8ff28bb23dba82dcc"},
-    "split_bf16_b9_s5": {"bytes": 6.4450e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
+    "split_bf16_b9_s5": {"bytes": 6.8021e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
                          "sha256": "1845cce1ddbcee26e5883e89e7f488deb807c39443e1e1d8ff28bb23dba82dcc"},
+    "split_fp16_s5": {"bytes": 6.4932e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
+                      "sha256": "1845cce1ddbcee26e5883e89e7f488deb807c39443e1e1d8ff28bb23dba82dcc"},
 }
 
 
@@ -706,32 +708,52 @@ def main():
            "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": None, "data": "synthetic",
            "config": {"workload": "C = AB, N = P = M = 8192, FP64 wide-range entries (+-2^u, u ~ U[-20,20], rows "
-                                  "x 2^v, v ~ U{-10..10}); split-precision product vs the plain FP64 matrix-core "
-                                  "GEMM; one product per step", "parallelism": "single GPU"}}
+                                  "x 2^v, v ~ U{-10..10}); split-precision product with 3-6 BF16 or FP16 slices "
+                                  "and FP32 accumulation vs the plain FP64 matrix-core GEMM; one product per step "
+                                  "(int8 digits beyond that under int8_extension)", "parallelism": "single GPU"}}
     if head is not None:
         cf = head["configs"]
-        splits = [k for k in cf if k.startswith("split") and cf[k]["fp64_grade"]]
-        best = max(splits, key=lambda k: cf[k]["tflops_fp64_grade"]) if splits else None
         dg = cf.get("dgemm")
-        if best is not None:
-            b = cf[best]
-            kw = [h for h in HEADLINE if h[0] == best][0][2]
+
+        def kw_of(name):
+            return [h for h in HEADLINE if h[0] == name][0][2]
+
+        def summary(name):
+            b, kw = cf[name], kw_of(name)
             peak = PEAK_INT8_MFMA_TOPS if kw["split_type"] == "int8" else PEAK_BF16_MFMA_TFLOPS
-            out.update({"value": b["tflops_fp64_grade"], "ms_per_step": b["ms_mean"],
-                        "dtype": {"int8": "i8 digits, i32 accumulation, f64 recombination",
-                                  "bf16": "bf16 digits, f32 accumulation, f64 recombination",
-                                  "fp16": "f16 digits, f32 accumulation, f64 recombination"}[kw["split_type"]],
-                        "p50_ms": b["ms_p50"], "p99_ms": b["ms_p99"],
-                        "rel_err_inf": b["rel_err_inf_sampled_rows"],
-                        "best_split": best})
-            out["config"].update({"split": best, "digits": kw["split_slices"], "digit_type": kw["split_type"]})
-            out["roofline"] = {"bound": "mfma", "kernel": "digit GEMM of %s" % best,
-                               "achieved": b["digit_gemm_T_ops_per_s"], "peak": peak, "unit": "TFLOP/s",
-                               "frac": b["digit_gemm_frac_peak"], "traffic": counted_traffic(best),
-                               "note": "achieved = %d digit pairs x 2NPM / mean launch time of the digit GEMM "
-                                       "kernel (HIP events on its stream, %d launches); peak = the published "
-                                       "dense %s matrix-core rate (int8: operations)"
-                                       % (b["digit_pairs"], b["dominant_kernel_launches"], kw["split_type"])}
+            r = {"value": b["tflops_fp64_grade"], "ms_per_step": b["ms_mean"],
+                 "dtype": {"int8": "i8 digits, i32 accumulation, f64 recombination",
+                           "bf16": "bf16 digits, f32 accumulation, f64 recombination",
+                           "fp16": "f16 digits, f32 accumulation, f64 recombination"}[kw["split_type"]],
+                 "p50_ms": b["ms_p50"], "p99_ms": b["ms_p99"], "rel_err_inf": b["rel_err_inf_sampled_rows"],
+                 "split": name, "digits": kw["split_slices"], "digit_type": kw["split_type"],
+                 "digit_bits": kw.get("split_bits", 0) or {"int8": 7, "bf16": 8, "fp16": 9}[kw["split_type"]]}
+            r["roofline"] = {"bound": "mfma", "kernel": "digit GEMM of %s" % name,
+                             "achieved": b["digit_gemm_T_ops_per_s"], "peak": peak, "unit": "TFLOP/s",
+                             "frac": b["digit_gemm_frac_peak"], "traffic": counted_traffic(name),
+                             "note": "achieved = %d digit pairs x 2NPM / mean launch time of the digit GEMM "
+                                     "kernel (HIP events on its stream, %d launches); peak = the published "
+                                     "dense %s matrix-core rate (int8: operations)"
+                                     % (b["digit_pairs"], b["dominant_kernel_launches"], kw["split_type"])}
+            if dg is not None:
+                r["vs_dgemm"] = b["tflops_fp64_grade"] / dg["tflops_fp64_grade"]
+            return r
+
+        ok = [k for k in cf if k.startswith("split") and cf[k]["fp64_grade"]]
+        # the headline: the configuration the metric names (3-6 BF16 or FP16 slices, FP32 accumulation)
+        named = [k for k in ok if kw_of(k)["split_type"] in ("bf16", "fp16") and 3 <= kw_of(k)["split_slices"] <= 6]
+        best = max(named, key=lambda k: cf[k]["tflops_fp64_grade"]) if named else None
+        if best is not None:
+            h = summary(best)
+            out.update({"value": h["value"], "ms_per_step": h["ms_per_step"], "dtype": h["dtype"],
+                        "p50_ms": h["p50_ms"], "p99_ms": h["p99_ms"], "rel_err_inf": h["rel_err_inf"],
+                        "best_split": best, "roofline": h["roofline"]})
+            out["config"].update({"split": best, "digits": h["digits"], "digit_type": h["digit_type"],
+                                  "digit_bits": h["digit_bits"]})
+        # beyond the named configuration: INT8 digits (7-bit nearest digits or 8-bit byte digits)
+        int8 = [k for k in ok if kw_of(k)["split_type"] == "int8"]
+        if int8:
+            out["int8_extension"] = summary(max(int8, key=lambda k: cf[k]["tflops_fp64_grade"]))
         if dg is not None:
             out["dgemm_tflops"] = dg["tflops_fp64_grade"]
             out["dgemm_ms"] = dg["ms_mean"]
