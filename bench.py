@@ -96,13 +96,13 @@ COUNTED_TRAFFIC = {
     "dgemm": {"bytes": 1.8792e+09, "file": "paper_1106_1347_amd/csrc/dgemm.hip",
               "sha256": "3d5b9cd6f817b5518e0aafbca82be4c003b8373516fa8beb8b3ddf410c48946b"},
     "split_int8_s7": {"bytes": 2.3680e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
-                      "sha256": "1845cce1ddbcee26e5883e89e7f488deb807c39443e1e1d8ff28bb23dba82dcc"},
+                      "sha256": "c9044333ed489838309c9d07b2c5991dc8a34080cecd3cff9871edef77dbcd53"},
     "split_int8_b8_s6": {"bytes": 2.0120e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
-                         "sha256": "1845cce1ddbcee26e5883e89e7f488deb807c39443e1e1d8ff28bb23dba82dcc"},
+                         "sha256": "c9044333ed489838309c9d07b2c5991dc8a34080cecd3cff9871edef77dbcd53"},
     "split_bf16_b9_s5": {"bytes": 6.8021e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
-                         "sha256": "1845cce1ddbcee26e5883e89e7f488deb807c39443e1e1d8ff28bb23dba82dcc"},
+                         "sha256": "c9044333ed489838309c9d07b2c5991dc8a34080cecd3cff9871edef77dbcd53"},
     "split_fp16_s5": {"bytes": 6.4932e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
-                      "sha256": "1845cce1ddbcee26e5883e89e7f488deb807c39443e1e1d8ff28bb23dba82dcc"},
+                      "sha256": "c9044333ed489838309c9d07b2c5991dc8a34080cecd3cff9871edef77dbcd53"},
 }
 
 

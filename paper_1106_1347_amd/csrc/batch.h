@@ -82,7 +82,8 @@ struct SplitTables {
 };
 // Workgroups of the digit passes for one job (host and device agree).
 __host__ __device__ inline i64 split_a_blocks(const SplitJob& j) { return (j.Np * (j.Kp / 8) + 255) / 256; }
-__host__ __device__ inline i64 split_b_blocks(const SplitJob& j) { return (j.Kp / 64) * (j.Mp / 64); }
+constexpr int kBJ = 32;  // columns of B per digit-pass workgroup (64 k each)
+__host__ __device__ inline i64 split_b_blocks(const SplitJob& j) { return (j.Kp / 64) * (j.Mp / kBJ); }
 
 // Workspace bytes for one split job; fills the job's Np/Mp/Kp and returns
 // (size_t)-1 when unsupported.  Offsets of the job's buffers inside its

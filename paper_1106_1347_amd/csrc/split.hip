@@ -291,34 +291,35 @@ __device__ __forceinline__ void split_a_body(const double* __restrict__ A, i64 N
     }
 }
 
-// B (P x M, row-major) to SB[kb][u][j][64 bytes]: a 64 (k) x 64 (j) tile
+// B (P x M, row-major) to SB[kb][u][j][64 bytes]: a 64 (k) x kBJ (j) tile
 // goes through LDS so both the loads (along j) and the stores (64-byte
-// blocks of neighbouring columns) are contiguous.
+// blocks of neighbouring columns) are contiguous.  kBJ = 32 keeps the tile
+// at 17 KiB of LDS, so the workgroups that share the launch (A's, which
+// need none) are not limited to four per CU by it.
 template <int DT>
 __device__ __forceinline__ void split_b_body(const double* __restrict__ B, i64 P, i64 M, i64 Mp, i64 Kp,
                                              const double* __restrict__ cmax, const int* lam, int s, int beta,
-                                             char* __restrict__ SB, int* __restrict__ fb, i64 block, double (*T)[65],
-                                             bool cmax_raw = false)
+                                             char* __restrict__ SB, int* __restrict__ fb, i64 block,
+                                             double (*T)[kBJ + 1], bool cmax_raw = false)
 {
     constexpr int ES = Digit<DT>::esize;
     constexpr int TB = KB / (8 * ES);  // threads per 64-byte block
-    const i64 tiles_j = Mp / 64;
+    const i64 tiles_j = Mp / kBJ;
     const i64 kt = block / tiles_j;
-    const i64 j0 = (block - kt * tiles_j) * 64, k0 = kt * 64;
+    const i64 j0 = (block - kt * tiles_j) * kBJ, k0 = kt * 64;
     const int tid = threadIdx.x;
     const double sc = lam ? ldexp(1.0, -*lam) : 1.0;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int e = q * 256 + tid, kr = e / 64, jc = e % 64;
+    for (int q = 0; q < 64 * kBJ / 256; ++q) {
+        const int e = q * 256 + tid, kr = e / kBJ, jc = e % kBJ;
         const i64 k = k0 + kr, j = j0 + jc;
         T[kr][jc] = (k < P && j < M) ? B[k * M + j] : 0.0;
     }
     __syncthreads();
-    // 512 chunks of 8 entries (64 columns x 64 k) over two passes of 256 threads
-#pragma unroll
-    for (int pass = 0; pass < 2; ++pass) {
-        const int c = pass * 256 + tid;
-        const int q = c % TB, jc = (c / TB) % 64, blk = c / (TB * 64);
+    // 256 chunks of 8 entries (kBJ columns x 64 k), one per thread
+    {
+        const int c = tid;
+        const int q = c % TB, jc = (c / TB) % kBJ, blk = c / (TB * kBJ);
         const int kk = blk * (KB / ES) + q * 8;
         const i64 j = j0 + jc;
         const int e = j < M ? vec_exponent(cmax_raw ? cmax[j] * sc : cmax[j]) + byte_digits(DT, beta) : 0;
@@ -333,7 +334,7 @@ __device__ __forceinline__ void split_b_body(const double* __restrict__ B, i64 P
 }
 
 // One launch for both operands' digits: workgroups below nblk_a stride over
-// A's (row, 8-entry chunk) pairs, the rest take one 64 x 64 tile of B each.
+// A's (row, 8-entry chunk) pairs, the rest take one 64 x kBJ tile of B each.
 template <int DT>
 __global__ __launch_bounds__(256) void split_ab_kernel(const double* __restrict__ A, i64 N, i64 P, i64 Np, i64 Kp,
                                                        const double* __restrict__ rmax, const int* lam, int s,
@@ -342,7 +343,7 @@ __global__ __launch_bounds__(256) void split_ab_kernel(const double* __restrict_
                                                        const double* __restrict__ cmax, char* __restrict__ SB,
                                                        int* __restrict__ fb)
 {
-    __shared__ double T[64][65];
+    __shared__ double T[64][kBJ + 1];
     const i64 b = blockIdx.x;
     if (b < nblk_a) split_a_body<DT>(A, N, P, Np, Kp, rmax, lam, s, beta, SA, ea, b, nblk_a, true);
     else split_b_body<DT>(B, P, M, Mp, Kp, cmax, lam, s, beta, SB, fb, b - nblk_a, T, true);
@@ -1143,14 +1144,14 @@ __global__ void jobs_lambda_kernel(const SplitJob* jobs, int n)
 
 // Digits of every job of a group in one launch: workgroups below na take
 // an entry of the A table (a range of one job's (row, 8-entry chunk)
-// pairs), the rest an entry of the B table (one 64 x 64 tile of a job's B).
+// pairs), the rest an entry of the B table (one 64 x kBJ tile of a job's B).
 template <int DT>
 __global__ __launch_bounds__(256) void jobs_split_ab_kernel(const SplitJob* __restrict__ jobs,
                                                             const JobBlock* __restrict__ ablocks, i64 na,
                                                             const JobBlock* __restrict__ bblocks, int beta,
                                                             bool scaled)
 {
-    __shared__ double T[64][65];
+    __shared__ double T[64][kBJ + 1];
     const i64 w = blockIdx.x;
     if (w < na) {
         const JobBlock b = ablocks[w];
@@ -1352,7 +1353,7 @@ hipError_t run_split_dt(const double* A, const double* B, double* C, i64 N, i64 
     {
         i64 blk_a = cdiv(L.Np * (L.Kp / 8), 256);
         if (blk_a > 256 * 64) blk_a = 256 * 64;
-        const i64 blk_b = (L.Kp / 64) * (L.Mp / 64);
+        const i64 blk_b = (L.Kp / 64) * (L.Mp / kBJ);
         if (blk_a + blk_b > 0x7fffffffLL) return hipErrorInvalidConfiguration;
         hipLaunchKernelGGL((split_ab_kernel<DT>), dim3((unsigned)(blk_a + blk_b)), dim3(256), 0, st, A, N, P, L.Np,
                            L.Kp, rmax, lam, L.s, L.beta, ws + L.SA, (int*)(ws + L.ea), blk_a, B, M, L.Mp, cmax,
