@@ -200,7 +200,10 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
                             mmm_batch** plan_out);
 
 /* Enqueue every product of the plan on `stream` (a fixed, short sequence of
- * persistent kernels; no host synchronisation, capturable in a HIP graph). */
+ * persistent kernels; no host synchronisation, capturable in a HIP graph).
+ * Launches of one plan must not overlap on the device (they share the
+ * plan's workspace and tile counters): keep them on one stream, or order
+ * them with events. */
 mmm_status mmm_batch_launch(mmm_batch* plan, void* stream);
 
 /* Free the plan's device memory (synchronises the plan's last stream). */

@@ -11,13 +11,38 @@ enum DgemmTile { DGEMM_TILE_AUTO = 0, DGEMM_TILE_128x128 = 1, DGEMM_TILE_64x64 =
 int dgemm_tile_bm(int tile);
 int dgemm_tile_bn(int tile);
 int dgemm_grouped_per_cu(int tile);
-// Tiles of a persistent grouped kernel per workgroup: workgroup w runs the
-// global tile indices list[off[w]] .. list[off[w + 1] - 1] (device arrays
-// of grid + 1 and total ints), a schedule balanced on the host.
+// Tiles of a persistent grouped kernel: the global tile indices list[0 ..
+// total - 1], longest first (sorted on the host).  Workgroups claim the
+// next position from ctr[0] by an atomic add until the list runs out, then
+// count themselves out on ctr[1]; the last one out puts both back to zero
+// for the next launch (the plan zeroes them once).  A workgroup that starts
+// late, with the chip busy on another branch of the batch, claims fewer
+// tiles instead of finishing last.  Launches sharing one counter pair must
+// not overlap.
 struct TileSchedule {
-    const int* off;
     const int* list;
+    int* ctr;
+    int total;
 };
+
+// Position of the calling workgroup's next tile (the same for every thread;
+// `slot` is a __shared__ int of the kernel).  The caller keeps a barrier
+// between its use of one position and the next claim.
+__device__ inline int claim_tile(const TileSchedule& sch, int* slot)
+{
+    if (threadIdx.x == 0) *slot = atomicAdd(sch.ctr, 1);
+    __syncthreads();
+    return *slot;
+}
+
+// Called once by every workgroup after its last (failed) claim.
+__device__ inline void release_tiles(const TileSchedule& sch)
+{
+    if (threadIdx.x == 0 && atomicAdd(sch.ctr + 1, 1) == (int)gridDim.x - 1) {
+        atomicExch(sch.ctr, 0);
+        atomicExch(sch.ctr + 1, 0);
+    }
+}
 
 // Persistent grid of `grid` workgroups over the `total` tiles of `nprob`
 // problems (device tables: probs[nprob], prefix[nprob + 1]).

@@ -3,22 +3,22 @@
 // The plan groups the FP64 problems by DGEMM tile shape and the split
 // problems by (digit type, digit count, flush scheme, tile variant,
 // accumulator scheme); every group runs as one persistent kernel over a
-// grid sized to the chip, each workgroup walking a tile list balanced here
-// (longest tiles first, each to the least-loaded workgroup).  All split
-// jobs share one preprocessing chain: one pass over every 64-row strip of
-// every problem's A and B for the norms and row/column maxima (a strip
-// table built here), lambda, and one digit pass over tables of row chunks
-// and column tiles.  The FP64 groups run on one branch of one HIP graph,
-// the split preprocessing on another, which then forks into one branch per
-// split group, so all of them overlap on the device.  A tile's arithmetic
-// does not depend on the tile shape or on which workgroup runs it, so every
-// result equals the single-call result bit for bit.
+// grid sized to the chip, whose workgroups claim the group's tiles longest
+// first from a counter (so one that starts late, behind another branch's
+// work, takes fewer tiles).  All split jobs share one preprocessing chain:
+// one pass over every 64-row strip of every problem's A and B for the norms
+// and row/column maxima (a strip table built here), lambda, and one digit
+// pass over tables of row chunks and column tiles.  The FP64 groups run on
+// one branch of one HIP graph, dispatched first; the split preprocessing
+// runs on another beside them and then forks into a few branches for the
+// split groups.  A tile's arithmetic does not depend on the tile shape or
+// on which workgroup runs it, so every result equals the single-call result
+// bit for bit.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
 #include <algorithm>
 #include <map>
-#include <queue>
 #include <tuple>
 #include <vector>
 
@@ -41,13 +41,19 @@ namespace {
 
 size_t al256(size_t x) { return (x + 255) / 256 * 256; }
 
+#ifndef MMM_BATCH_SPLIT_BRANCHES
+#define MMM_BATCH_SPLIT_BRANCHES 2
+#endif
+// graph branches the split groups spread over (beside the FP64 branch)
+constexpr size_t kSplitBranches = MMM_BATCH_SPLIT_BRANCHES;
+
 struct DGroup {
     int tile;
     std::vector<Gemm> probs;
     std::vector<i64> prefix;
-    std::vector<int> soff, slist;
+    std::vector<int> slist;
     int grid = 0;
-    size_t off_probs = 0, off_prefix = 0, off_soff = 0, off_slist = 0;
+    size_t off_probs = 0, off_prefix = 0, off_ctr = 0, off_slist = 0;
 };
 
 struct SGroup {
@@ -55,10 +61,10 @@ struct SGroup {
     std::vector<SplitJob> jobs;
     std::vector<size_t> ws_off;
     std::vector<i64> prefix;
-    std::vector<int> soff, slist;
+    std::vector<int> slist;
     int grid = 0;
     int first = 0;  // index of the group's first job in the plan's job table
-    size_t off_prefix = 0, off_soff = 0, off_slist = 0;
+    size_t off_prefix = 0, off_ctr = 0, off_slist = 0;
 };
 
 struct Interval {
@@ -67,30 +73,14 @@ struct Interval {
     int idx;
 };
 
-// Longest first: tiles sorted by estimated cost (stable, descending), each
-// given to the workgroup with the least work so far (ties: lowest index).
-// off[w] .. off[w + 1] - 1 index workgroup w's tiles in list.
-void balance(const std::vector<i64>& cost, int grid, std::vector<int>& off, std::vector<int>& list)
+// Claim order of a group's tiles: longest first by estimated cost (stable,
+// so the tiles of one problem stay together within a cost), each claimed
+// by whichever workgroup is free next.
+void longest_first(const std::vector<i64>& cost, std::vector<int>& list)
 {
-    std::vector<int> order(cost.size());
-    for (size_t t = 0; t < order.size(); ++t) order[t] = (int)t;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-    typedef std::pair<i64, int> Load;
-    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
-    for (int w = 0; w < grid; ++w) heap.push(Load{0, w});
-    std::vector<std::vector<int>> per(grid);
-    for (int t : order) {
-        const Load l = heap.top();
-        heap.pop();
-        per[l.second].push_back(t);
-        heap.push(Load{l.first + cost[t], l.second});
-    }
-    off.assign(grid + 1, 0);
-    list.clear();
-    for (int w = 0; w < grid; ++w) {
-        list.insert(list.end(), per[w].begin(), per[w].end());
-        off[w + 1] = (int)list.size();
-    }
+    list.resize(cost.size());
+    for (size_t t = 0; t < list.size(); ++t) list[t] = (int)t;
+    std::stable_sort(list.begin(), list.end(), [&](int a, int b) { return cost[a] > cost[b]; });
 }
 
 int pick_tile(const mmm_problem& p)
@@ -205,10 +195,10 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
         }
         if (g.prefix.back() > 0x7fffffff) return bfail(MMM_EUNSUPPORTED, "batch: too many DGEMM tiles in one plan");
         g.grid = (int)std::min<i64>(g.prefix.back(), (i64)cus * dgemm_grouped_per_cu(g.tile));
-        balance(cost, g.grid, g.soff, g.slist);
+        longest_first(cost, g.slist);
         g.off_probs = take(sizeof(Gemm) * g.probs.size());
         g.off_prefix = take(sizeof(i64) * g.prefix.size());
-        g.off_soff = take(sizeof(int) * g.soff.size());
+        g.off_ctr = take(2 * sizeof(int));
         g.off_slist = take(sizeof(int) * (g.slist.size() ? g.slist.size() : 1));
     }
     // every split job of every group in one table (group by group), with
@@ -249,8 +239,8 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
         }
         if (g.prefix.back() > 0x7fffffff) return bfail(MMM_EUNSUPPORTED, "batch: too many split tiles in one plan");
         g.grid = (int)std::min<i64>(g.prefix.back(), (i64)cus * g.g.per_cu);
-        balance(cost, g.grid, g.soff, g.slist);
-        g.off_soff = take(sizeof(int) * g.soff.size());
+        longest_first(cost, g.slist);
+        g.off_ctr = take(2 * sizeof(int));
         g.off_slist = take(sizeof(int) * (g.slist.size() ? g.slist.size() : 1));
     }
     const size_t off_ws = off;
@@ -273,7 +263,6 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
     for (auto& kv : dg) {
         memcpy(host.data() + kv.second.off_probs, kv.second.probs.data(), sizeof(Gemm) * kv.second.probs.size());
         memcpy(host.data() + kv.second.off_prefix, kv.second.prefix.data(), sizeof(i64) * kv.second.prefix.size());
-        memcpy(host.data() + kv.second.off_soff, kv.second.soff.data(), sizeof(int) * kv.second.soff.size());
         memcpy(host.data() + kv.second.off_slist, kv.second.slist.data(), sizeof(int) * kv.second.slist.size());
     }
     memcpy(host.data() + off_strips, strips.data(), sizeof(JobBlock) * strips.size());
@@ -283,9 +272,9 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
         memcpy(host.data() + off_jobs + sizeof(SplitJob) * (size_t)kv.second.first, kv.second.jobs.data(),
                sizeof(SplitJob) * kv.second.jobs.size());
         memcpy(host.data() + kv.second.off_prefix, kv.second.prefix.data(), sizeof(i64) * kv.second.prefix.size());
-        memcpy(host.data() + kv.second.off_soff, kv.second.soff.data(), sizeof(int) * kv.second.soff.size());
         memcpy(host.data() + kv.second.off_slist, kv.second.slist.data(), sizeof(int) * kv.second.slist.size());
     }
+    // (the tile counters stay zero: the host image is zero-filled)
     hipError_t e = hipSuccess;
     if (off_ws > 0) e = hipMemcpyAsync(base, host.data(), off_ws, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -293,17 +282,29 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
     for (auto& kv : sg)
         if (e == hipSuccess) e = split_grouped_prepare(kv.second.g);
 
-    // record the launch sequence: the split branch forked first, so its
-    // short memory-bound preprocessing kernels are dispatched before the
-    // persistent FP64 kernels take every workgroup slot; after the shared
-    // preprocessing each split group's GEMM on a branch of its own (largest
-    // first), so the small groups run beside the large one instead of after
-    // it; FP64 groups on the capture stream
+    // record the launch sequence.  The FP64 groups come first, on the
+    // capture stream: their persistent grids are dispatched at once and
+    // keep the matrix cores busy while the split branch's memory-bound
+    // preprocessing runs beside them.  After that shared preprocessing the
+    // split groups (largest first, each to the branch with the fewest tiles
+    // so far) run on at most kSplitBranches branches, so that every branch
+    // of the graph keeps a hardware queue of its own: a branch that shares
+    // one waits behind the other's persistent kernel.
     std::vector<SGroup*> order;
     for (auto& kv : sg) order.push_back(&kv.second);
     std::stable_sort(order.begin(), order.end(),
                      [](const SGroup* a, const SGroup* b) { return a->prefix.back() > b->prefix.back(); });
-    const size_t nbr = order.empty() ? 0 : order.size() - 1;  // extra split branches
+    const size_t nlanes = std::min<size_t>(order.size(), kSplitBranches);
+    std::vector<std::vector<SGroup*>> lanes(nlanes);
+    {
+        std::vector<i64> load(nlanes, 0);
+        for (SGroup* g : order) {
+            const size_t b = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+            lanes[b].push_back(g);
+            load[b] += g->prefix.back();
+        }
+    }
+    const size_t nbr = nlanes > 0 ? nlanes - 1 : 0;  // split branches beside `side`
     hipStream_t cap = nullptr, side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr, prepped = nullptr;
     std::vector<hipStream_t> br(nbr, nullptr);
@@ -320,6 +321,13 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
     if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         hipError_t le = hipEventRecord(fork, cap);
+        for (auto& kv : dg) {
+            if (le != hipSuccess) break;
+            DGroup& g = kv.second;
+            const TileSchedule sch{(const int*)(base + g.off_slist), (int*)(base + g.off_ctr), (int)g.slist.size()};
+            le = launch_dgemm_grouped(g.tile, (const Gemm*)(base + g.off_probs), (const i64*)(base + g.off_prefix),
+                                      (int)g.probs.size(), g.prefix.back(), g.grid, sch, cap);
+        }
         if (le == hipSuccess) le = hipStreamWaitEvent(side, fork, 0);
         const SplitJob* jobs = (const SplitJob*)(base + off_jobs);
         if (le == hipSuccess && njobs > 0) {
@@ -330,30 +338,22 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
             le = launch_split_prep(g0.dt, g0.beta, jobs, njobs, tab, c.split_scale_lambda != 0, side);
         }
         if (le == hipSuccess && nbr > 0) le = hipEventRecord(prepped, side);
-        for (size_t i = 0; i < order.size(); ++i) {
-            if (le != hipSuccess) break;
-            SGroup& g = *order[i];
-            hipStream_t gs = i == 0 ? side : br[i - 1];
-            if (i > 0) le = hipStreamWaitEvent(gs, prepped, 0);
-            if (le == hipSuccess)
-                le = launch_split_group_gemm(g.g, jobs + g.first, (int)g.jobs.size(),
-                                             (const i64*)(base + g.off_prefix), g.prefix.back(),
-                                             TileSchedule{(const int*)(base + g.off_soff),
-                                                          (const int*)(base + g.off_slist)},
-                                             g.grid, gs);
-            if (le == hipSuccess && i > 0) le = hipEventRecord(brj[i - 1], gs);
-        }
-        for (auto& kv : dg) {
-            if (le != hipSuccess) break;
-            DGroup& g = kv.second;
-            const TileSchedule sch{(const int*)(base + g.off_soff), (const int*)(base + g.off_slist)};
-            le = launch_dgemm_grouped(g.tile, (const Gemm*)(base + g.off_probs), (const i64*)(base + g.off_prefix),
-                                      (int)g.probs.size(), g.prefix.back(), g.grid, sch, cap);
+        for (size_t b = 0; b < nlanes && le == hipSuccess; ++b) {
+            hipStream_t gs = b == 0 ? side : br[b - 1];
+            if (b > 0) le = hipStreamWaitEvent(gs, prepped, 0);
+            for (SGroup* gp : lanes[b]) {
+                if (le != hipSuccess) break;
+                SGroup& g = *gp;
+                const TileSchedule sch{(const int*)(base + g.off_slist), (int*)(base + g.off_ctr),
+                                       (int)g.slist.size()};
+                le = launch_split_group_gemm(g.g, jobs + g.first, (int)g.jobs.size(), (const i64*)(base + g.off_prefix),
+                                             g.prefix.back(), sch, g.grid, gs);
+            }
+            if (le == hipSuccess && b > 0) le = hipEventRecord(brj[b - 1], gs);
         }
         if (le == hipSuccess) le = hipEventRecord(join, side);
         if (le == hipSuccess) le = hipStreamWaitEvent(cap, join, 0);
-        for (size_t i = 0; i < nbr && le == hipSuccess; ++i)
-            if (i + 1 < order.size()) le = hipStreamWaitEvent(cap, brj[i], 0);
+        for (size_t i = 0; i < nbr && le == hipSuccess; ++i) le = hipStreamWaitEvent(cap, brj[i], 0);
         e = hipStreamEndCapture(cap, &plan->graph);
         if (le != hipSuccess) e = le;
     }

@@ -317,17 +317,19 @@ __global__ __launch_bounds__(NT, MMM_DGEMM_MINWAVES) void dgemm_dma_kernel(Src s
 
 // Persistent grid over the tiles of many problems: tile t belongs to the
 // problem p with prefix[p] <= t < prefix[p+1] and is its (t - prefix[p])-th
-// tile in row-major tile order.  Workgroup b takes tiles b, b + grid, ...
+// tile in row-major tile order.  Workgroups claim tiles from the schedule.
 template <int WMB, int WNB>
 __global__ __launch_bounds__(NT, MMM_DGEMM_MINWAVES) void dgemm_grouped_kernel(const Gemm* __restrict__ probs,
                                                            const i64* __restrict__ prefix, int nprob,
-                                                           const int* __restrict__ soff,
-                                                           const int* __restrict__ slist)
+                                                           TileSchedule sch)
 {
     typedef DTile<WMB, WNB> T;
     __shared__ __align__(16) typename T::Smem sm;
-    for (int q = soff[blockIdx.x]; q < soff[blockIdx.x + 1]; ++q) {
-        const i64 t = slist[q];
+    __shared__ int slot;
+    for (;;) {
+        const int q = claim_tile(sch, &slot);
+        if (q >= sch.total) break;
+        const i64 t = sch.list[q];
         int lo = 0, hi = nprob - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -340,6 +342,7 @@ __global__ __launch_bounds__(NT, MMM_DGEMM_MINWAVES) void dgemm_grouped_kernel(c
         T::run(g, local / tiles_n, local % tiles_n, sm);
         __syncthreads();
     }
+    release_tiles(sch);
 }
 
 template <int WMB, int WNB, class Src>
@@ -446,14 +449,11 @@ hipError_t launch_dgemm_grouped(int tile, const Gemm* probs, const i64* prefix, 
 {
     if (total == 0 || nprob == 0) return hipSuccess;
     if (tile == DGEMM_TILE_128x128)
-        hipLaunchKernelGGL((dgemm_grouped_kernel<4, 4>), dim3(grid), dim3(NT), 0, s, probs, prefix, nprob, sch.off,
-                           sch.list);
+        hipLaunchKernelGGL((dgemm_grouped_kernel<4, 4>), dim3(grid), dim3(NT), 0, s, probs, prefix, nprob, sch);
     else if (tile == DGEMM_TILE_64x64)
-        hipLaunchKernelGGL((dgemm_grouped_kernel<2, 2>), dim3(grid), dim3(NT), 0, s, probs, prefix, nprob, sch.off,
-                           sch.list);
+        hipLaunchKernelGGL((dgemm_grouped_kernel<2, 2>), dim3(grid), dim3(NT), 0, s, probs, prefix, nprob, sch);
     else
-        hipLaunchKernelGGL((dgemm_grouped_kernel<4, 2>), dim3(grid), dim3(NT), 0, s, probs, prefix, nprob, sch.off,
-                           sch.list);
+        hipLaunchKernelGGL((dgemm_grouped_kernel<4, 2>), dim3(grid), dim3(NT), 0, s, probs, prefix, nprob, sch);
     return hipGetLastError();
 }
 

@@ -895,13 +895,15 @@ __global__ __launch_bounds__(tile_cfg(DT, S, FLUSH).threads(), tile_cfg(DT, S, F
 template <int DT, int S, bool FLUSH, int V, int PPA>
 __global__ __launch_bounds__(grouped_tile_cfg(DT, S, FLUSH, V, PPA).threads(), grouped_tile_cfg(DT, S, FLUSH, V, PPA).minw) void split_gemm_grouped_kernel(const SplitJob* __restrict__ jobs,
                                                                  const i64* __restrict__ prefix, int njobs,
-                                                                 int beta, int unit, const int* __restrict__ soff,
-                                                                 const int* __restrict__ slist)
+                                                                 int beta, int unit, TileSchedule sch)
 {
     extern __shared__ __align__(16) char lds[];
+    __shared__ int slot;
     constexpr TileCfg TC = grouped_tile_cfg(DT, S, FLUSH, V, PPA);
-    for (int q = soff[blockIdx.x]; q < soff[blockIdx.x + 1]; ++q) {
-        const i64 t = slist[q];
+    for (;;) {
+        const int q = claim_tile(sch, &slot);
+        if (q >= sch.total) break;
+        const i64 t = sch.list[q];
         int lo = 0, hi = njobs - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -915,6 +917,7 @@ __global__ __launch_bounds__(grouped_tile_cfg(DT, S, FLUSH, V, PPA).threads(), g
                                  local % tiles_n, beta, unit, j.runlen, lds);
         __syncthreads();
     }
+    release_tiles(sch);
 }
 
 // ---- batched preprocessing: blockIdx.y selects the job -----------------------
@@ -1375,7 +1378,7 @@ hipError_t launch_grouped_gemm(const SplitJob* jobs, const i64* prefix, int n, i
     const size_t lds = split_lds_bytes(TC, S);
     auto kern = split_gemm_grouped_kernel<DT, S, FLUSH, V, PPA>;
     if (!jobs) return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(TC.threads()), lds, st, jobs, prefix, n, beta, unit, sch.off, sch.list);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(TC.threads()), lds, st, jobs, prefix, n, beta, unit, sch);
     return hipGetLastError();
 }
 
@@ -1530,9 +1533,9 @@ hipError_t split_grouped_prepare(const SplitGroup& g)
 {
     // a null job table only sets the kernel's dynamic LDS limit
     switch (g.dt) {
-    case DT_BF16: return grouped_s<DT_BF16>(g, nullptr, nullptr, 0, 0, TileSchedule{nullptr, nullptr}, nullptr);
-    case DT_FP16: return grouped_s<DT_FP16>(g, nullptr, nullptr, 0, 0, TileSchedule{nullptr, nullptr}, nullptr);
-    case DT_INT8: return grouped_s<DT_INT8>(g, nullptr, nullptr, 0, 0, TileSchedule{nullptr, nullptr}, nullptr);
+    case DT_BF16: return grouped_s<DT_BF16>(g, nullptr, nullptr, 0, 0, TileSchedule{nullptr, nullptr, 0}, nullptr);
+    case DT_FP16: return grouped_s<DT_FP16>(g, nullptr, nullptr, 0, 0, TileSchedule{nullptr, nullptr, 0}, nullptr);
+    case DT_INT8: return grouped_s<DT_INT8>(g, nullptr, nullptr, 0, 0, TileSchedule{nullptr, nullptr, 0}, nullptr);
     default: return hipErrorNotSupported;
     }
 }

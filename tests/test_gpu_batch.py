@@ -3,7 +3,9 @@
 Every batched product must equal the single mmm_multiply result with the
 same method and config bit for bit (the tile arithmetic does not depend on
 the tile shape or on the workgroup that runs it), on every replay of the
-graph, with unrelated eager work between replays.
+graph, with unrelated eager work between replays.  The outputs are reset
+to NaN before each replay, so a replay whose tile counters were not put
+back to zero (its workgroups would claim nothing) fails.
 """
 import numpy as np
 import pytest
