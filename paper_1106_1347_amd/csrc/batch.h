@@ -10,7 +10,7 @@ enum DgemmTile { DGEMM_TILE_AUTO = 0, DGEMM_TILE_128x128 = 1, DGEMM_TILE_64x64 =
 
 int dgemm_tile_bm(int tile);
 int dgemm_tile_bn(int tile);
-int dgemm_grouped_per_cu(int tile);
+int dgemm_grouped_per_cu(int tile, bool share);
 // Tiles of a persistent grouped kernel: the global tile indices list[0 ..
 // total - 1], longest first (sorted on the host).  Workgroups claim the
 // next position from ctr[0] by an atomic add until the list runs out, then

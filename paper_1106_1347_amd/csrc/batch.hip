@@ -194,7 +194,8 @@ mmm_status mmm_batch_create(const mmm_problem* problems, int32_t count, const mm
             cost.insert(cost.end(), (size_t)nt, cdiv(g.probs[k].P, 16) + 4);
         }
         if (g.prefix.back() > 0x7fffffff) return bfail(MMM_EUNSUPPORTED, "batch: too many DGEMM tiles in one plan");
-        g.grid = (int)std::min<i64>(g.prefix.back(), (i64)cus * dgemm_grouped_per_cu(g.tile));
+        // beside split jobs, leave registers for the split branch's kernels
+        g.grid = (int)std::min<i64>(g.prefix.back(), (i64)cus * dgemm_grouped_per_cu(g.tile, !sg.empty()));
         longest_first(cost, g.slist);
         g.off_probs = take(sizeof(Gemm) * g.probs.size());
         g.off_prefix = take(sizeof(i64) * g.prefix.size());

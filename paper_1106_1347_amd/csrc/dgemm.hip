@@ -426,22 +426,33 @@ int dgemm_tile_bn(int tile) { return tile == DGEMM_TILE_128x128 ? 128 : 64; }
 // Workgroups of the persistent grouped kernel that fit on one CU at once (its
 // register and LDS footprint for that tile shape), so the grid can fill the
 // chip: smaller tiles leave room for more resident workgroups, whose loads
-// then overlap.
-int dgemm_grouped_per_cu(int tile)
+// then overlap.  With `share`, only as many as leave each SIMD at least
+// kShareVgprs of its 512 registers per lane for the kernels of another graph
+// branch: a grid that takes the whole register file keeps every other
+// kernel's waves off the chip while it runs (a workgroup of NT = 256 threads
+// puts one wave on each of the CU's four SIMDs).
+constexpr int kShareVgprs = 64;
+
+template <class K>
+int grouped_per_cu(K kern, bool share)
 {
     int n = 0;
-    hipError_t e;
-    if (tile == DGEMM_TILE_128x128)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, dgemm_grouped_kernel<4, 4>, NT, 0);
-    else if (tile == DGEMM_TILE_64x64)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, dgemm_grouped_kernel<2, 2>, NT, 0);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, dgemm_grouped_kernel<4, 2>, NT, 0);
-    if (e != hipSuccess || n < 1) {
+    hipFuncAttributes fa;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, NT, 0) != hipSuccess || n < 1 ||
+        hipFuncGetAttributes(&fa, (const void*)kern) != hipSuccess) {
         (void)hipGetLastError();
         return 2;
     }
+    const int vgprs = (fa.numRegs + 7) / 8 * 8;  // allocated in granules of 8
+    while (share && n > 1 && vgprs > 0 && 512 - n * vgprs < kShareVgprs) --n;
     return n;
+}
+
+int dgemm_grouped_per_cu(int tile, bool share)
+{
+    if (tile == DGEMM_TILE_128x128) return grouped_per_cu(dgemm_grouped_kernel<4, 4>, share);
+    if (tile == DGEMM_TILE_64x64) return grouped_per_cu(dgemm_grouped_kernel<2, 2>, share);
+    return grouped_per_cu(dgemm_grouped_kernel<4, 2>, share);
 }
 
 hipError_t launch_dgemm_grouped(int tile, const Gemm* probs, const i64* prefix, int nprob, i64 total, int grid,
