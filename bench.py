@@ -94,15 +94,15 @@ COUNTED_TRAFFIC = {
     "kahan": {"bytes": 3.3574e+09, "file": "paper_1106_1347_amd/csrc/valu_gemm.hip",
               "sha256": "3999925ed4c1c3b6c10677ab9428b5bb88f03d0fe1879683c810a2951565c401"},
     "dgemm": {"bytes": 1.8792e+09, "file": "paper_1106_1347_amd/csrc/dgemm.hip",
-              "sha256": "c769ca308290e90d267f4eed0542a308936ffd803c9efa844ffd86acdba2757e"},
+              "sha256": "a04198f0f018baea045a670da854d8cc2ac60034d88b563e4e5ee106d2248c49"},
     "split_int8_s7": {"bytes": 2.3680e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
-                      "sha256": "bfc653e9ea23a1a7a2206ed4a108ee390edd9128b142f0ab27e392e9833945e3"},
+                      "sha256": "c76702c8d4187d34db9bd884f660f047ef2b31b6f19fe0f78b868f7ff295d3ef"},
     "split_int8_b8_s6": {"bytes": 2.0120e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
-                         "sha256": "bfc653e9ea23a1a7a2206ed4a108ee390edd9128b142f0ab27e392e9833945e3"},
+                         "sha256": "c76702c8d4187d34db9bd884f660f047ef2b31b6f19fe0f78b868f7ff295d3ef"},
     "split_bf16_b9_s5": {"bytes": 6.8021e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
-                         "sha256": "bfc653e9ea23a1a7a2206ed4a108ee390edd9128b142f0ab27e392e9833945e3"},
+                         "sha256": "c76702c8d4187d34db9bd884f660f047ef2b31b6f19fe0f78b868f7ff295d3ef"},
     "split_fp16_s5": {"bytes": 6.4932e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
-                      "sha256": "bfc653e9ea23a1a7a2206ed4a108ee390edd9128b142f0ab27e392e9833945e3"},
+                      "sha256": "c76702c8d4187d34db9bd884f660f047ef2b31b6f19fe0f78b868f7ff295d3ef"},
 }
 
 

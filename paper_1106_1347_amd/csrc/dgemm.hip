@@ -139,10 +139,6 @@ struct DTile {
 
     __device__ __forceinline__ static void run(const Gemm& g, i64 tm, i64 tn, Smem& sm)
     {
-        const int tid = threadIdx.x;
-        const int lane = tid & 63, wave = tid >> 6;
-        const int wm = wave >> 1, wn = wave & 1;
-        const int li = lane & 15, lk = lane >> 4;
         const i64 m0 = tm * BM, n0 = tn * BN;
         v4d acc[WMB][WNB];
 #pragma unroll

@@ -1210,8 +1210,12 @@ int split_run_length(int s, int beta, i64 P)
 int flush_unit(int dt, int beta)
 {
     const double prod = ldexp(1.0, 2 * beta - 2);
-    const double budget = dt == DT_INT8 ? Digit<DT_INT8>::budget : Digit<DT_BF16>::budget;
-    const int mk = dt == DT_INT8 ? Digit<DT_INT8>::mfma_k : Digit<DT_BF16>::mfma_k;
+    const double budget = dt == DT_INT8   ? Digit<DT_INT8>::budget
+                          : dt == DT_FP16 ? Digit<DT_FP16>::budget
+                                          : Digit<DT_BF16>::budget;
+    const int mk = dt == DT_INT8   ? Digit<DT_INT8>::mfma_k
+                   : dt == DT_FP16 ? Digit<DT_FP16>::mfma_k
+                                   : Digit<DT_BF16>::mfma_k;
     const double steps = budget / prod / mk;
     return steps >= 1e9 ? 1000000000 : (int)steps;
 }
