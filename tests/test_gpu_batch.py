@@ -75,6 +75,30 @@ def test_batch_equals_single_calls_and_replays(mmm, typ, slices, bits):
     plan.close()
 
 
+@pytest.mark.parametrize("methods,slices", [(["dgemm"], [0]), (["split"], [3, 5, 6, 4])])
+def test_batch_single_kind_plans(mmm, methods, slices):
+    """Plans holding one kind of problem: only FP64 (no split branch; the FP64
+    grids take their full occupancy) or only split products of several digit
+    counts and tile variants (many split groups, several per graph branch,
+    each with its own tile counters).  Bitwise equal to single calls on every
+    replay."""
+    print("case batch single kind", methods, slices, flush=True)
+    cfg = mmm.Config(split_type="bf16", split_slices=6)
+    shapes = synth.batch_shapes(36, 11, 1, 300) + [(257, 129, 300), (3, 700, 5)]
+    probs = make_problems(shapes, 400, methods, slices)
+    want = [single(mmm, A, B, m, s, cfg).cpu() for (A, B, C, m, s, t) in probs]
+    plan = mmm.Batch(probs, cfg)
+    for rep in range(3):
+        for p in probs:
+            p[2].fill_(float("nan"))
+        plan.launch()
+        torch.cuda.synchronize()
+        for k, (p, w) in enumerate(zip(probs, want)):
+            got = p[2].cpu()
+            assert np.array_equal(got.numpy().view(np.int64), w.numpy().view(np.int64)), (rep, k, shapes[k], p[3])
+    plan.close()
+
+
 def test_batch_full_workload(mmm, orc):
     """2048 problems, N, P, M uniform on 16..512, even index FP64 DGEMM, odd
     index split (bf16, 6 digits): one graph launch; sampled results checked
