@@ -96,13 +96,13 @@ COUNTED_TRAFFIC = {
     "dgemm": {"bytes": 1.8792e+09, "file": "paper_1106_1347_amd/csrc/dgemm.hip",
               "sha256": "a04198f0f018baea045a670da854d8cc2ac60034d88b563e4e5ee106d2248c49"},
     "split_int8_s7": {"bytes": 2.3680e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
-                      "sha256": "c76702c8d4187d34db9bd884f660f047ef2b31b6f19fe0f78b868f7ff295d3ef"},
+                      "sha256": "bb68fc774998d9c613771b7561f5f4733392e02503be299b3edd28b35a99e945"},
     "split_int8_b8_s6": {"bytes": 2.0120e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
-                         "sha256": "c76702c8d4187d34db9bd884f660f047ef2b31b6f19fe0f78b868f7ff295d3ef"},
+                         "sha256": "bb68fc774998d9c613771b7561f5f4733392e02503be299b3edd28b35a99e945"},
     "split_bf16_b9_s5": {"bytes": 6.8021e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
-                         "sha256": "c76702c8d4187d34db9bd884f660f047ef2b31b6f19fe0f78b868f7ff295d3ef"},
+                         "sha256": "bb68fc774998d9c613771b7561f5f4733392e02503be299b3edd28b35a99e945"},
     "split_fp16_s5": {"bytes": 6.4932e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
-                      "sha256": "c76702c8d4187d34db9bd884f660f047ef2b31b6f19fe0f78b868f7ff295d3ef"},
+                      "sha256": "bb68fc774998d9c613771b7561f5f4733392e02503be299b3edd28b35a99e945"},
 }
 
 
@@ -174,7 +174,7 @@ def _cpu_model():
 
 
 def _host_threads():
-    # the host cores this process may use (the GPU machine grants 16 per GPU)
+    # the host cores this process may use (its CPU affinity, at most OMP_NUM_THREADS)
     return max(1, min(len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS", "16"))))
 
 

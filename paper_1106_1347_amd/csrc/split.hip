@@ -645,23 +645,23 @@ struct FlushSched {
 
 constexpr int popcount_c(unsigned m) { return m ? (int)(m & 1u) + popcount_c(m >> 1) : 0; }
 
-// Round 0 of a step in the LDS kernel: 4 S products, and 32 flush operations
+// Digit level 0 of a step in the LDS kernel: 4 S products, and 32 flush operations
 // (16 conversions, 16 fused adds) per group starting a window; interleave
 // them so that the flushes issue in the shadow of the products.
 template <int NM, int NV, int K = 0>
-__device__ __forceinline__ void sched_round0_k()
+__device__ __forceinline__ void sched_level0_k()
 {
     if constexpr (K < NM) {
         constexpr int nv = NV / NM + (K < NV % NM ? 1 : 0);
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
         if constexpr (nv > 0) __builtin_amdgcn_sched_group_barrier(0x002, nv, 0);
-        sched_round0_k<NM, NV, K + 1>();
+        sched_level0_k<NM, NV, K + 1>();
     }
 }
 template <int S, int NFLUSH>
-__device__ __forceinline__ void sched_round0()
+__device__ __forceinline__ void sched_level0()
 {
-    sched_round0_k<4 * S, 32 * NFLUSH>();
+    sched_level0_k<4 * S, 32 * NFLUSH>();
 }
 
 template <int DT, int S, int BETA, int NST, int WM, int WN>
@@ -721,10 +721,11 @@ __device__ __forceinline__ void split_tile_lds2(const char* __restrict__ SA, con
     // one K block: J = stage; the groups in START begin a new exact-range
     // window at this step: the FP32 value of their previous window goes into
     // their run's FP64 accumulator (weighted by 2^(beta pos), exact) and
-    // their first product here takes a zero accumulator.  Products run digit
-    // t of A by digit t of A (round t); round 0 gives group u its first
-    // product at position u, so the flush of group u can issue while the
-    // matrix cores work on groups 0 .. u - 1.
+    // their first product here takes a zero accumulator.  Products run level
+    // by level, level t taking digit t of A against every digit u of B with
+    // t + u < S; level 0 gives group u its first product at position u, so
+    // the flush of group u can issue while the matrix cores work on groups
+    // 0 .. u - 1.
     // K block kb lives in stage kb % NST; the loads of the next NST - 2
     // blocks may still be in flight while it is used
     auto step = [&](auto Sc, i64 kb) __attribute__((always_inline)) {
@@ -776,10 +777,10 @@ __device__ __forceinline__ void split_tile_lds2(const char* __restrict__ SA, con
                     for (int j = 0; j < 2; ++j)
                         acc[g][i][j] = Mfma<DT>::run(af[i], bf[u][j], restart ? (acc_t){0, 0, 0, 0} : acc[g][i][j]);
             }
-            // round 0: each product of group u issues between the flush
+            // level 0: each product of group u issues between the flush
             // operations of the groups after it (cvt + fma per value)
-            if (t == 0) sched_round0<S, popcount_c(START)>();
-            // keep the rounds in order (LDS reads may move up a round): the
+            if (t == 0) sched_level0<S, popcount_c(START)>();
+            // keep the levels in order (LDS reads may move up a level): the
             // scheduler would otherwise gather the zero-accumulator products
             // at the end and lengthen the fragments' lifetimes past the
             // register budget
