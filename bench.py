@@ -492,9 +492,9 @@ def batch_section(mmm, torch, synth, dev, stream, split_type="bf16", split_slice
     tuner = TileTuner(path=tuner_path)
     tuner.tune([s for g, s in enumerate(shapes) if g % 2 == 0], split=[s for g, s in enumerate(shapes) if g % 2 == 1],
                split_config=cfg)
+    policy = tuner.tune_batch(probs, cfg)
     tune_s = time.perf_counter() - t0
-    plan_probs = [(A, B, C, m, 0, tuner.tile_for(A.shape[0], A.shape[1], B.shape[1], m, cfg))
-                  for (A, B, C, m) in probs]
+    plan_probs = [(A, B, C, m, 0, t) for (A, B, C, m), t in zip(probs, tuner.tiles_for(probs, cfg))]
     t0 = time.perf_counter()
     plan = mmm.Batch(plan_probs, cfg, stream=stream)
     create_s = time.perf_counter() - t0
@@ -528,8 +528,9 @@ def batch_section(mmm, torch, synth, dev, stream, split_type="bf16", split_slice
     cfg8 = mmm.Config(split_type="int8", split_slices=6, split_bits=8)
     tuner.tune([s for g, s in enumerate(shapes) if g % 2 == 0], split=[s for g, s in enumerate(shapes) if g % 2 == 1],
                split_config=cfg8)
-    plan8 = mmm.Batch([(A, B, C, m, 0, tuner.tile_for(A.shape[0], A.shape[1], B.shape[1], m, cfg8))
-                       for (A, B, C, m) in probs], cfg8, stream=stream)
+    policy8 = tuner.tune_batch(probs, cfg8)
+    plan8 = mmm.Batch([(A, B, C, m, 0, t) for (A, B, C, m), t in zip(probs, tuner.tiles_for(probs, cfg8))], cfg8,
+                      stream=stream)
     plan8.launch(stream)
     ms8 = _time(torch, stream, lambda: plan8.launch(stream), 10)
     plan8.launch(stream)
@@ -564,8 +565,8 @@ def batch_section(mmm, torch, synth, dev, stream, split_type="bf16", split_slice
             "oracle_check": "every product in full against the naive definition, %.1f s" % check_s,
             "extra_int8_byte_digits": {"split": "int8 x6, 8-bit byte digits", "ms_graph_p50": ms8,
                                        "tflops_fp64_grade_graph": flop / (ms8 / 1e3) / 1e12,
-                                       "rel_err_inf_worst_split": worst8},
-            "tiles": tuner.summary()}
+                                       "rel_err_inf_worst_split": worst8, "dgemm_tile_policy": policy8},
+            "dgemm_tile_policy": policy, "tiles": tuner.summary()}
 
 
 def serve_section(args, mmm, torch, synth, dev):

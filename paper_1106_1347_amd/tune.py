@@ -5,12 +5,19 @@ P).  For each class the tuner builds a batch of that class's problems once
 per candidate tile shape, times the graph launch with HIP events and keeps
 the fastest.  DGEMM problems choose among three tile shapes, split problems
 (per digit type and count) between the wide tile and the narrow one (half
-its rows).  Choices persist in a JSON cache keyed by device architecture,
-method, shape class and data type, so a later process picks them up without
-re-measuring; a batch plan takes its tiles from ``tile_for``.
+its rows).  A class timed alone has the chip to itself, while in a mixed
+batch the FP64 groups share it with the split branch (their grids then leave
+registers free for it), so a second step times the whole batch under a few
+DGEMM tile policies -- the per-class choices, the library's own rule, and
+each shape for every class -- and keeps the fastest for batches with that
+split configuration.  Choices persist in a JSON cache keyed by device
+architecture, method, shape class and data type (the policy by the split
+configuration), so a later process picks them up without re-measuring.
 
     tuner = TileTuner()                          # loads the cache if present
     tuner.tune(dgemm_shapes, split=split_shapes, split_config=cfg)
+    tuner.tune_batch(problems, cfg)              # (A, B, C, method) tuples of the batch
+    tiles = tuner.tiles_for(problems, cfg)       # one tile per problem, for Batch
     tile = tuner.tile_for(N, P, M)               # "128x128", "64x64", ... or "auto"
     tile = tuner.tile_for(N, P, M, "split", cfg) # "wide", "narrow" or "auto"
 """
@@ -24,6 +31,9 @@ import torch
 from ._lib import Batch, Config
 
 CANDIDATES = ("128x128", "64x64", "128x64")
+# DGEMM tile policies of a whole batch: the per-class choices, the library's
+# rule ("auto"), or one shape for every class
+POLICIES = ("per-class", "auto") + CANDIDATES
 SPLIT_CANDIDATES = ("wide", "narrow")
 SPLIT_TILE_CODES = {"auto": 0, "wide": 1, "narrow": 2}
 
@@ -65,6 +75,42 @@ class TileTuner:
         split problems the integer code of the chosen variant."""
         t = self.table.get(self.key(shape_class(N, P, M), method, config), "auto")
         return t if method == "dgemm" else SPLIT_TILE_CODES[t]
+
+    def _policy_key(self, config: Optional[Config]) -> str:
+        c = config or Config()
+        return "%s/batch/dgemm_policy/with_%s_s%d_b%d" % (self.arch, c.split_type, c.split_slices, c.split_bits)
+
+    def tiles_for(self, problems: Sequence[tuple], config: Optional[Config] = None) -> list:
+        """One tile per problem of a batch ((A, B, C, method) tuples): split
+        problems take their class's variant; DGEMM problems follow the policy
+        ``tune_batch`` chose for batches with this split configuration (the
+        per-class choices when none was chosen)."""
+        pol = self.table.get(self._policy_key(config), "per-class")
+        out = []
+        for p in problems:
+            A, B, m = p[0], p[1], p[3]
+            if m == "dgemm" and pol != "per-class":
+                out.append(pol)
+            else:
+                out.append(self.tile_for(A.shape[0], A.shape[1], B.shape[1], m, config))
+        return out
+
+    def tune_batch(self, problems: Sequence[tuple], config: Optional[Config] = None, reps: int = 10) -> str:
+        """Time the whole batch under each DGEMM tile policy and keep the
+        fastest for batches with this split configuration (unless the cache
+        holds one).  Returns the policy."""
+        k = self._policy_key(config)
+        if k in self.table:
+            return self.table[k]
+        res = {}
+        for pol in POLICIES:
+            self.table[k] = pol
+            tiles = self.tiles_for(problems, config)
+            res[pol] = self._time([(p[0], p[1], p[2], p[3], 0, t) for p, t in zip(problems, tiles)], config, reps)
+        self.timings[k] = res
+        self.table[k] = min(res, key=res.get)
+        self.save()
+        return self.table[k]
 
     def _time(self, problems, config, reps):
         b = Batch(problems, config)

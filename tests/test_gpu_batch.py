@@ -131,6 +131,35 @@ def test_batch_full_workload(mmm, orc):
     plan.close()
 
 
+def test_autotuner_batch_policy(mmm, tmp_path):
+    """The whole-batch step: one of the policies is chosen, persisted per
+    split configuration, and applied by tiles_for; the tuned plan still
+    gives every product bitwise equal to its single call."""
+    from paper_1106_1347_amd.tune import POLICIES, TileTuner
+
+    cfg = mmm.Config(split_type="bf16", split_slices=6)
+    shapes = synth.batch_shapes(24, 21, 16, 300)
+    probs = [(p[0], p[1], p[2], p[3]) for p in make_problems(shapes, 700, ["dgemm", "split"], [0])]
+    t = TileTuner(path=str(tmp_path / "tiles.json"))
+    t.tune([s for g, s in enumerate(shapes) if g % 2 == 0], reps=2, split=[s for g, s in enumerate(shapes) if g % 2 == 1],
+           split_config=cfg)
+    pol = t.tune_batch(probs, cfg, reps=2)
+    assert pol in POLICIES and set(t.timings[t._policy_key(cfg)]) == set(POLICIES)
+    tiles = t.tiles_for(probs, cfg)
+    for (A, B, C, m), tile in zip(probs, tiles):
+        if m == "dgemm" and pol != "per-class":
+            assert tile == pol
+    t2 = TileTuner(path=str(tmp_path / "tiles.json"))
+    assert t2.tiles_for(probs, cfg) == tiles and t2.tune_batch(probs, cfg) == pol
+    plan = mmm.Batch([(A, B, C, m, 0, tile) for (A, B, C, m), tile in zip(probs, tiles)], cfg)
+    plan.launch()
+    torch.cuda.synchronize()
+    for (A, B, C, m) in probs:
+        w = single(mmm, A, B, m, 0, cfg)
+        assert torch.equal(C.view(torch.int64), w.view(torch.int64))
+    plan.close()
+
+
 def test_autotuner_picks_and_persists(mmm, tmp_path):
     from paper_1106_1347_amd.tune import TileTuner
 
