@@ -565,8 +565,8 @@ def batch_section(mmm, torch, synth, dev, stream, split_type="bf16", split_slice
             "oracle_check": "every product in full against the naive definition, %.1f s" % check_s,
             "extra_int8_byte_digits": {"split": "int8 x6, 8-bit byte digits", "ms_graph_p50": ms8,
                                        "tflops_fp64_grade_graph": flop / (ms8 / 1e3) / 1e12,
-                                       "rel_err_inf_worst_split": worst8, "dgemm_tile_policy": policy8},
-            "dgemm_tile_policy": policy, "tiles": tuner.summary()}
+                                       "rel_err_inf_worst_split": worst8, "tile_policy": {"dgemm": policy8[0], "split": policy8[1]}},
+            "tile_policy": {"dgemm": policy[0], "split": policy[1]}, "tiles": tuner.summary()}
 
 
 def serve_section(args, mmm, torch, synth, dev):

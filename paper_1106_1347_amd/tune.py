@@ -10,7 +10,8 @@ batch the FP64 groups share it with the split branch (their grids then leave
 registers free for it), so a second step times the whole batch under a few
 DGEMM tile policies -- the per-class choices, the library's own rule, and
 each shape for every class -- and keeps the fastest for batches with that
-split configuration.  Choices persist in a JSON cache keyed by device
+split configuration, then does the same for the split tiles (per-class,
+the library's rule, all wide, all narrow) under the chosen DGEMM policy.  Choices persist in a JSON cache keyed by device
 architecture, method, shape class and data type (the policy by the split
 configuration), so a later process picks them up without re-measuring.
 
@@ -31,11 +32,13 @@ import torch
 from ._lib import Batch, Config
 
 CANDIDATES = ("128x128", "64x64", "128x64")
+SPLIT_CANDIDATES = ("wide", "narrow")
+SPLIT_TILE_CODES = {"auto": 0, "wide": 1, "narrow": 2}
 # DGEMM tile policies of a whole batch: the per-class choices, the library's
 # rule ("auto"), or one shape for every class
 POLICIES = ("per-class", "auto") + CANDIDATES
-SPLIT_CANDIDATES = ("wide", "narrow")
-SPLIT_TILE_CODES = {"auto": 0, "wide": 1, "narrow": 2}
+# and of its split problems
+SPLIT_POLICIES = ("per-class",) + tuple(SPLIT_TILE_CODES)
 
 
 def default_cache_path() -> str:
@@ -76,41 +79,43 @@ class TileTuner:
         t = self.table.get(self.key(shape_class(N, P, M), method, config), "auto")
         return t if method == "dgemm" else SPLIT_TILE_CODES[t]
 
-    def _policy_key(self, config: Optional[Config]) -> str:
+    def _policy_key(self, config: Optional[Config], method: str = "dgemm") -> str:
         c = config or Config()
-        return "%s/batch/dgemm_policy/with_%s_s%d_b%d" % (self.arch, c.split_type, c.split_slices, c.split_bits)
+        return "%s/batch/%s_policy/with_%s_s%d_b%d" % (self.arch, method, c.split_type, c.split_slices, c.split_bits)
 
     def tiles_for(self, problems: Sequence[tuple], config: Optional[Config] = None) -> list:
         """One tile per problem of a batch ((A, B, C, method) tuples): split
-        problems take their class's variant; DGEMM problems follow the policy
-        ``tune_batch`` chose for batches with this split configuration (the
-        per-class choices when none was chosen)."""
-        pol = self.table.get(self._policy_key(config), "per-class")
+        problems and split problems follow the policies ``tune_batch`` chose
+        for batches with this split configuration (the per-class choices
+        when none was chosen)."""
+        pol = {m: self.table.get(self._policy_key(config, m), "per-class") for m in ("dgemm", "split")}
         out = []
         for p in problems:
             A, B, m = p[0], p[1], p[3]
-            if m == "dgemm" and pol != "per-class":
-                out.append(pol)
-            else:
+            if pol[m] == "per-class":
                 out.append(self.tile_for(A.shape[0], A.shape[1], B.shape[1], m, config))
+            else:
+                out.append(pol[m] if m == "dgemm" else SPLIT_TILE_CODES[pol[m]])
         return out
 
-    def tune_batch(self, problems: Sequence[tuple], config: Optional[Config] = None, reps: int = 10) -> str:
+    def tune_batch(self, problems: Sequence[tuple], config: Optional[Config] = None, reps: int = 10) -> Tuple[str, str]:
         """Time the whole batch under each DGEMM tile policy and keep the
-        fastest for batches with this split configuration (unless the cache
-        holds one).  Returns the policy."""
-        k = self._policy_key(config)
-        if k in self.table:
-            return self.table[k]
-        res = {}
-        for pol in POLICIES:
-            self.table[k] = pol
-            tiles = self.tiles_for(problems, config)
-            res[pol] = self._time([(p[0], p[1], p[2], p[3], 0, t) for p, t in zip(problems, tiles)], config, reps)
-        self.timings[k] = res
-        self.table[k] = min(res, key=res.get)
+        fastest for batches with this split configuration, then likewise for
+        the split tiles under that DGEMM policy (a policy the cache holds is
+        kept).  Returns the (DGEMM, split) policies."""
+        for method, pols in (("dgemm", POLICIES), ("split", SPLIT_POLICIES)):
+            k = self._policy_key(config, method)
+            if k in self.table:
+                continue
+            res = {}
+            for pol in pols:
+                self.table[k] = pol
+                tiles = self.tiles_for(problems, config)
+                res[pol] = self._time([(p[0], p[1], p[2], p[3], 0, t) for p, t in zip(problems, tiles)], config, reps)
+            self.timings[k] = res
+            self.table[k] = min(res, key=res.get)
         self.save()
-        return self.table[k]
+        return self.table[self._policy_key(config, "dgemm")], self.table[self._policy_key(config, "split")]
 
     def _time(self, problems, config, reps):
         b = Batch(problems, config)

@@ -135,7 +135,7 @@ def test_autotuner_batch_policy(mmm, tmp_path):
     """The whole-batch step: one of the policies is chosen, persisted per
     split configuration, and applied by tiles_for; the tuned plan still
     gives every product bitwise equal to its single call."""
-    from paper_1106_1347_amd.tune import POLICIES, TileTuner
+    from paper_1106_1347_amd.tune import POLICIES, SPLIT_POLICIES, SPLIT_TILE_CODES, TileTuner
 
     cfg = mmm.Config(split_type="bf16", split_slices=6)
     shapes = synth.batch_shapes(24, 21, 16, 300)
@@ -143,14 +143,17 @@ def test_autotuner_batch_policy(mmm, tmp_path):
     t = TileTuner(path=str(tmp_path / "tiles.json"))
     t.tune([s for g, s in enumerate(shapes) if g % 2 == 0], reps=2, split=[s for g, s in enumerate(shapes) if g % 2 == 1],
            split_config=cfg)
-    pol = t.tune_batch(probs, cfg, reps=2)
-    assert pol in POLICIES and set(t.timings[t._policy_key(cfg)]) == set(POLICIES)
+    pol, spol = t.tune_batch(probs, cfg, reps=2)
+    assert pol in POLICIES and set(t.timings[t._policy_key(cfg, "dgemm")]) == set(POLICIES)
+    assert spol in SPLIT_POLICIES and set(t.timings[t._policy_key(cfg, "split")]) == set(SPLIT_POLICIES)
     tiles = t.tiles_for(probs, cfg)
     for (A, B, C, m), tile in zip(probs, tiles):
         if m == "dgemm" and pol != "per-class":
             assert tile == pol
+        if m == "split" and spol != "per-class":
+            assert tile == SPLIT_TILE_CODES[spol]
     t2 = TileTuner(path=str(tmp_path / "tiles.json"))
-    assert t2.tiles_for(probs, cfg) == tiles and t2.tune_batch(probs, cfg) == pol
+    assert t2.tiles_for(probs, cfg) == tiles and t2.tune_batch(probs, cfg) == (pol, spol)
     plan = mmm.Batch([(A, B, C, m, 0, tile) for (A, B, C, m), tile in zip(probs, tiles)], cfg)
     plan.launch()
     torch.cuda.synchronize()
