@@ -186,6 +186,7 @@ def test_batch_validation_before_any_allocation(lib):
 
     ok = P(A=0x10000, B=0x20000, C=0x30000, N=4, P=4, M=4, method=6)
     assert f(arr(ok), 0, r(c), None, r(h)) == 1            # count 0
+    assert f(arr(ok), 65536, r(c), None, r(h)) == 1        # count above 65535 (refused before reading the array)
     assert f(arr(P(A=8, B=8, C=8, N=-1, P=1, M=1, method=6)), 1, r(c), None, r(h)) == 1
     assert f(arr(P(A=8, B=8, C=8, N=1, P=1, M=1, method=2)), 1, r(c), None, r(h)) == 1  # not dgemm/split
     assert f(arr(P(A=8, B=8, C=8, N=1, P=1, M=1, method=6, tile=9)), 1, r(c), None, r(h)) == 1

@@ -99,6 +99,36 @@ def test_batch_single_kind_plans(mmm, methods, slices):
     plan.close()
 
 
+def test_batch_at_the_count_limit(mmm):
+    """65535 problems (the most one plan takes), half DGEMM and half split
+    (int8 byte digits), dimensions 1..8, operands as views into one buffer:
+    one graph launch, sampled results bitwise equal to single calls."""
+    n = 65535
+    rng = np.random.default_rng(5)
+    dims = rng.integers(1, 9, size=(n, 3))
+    na, nb, nc = (dims[:, 0] * dims[:, 1]), (dims[:, 1] * dims[:, 2]), (dims[:, 0] * dims[:, 2])
+    oa = np.concatenate([[0], np.cumsum(na)])
+    ob = oa[-1] + np.concatenate([[0], np.cumsum(nb)])
+    oc = np.concatenate([[0], np.cumsum(nc)])
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    buf = torch.rand(int(ob[-1]), dtype=torch.float64, device="cuda", generator=gen) * 2 - 1
+    cbuf = torch.full((int(oc[-1]),), float("nan"), dtype=torch.float64, device="cuda")
+    probs = []
+    for i, (N, P, M) in enumerate(dims.tolist()):
+        probs.append((buf[oa[i]:oa[i + 1]].view(N, P), buf[ob[i]:ob[i + 1]].view(P, M), cbuf[oc[i]:oc[i + 1]].view(N, M),
+                      "dgemm" if i % 2 == 0 else "split"))
+    cfg = mmm.Config(split_type="int8", split_slices=6, split_bits=8)
+    plan = mmm.Batch(probs, cfg)
+    plan.launch()
+    torch.cuda.synchronize()
+    assert not torch.isnan(cbuf).any()
+    for i in sorted(set(rng.integers(0, n, 300).tolist()) | {0, 1, n - 2, n - 1}):
+        A, B, C, m = probs[i]
+        w = mmm.multiply(A, B, m, cfg)
+        assert torch.equal(C.view(torch.int64), w.view(torch.int64)), (i, dims[i], m)
+    plan.close()
+
+
 def test_batch_full_workload(mmm, orc):
     """2048 problems, N, P, M uniform on 16..512, even index FP64 DGEMM, odd
     index split (bf16, 6 digits): one graph launch; sampled results checked
