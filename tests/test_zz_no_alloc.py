@@ -58,3 +58,33 @@ def test_noalloc_refuses_oversized_product(mmm):
     with pytest.raises(mmm.MmmError) as e:
         mmm.multiply_noalloc(A, A, C, "split", cfg)
     assert e.value.status == 3
+
+
+def test_noalloc_at_the_array_limit(mmm):
+    """The largest square split product (bf16, 6 digits) whose workspace fits
+    the static array runs and equals mmm_multiply bitwise; the next size up
+    is refused before anything is enqueued."""
+    cfg = mmm.Config(split_type="bf16", split_slices=6)
+    cap = mmm.noalloc_scratch_bytes()
+    lo, hi = 1, 8192  # workspace_bytes grows with n: fits at lo, not at hi
+    assert mmm.workspace_bytes("split", lo, lo, lo, cfg) <= cap < mmm.workspace_bytes("split", hi, hi, hi, cfg)
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if mmm.workspace_bytes("split", mid, mid, mid, cfg) <= cap:
+            lo = mid
+        else:
+            hi = mid
+    n = lo
+    print("noalloc limit: n = %d, %d of %d bytes" % (n, mmm.workspace_bytes("split", n, n, n, cfg), cap), flush=True)
+    A = torch.from_numpy(synth.uniform((n, n), 960)).cuda()
+    B = torch.from_numpy(synth.uniform((n, n), 961)).cuda()
+    want = mmm.multiply(A, B, "split", cfg)
+    got = torch.full((n, n), float("nan"), dtype=torch.float64, device="cuda")
+    mmm.multiply_noalloc(A, B, got, "split", cfg)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy().view(np.int64), want.cpu().numpy().view(np.int64))
+    A1 = torch.zeros(n + 1, n + 1, dtype=torch.float64, device="cuda")
+    C1 = torch.zeros(n + 1, n + 1, dtype=torch.float64, device="cuda")
+    with pytest.raises(mmm.MmmError) as e:
+        mmm.multiply_noalloc(A1, A1, C1, "split", cfg)
+    assert e.value.status == 3
