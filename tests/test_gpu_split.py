@@ -103,6 +103,30 @@ def test_split_zero_rows_and_columns(mmm, orc, typ, s, bits):
     assert bits_equal(split(mmm, Z, B, typ, s, bits=bits), model(orc, Z, B, typ, s, bits))
 
 
+@pytest.mark.parametrize("typ,s,bits", [("bf16", 5, 9), ("int8", 6, 8), ("fp16", 6, 0)])
+def test_split_operands_at_odd_offsets(mmm, orc, typ, s, bits):
+    """A, B and C as views one element (8 bytes) into larger buffers, so no
+    row start is 16-byte aligned: the statistics and digit passes read them
+    as they lie, and the result equals the model's bits (written into the
+    view only)."""
+    N, P, M = 97, 131, 75
+    A = synth.wide_range((N, P), 41)
+    B = synth.wide_range((P, M), 42)
+    bufA = torch.zeros(N * P + 3, dtype=torch.float64, device="cuda")
+    bufB = torch.zeros(P * M + 3, dtype=torch.float64, device="cuda")
+    bufC = torch.full((N * M + 3,), float("nan"), dtype=torch.float64, device="cuda")
+    bufA[1:1 + N * P] = dev(A).reshape(-1)
+    bufB[1:1 + P * M] = dev(B).reshape(-1)
+    Av, Bv, Cv = bufA[1:1 + N * P].view(N, P), bufB[1:1 + P * M].view(P, M), bufC[1:1 + N * M].view(N, M)
+    assert Av.data_ptr() % 16 == 8 and Bv.data_ptr() % 16 == 8 and Cv.data_ptr() % 16 == 8
+    cfg = mmm.Config(split_type=typ, split_slices=s, split_bits=bits)
+    mmm.multiply(Av, Bv, "split", cfg, out=Cv)
+    torch.cuda.synchronize()
+    assert bits_equal(Cv.cpu().numpy(), model(orc, A, B, typ, s, bits))
+    edge = bufC.cpu().numpy()
+    assert np.isnan(edge[0]) and np.isnan(edge[1 + N * M:]).all()
+
+
 def test_split_integer_inputs_exact(mmm):
     A = synth.integers((100, 257), 3)
     B = synth.integers((257, 90), 4)
