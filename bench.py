@@ -92,7 +92,7 @@ LATENCY_METHODS = [
 # while the kernel's source is the one measured (sha256 below), otherwise reported as null.
 COUNTED_TRAFFIC = {
     "kahan": {"bytes": 3.3573e+09, "file": "paper_1106_1347_amd/csrc/valu_gemm.hip",
-              "sha256": "3999925ed4c1c3b6c10677ab9428b5bb88f03d0fe1879683c810a2951565c401"},
+              "sha256": "784fd6af09d049f1b0e0437e1f9ddc7e8f26bb308359eddad475efd03dd2ae02"},
     "dgemm": {"bytes": 1.8793e+09, "file": "paper_1106_1347_amd/csrc/dgemm.hip",
               "sha256": "a04198f0f018baea045a670da854d8cc2ac60034d88b563e4e5ee106d2248c49"},
     "split_int8_s7": {"bytes": 2.8035e+10, "file": "paper_1106_1347_amd/csrc/split.hip",

@@ -257,6 +257,7 @@ struct ValuTile {
     static constexpr int Q = unroll_q(OP);
     static_assert((BM / TM) * (BN / TN) == NT, "256 threads");
     static_assert(BM / TM == 16 && BN / TN == 16, "16 x 16 thread grid");
+    static_assert((BM * BK) % NT == 0 && (BK * BN) % NT == 0, "every thread moves whole elements of a step");
     static constexpr int LA = BM * BK / NT;  // A elements each thread moves per step (register staging)
     static constexpr int LB = BK * BN / NT;
     static constexpr int TH = TN / 2;        // columns per half
@@ -348,11 +349,17 @@ struct ValuTile {
             }
         };
         auto frag_a = [&](int k, double(&a)[TM]) __attribute__((always_inline)) {
+            if constexpr (TM % 2 == 0) {
 #pragma unroll
-            for (int i = 0; i < TM; i += 2) {
-                const double2 v = *reinterpret_cast<const double2*>(&sm.As[k][ty * TM + i]);
-                a[i] = v.x;
-                a[i + 1] = v.y;
+                for (int i = 0; i < TM; i += 2) {
+                    const double2 v = *reinterpret_cast<const double2*>(&sm.As[k][ty * TM + i]);
+                    a[i] = v.x;
+                    a[i + 1] = v.y;
+                }
+            } else {
+                // one row per lane (the 16 x 32 latency tile): no pairs to read
+#pragma unroll
+                for (int i = 0; i < TM; ++i) a[i] = sm.As[k][ty * TM + i];
             }
         };
         auto frag_b = [&](int k, double(&b)[TN]) __attribute__((always_inline)) {
@@ -733,12 +740,40 @@ struct ShapeOf {
         type;
 };
 
+// A product whose tiles would not give every CU a workgroup (fewer than
+// kFillTiles of the method's own shape) is bound by latency, not by
+// throughput: it takes the 32 x 32 tile (2 x 2 entries per lane) when that
+// still gives half the CUs a workgroup, else the 16 x 32 one (1 x 2).  The
+// tile shape only decides which lane computes an entry, never the order of
+// its operations, so every shape gives the same bits.
+constexpr i64 kFillTiles = 256;
+
+template <int OP, class Src>
+bool launch_latency_tile(const Src& src, i64 N, i64 M, const double* yv, const double* zv, hipStream_t s,
+                         hipError_t& err)
+{
+    typedef typename ShapeOf<OP>::type S;
+    const i64 cnt = src.count();
+    if (cdiv(N, S::bm) * cdiv(M, S::bn) * cnt >= kFillTiles) return false;
+    // NaivLoopUnrollingThree's K step of 24 does not split into whole loads
+    // of a 16-row tile's 256 threads: it keeps the 32 x 32 tile
+    if constexpr (OP == OP_UNROLL3) {
+        err = launch_valu<32, 32, 2, 2, OP>(src, N, M, yv, zv, s);
+    } else {
+        if (cdiv(N, 32) * cdiv(M, 32) * cnt >= kFillTiles / 2) err = launch_valu<32, 32, 2, 2, OP>(src, N, M, yv, zv, s);
+        else err = launch_valu<16, 32, 1, 2, OP>(src, N, M, yv, zv, s);
+    }
+    return true;
+}
+
 // Small problems (every dimension <= 48, e.g. the m x m leaves of the
 // paper's Strassen embedding) use 32 x 32 tiles.
 template <int OP, class Src>
 hipError_t launch_naive_like(const Src& src, i64 N, i64 M, hipStream_t s)
 {
     if (N <= 48 && M <= 48) return launch_valu<32, 32, 2, 2, OP>(src, N, M, nullptr, nullptr, s);
+    hipError_t lerr = hipSuccess;
+    if (launch_latency_tile<OP>(src, N, M, nullptr, nullptr, s, lerr)) return lerr;
     if constexpr (OP == OP_NAIVE || OP == OP_NAIVE_FMA) {
         typedef Shape<MMM_VALU_NAIVE_DMA_TILE> D;
         hipError_t err = hipSuccess;
@@ -829,6 +864,7 @@ hipError_t launch_winograd_main(const Gemm& g, const double* y, const double* z,
     typedef typename ShapeOf<OP_WINOGRAD>::type S;
     typedef Shape<MMM_VALU_WINO_DMA_TILE> D;
     hipError_t err = hipSuccess;
+    if (launch_latency_tile<OP_WINOGRAD>(src, g.N, g.M, y, z, s, err)) return err;
     if (try_launch_direct<D::bm, D::bn, D::tm, D::tn, OP_WINOGRAD>(src, g.N, g.M, y, z, s, err))
         return err;
     return launch_valu<S::bm, S::bn, S::tm, S::tn, OP_WINOGRAD>(src, g.N, g.M, y, z, s);
