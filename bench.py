@@ -94,7 +94,7 @@ COUNTED_TRAFFIC = {
     "kahan": {"bytes": 3.3573e+09, "file": "paper_1106_1347_amd/csrc/valu_gemm.hip",
               "sha256": "784fd6af09d049f1b0e0437e1f9ddc7e8f26bb308359eddad475efd03dd2ae02"},
     "dgemm": {"bytes": 1.8793e+09, "file": "paper_1106_1347_amd/csrc/dgemm.hip",
-              "sha256": "a04198f0f018baea045a670da854d8cc2ac60034d88b563e4e5ee106d2248c49"},
+              "sha256": "9d31101e8996d414e7cb07292a174fa4a17b51f0e9da174eb074a984527ad929"},
     "split_int8_s7": {"bytes": 2.8035e+10, "file": "paper_1106_1347_amd/csrc/split.hip",
                       "sha256": "bb68fc774998d9c613771b7561f5f4733392e02503be299b3edd28b35a99e945"},
     "split_int8_b8_s6": {"bytes": 2.0162e+10, "file": "paper_1106_1347_amd/csrc/split.hip",

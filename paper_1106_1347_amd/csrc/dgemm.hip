@@ -370,10 +370,14 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 template <class Src>
 hipError_t launch_dgemm_auto(const Src& src, i64 N, i64 M, hipStream_t s)
 {
-    // 128 x 128 tiles when they alone fill the 256 CUs, 64 x 64 otherwise
+    // 128 x 128 tiles when they alone fill the 256 CUs, 64 x 64 when those
+    // still give half the CUs a workgroup, else 32 x 32 (a small product is
+    // bound by latency; every output takes the same MFMAs in the same order
+    // whatever the tile, so the bits do not change)
     const i64 big = cdiv(N, 128) * cdiv(M, 128) * src.count();
     if (big >= 256) return launch_dgemm_src<4, 4>(src, N, M, s);
-    return launch_dgemm_src<2, 2>(src, N, M, s);
+    if (cdiv(N, 64) * cdiv(M, 64) * src.count() >= 128) return launch_dgemm_src<2, 2>(src, N, M, s);
+    return launch_dgemm_src<1, 1>(src, N, M, s);
 }
 
 }  // namespace
