@@ -133,6 +133,8 @@ def parse(argv=None):
     ap.add_argument("--headline", default="", help="comma-separated subset of the 8192^3 configurations")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-budget-gib", type=float, default=96.0)
+    ap.add_argument("--serve-rate", type=float, default=3000.0,
+                    help="fixed Poisson arrival rate (requests/s) of the serving run the headline p50/p99 come from")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args(argv)
@@ -573,8 +575,9 @@ def serve_section(args, mmm, torch, synth, dev):
     """Poisson request stream, dims log-uniform on 32..4096 (half square),
     tolerance 1e-13 or 1e-10, methods routed by measured cost: capacity
     measured closed-loop, then p50/p99 latency (arrival to completion event)
-    at 50% and 80% of it; afterwards every result of the 80% run against the
-    CPU oracle on sampled rows."""
+    at a fixed rate (``--serve-rate``, the headline's) and at 50% and 80% of
+    the capacity; afterwards every result of the 80% run against the CPU
+    oracle on sampled rows."""
     import oracle
     from paper_1106_1347_amd.serve import Router, Server
 
@@ -608,8 +611,8 @@ def serve_section(args, mmm, torch, synth, dev):
            "router_calibration_s": cal_s, "router_ms": router.table, "router_sizes": router.sizes,
            "capacity_req_per_s": cap["req_per_s"], "closed_loop": cap}
     results = None
-    for frac in (0.5, 0.8):
-        rate = frac * cap["req_per_s"]
+    for key, rate in (("fixed_rate", args.serve_rate), ("load_50", 0.5 * cap["req_per_s"]),
+                      ("load_80", 0.8 * cap["req_per_s"])):
         arrivals = np.cumsum(np.random.default_rng(4004).exponential(1.0 / rate, size=n))
         srv = Server(budget, streams=4, router=router)
         t0 = time.perf_counter()
@@ -623,7 +626,7 @@ def serve_section(args, mmm, torch, synth, dev):
         st = srv.stats()
         srv.close()
         st["offered_req_per_s"] = rate
-        out["load_%d" % int(frac * 100)] = st
+        out[key] = st
     # every result of the last run against the oracle: 4 rows each (the row of
     # A with the largest absolute row sum among them)
     oracle.set_threads(_host_threads())
@@ -764,8 +767,11 @@ def main():
         out["precision_8192"] = head
     out["cpu_baseline"] = cpu
     if "serving" in extra:
-        out["serving_p50_ms"] = extra["serving"]["load_80"]["p50_ms"]
-        out["serving_p99_ms"] = extra["serving"]["load_80"]["p99_ms"]
+        # at a fixed arrival rate, so that the figure does not move with the
+        # capacity a box measures (the 50% / 80% runs are under "serving")
+        out["serving_rate_req_per_s"] = extra["serving"]["fixed_rate"]["offered_req_per_s"]
+        out["serving_p50_ms"] = extra["serving"]["fixed_rate"]["p50_ms"]
+        out["serving_p99_ms"] = extra["serving"]["fixed_rate"]["p99_ms"]
     out.update(extra)
     out["device"] = torch.cuda.get_device_name(0)
     print(json.dumps(out), flush=True)

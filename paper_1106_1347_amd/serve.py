@@ -200,6 +200,8 @@ class Admission:
         self.waiting.append(req)
 
     def admit(self):
+        if not self.free_slots:  # nothing can be admitted; skip the scan of the queue
+            return []
         now = self.clock()
         out, keep = [], collections.deque()
         blocked = False
