@@ -322,7 +322,7 @@ mmm_status run_strassen(int variant, const double* A, const double* B, double* C
 // ---- Winograd (Section 2.3) workspace ---------------------------------------
 
 struct WinoLayout {
-    size_t y = 0, z = 0, nA = 0, nB = 0, lam = 0, bytes = 0;
+    size_t y = 0, z = 0, nA = 0, nB = 0, bytes = 0;
 };
 
 WinoLayout wino_layout(i64 N, i64 M, bool scaled)
@@ -338,8 +338,6 @@ WinoLayout wino_layout(i64 N, i64 M, bool scaled)
         off = align_up(off + sizeof(double));
         w.nB = off;
         off = align_up(off + sizeof(double));
-        w.lam = off;
-        off = align_up(off + sizeof(int));
     }
     w.bytes = off;
     return w;
@@ -361,22 +359,22 @@ mmm_status run_winograd(const double* A, const double* B, const Gemm& g, bool sc
     if (scaled) {
         double* nA = (double*)(ws + w.nA);
         double* nB = (double*)(ws + w.nB);
-        int* lam = (int*)(ws + w.lam);
         if ((e = launch_norm_inf_pair(A, N, P, nA, B, M, nB, s)) != hipSuccess) return from_hip(e, "norms");
-        if ((e = launch_lambda(nA, nB, lam, s)) != hipSuccess) return from_hip(e, "lambda");
         double* As = g.A != A ? (double*)g.A : (double*)sws;
         if (g.A == A) {
             gs.A = As;
             gs.lda = P;
             sws += align_up(sizeof(double) * (size_t)N * (size_t)P);
         }
-        if ((e = launch_scale_pow2(g.A, g.lda, N, P, As, gs.lda, lam, +1, s)) != hipSuccess) return from_hip(e, "scale A");
         double* Bs = g.B != B ? (double*)g.B : (double*)sws;
         if (g.B == B) {
             gs.B = Bs;
             gs.ldb = M;
         }
-        if ((e = launch_scale_pow2(g.B, g.ldb, P, M, Bs, gs.ldb, lam, -1, s)) != hipSuccess) return from_hip(e, "scale B");
+        // 2^lambda A and 2^-lambda B in one launch, lambda taken from the norms there
+        if ((e = launch_scale_pow2_pair(g.A, g.lda, N, P, As, gs.lda, g.B, g.ldb, P, M, Bs, gs.ldb, nA, nB, s)) !=
+            hipSuccess)
+            return from_hip(e, "scale");
     }
     // y_i over the rows of (scaled) A, z_k over the columns of (scaled) B
     if ((e = launch_winograd_yz(gs.A, gs.lda, N, P, y, gs.B, gs.ldb, M, z, s)) != hipSuccess) return from_hip(e, "y, z");

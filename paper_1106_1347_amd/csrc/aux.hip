@@ -7,6 +7,8 @@
 // Built with -ffp-contract=off: every sum and product is rounded on its
 // own, and each reduction runs over its vector in ascending order, so the
 // results equal a sequential binary64 evaluation bit for bit.
+#include <algorithm>
+
 #include "common.h"
 #include "launch.h"
 #include "reduce.h"
@@ -103,9 +105,8 @@ __device__ inline long long floor_half(long long x) { return x >= 0 ? x / 2 : -(
 // holds for x in {0, 1}, for b < a for x in {-1, 0}, for a = b for
 // x in {-1, 0, 1}; the largest lambda is floor((d+1)/2) when b >= a and
 // floor(d/2) otherwise.
-__global__ void lambda_kernel(const double* nA, const double* nB, int* lam)
+__device__ inline int winograd_lambda(double a, double b)
 {
-    const double a = *nA, b = *nB;
     int res = 0;
     if (a > 0.0 && b > 0.0 && !isinf(a) && !isinf(b)) {
         int eA, eB;
@@ -114,8 +115,10 @@ __global__ void lambda_kernel(const double* nA, const double* nB, int* lam)
         const long long d = (long long)eB - (long long)eA;
         res = (int)(fb >= fa ? floor_half(d + 1) : floor_half(d));
     }
-    *lam = res;
+    return res;
 }
+
+__global__ void lambda_kernel(const double* nA, const double* nB, int* lam) { *lam = winograd_lambda(*nA, *nB); }
 
 // Row-block copies: workgroup b takes row b / chunks, columns
 // 1024 (b % chunks) .. + 1023, 4 entries per thread, loads first; the grid
@@ -159,6 +162,39 @@ __global__ __launch_bounds__(256) void scale_kernel(const double* src, i64 lds, 
         for (int u = 0; u < 4; ++u)
             if (j0 + u * 256 < cols) dst[i * ldd + j0 + u * 256] = v[u] * sc;
     }
+}
+
+// Both of WinogradScaled's operands in one launch: workgroups below blk_a
+// write 2^lambda A, the rest 2^-lambda B, each workgroup taking lambda from
+// the two norms itself (the rule above), so no separate lambda launch is
+// needed.  Same layout and exact products as scale_kernel.
+__device__ __forceinline__ void scale_rows(const double* src, i64 lds, i64 rows, i64 cols, double* dst, i64 ldd,
+                                           double sc, i64 first, i64 stride)
+{
+    const i64 chunks = (cols + 1023) / 1024;
+    for (i64 vb = first; vb < rows * chunks; vb += stride) {
+        const i64 i = vb / chunks, j0 = (vb - i * chunks) * 1024 + threadIdx.x;
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const i64 j = j0 + u * 256;
+            v[u] = j < cols ? src[i * lds + j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (j0 + u * 256 < cols) dst[i * ldd + j0 + u * 256] = v[u] * sc;
+    }
+}
+
+__global__ __launch_bounds__(256) void scale_pair_kernel(const double* srcA, i64 ldsA, i64 rowsA, i64 colsA,
+                                                          double* dstA, i64 lddA, i64 blk_a, const double* srcB,
+                                                          i64 ldsB, i64 rowsB, i64 colsB, double* dstB, i64 lddB,
+                                                          const double* nA, const double* nB)
+{
+    const int lam = winograd_lambda(*nA, *nB);
+    const i64 b = blockIdx.x;
+    if (b < blk_a) scale_rows(srcA, ldsA, rowsA, colsA, dstA, lddA, ldexp(1.0, lam), b, blk_a);
+    else scale_rows(srcB, ldsB, rowsB, colsB, dstB, lddB, ldexp(1.0, -lam), b - blk_a, (i64)gridDim.x - blk_a);
 }
 
 __global__ __launch_bounds__(256) void zero_kernel(double* dst, i64 n)
@@ -247,6 +283,19 @@ hipError_t launch_scale_pow2(const double* src, i64 lds, i64 rows, i64 cols, dou
     if (rows <= 0 || cols <= 0) return hipSuccess;
     hipLaunchKernelGGL(scale_kernel, dim3(grid_for(rows * cdiv(cols, 1024) * 256, 1)), dim3(256), 0, s, src, lds, rows,
                        cols, dst, ldd, lam, sign);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_pow2_pair(const double* srcA, i64 ldsA, i64 rowsA, i64 colsA, double* dstA, i64 lddA,
+                                  const double* srcB, i64 ldsB, i64 rowsB, i64 colsB, double* dstB, i64 lddB,
+                                  const double* nA, const double* nB, hipStream_t s)
+{
+    // each half at most 2^30 workgroups (they loop beyond), so the sum fits the grid
+    const i64 ba = rowsA > 0 && colsA > 0 ? std::min<i64>(grid_for(rowsA * cdiv(colsA, 1024) * 256, 1), 1 << 30) : 0;
+    const i64 bb = rowsB > 0 && colsB > 0 ? std::min<i64>(grid_for(rowsB * cdiv(colsB, 1024) * 256, 1), 1 << 30) : 0;
+    if (ba + bb == 0) return hipSuccess;
+    hipLaunchKernelGGL(scale_pair_kernel, dim3((unsigned)(ba + bb)), dim3(256), 0, s, srcA, ldsA, rowsA, colsA, dstA,
+                       lddA, ba, srcB, ldsB, rowsB, colsB, dstB, lddB, nA, nB);
     return hipGetLastError();
 }
 

@@ -78,6 +78,11 @@ hipError_t launch_fill_zero(double* dst, i64 n, hipStream_t s);
 // the device); dst may equal src.
 hipError_t launch_scale_pow2(const double* src, i64 lds, i64 rows, i64 cols, double* dst, i64 ldd, const int* lam,
                              int sign, hipStream_t s);
+// Both scaled operands of WinogradScaled in one launch (2^lambda A and
+// 2^-lambda B, lambda from the device norms nA, nB by Section 2.3.2's rule).
+hipError_t launch_scale_pow2_pair(const double* srcA, i64 ldsA, i64 rowsA, i64 colsA, double* dstA, i64 lddA,
+                                  const double* srcB, i64 ldsB, i64 rowsB, i64 colsB, double* dstB, i64 lddB,
+                                  const double* nA, const double* nB, hipStream_t s);
 
 // strassen.hip
 hipError_t launch_strassen_pre(const StrassenTree& T, int level, hipStream_t s);

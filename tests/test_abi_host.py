@@ -58,13 +58,13 @@ def test_workspace_arithmetic(lib):
     # Winograd's pairs end at 4096 (a whole step): only A is copied, to an
     # even row length, after y and z
     assert ws("winograd", 4096, 4097, 4096) == 2 * 32768 + 4096 * 4098 * 8
-    # (2^l A is scaled in place in A's copy; 2^-l B needs a buffer of its own)
-    assert ws("winograd_scaled", 4096, 4097, 4096) == 2 * 32768 + 3 * 256 + 4096 * 4098 * 8 + 4097 * 4096 * 8
+    # (the two norms; 2^l A is scaled in place in A's copy; 2^-l B needs a buffer of its own)
+    assert ws("winograd_scaled", 4096, 4097, 4096) == 2 * 32768 + 2 * 256 + 4096 * 4098 * 8 + 4097 * 4096 * 8
     # P even but not a multiple of the step: the same copies
     assert ws("naive", 4096, 4100, 4096) == 2 * 4096 * 4112 * 8
     assert ws("winograd", 100, 7, 300) == 1024 + 2560  # y: 800 B -> 1024, z: 2400 B -> 2560
     # WinogradScaled also holds 2^l A (5600 B -> 5632) and 2^-l B (16800 B -> 16896)
-    assert ws("winograd_scaled", 100, 7, 300) == 1024 + 2560 + 3 * 256 + 5632 + 16896
+    assert ws("winograd_scaled", 100, 7, 300) == 1024 + 2560 + 2 * 256 + 5632 + 16896
     cfg = lib.Config(strassen_levels=2)
     # no padding at 4096^3: the deepest two levels run fused, so level 1 (the
     # fused level) holds nothing and level 2 holds 49 slots of A, B and products
