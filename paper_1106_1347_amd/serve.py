@@ -94,14 +94,27 @@ class Router:
         self.sizes = list(sizes)
         self.table = dict(table or {})
 
+    @property
+    def table(self) -> Dict[str, List[float]]:
+        return self._table
+
+    @table.setter
+    def table(self, table: Dict[str, List[float]]) -> None:
+        # the per-size terms of the pricing, computed once per table (the same
+        # values cost_ms would form on every call)
+        self._table = table
+        self._xs = [math.log(s) for s in self.sizes]
+        self._per = {n: [t / float(s) ** 3 for t, s in zip(ms, self.sizes)] for n, ms in table.items()}
+        self._lper = {n: [math.log(v) for v in per] for n, per in self._per.items()}
+
     # -- pricing ---------------------------------------------------------------
     def cost_ms(self, name: str, N: int, P: int, M: int) -> float:
-        ms = self.table[name]
+        ms = self._table[name]
+        per = self._per[name]  # ms per multiply-add at each size
+        xs = self._xs
         macs = float(N) * P * M
         d = macs ** (1.0 / 3.0)
-        per = [t / float(s) ** 3 for t, s in zip(ms, self.sizes)]  # ms per multiply-add at each size
         x = math.log(max(d, 1.0))
-        xs = [math.log(s) for s in self.sizes]
         if x <= xs[0]:
             # below the smallest size the time is launch-bound: no less than there
             return max(per[0] * macs, ms[0])
@@ -109,7 +122,8 @@ class Router:
             return per[-1] * macs
         k = bisect.bisect_right(xs, x) - 1
         w = (x - xs[k]) / (xs[k + 1] - xs[k])
-        lp = (1 - w) * math.log(per[k]) + w * math.log(per[k + 1])
+        lper = self._lper[name]
+        lp = (1 - w) * lper[k] + w * lper[k + 1]
         return math.exp(lp) * macs
 
     def choose(self, N: int, P: int, M: int, tol: float) -> Tuple[str, Config]:
@@ -236,6 +250,7 @@ class Request:
     method: str = ""
     cfg: Optional[Config] = None
     footprint: int = 0
+    ws_bytes: int = 0  # workspace of the chosen method (part of the footprint)
     slot: int = -1
     C: Optional[torch.Tensor] = None
     ws: Optional[torch.Tensor] = None
@@ -300,10 +315,11 @@ class Server:
             raise ValueError("inner dimensions differ: A is %dx%d, B is %dx%d" % (N, P, B.shape[0], B.shape[1]))
         M = B.shape[1]
         method, cfg = self.router.choose(N, P, M, tol)
-        fp = 8 * (N * P + P * M + N * M) + workspace_bytes(method, N, P, M, cfg)
+        ws = workspace_bytes(method, N, P, M, cfg)
+        fp = 8 * (N * P + P * M + N * M) + ws
         fut = Future()
         with self.lock:
-            r = Request(self.next_id, A, B, tol, self.adm.clock(), fut, method, cfg, fp, shape=(N, P, M))
+            r = Request(self.next_id, A, B, tol, self.adm.clock(), fut, method, cfg, fp, ws, shape=(N, P, M))
             self.adm.push(r)
             self.next_id += 1
         self.wake.set()
@@ -331,8 +347,7 @@ class Server:
                 with torch.cuda.stream(s):
                     N, P, M = r.shape
                     r.C = torch.empty((N, M), dtype=torch.float64, device=self.device)
-                    need = workspace_bytes(r.method, N, P, M, r.cfg)
-                    r.ws = torch.empty(max(need, 1), dtype=torch.uint8, device=self.device)
+                    r.ws = torch.empty(max(r.ws_bytes, 1), dtype=torch.uint8, device=self.device)
                     if self.gpu:
                         # the operands were produced on other streams: order this stream after them
                         s.wait_stream(torch.cuda.default_stream(self.device))
