@@ -129,6 +129,36 @@ def test_batch_at_the_count_limit(mmm):
     plan.close()
 
 
+def test_batch_empty_and_zero_depth_problems(mmm):
+    """Degenerate plans: problems with P = 0 (C is the empty sum, exact
+    zeros, for both methods) beside empty ones (N = 0 or M = 0: nothing
+    written), and a plan with no work at all, which still creates, launches
+    and closes cleanly."""
+    cfg = mmm.Config(split_type="int8", split_slices=6, split_bits=8)
+
+    def mats(N, P, M):
+        A = torch.rand(N, P, dtype=torch.float64, device="cuda")
+        B = torch.rand(P, M, dtype=torch.float64, device="cuda")
+        C = torch.full((N, M), float("nan"), dtype=torch.float64, device="cuda")
+        return A, B, C
+
+    probs = [(*mats(5, 0, 7), "dgemm"), (*mats(3, 0, 4), "split"), (*mats(0, 5, 5), "dgemm"), (*mats(4, 6, 0), "split"),
+             (*mats(6, 9, 5), "split")]
+    plan = mmm.Batch(probs, cfg)
+    for rep in range(2):
+        plan.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(probs[0][2], torch.zeros(5, 7, dtype=torch.float64, device="cuda"))
+        assert torch.equal(probs[1][2], torch.zeros(3, 4, dtype=torch.float64, device="cuda"))
+        w = mmm.multiply(probs[4][0], probs[4][1], "split", cfg)
+        assert torch.equal(probs[4][2].view(torch.int64), w.view(torch.int64))
+    plan.close()
+    empty = mmm.Batch([(*mats(0, 5, 5), "dgemm"), (*mats(4, 6, 0), "split")], cfg)
+    empty.launch()
+    torch.cuda.synchronize()
+    empty.close()
+
+
 def test_batch_full_workload(mmm, orc):
     """2048 problems, N, P, M uniform on 16..512, even index FP64 DGEMM, odd
     index split (bf16, 6 digits): one graph launch; sampled results checked
