@@ -94,3 +94,25 @@ def test_alone_equals_mix_up_to_4096_routed_by_measured_cost(serve, orc):
         e = orc.rel_err_inf(got, orc.naive_rows(An, Bn, rows), orc.norm_inf(An), orc.norm_inf(Bn))
         assert e <= tol, (k, e)
     print("methods used", sorted(methods), flush=True)
+
+
+def test_degenerate_requests(serve):
+    """Requests with an empty side (N = 0 or M = 0: an empty result) and with
+    P = 0 (the empty sum: exact zeros), at both tolerance classes, mixed with
+    an ordinary one; every future resolves with the right shape."""
+    z = lambda *s: torch.zeros(*s, dtype=torch.float64, device="cuda")  # noqa: E731
+    g = torch.Generator(device="cuda").manual_seed(21)
+    A = torch.rand((70, 90), generator=g, dtype=torch.float64, device="cuda")
+    B = torch.rand((90, 40), generator=g, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    cases = [(z(0, 5), z(5, 3), 1e-13), (z(4, 6), z(6, 0), 1e-10), (z(5, 0), z(0, 7), 1e-13), (z(3, 0), z(0, 4), 1e-10),
+             (A, B, 1e-13)]
+    srv = serve.Server(budget_bytes=1 << 30, streams=4)
+    out = [f.result(timeout=60) for f in [srv.submit(a, b, tol) for (a, b, tol) in cases]]
+    srv.close()
+    assert [tuple(c.shape) for c in out] == [(0, 3), (4, 0), (5, 7), (3, 4), (70, 40)]
+    assert torch.equal(out[2], z(5, 7)) and torch.equal(out[3], z(3, 4))
+    m, cfg = srv.router.choose(70, 90, 40, 1e-13)
+    from paper_1106_1347_amd import multiply
+
+    assert torch.equal(out[4].view(torch.int64), multiply(A, B, m, cfg).view(torch.int64))
