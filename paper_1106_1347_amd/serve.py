@@ -91,7 +91,7 @@ class Router:
     thumb is DGEMM below d = 1024 and the byte-digit int8 split above."""
 
     def __init__(self, table: Optional[Dict[str, List[float]]] = None, sizes: Sequence[int] = CAL_SIZES):
-        self.sizes = list(sizes)
+        self._sizes = list(sizes)
         self.table = dict(table or {})
 
     @property
@@ -100,11 +100,24 @@ class Router:
 
     @table.setter
     def table(self, table: Dict[str, List[float]]) -> None:
-        # the per-size terms of the pricing, computed once per table (the same
-        # values cost_ms would form on every call)
         self._table = table
-        self._xs = [math.log(s) for s in self.sizes]
-        self._per = {n: [t / float(s) ** 3 for t, s in zip(ms, self.sizes)] for n, ms in table.items()}
+        self._reprice()
+
+    @property
+    def sizes(self) -> List[int]:
+        return self._sizes
+
+    @sizes.setter
+    def sizes(self, sizes: Sequence[int]) -> None:
+        self._sizes = list(sizes)
+        self._reprice()
+
+    def _reprice(self) -> None:
+        # the per-size terms of the pricing, formed once whenever the table or
+        # the sizes are assigned (the same values cost_ms would form on every
+        # call); a table changed in place must be assigned again
+        self._xs = [math.log(s) for s in self._sizes]
+        self._per = {n: [t / float(s) ** 3 for t, s in zip(ms, self._sizes)] for n, ms in self._table.items()}
         self._lper = {n: [math.log(v) for v in per] for n, per in self._per.items()}
 
     # -- pricing ---------------------------------------------------------------

@@ -3,6 +3,7 @@ clock (the aging bound), method routing by a measured-cost table, and
 failure handling with a stub launch (no GPU)."""
 import types
 
+import numpy as np
 import pytest
 import torch
 
@@ -131,6 +132,41 @@ def test_router_prices_by_measured_table():
     assert r.cost_ms("dgemm", 4096, 4096, 4096) == pytest.approx(16.0)
     # the choice depends on the request only: repeated calls agree
     assert all(r.choose(300, 700, 900, 1e-10) == r.choose(300, 700, 900, 1e-10) for _ in range(3))
+
+
+def _price_by_definition(sizes, ms, N, P, M):
+    # time per multiply-add interpolated linearly in log d between the measured
+    # sizes (d = (N P M)^(1/3)), times N P M; below the smallest size no less than
+    # its measured time, above the largest its time per multiply-add
+    macs = float(N) * P * M
+    d = max(macs ** (1.0 / 3.0), 1.0)
+    per = np.array(ms) / np.array(sizes, dtype=np.float64) ** 3
+    if d <= sizes[0]:
+        return max(per[0] * macs, ms[0])
+    if d >= sizes[-1]:
+        return per[-1] * macs
+    return float(np.exp(np.interp(np.log(d), np.log(sizes), np.log(per)))) * macs
+
+
+def test_router_prices_follow_the_definition_after_any_assignment():
+    rng = np.random.default_rng(7)
+    names = sorted({n for c in CANDIDATES.values() for n, _, _ in c})
+    sizes = [32, 128, 512, 2048, 8192]
+    table = {n: sorted(rng.uniform(0.004, 40.0, len(sizes)).tolist()) for n in names}
+    r = Router(table, sizes)
+    shapes = [tuple(int(x) for x in rng.integers(1, 12000, 3)) for _ in range(400)] + [(1, 1, 1), (8192, 8192, 8192)]
+    for stage in range(3):
+        if stage == 1:
+            # new sizes for the same table: every price follows them
+            sizes = [64, 256, 1024, 4096, 16384]
+            r.sizes = sizes
+        if stage == 2:
+            table = {n: sorted(rng.uniform(0.004, 40.0, len(sizes)).tolist()) for n in names}
+            r.table = table
+        for n in names:
+            for (N, P, M) in shapes:
+                assert r.cost_ms(n, N, P, M) == pytest.approx(_price_by_definition(sizes, table[n], N, P, M),
+                                                              rel=1e-12), (stage, n, N, P, M)
 
 
 def test_router_table_round_trip(tmp_path):
