@@ -84,7 +84,7 @@ class TileTuner:
         return "%s/batch/%s_policy/with_%s_s%d_b%d" % (self.arch, method, c.split_type, c.split_slices, c.split_bits)
 
     def tiles_for(self, problems: Sequence[tuple], config: Optional[Config] = None) -> list:
-        """One tile per problem of a batch ((A, B, C, method) tuples): split
+        """One tile per problem of a batch ((A, B, C, method) tuples): DGEMM
         problems and split problems follow the policies ``tune_batch`` chose
         for batches with this split configuration (the per-class choices
         when none was chosen)."""
